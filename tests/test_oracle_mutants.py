@@ -1,0 +1,93 @@
+"""Planted mistakes in the oracle must be caught by its pins.
+
+Each case swaps one oracle function for a plausible wrong version (a dropped
+term, a wrong sign or index, a transposed operand) and checks that at least one
+pin test fails.  Everything runs on the CPU; nothing touches the GPU path.
+"""
+import numpy as np
+import pytest
+
+from oracle import nrc_oracle as O
+import tests.test_oracle_pins as P
+
+
+def _freq_no_pi(p, preset=O.PRESET_CONFIG):
+    return O.__dict__["_orig_freq"](p / np.pi, preset)
+
+
+def _one_blob_no_tails(s, k=O.N_BLOBS):
+    c = k * np.asarray(s, dtype=np.float64)
+    out = np.empty(np.shape(s) + (k,))
+    for j in range(k):
+        out[..., j] = O.quartic_cdf(j + 1 - c) - O.quartic_cdf(j - c)
+    return out
+
+
+def _forward_transposed(mats, h0):
+    return O.__dict__["_orig_forward"]([np.asarray(w).T if w.shape[0] == w.shape[1] else w for w in mats], h0)
+
+
+def _loss_no_stop_gradient(y_hat, y, eps=O.LOSS_EPS):
+    # differentiates through the denominator as well
+    y_hat = np.asarray(y_hat, float)
+    n = y_hat.shape[0]
+    lum = y_hat.mean(axis=1, keepdims=True)
+    den = lum * lum + eps
+    diff = y_hat - y
+    loss = float((diff * diff / den).sum() / (3 * n))
+    d_den = -(diff * diff / den ** 2).sum(axis=1, keepdims=True) * 2 * lum / 3
+    return loss, (2 * diff / den + d_den) / (3 * n)
+
+
+def _loss_wrong_sign(y_hat, y, eps=O.LOSS_EPS):
+    loss, g = O.__dict__["_orig_relative_l2"](y_hat, y, eps)
+    return loss, -g
+
+
+def _backward_no_mask(mats, hs, delta_out):
+    grads = [None] * len(mats)
+    delta = np.asarray(delta_out, float)
+    for l in range(len(mats) - 1, -1, -1):
+        grads[l] = delta.T @ hs[l]
+        g_in = delta @ np.asarray(mats[l], float)
+        if l == 0:
+            return grads, g_in
+        delta = g_in
+
+
+def _adam_swapped_betas(w, m, v, t, g, cfg):
+    swapped = O.AdamConfig(lr=cfg.lr, beta1=cfg.beta2, beta2=cfg.beta1, eps=cfg.eps)
+    return O.__dict__["_orig_adam"](w, m, v, t, g, swapped)
+
+
+def _adam_no_bias_correction(w, m, v, t, g, cfg):
+    t = t + 1
+    m = cfg.beta1 * m + (1 - cfg.beta1) * g
+    v = cfg.beta2 * v + (1 - cfg.beta2) * g * g
+    return w - cfg.lr * m / (np.sqrt(v) + cfg.eps), m, v, t
+
+
+MUTANTS = [
+    ("freq", _freq_no_pi, [P.test_freq_matches_libm_closed_form, P.test_freq_dyadic_points_exact]),
+    ("one_blob", _one_blob_no_tails, [P.test_one_blob_exact_dyadic_fixture, P.test_one_blob_invariants]),
+    ("forward", _forward_transposed, [P.test_forward_brute_force_tiny]),
+    ("relative_l2", _loss_no_stop_gradient, [P.test_loss_gradient_is_stop_gradient_derivative]),
+    ("relative_l2", _loss_wrong_sign, [P.test_loss_gradient_is_stop_gradient_derivative,
+                                       P.test_backward_matches_torch_autograd_fp64]),
+    ("backward", _backward_no_mask, [P.test_backward_central_differences_weights_and_inputs]),
+    ("adam", _adam_swapped_betas, [P.test_adam_matches_torch_optim_fp64]),
+    ("adam", _adam_no_bias_correction, [P.test_adam_constant_gradient_closed_form]),
+]
+
+
+@pytest.mark.parametrize("name,mutant,pins", MUTANTS, ids=[m[1].__name__ for m in MUTANTS])
+def test_pins_catch_planted_mistake(monkeypatch, name, mutant, pins):
+    monkeypatch.setitem(O.__dict__, "_orig_" + name, getattr(O, name))
+    monkeypatch.setattr(O, name, mutant)
+    caught = 0
+    for pin in pins:
+        try:
+            pin()
+        except AssertionError:
+            caught += 1
+    assert caught >= 1, f"no pin caught the planted mistake in {name}"
