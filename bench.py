@@ -1,0 +1,221 @@
+"""Benchmark of the radiance-cache hot path on one MI355X.
+
+A step is one 1920x1080 frame of the cache: encode 2,073,600 synthetic query
+records and run inference on them, encode 65,536 training records, and take
+four Adam steps of 16,384 records each (Sec. 3.4-3.5 of the paper).  Inputs
+are resident in HBM before the timed region.  The default form is plain FP32
+(vector ALUs); the FP16 and BF16 matrix-core forms run the same frame and are
+reported under "forms".  Prints one JSON line.
+
+    python bench.py [--steps K] [--warmup W] [--form fp32|fp16|bf16] [--no-forms]
+                    [--no-cpu-baseline] [--serve-requests R]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import synthdata as sd  # noqa: E402
+
+METRIC = "MLP queries/s + train samples/s (64-wide, 5 hidden); p50/p99 serve latency"
+N_QUERIES = 1920 * 1080
+N_TRAIN_BATCHES = 4
+TRAIN_BATCH = 16384
+WIDTH, N_HIDDEN = 64, 5
+FLOP_PER_QUERY = 2 * sd.n_params(WIDTH, N_HIDDEN)                 # 41,344
+FLOP_PER_TRAIN_SAMPLE = 2 * (sd.n_params() + (sd.n_params() - 64 * 64) + sd.n_params())  # 115,840
+PEAK_TFLOPS = {"fp32": 157.3, "fp16": 2500.0, "bf16": 2500.0}
+BOUND = {"fp32": "alu", "fp16": "mfma", "bf16": "mfma"}
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def frame_bench(form: str, steps: int, warmup: int):
+    import torch
+    from paper_2106_12372_amd import nrc as N
+
+    dev = torch.device("cuda", 0)
+    cfg = N.make_config(width=WIDTH, n_hidden=N_HIDDEN, precision=form)
+    cache = N.Cache(cfg, device=dev)
+    cache.set_weights(sd.glorot_weights(WIDTH, N_HIDDEN))
+    raw_q = torch.from_numpy(sd.raw_records(N_QUERIES, sd.SEED_QUERIES)).to(dev)
+    raw_r_np = sd.raw_records(N_TRAIN_BATCHES * TRAIN_BATCH, sd.SEED_RECORDS)
+    raw_r = torch.from_numpy(raw_r_np).to(dev)
+    y = torch.from_numpy(sd.targets(raw_r_np)).to(dev)
+    enc_q = torch.empty((N_QUERIES, 64), dtype=cache.enc_dtype, device=dev)
+    enc_r = torch.empty((N_TRAIN_BATCHES * TRAIN_BATCH, 64), dtype=cache.enc_dtype, device=dev)
+    rgb = torch.empty((N_QUERIES, 3), dtype=torch.float32, device=dev)
+    loss = torch.empty(N_TRAIN_BATCHES, dtype=torch.float32, device=dev)
+    skipped = torch.empty(N_TRAIN_BATCHES, dtype=torch.int32, device=dev)
+    scratch, _ = cache.scratch(TRAIN_BATCH)
+    y_b = [y[s * TRAIN_BATCH:(s + 1) * TRAIN_BATCH] for s in range(N_TRAIN_BATCHES)]
+    e_b = [enc_r[s * TRAIN_BATCH:(s + 1) * TRAIN_BATCH] for s in range(N_TRAIN_BATCHES)]
+    stream = torch.cuda.current_stream(dev)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+
+    def step(record: bool):
+        if record:
+            ev[0].record(stream)
+        N.nrc_encode(cache, raw_q, enc=enc_q)
+        if record:
+            ev[1].record(stream)
+        N.nrc_forward(cache, enc_q, rgb=rgb)
+        if record:
+            ev[2].record(stream)
+        N.nrc_encode(cache, raw_r, enc=enc_r)
+        if record:
+            ev[3].record(stream)
+        for s in range(N_TRAIN_BATCHES):
+            N.nrc_train_step(cache, e_b[s], y_b[s], loss=loss[s:s + 1], skipped=skipped[s:s + 1],
+                             scratch=scratch)
+        if record:
+            ev[4].record(stream)
+
+    for _ in range(warmup):
+        step(False)
+    torch.cuda.synchronize()
+    comp = np.zeros(4)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step(True)
+        ev[4].synchronize()
+        comp += [ev[i].elapsed_time(ev[i + 1]) for i in range(4)]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    comp /= steps
+    ms = elapsed * 1e3 / steps
+    t_fwd_s = comp[1] * 1e-3
+    achieved = N_QUERIES * FLOP_PER_QUERY / t_fwd_s / 1e12
+    enc_bytes = 2 if form != "fp32" else 4
+    out = {
+        "form": form,
+        "ms_per_step": ms,
+        "queries_per_s": N_QUERIES / (ms * 1e-3),
+        "train_samples_per_s": N_TRAIN_BATCHES * TRAIN_BATCH / (ms * 1e-3),
+        "components_ms": {"encode_queries": comp[0], "forward": comp[1], "encode_records": comp[2],
+                          "train_4_steps": comp[3]},
+        "query_pass_queries_per_s": N_QUERIES / ((comp[0] + comp[1]) * 1e-3),
+        "mlp_only_queries_per_s": N_QUERIES / t_fwd_s,
+        "train_only_samples_per_s": N_TRAIN_BATCHES * TRAIN_BATCH / (comp[3] * 1e-3),
+        "roofline": {
+            "kernel": "k_fwd_mfma" if form != "fp32" else "k_fwd_fp32",
+            "bound": BOUND[form],
+            "achieved": achieved,
+            "peak": PEAK_TFLOPS[form],
+            "unit": "TFLOP/s",
+            "frac": achieved / PEAK_TFLOPS[form],
+            "traffic": None,
+            "flop_per_query": FLOP_PER_QUERY,
+            "queries_per_launch": N_QUERIES,
+            "avg_launch_ms": comp[1],
+            "hbm_gbs_algorithmic": N_QUERIES * (64 * enc_bytes + 12) / t_fwd_s / 1e9,
+        },
+        "final_loss": float(loss[-1].item()),
+        "skipped_steps": int(skipped.sum().item()),
+    }
+    frame_flop = N_QUERIES * FLOP_PER_QUERY + N_TRAIN_BATCHES * TRAIN_BATCH * FLOP_PER_TRAIN_SAMPLE
+    out["frame_tflops"] = frame_flop / (ms * 1e-3) / 1e12
+    return out
+
+
+def cpu_baseline():
+    """The FP64 oracle on the host cores: one full frame (encode + inference of
+    2,073,600 queries, encode of 65,536 records, four training steps)."""
+    from oracle import nrc_oracle as O
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:  # pragma: no cover
+        threads = len(os.sched_getaffinity(0))
+    raw_q = sd.raw_records(N_QUERIES, sd.SEED_QUERIES)
+    raw_r = sd.raw_records(N_TRAIN_BATCHES * TRAIN_BATCH, sd.SEED_RECORDS)
+    y = sd.targets(raw_r).astype(np.float64)
+    st = O.CacheState(sd.glorot_weights(WIDTH, N_HIDDEN))
+    t0 = time.perf_counter()
+    q_enc = O.encode(raw_q)
+    O.predict(st, q_enc)
+    r_enc = O.encode(raw_r)
+    for s in range(N_TRAIN_BATCHES):
+        sl = slice(s * TRAIN_BATCH, (s + 1) * TRAIN_BATCH)
+        O.train_step(st, r_enc[sl], y[sl])
+    t = time.perf_counter() - t0
+    return {"value": N_QUERIES / t, "unit": "queries/s", "cores": int(threads), "kind": "oracle",
+            "sample": "one full frame: FP64 NumPy encode + inference of 2,073,600 queries, encode of "
+                      "65,536 records, four 16,384-record training steps",
+            "seconds": t, "train_samples_per_s": N_TRAIN_BATCHES * TRAIN_BATCH / t}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--form", default="fp32", choices=["fp32", "fp16", "bf16"])
+    ap.add_argument("--no-forms", action="store_true", help="skip the other precision forms")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (the cache is a "
+              "single-GPU workload; see the sharding notes in the design document)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    torch.cuda.set_device(0)
+
+    log(f"frame bench: form {args.form}, {args.warmup} warmup + {args.steps} timed steps")
+    main_res = frame_bench(args.form, args.steps, args.warmup)
+    forms = {}
+    if not args.no_forms:
+        for f in ("fp32", "fp16", "bf16"):
+            if f == args.form:
+                continue
+            log(f"frame bench: form {f}")
+            forms[f] = frame_bench(f, args.steps, args.warmup)
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline: oracle on one frame")
+        cpu = cpu_baseline()
+    res = {
+        "metric": METRIC,
+        "value": main_res["queries_per_s"],
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": main_res["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp32": "f32", "fp16": "f16", "bf16": "bf16"}[args.form],
+        "data": "synthetic",
+        "config": {"workload": f"1920x1080 frame: {N_QUERIES} queries (encode + inference) and "
+                               f"{N_TRAIN_BATCHES}x{TRAIN_BATCH}-record training steps, {args.form} form",
+                   "width": WIDTH, "n_hidden": N_HIDDEN, "queries": N_QUERIES,
+                   "train_batches": N_TRAIN_BATCHES, "train_batch": TRAIN_BATCH, "form": args.form},
+        "train_samples_per_s": main_res["train_samples_per_s"],
+        "components_ms": main_res["components_ms"],
+        "mlp_only_queries_per_s": main_res["mlp_only_queries_per_s"],
+        "train_only_samples_per_s": main_res["train_only_samples_per_s"],
+        "frame_tflops": main_res["frame_tflops"],
+        "roofline": main_res["roofline"],
+        "cpu_baseline": cpu,
+        "forms": forms,
+    }
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

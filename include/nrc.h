@@ -1,0 +1,248 @@
+/*
+ * nrc.h - C ABI of the MI355X neural radiance cache library.
+ *
+ * The cache is the network of Mueller et al., "Real-time Neural Radiance
+ * Caching for Path Tracing" (arXiv 2106.12372): a bias-free ReLU MLP that maps
+ * an encoded path vertex to cached scattered radiance (Sec. 3, Eq. 1), queried
+ * once per terminal vertex and trained online from arrays of training records
+ * (Sec. 3.5), with the input encodings of Sec. 3.6 / Table "parameters", the
+ * architecture of Sec. 5, the relative L2 loss of Eq. 5 and Adam (Sec. 5).
+ *
+ * Conventions shared by every entry point:
+ *  - Every call returns an int status (NRC_OK or a negative error code); no
+ *    exception crosses the ABI.  nrc_last_error() gives a message for the last
+ *    failing call on the calling thread.
+ *  - Argument errors (null or misaligned pointers, negative sizes, bad enums,
+ *    too-small workspaces) are reported before any device call is made.
+ *  - The library never allocates device memory: the caller allocates and frees
+ *    every device buffer (the cache workspace, scratch, inputs, outputs).
+ *    Host-side handles are allocated by the library and freed by *_destroy.
+ *  - "stream" arguments are hipStream_t values passed as void*; NULL is the
+ *    default stream.  Work is enqueued asynchronously; nothing synchronises
+ *    the host unless stated.
+ *  - Device pointers must be 16-byte aligned.  Row-major layouts throughout.
+ *  - A cache handle must not be used from two threads at once; the serving
+ *    entry points (nrc_serve_*) are thread-safe.
+ */
+#ifndef NRC_H
+#define NRC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+#define NRC_OK 0
+#define NRC_PENDING 1
+#define NRC_EINVAL (-1)
+#define NRC_ENOMEM (-2)
+#define NRC_EDEVICE (-3)
+#define NRC_EBUSY (-4)
+#define NRC_ENOTFOUND (-5)
+
+/* Arithmetic of the layer products. */
+#define NRC_FP32 0 /* plain FP32 vector arithmetic, FP32 encoded input */
+#define NRC_FP16 1 /* FP16 matrix-core products, FP32 accumulation and master weights */
+#define NRC_BF16 2 /* BF16 matrix-core products, FP32 accumulation and master weights */
+
+/* Input encoding presets (Sec. 3.6, Table "parameters"). */
+#define NRC_PRESET_CONFIG 0 /* 6 octaves sin+cos, roughness as is, zero pad */
+#define NRC_PRESET_PAPER 1  /* 12 sines, one-blob of 1-exp(-r), pad with one */
+
+/* Raw path-vertex record layouts (FP32, row-major). */
+#define NRC_RAW14 0 /* pos 3 | dir (u,w) 2 | normal (u,w) 2 | roughness | diffuse 3 | specular 3 */
+#define NRC_RAW16 1 /* pos 3 | dir xyz 3 | normal xyz 3 | roughness | diffuse 3 | specular 3 */
+
+/* Width of the encoded input (62 features padded to 64, Sec. 3.6). */
+#define NRC_ENC_WIDTH 64
+
+/*
+ * Cache configuration.  Architecture of Sec. 5: `n_hidden` hidden layers of
+ * `width` ReLU neurons, no biases, a linear output of `n_out` (= 3, RGB).
+ * Supported: width 64 or 128 (FP32: 64 only); n_hidden 1..8; n_out 3.
+ * Adam (Sec. 5 Optimizer): lr, beta1, beta2, adam_eps; loss_eps is the eps of
+ * Eq. 5; loss_scale multiplies the loss gradient before the reduced-precision
+ * backward pass and is divided out before Adam (use 1 for FP32).
+ */
+typedef struct nrc_config {
+    int32_t width;
+    int32_t n_hidden;
+    int32_t n_out;
+    int32_t precision;  /* NRC_FP32 / NRC_FP16 / NRC_BF16 */
+    int32_t enc_preset; /* NRC_PRESET_* */
+    float lr;
+    float beta1;
+    float beta2;
+    float adam_eps;
+    float loss_eps;
+    float loss_scale;
+    uint64_t seed; /* reserved; weights are always set explicitly */
+} nrc_config;
+
+typedef struct nrc_cache nrc_cache;
+
+/* Fills *cfg with the defaults: 64, 5, 3, FP16, CONFIG, 1e-2, 0.9, 0.99, 1e-8,
+ * 0.01, 128, 0.  Returns NRC_EINVAL on NULL. */
+int nrc_config_default(nrc_config* cfg);
+
+/* Message describing the last failure on the calling thread ("" if none).
+ * Valid until the next nrc_* call on the same thread. */
+const char* nrc_last_error(void);
+
+/* Number of weights: width*64 + (n_hidden-1)*width^2 + 3*width (Sec. 5). */
+int64_t nrc_param_count(const nrc_config* cfg);
+
+/* Bytes of device workspace a cache needs (master weights, Adam moments, step
+ * counter, reduced-precision weight copies).  0 on an invalid config. */
+size_t nrc_cache_bytes(const nrc_config* cfg);
+
+/* Bytes of device scratch one nrc_train_step / nrc_backward over n records
+ * needs (per-tile weight-gradient partials and loss partials). */
+size_t nrc_train_scratch_bytes(const nrc_config* cfg, int64_t n);
+
+/* Bytes per element of the encoded input at the cache precision (4 or 2). */
+int nrc_enc_elem_bytes(const nrc_config* cfg);
+
+/*
+ * Creates a cache in the caller's device workspace `dev_ws` of at least
+ * nrc_cache_bytes(cfg) bytes.  Weights start at zero; call nrc_set_weights.
+ * Does not take ownership of dev_ws; nrc_cache_destroy does not free it.
+ * `stream` is the stream used for the set-up copies.
+ */
+int nrc_cache_create(const nrc_config* cfg, void* dev_ws, size_t ws_bytes, void* stream,
+                     nrc_cache** out);
+int nrc_cache_destroy(nrc_cache* cache);
+int nrc_cache_config(const nrc_cache* cache, nrc_config* out);
+
+/*
+ * Weights as one flat FP32 host array, matrices in layer order W_0 .. W_L,
+ * each row-major [out][in] (Sec. 5 architecture; n = nrc_param_count).
+ * set: also resets the Adam moments and step count; synchronises `stream`.
+ * get: copies the FP32 master weights out; synchronises `stream`.
+ */
+int nrc_set_weights(nrc_cache* cache, const float* host_w, int64_t n, void* stream);
+int nrc_get_weights(const nrc_cache* cache, float* host_w, int64_t n, void* stream);
+
+/*
+ * Same as nrc_set_weights with the weights in device memory (FP32, n floats):
+ * enqueues the copy and the rebuild of the reduced-precision copies on
+ * `stream` without synchronising.  Adam moments and step count are reset.
+ * Used by the autograd wrapper, whose weights are a device tensor.
+ */
+int nrc_set_weights_device(nrc_cache* cache, const float* dev_w, int64_t n, void* stream);
+
+/*
+ * Full optimiser state for checkpoint/resume: weights, Adam first and second
+ * moments (each n floats, host) and the step count t.  Synchronises `stream`.
+ */
+int nrc_get_state(const nrc_cache* cache, float* host_w, float* host_m, float* host_v,
+                  int64_t n, int64_t* t, void* stream);
+int nrc_set_state(nrc_cache* cache, const float* host_w, const float* host_m,
+                  const float* host_v, int64_t n, int64_t t, void* stream);
+
+/*
+ * Input encoding (Sec. 3.6, Table "parameters"): raw device records
+ * [n][14] (NRC_RAW14) or [n][16] (NRC_RAW16) FP32 -> enc [n][64] at the cache
+ * precision (FP32 for NRC_FP32, else FP16/BF16), using the cache's preset.
+ * Position: frequency encoding; direction and normal: spherical coordinates
+ * then one-blob with 4 quartic blobs; roughness, albedos as in the preset.
+ * n == 0 is a no-op.
+ */
+int nrc_encode(const nrc_cache* cache, const float* raw, int raw_layout, int64_t n, void* enc,
+               void* stream);
+
+/*
+ * Batched inference (Sec. 4, Fig. "fully-fused-illustration"): rgb[n][3]
+ * (FP32, device) = network(enc[n][64]) with the current weights.  Any n >= 0.
+ */
+int nrc_forward(nrc_cache* cache, const void* enc, int64_t n, float* rgb, void* stream);
+
+/*
+ * One optimisation step (Sec. 3.4-3.5, Eq. 5, Sec. 5): forward over the batch
+ * enc[n][64] with targets target[n][3] (FP32), relative L2 loss, backward,
+ * weight gradients summed over the batch, then one Adam update of the master
+ * weights.  The loss (FP32 scalar) is written to *loss_dev and the skip flag
+ * (1 if the gradient was not finite and the step was skipped, else 0) to
+ * *skipped_dev, both device pointers (may be NULL).  `scratch` is device memory
+ * of nrc_train_scratch_bytes(cfg, n) bytes.  n must be >= 1.
+ */
+int nrc_train_step(nrc_cache* cache, const void* enc, const float* target, int64_t n,
+                   void* scratch, size_t scratch_bytes, float* loss_dev, int32_t* skipped_dev,
+                   void* stream);
+
+/*
+ * Backward pass for the autograd form (Sec. 4 "Training the fully fused
+ * neural network"): given any upstream gradient grad_rgb[n][3] (FP32, device)
+ * of the outputs nrc_forward produced for enc[n][64], writes grad_w (FP32,
+ * device, nrc_param_count floats in the weight layout above, summed over the
+ * batch) and, if grad_enc is not NULL, grad_enc[n][64] (FP32, device).  The
+ * kernel recomputes the forward activations from enc instead of storing them
+ * between the calls.  No loss scaling is applied; the reduced-precision forms
+ * carry the gradients in FP16/BF16 inside the kernel.  `scratch` as for
+ * nrc_train_step.  n must be >= 1.
+ */
+int nrc_backward(nrc_cache* cache, const void* enc, const float* grad_rgb, int64_t n,
+                 void* scratch, size_t scratch_bytes, float* grad_w, float* grad_enc,
+                 void* stream);
+
+/* ------------------------------------------------------------------------- */
+/* Serving: continuous batching of inference and training requests over     */
+/* several resident caches.                                                  */
+/* ------------------------------------------------------------------------- */
+#define NRC_REQ_INFER 0
+#define NRC_REQ_TRAIN 1
+
+typedef struct nrc_server nrc_server;
+
+typedef struct nrc_serve_config {
+    int32_t n_caches;        /* number of independent caches (1..64) */
+    nrc_config cache_cfg;    /* configuration shared by all caches */
+    void* arena;             /* device memory for caches and per-request scratch */
+    size_t arena_bytes;
+    int32_t n_streams;       /* HIP streams the scheduler launches on (1..16) */
+    int32_t max_inflight;    /* requests on the device at once (>= 1) */
+} nrc_serve_config;
+
+typedef struct nrc_request {
+    int32_t kind;            /* NRC_REQ_INFER or NRC_REQ_TRAIN */
+    const void* enc;         /* device [n][64] at the cache precision */
+    const float* target;     /* device [n][3] (training only) */
+    float* rgb;              /* device [n][3] output (inference only) */
+    int64_t n;
+} nrc_request;
+
+typedef struct nrc_result {
+    int32_t status;          /* NRC_OK, NRC_PENDING or an error */
+    int32_t skipped;         /* training: step skipped on a non-finite gradient */
+    float loss;              /* training: loss of the step */
+    double t_submit;         /* seconds, monotonic clock */
+    double t_start;          /* seconds, when launched */
+    double t_done;           /* seconds, when its completion was observed */
+} nrc_result;
+
+/* Creates the server: carves one cache workspace per cache out of the arena
+ * and keeps the remainder for per-request scratch.  Weights start at zero. */
+int nrc_serve_create(const nrc_serve_config* cfg, nrc_server** out);
+/* Sets the weights of one cache (synchronous). */
+int nrc_serve_set_weights(nrc_server* srv, int cache_id, const float* host_w, int64_t n);
+int nrc_serve_get_weights(nrc_server* srv, int cache_id, float* host_w, int64_t n);
+/* Queues a request and returns a ticket without blocking.  NRC_ENOMEM if the
+ * request could never fit the arena.  Request buffers must stay valid until
+ * nrc_serve_poll returns NRC_OK for the ticket.  Requests on one cache run in
+ * submission order. */
+int nrc_serve_submit(nrc_server* srv, int cache_id, const nrc_request* req, uint64_t* ticket);
+/* NRC_PENDING until the request has finished, then NRC_OK and *res filled
+ * (once; a finished ticket is then forgotten: NRC_ENOTFOUND afterwards). */
+int nrc_serve_poll(nrc_server* srv, uint64_t ticket, nrc_result* res);
+/* Blocks until every submitted request has finished. */
+int nrc_serve_drain(nrc_server* srv);
+/* NRC_EBUSY while requests are pending (call nrc_serve_drain first). */
+int nrc_serve_destroy(nrc_server* srv);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NRC_H */

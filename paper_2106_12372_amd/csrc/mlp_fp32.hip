@@ -1,0 +1,292 @@
+// Plain FP32 form of the network (Sec. 4 and Sec. 5 "Architecture"), on the
+// vector ALUs only: the precision baseline for the matrix-core forms.
+//
+// Inference: one lane per query; the query's 64 activations live in VGPRs and
+// every weight is a wave-uniform operand fetched with scalar loads, so a layer
+// is 4096 FMAs per lane with no LDS or cross-lane traffic.
+//
+// Training: a workgroup of 4 waves owns a tile of 64 records.  Activations of
+// every layer stay in LDS ([sample][feature], padded rows).  In the forward and
+// data-backward passes wave w produces features 16w..16w+15 of all 64 samples
+// (lane = sample); for the weight gradient it produces rows 16w..16w+15 of
+// dW_l for all 64 input features (lane = input feature), summing over the
+// tile's samples.  Each tile writes its dW partial; a separate fixed-order
+// reduction sums the partials (no atomics, so results are reproducible).
+#include "nrc_internal.h"
+
+namespace nrc {
+namespace {
+
+constexpr int kW = 64;      // the FP32 form supports width 64
+constexpr int kLd = 68;     // padded LDS row stride (floats)
+constexpr int kTile = kTrainTile;
+
+__global__ __launch_bounds__(256) void k_fwd_fp32(const float* __restrict__ w,
+                                                  const float* __restrict__ enc, int64_t n,
+                                                  float* __restrict__ rgb, int n_hidden) {
+    const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (s >= n) return;
+    float h[kW];
+    const float4* row = reinterpret_cast<const float4*>(enc + s * kEncWidth);
+    #pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const float4 v = row[q];
+        h[4 * q] = v.x; h[4 * q + 1] = v.y; h[4 * q + 2] = v.z; h[4 * q + 3] = v.w;
+    }
+    const float* wl = w;
+    for (int l = 0; l < n_hidden; ++l) {
+        float z[kW];
+        #pragma unroll
+        for (int o = 0; o < kW; ++o) {
+            float acc = 0.0f;
+            #pragma unroll
+            for (int k = 0; k < kW; ++k) acc = fmaf(wl[o * kW + k], h[k], acc);
+            z[o] = acc;
+        }
+        #pragma unroll
+        for (int o = 0; o < kW; ++o) h[o] = fmaxf(z[o], 0.0f);
+        wl += kW * kW;
+    }
+    float y[kNOut];
+    #pragma unroll
+    for (int o = 0; o < kNOut; ++o) {
+        float acc = 0.0f;
+        #pragma unroll
+        for (int k = 0; k < kW; ++k) acc = fmaf(wl[o * kW + k], h[k], acc);
+        y[o] = acc;
+    }
+    rgb[s * 3 + 0] = y[0];
+    rgb[s * 3 + 1] = y[1];
+    rgb[s * 3 + 2] = y[2];
+}
+
+// Fixed-order sum over the 64 lanes of a wave (same tree on every call).
+__device__ inline float wave_sum(float v) {
+    #pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// UPSTREAM = false: targets given, relative L2 loss (Eq. 5) produces dL/dy.
+// UPSTREAM = true : tgt holds an upstream gradient dL/dy directly.
+template <bool UPSTREAM, bool GENC>
+__global__ __launch_bounds__(256) void k_train_fp32(const float* __restrict__ w,
+                                                    const float* __restrict__ enc,
+                                                    const float* __restrict__ tgt, int64_t n,
+                                                    int n_hidden, int n_params, float loss_eps,
+                                                    float grad_scale, float* __restrict__ partials,
+                                                    float* __restrict__ loss_part,
+                                                    float* __restrict__ genc) {
+    extern __shared__ __attribute__((aligned(16))) float smem[];
+    float* hs = smem;                                     // (n_hidden+1) x [64][kLd]
+    float* dbuf0 = hs + (n_hidden + 1) * kTile * kLd;     // 2 x [64][kLd]
+    float* dbuf1 = dbuf0 + kTile * kLd;
+    float* dout = dbuf1 + kTile * kLd;                    // [64][4]
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t tile = blockIdx.x;
+    const int64_t row = tile * kTile + lane;
+    const bool valid = row < n;
+    float* part = partials + tile * (int64_t)n_params;
+
+    // Stage the tile's inputs as h_0 (zeros past the end of the batch).
+    for (int i = tid; i < kTile * 16; i += 256) {
+        const int s = i >> 4, q = i & 15;
+        const int64_t r = tile * kTile + s;
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (r < n) v = reinterpret_cast<const float4*>(enc + r * kEncWidth)[q];
+        *reinterpret_cast<float4*>(hs + s * kLd + 4 * q) = v;
+    }
+    __syncthreads();
+
+    // Forward: wave w writes features 16w..16w+15 of every sample (lane = sample).
+    const float* wl = w;
+    for (int l = 0; l < n_hidden; ++l) {
+        const float* hin = hs + l * kTile * kLd + lane * kLd;
+        float* hout = hs + (l + 1) * kTile * kLd + lane * kLd;
+        float acc[16];
+        #pragma unroll
+        for (int j = 0; j < 16; ++j) acc[j] = 0.0f;
+        #pragma unroll
+        for (int k4 = 0; k4 < 16; ++k4) {
+            const float4 hv = *reinterpret_cast<const float4*>(hin + 4 * k4);
+            #pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                const float* wr = wl + (16 * wave + j) * kW + 4 * k4;
+                acc[j] = fmaf(wr[0], hv.x, acc[j]);
+                acc[j] = fmaf(wr[1], hv.y, acc[j]);
+                acc[j] = fmaf(wr[2], hv.z, acc[j]);
+                acc[j] = fmaf(wr[3], hv.w, acc[j]);
+            }
+        }
+        #pragma unroll
+        for (int j4 = 0; j4 < 4; ++j4)
+            *reinterpret_cast<float4*>(hout + 16 * wave + 4 * j4) =
+                make_float4(fmaxf(acc[4 * j4], 0.f), fmaxf(acc[4 * j4 + 1], 0.f),
+                            fmaxf(acc[4 * j4 + 2], 0.f), fmaxf(acc[4 * j4 + 3], 0.f));
+        wl += kW * (l == 0 ? kEncWidth : kW);
+        __syncthreads();
+    }
+    const float* wout = wl;                               // [3][64]
+    const float* hlast = hs + n_hidden * kTile * kLd;
+
+    // Output layer, loss and dL/dy (wave 0, lane = sample).
+    if (wave == 0) {
+        float y[kNOut] = {0.f, 0.f, 0.f};
+        const float* hr = hlast + lane * kLd;
+        #pragma unroll
+        for (int k = 0; k < kW; ++k) {
+            const float hv = hr[k];
+            #pragma unroll
+            for (int o = 0; o < kNOut; ++o) y[o] = fmaf(wout[o * kW + k], hv, y[o]);
+        }
+        float d[kNOut] = {0.f, 0.f, 0.f};
+        float lterm = 0.0f;
+        if (valid) {
+            if (UPSTREAM) {
+                #pragma unroll
+                for (int o = 0; o < kNOut; ++o) d[o] = tgt[row * 3 + o] * grad_scale;
+            } else {
+                const float lum = (y[0] + y[1] + y[2]) * (1.0f / 3.0f);
+                const float inv_den = 1.0f / (lum * lum + loss_eps);
+                #pragma unroll
+                for (int o = 0; o < kNOut; ++o) {
+                    const float diff = y[o] - tgt[row * 3 + o];
+                    lterm = fmaf(diff * diff, inv_den, lterm);
+                    d[o] = 2.0f * diff * inv_den * grad_scale;
+                }
+            }
+        }
+        *reinterpret_cast<float4*>(dout + lane * 4) = make_float4(d[0], d[1], d[2], 0.f);
+        const float tot = wave_sum(lterm);
+        if (lane == 0) loss_part[tile] = tot;
+    }
+    __syncthreads();
+
+    // delta_H = W_H^T dL/dy, masked by ReLU'(z_H); wave w: features 16w..16w+15.
+    {
+        const float4 dv = *reinterpret_cast<const float4*>(dout + lane * 4);
+        const float* hr = hlast + lane * kLd + 16 * wave;
+        float* dst = dbuf0 + lane * kLd + 16 * wave;
+        #pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const int i = 16 * wave + j;
+            float g = wout[i] * dv.x;
+            g = fmaf(wout[kW + i], dv.y, g);
+            g = fmaf(wout[2 * kW + i], dv.z, g);
+            dst[j] = hr[j] > 0.0f ? g : 0.0f;
+        }
+    }
+    // dW_H[o][i] = sum_s dL/dy[s][o] h_H[s][i]; wave o < 3, lane = i.
+    if (wave < kNOut) {
+        float acc = 0.0f;
+        for (int s = 0; s < kTile; ++s) acc = fmaf(dout[s * 4 + wave], hlast[s * kLd + lane], acc);
+        part[(n_params - kNOut * kW) + wave * kW + lane] = acc;
+    }
+    __syncthreads();
+
+    float* dcur = dbuf0;
+    float* dnxt = dbuf1;
+    int off = n_params - kNOut * kW;
+    for (int l = n_hidden - 1; l >= 0; --l) {
+        const int cols = (l == 0) ? kEncWidth : kW;
+        off -= kW * cols;
+        const float* wlay = w + off;
+        const float* hl = hs + l * kTile * kLd;
+        // dW_l rows 16w..16w+15, lane = input feature i.
+        {
+            float acc[16];
+            #pragma unroll
+            for (int j = 0; j < 16; ++j) acc[j] = 0.0f;
+            for (int s = 0; s < kTile; ++s) {
+                const float hv = hl[s * kLd + lane];
+                const float* dr = dcur + s * kLd + 16 * wave;
+                #pragma unroll
+                for (int j4 = 0; j4 < 4; ++j4) {
+                    const float4 dv = *reinterpret_cast<const float4*>(dr + 4 * j4);
+                    acc[4 * j4] = fmaf(dv.x, hv, acc[4 * j4]);
+                    acc[4 * j4 + 1] = fmaf(dv.y, hv, acc[4 * j4 + 1]);
+                    acc[4 * j4 + 2] = fmaf(dv.z, hv, acc[4 * j4 + 2]);
+                    acc[4 * j4 + 3] = fmaf(dv.w, hv, acc[4 * j4 + 3]);
+                }
+            }
+            #pragma unroll
+            for (int j = 0; j < 16; ++j) part[off + (16 * wave + j) * cols + lane] = acc[j];
+        }
+        // delta_l = W_l^T delta_{l+1}, masked (l >= 1); or dL/dh_0 (l == 0).
+        if (l >= 1 || GENC) {
+            float acc[16];
+            #pragma unroll
+            for (int j = 0; j < 16; ++j) acc[j] = 0.0f;
+            const float* dr = dcur + lane * kLd;
+            #pragma unroll
+            for (int o4 = 0; o4 < 16; ++o4) {
+                const float4 dv = *reinterpret_cast<const float4*>(dr + 4 * o4);
+                #pragma unroll
+                for (int j = 0; j < 16; ++j) {
+                    const float* wc = wlay + (4 * o4) * cols + 16 * wave + j;
+                    acc[j] = fmaf(wc[0], dv.x, acc[j]);
+                    acc[j] = fmaf(wc[cols], dv.y, acc[j]);
+                    acc[j] = fmaf(wc[2 * cols], dv.z, acc[j]);
+                    acc[j] = fmaf(wc[3 * cols], dv.w, acc[j]);
+                }
+            }
+            if (l >= 1) {
+                const float* hr = hl + lane * kLd + 16 * wave;
+                float* dst = dnxt + lane * kLd + 16 * wave;
+                #pragma unroll
+                for (int j = 0; j < 16; ++j) dst[j] = hr[j] > 0.0f ? acc[j] : 0.0f;
+            } else if (valid) {
+                #pragma unroll
+                for (int j4 = 0; j4 < 4; ++j4)
+                    *reinterpret_cast<float4*>(genc + row * kEncWidth + 16 * wave + 4 * j4) =
+                        make_float4(acc[4 * j4], acc[4 * j4 + 1], acc[4 * j4 + 2], acc[4 * j4 + 3]);
+            }
+        }
+        __syncthreads();
+        float* t = dcur; dcur = dnxt; dnxt = t;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_fwd_fp32(const Geo& d, const float* w, const float* enc, int64_t n, float* rgb,
+                           hipStream_t s) {
+    const int64_t blocks = (n + 255) / 256;
+    if (blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fwd_fp32, dim3((unsigned)blocks), dim3(256), 0, s, w, enc, n, rgb,
+                       d.H);
+    return hipGetLastError();
+}
+
+size_t fp32_train_lds_bytes(int n_hidden) {
+    return ((size_t)(n_hidden + 1) * kTile * kLd + 2 * kTile * kLd + kTile * 4) * sizeof(float);
+}
+
+hipError_t launch_train_fp32(const Geo& d, const float* w, const float* enc, const float* tgt,
+                             int64_t n, bool upstream, float loss_eps, float grad_scale,
+                             float* partials, float* loss_part, float* genc, hipStream_t s) {
+    const int64_t tiles = (n + kTile - 1) / kTile;
+    if (tiles == 0) return hipSuccess;
+    const size_t lds = fp32_train_lds_bytes(d.H);
+    const dim3 grid((unsigned)tiles), block(256);
+    if (!upstream) {
+        auto k = k_train_fp32<false, false>;
+        (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipLaunchKernelGGL(k, grid, block, lds, s, w, enc, tgt, n, d.H, d.n_params(),
+                           loss_eps, grad_scale, partials, loss_part, genc);
+    } else if (genc) {
+        auto k = k_train_fp32<true, true>;
+        (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipLaunchKernelGGL(k, grid, block, lds, s, w, enc, tgt, n, d.H, d.n_params(),
+                           loss_eps, grad_scale, partials, loss_part, genc);
+    } else {
+        auto k = k_train_fp32<true, false>;
+        (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipLaunchKernelGGL(k, grid, block, lds, s, w, enc, tgt, n, d.H, d.n_params(),
+                           loss_eps, grad_scale, partials, loss_part, genc);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace nrc

@@ -1,0 +1,409 @@
+// C ABI of the radiance-cache library: argument validation, the layout of the
+// caller-owned device workspaces, and the launch sequences of each entry point.
+// The library allocates no device memory of its own.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "nrc_api_internal.h"
+#include "nrc_internal.h"
+
+using nrc::Geo;
+
+namespace {
+
+thread_local std::string g_err;
+
+}  // namespace
+
+namespace nrc {
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int ok() {
+    g_err.clear();
+    return NRC_OK;
+}
+
+int device_fail(hipError_t e, const char* what) {
+    return fail(NRC_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
+
+int validate_config(const nrc_config* c) {
+    if (!c) return fail(NRC_EINVAL, "config is NULL");
+    if (c->width != 64 && c->width != 128) return fail(NRC_EINVAL, "width must be 64 or 128 (got %d)", c->width);
+    if (c->n_hidden < 1 || c->n_hidden > 8) return fail(NRC_EINVAL, "n_hidden must be in 1..8 (got %d)", c->n_hidden);
+    if (c->n_out != 3) return fail(NRC_EINVAL, "n_out must be 3 (got %d)", c->n_out);
+    if (c->precision != NRC_FP32 && c->precision != NRC_FP16 && c->precision != NRC_BF16)
+        return fail(NRC_EINVAL, "unknown precision %d", c->precision);
+    if (c->enc_preset != NRC_PRESET_CONFIG && c->enc_preset != NRC_PRESET_PAPER)
+        return fail(NRC_EINVAL, "unknown encoding preset %d", c->enc_preset);
+    if (c->precision == NRC_FP32 && (c->width != 64 || c->n_hidden > 6))
+        return fail(NRC_EINVAL, "the FP32 form supports width 64 and n_hidden <= 6");
+    if (c->precision != NRC_FP32 && c->width == 128 && c->n_hidden > 5)
+        return fail(NRC_EINVAL, "width 128 supports n_hidden <= 5");
+    if (!(c->lr > 0.0f) || !std::isfinite(c->lr)) return fail(NRC_EINVAL, "lr must be positive");
+    if (!(c->beta1 >= 0.0f && c->beta1 < 1.0f) || !(c->beta2 >= 0.0f && c->beta2 < 1.0f))
+        return fail(NRC_EINVAL, "Adam betas must be in [0, 1)");
+    if (!(c->adam_eps >= 0.0f) || !std::isfinite(c->adam_eps)) return fail(NRC_EINVAL, "adam_eps must be >= 0");
+    if (!(c->loss_eps > 0.0f) || !std::isfinite(c->loss_eps)) return fail(NRC_EINVAL, "loss_eps must be positive");
+    if (!(c->loss_scale > 0.0f) || !std::isfinite(c->loss_scale)) return fail(NRC_EINVAL, "loss_scale must be positive");
+    return NRC_OK;
+}
+
+CacheLayout cache_layout(const nrc_config& c) {
+    const Geo d(c.width, c.n_hidden);
+    const size_t P = (size_t)d.n_params();
+    CacheLayout L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) { const size_t o = off; off = align256(off + bytes); return o; };
+    L.w = take(P * 4);
+    L.m = take(P * 4);
+    L.v = take(P * 4);
+    L.t = take(16);
+    if (c.precision != NRC_FP32) {
+        L.ffr = take((size_t)d.n_fwd_frags() * kFragElems * 2);
+        L.bfr = take((size_t)d.n_bwd_frags() * kFragElems * 2);
+    } else {
+        L.ffr = L.bfr = 0;
+    }
+    L.total = off;
+    return L;
+}
+
+ScratchLayout scratch_layout(const nrc_config& c, int64_t n) {
+    const Geo d(c.width, c.n_hidden);
+    const size_t P = (size_t)d.n_params();
+    const size_t tiles = (size_t)((n + kTrainTile - 1) / kTrainTile);
+    ScratchLayout L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) { const size_t o = off; off = align256(off + bytes); return o; };
+    L.tiles = (int64_t)tiles;
+    L.partials = take(tiles * P * 4);
+    L.loss_part = take(tiles * 4);
+    L.grad = take(P * 4);
+    L.flags = take((size_t)reduce_blocks((int)P) * 4);
+    L.loss = take(16);
+    L.skipped = take(16);
+    L.total = off;
+    return L;
+}
+
+// Enqueue one training step (forward, loss, backward, reduction, Adam) on s.
+int enqueue_train_step(nrc_cache* c, const void* enc, const float* target, int64_t n, char* scratch,
+                       float* loss_dev, int32_t* skipped_dev, hipStream_t s) {
+    const nrc_config& cfg = c->cfg;
+    const Geo d(cfg.width, cfg.n_hidden);
+    const ScratchLayout sl = scratch_layout(cfg, n);
+    float* partials = (float*)(scratch + sl.partials);
+    float* loss_part = (float*)(scratch + sl.loss_part);
+    float* grad = (float*)(scratch + sl.grad);
+    int32_t* flags = (int32_t*)(scratch + sl.flags);
+    const float scale = cfg.loss_scale;
+    const float grad_scale = (float)((double)scale / (3.0 * (double)n));
+    hipError_t e;
+    if (cfg.precision == NRC_FP32)
+        e = launch_train_fp32(d, c->w(), (const float*)enc, target, n, false, cfg.loss_eps, grad_scale,
+                              partials, loss_part, nullptr, s);
+    else
+        e = launch_train_mfma(cfg.precision, d, c->ffr(), c->bfr(), enc, target, n, false, cfg.loss_eps,
+                              grad_scale, partials, loss_part, nullptr, s);
+    if (e != hipSuccess) return device_fail(e, "training kernel launch");
+    float* loss_out = loss_dev ? loss_dev : (float*)(scratch + sl.loss);
+    e = launch_reduce(partials, (int)sl.tiles, d.n_params(), 1.0f / scale, grad, flags, loss_part,
+                      (float)(1.0 / (3.0 * (double)n)), loss_out, s);
+    if (e != hipSuccess) return device_fail(e, "gradient reduction launch");
+    const AdamHyper hp{cfg.lr, cfg.beta1, cfg.beta2, cfg.adam_eps};
+    int32_t* skipped_out = skipped_dev ? skipped_dev : (int32_t*)(scratch + sl.skipped);
+    e = launch_adam(cfg.precision, d, c->w(), c->m(), c->v(), c->tslots(), c->parity, grad, flags,
+                    reduce_blocks(d.n_params()), hp, skipped_out, c->ffr(), c->bfr(), s);
+    if (e != hipSuccess) return device_fail(e, "Adam launch");
+    c->parity ^= 1;
+    return NRC_OK;
+}
+
+int enqueue_forward(nrc_cache* c, const void* enc, int64_t n, float* rgb, hipStream_t s) {
+    const Geo d(c->cfg.width, c->cfg.n_hidden);
+    hipError_t e;
+    if (c->cfg.precision == NRC_FP32)
+        e = launch_fwd_fp32(d, c->w(), (const float*)enc, n, rgb, s);
+    else
+        e = launch_fwd_mfma(c->cfg.precision, d, c->ffr(), enc, n, rgb, s);
+    if (e != hipSuccess) return device_fail(e, "forward launch");
+    return NRC_OK;
+}
+
+}  // namespace nrc
+
+using namespace nrc;
+
+extern "C" {
+
+int nrc_config_default(nrc_config* cfg) {
+    if (!cfg) return fail(NRC_EINVAL, "config is NULL");
+    std::memset(cfg, 0, sizeof *cfg);
+    cfg->width = 64;
+    cfg->n_hidden = 5;
+    cfg->n_out = 3;
+    cfg->precision = NRC_FP16;
+    cfg->enc_preset = NRC_PRESET_CONFIG;
+    cfg->lr = 1e-2f;
+    cfg->beta1 = 0.9f;
+    cfg->beta2 = 0.99f;
+    cfg->adam_eps = 1e-8f;
+    cfg->loss_eps = 0.01f;
+    cfg->loss_scale = 128.0f;
+    cfg->seed = 0;
+    return ok();
+}
+
+const char* nrc_last_error(void) { return g_err.c_str(); }
+
+int64_t nrc_param_count(const nrc_config* cfg) {
+    if (validate_config(cfg) != NRC_OK) return -1;
+    ok();
+    return Geo(cfg->width, cfg->n_hidden).n_params();
+}
+
+size_t nrc_cache_bytes(const nrc_config* cfg) {
+    if (validate_config(cfg) != NRC_OK) return 0;
+    ok();
+    return cache_layout(*cfg).total;
+}
+
+size_t nrc_train_scratch_bytes(const nrc_config* cfg, int64_t n) {
+    if (validate_config(cfg) != NRC_OK) return 0;
+    if (n < 0) { fail(NRC_EINVAL, "n must be >= 0"); return 0; }
+    ok();
+    return scratch_layout(*cfg, n).total;
+}
+
+int nrc_enc_elem_bytes(const nrc_config* cfg) {
+    if (validate_config(cfg) != NRC_OK) return NRC_EINVAL;
+    ok();
+    return cfg->precision == NRC_FP32 ? 4 : 2;
+}
+
+int nrc_cache_create(const nrc_config* cfg, void* dev_ws, size_t ws_bytes, void* stream,
+                     nrc_cache** out) {
+    if (!out) return fail(NRC_EINVAL, "out is NULL");
+    *out = nullptr;
+    int rc = validate_config(cfg);
+    if (rc != NRC_OK) return rc;
+    if (!dev_ws) return fail(NRC_EINVAL, "workspace is NULL");
+    if (((uintptr_t)dev_ws & 255) != 0) return fail(NRC_EINVAL, "workspace must be 256-byte aligned");
+    const CacheLayout L = cache_layout(*cfg);
+    if (ws_bytes < L.total)
+        return fail(NRC_ENOMEM, "workspace of %zu bytes is smaller than the %zu bytes needed", ws_bytes, L.total);
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return device_fail(e, "hipGetDevice");
+    nrc_cache* c = new (std::nothrow) nrc_cache();
+    if (!c) return fail(NRC_ENOMEM, "host allocation failed");
+    c->cfg = *cfg;
+    c->lay = L;
+    c->ws = (char*)dev_ws;
+    c->parity = 0;
+    c->device = dev;
+    e = hipMemsetAsync(dev_ws, 0, L.total, (hipStream_t)stream);
+    if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
+    if (e != hipSuccess) {
+        delete c;
+        return device_fail(e, "workspace clear");
+    }
+    *out = c;
+    return ok();
+}
+
+int nrc_cache_destroy(nrc_cache* cache) {
+    if (!cache) return fail(NRC_EINVAL, "cache is NULL");
+    delete cache;
+    return ok();
+}
+
+int nrc_cache_config(const nrc_cache* cache, nrc_config* out) {
+    if (!cache || !out) return fail(NRC_EINVAL, "NULL argument");
+    *out = cache->cfg;
+    return ok();
+}
+
+static int upload_state(nrc_cache* c, const float* w, const float* m, const float* v, int64_t t,
+                        hipStream_t s) {
+    const Geo d(c->cfg.width, c->cfg.n_hidden);
+    const size_t bytes = (size_t)d.n_params() * 4;
+    hipError_t e = hipMemcpyAsync(c->w(), w, bytes, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = m ? hipMemcpyAsync(c->m(), m, bytes, hipMemcpyHostToDevice, s) : hipMemsetAsync(c->m(), 0, bytes, s);
+    if (e == hipSuccess)
+        e = v ? hipMemcpyAsync(c->v(), v, bytes, hipMemcpyHostToDevice, s) : hipMemsetAsync(c->v(), 0, bytes, s);
+    int32_t ts[4] = {(int32_t)t, (int32_t)t, 0, 0};
+    if (e == hipSuccess) e = hipMemcpyAsync(c->tslots(), ts, sizeof ts, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && c->cfg.precision != NRC_FP32) {
+        e = hipMemsetAsync(c->ffr(), 0, (size_t)d.n_fwd_frags() * kFragElems * 2, s);
+        if (e == hipSuccess) e = hipMemsetAsync(c->bfr(), 0, (size_t)d.n_bwd_frags() * kFragElems * 2, s);
+        if (e == hipSuccess) e = launch_build_frags(c->cfg.precision, d, c->w(), c->ffr(), c->bfr(), s);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return device_fail(e, "state upload");
+    c->parity = 0;
+    return ok();
+}
+
+int nrc_set_weights(nrc_cache* cache, const float* host_w, int64_t n, void* stream) {
+    if (!cache || !host_w) return fail(NRC_EINVAL, "NULL argument");
+    const int64_t P = Geo(cache->cfg.width, cache->cfg.n_hidden).n_params();
+    if (n != P) return fail(NRC_EINVAL, "expected %lld weights, got %lld", (long long)P, (long long)n);
+    for (int64_t i = 0; i < n; ++i)
+        if (!std::isfinite(host_w[i])) return fail(NRC_EINVAL, "weight %lld is not finite", (long long)i);
+    return upload_state(cache, host_w, nullptr, nullptr, 0, (hipStream_t)stream);
+}
+
+int nrc_set_weights_device(nrc_cache* cache, const float* dev_w, int64_t n, void* stream) {
+    if (!cache || !dev_w) return fail(NRC_EINVAL, "NULL argument");
+    if (((uintptr_t)dev_w & 3) != 0) return fail(NRC_EINVAL, "misaligned weights");
+    const Geo d(cache->cfg.width, cache->cfg.n_hidden);
+    if (n != d.n_params()) return fail(NRC_EINVAL, "expected %d weights, got %lld", d.n_params(), (long long)n);
+    hipStream_t s = (hipStream_t)stream;
+    const size_t bytes = (size_t)d.n_params() * 4;
+    hipError_t e = hipMemcpyAsync(cache->w(), dev_w, bytes, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) e = hipMemsetAsync(cache->m(), 0, bytes, s);
+    if (e == hipSuccess) e = hipMemsetAsync(cache->v(), 0, bytes, s);
+    if (e == hipSuccess) e = hipMemsetAsync(cache->tslots(), 0, 16, s);
+    if (e == hipSuccess && cache->cfg.precision != NRC_FP32)
+        e = launch_build_frags(cache->cfg.precision, d, cache->w(), cache->ffr(), cache->bfr(), s);
+    if (e != hipSuccess) return device_fail(e, "device weight upload");
+    cache->parity = 0;
+    return ok();
+}
+
+int nrc_get_weights(const nrc_cache* cache, float* host_w, int64_t n, void* stream) {
+    if (!cache || !host_w) return fail(NRC_EINVAL, "NULL argument");
+    const int64_t P = Geo(cache->cfg.width, cache->cfg.n_hidden).n_params();
+    if (n != P) return fail(NRC_EINVAL, "expected %lld weights, got %lld", (long long)P, (long long)n);
+    hipError_t e = hipMemcpyAsync(host_w, const_cast<nrc_cache*>(cache)->w(), (size_t)P * 4,
+                                  hipMemcpyDeviceToHost, (hipStream_t)stream);
+    if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
+    if (e != hipSuccess) return device_fail(e, "weight download");
+    return ok();
+}
+
+int nrc_get_state(const nrc_cache* cache, float* host_w, float* host_m, float* host_v, int64_t n,
+                  int64_t* t, void* stream) {
+    if (!cache || !host_w || !host_m || !host_v || !t) return fail(NRC_EINVAL, "NULL argument");
+    nrc_cache* c = const_cast<nrc_cache*>(cache);
+    const int64_t P = Geo(c->cfg.width, c->cfg.n_hidden).n_params();
+    if (n != P) return fail(NRC_EINVAL, "expected %lld weights, got %lld", (long long)P, (long long)n);
+    hipStream_t s = (hipStream_t)stream;
+    int32_t ts[4];
+    hipError_t e = hipMemcpyAsync(host_w, c->w(), (size_t)P * 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(host_m, c->m(), (size_t)P * 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(host_v, c->v(), (size_t)P * 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(ts, c->tslots(), sizeof ts, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return device_fail(e, "state download");
+    *t = ts[c->parity];
+    return ok();
+}
+
+int nrc_set_state(nrc_cache* cache, const float* host_w, const float* host_m, const float* host_v,
+                  int64_t n, int64_t t, void* stream) {
+    if (!cache || !host_w || !host_m || !host_v) return fail(NRC_EINVAL, "NULL argument");
+    const int64_t P = Geo(cache->cfg.width, cache->cfg.n_hidden).n_params();
+    if (n != P) return fail(NRC_EINVAL, "expected %lld weights, got %lld", (long long)P, (long long)n);
+    if (t < 0 || t > INT32_MAX) return fail(NRC_EINVAL, "step count out of range");
+    return upload_state(cache, host_w, host_m, host_v, t, (hipStream_t)stream);
+}
+
+int nrc_encode(const nrc_cache* cache, const float* raw, int raw_layout, int64_t n, void* enc,
+               void* stream) {
+    if (!cache) return fail(NRC_EINVAL, "cache is NULL");
+    if (raw_layout != NRC_RAW14 && raw_layout != NRC_RAW16) return fail(NRC_EINVAL, "unknown raw layout %d", raw_layout);
+    if (n < 0) return fail(NRC_EINVAL, "n must be >= 0");
+    if (n == 0) return ok();
+    if (!raw || !enc) return fail(NRC_EINVAL, "NULL buffer");
+    if (!aligned16(raw) || !aligned16(enc)) return fail(NRC_EINVAL, "buffers must be 16-byte aligned");
+    hipError_t e = launch_encode(cache->cfg.precision, cache->cfg.enc_preset, raw_layout, raw, n, enc,
+                                 (hipStream_t)stream);
+    if (e != hipSuccess) return device_fail(e, "encode launch");
+    return ok();
+}
+
+int nrc_forward(nrc_cache* cache, const void* enc, int64_t n, float* rgb, void* stream) {
+    if (!cache) return fail(NRC_EINVAL, "cache is NULL");
+    if (n < 0) return fail(NRC_EINVAL, "n must be >= 0");
+    if (n == 0) return ok();
+    if (!enc || !rgb) return fail(NRC_EINVAL, "NULL buffer");
+    if (!aligned16(enc) || ((uintptr_t)rgb & 3)) return fail(NRC_EINVAL, "misaligned buffer");
+    const int rc = enqueue_forward(cache, enc, n, rgb, (hipStream_t)stream);
+    return rc == NRC_OK ? ok() : rc;
+}
+
+int nrc_train_step(nrc_cache* cache, const void* enc, const float* target, int64_t n,
+                   void* scratch, size_t scratch_bytes, float* loss_dev, int32_t* skipped_dev,
+                   void* stream) {
+    if (!cache) return fail(NRC_EINVAL, "cache is NULL");
+    if (n < 1) return fail(NRC_EINVAL, "a training batch needs n >= 1");
+    if (n > ((int64_t)1 << 31)) return fail(NRC_EINVAL, "training batch too large");
+    if (!enc || !target || !scratch) return fail(NRC_EINVAL, "NULL buffer");
+    if (!aligned16(enc) || ((uintptr_t)target & 3) || ((uintptr_t)scratch & 255))
+        return fail(NRC_EINVAL, "misaligned buffer (scratch must be 256-byte aligned)");
+    if (((uintptr_t)loss_dev & 3) || ((uintptr_t)skipped_dev & 3)) return fail(NRC_EINVAL, "misaligned output");
+    const size_t need = scratch_layout(cache->cfg, n).total;
+    if (scratch_bytes < need)
+        return fail(NRC_ENOMEM, "scratch of %zu bytes is smaller than the %zu bytes needed", scratch_bytes, need);
+    const int rc = enqueue_train_step(cache, enc, target, n, (char*)scratch, loss_dev, skipped_dev,
+                                      (hipStream_t)stream);
+    return rc == NRC_OK ? ok() : rc;
+}
+
+int nrc_backward(nrc_cache* cache, const void* enc, const float* grad_rgb, int64_t n, void* scratch,
+                 size_t scratch_bytes, float* grad_w, float* grad_enc, void* stream) {
+    if (!cache) return fail(NRC_EINVAL, "cache is NULL");
+    if (n < 1) return fail(NRC_EINVAL, "a backward batch needs n >= 1");
+    if (n > ((int64_t)1 << 31)) return fail(NRC_EINVAL, "batch too large");
+    if (!enc || !grad_rgb || !scratch || !grad_w) return fail(NRC_EINVAL, "NULL buffer");
+    if (!aligned16(enc) || ((uintptr_t)grad_rgb & 3) || ((uintptr_t)scratch & 255) ||
+        ((uintptr_t)grad_w & 3) || (grad_enc && !aligned16(grad_enc)))
+        return fail(NRC_EINVAL, "misaligned buffer");
+    const nrc_config& cfg = cache->cfg;
+    const ScratchLayout sl = scratch_layout(cfg, n);
+    if (scratch_bytes < sl.total)
+        return fail(NRC_ENOMEM, "scratch of %zu bytes is smaller than the %zu bytes needed", scratch_bytes, sl.total);
+    const Geo d(cfg.width, cfg.n_hidden);
+    char* sc = (char*)scratch;
+    float* partials = (float*)(sc + sl.partials);
+    float* loss_part = (float*)(sc + sl.loss_part);
+    int32_t* flags = (int32_t*)(sc + sl.flags);
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e;
+    if (cfg.precision == NRC_FP32)
+        e = launch_train_fp32(d, cache->w(), (const float*)enc, grad_rgb, n, true, cfg.loss_eps, 1.0f,
+                              partials, loss_part, grad_enc, s);
+    else
+        e = launch_train_mfma(cfg.precision, d, cache->ffr(), cache->bfr(), enc, grad_rgb, n, true,
+                              cfg.loss_eps, 1.0f, partials, loss_part, grad_enc, s);
+    if (e != hipSuccess) return device_fail(e, "backward kernel launch");
+    e = launch_reduce(partials, (int)sl.tiles, d.n_params(), 1.0f, grad_w, flags, loss_part, 1.0f,
+                      nullptr, s);
+    if (e != hipSuccess) return device_fail(e, "gradient reduction launch");
+    return ok();
+}
+
+}  // extern "C"

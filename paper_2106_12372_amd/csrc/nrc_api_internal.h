@@ -1,0 +1,52 @@
+// Host-side state of a cache and the layouts of the caller-owned device
+// workspaces; shared by the C ABI and the serving loop.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "nrc_internal.h"
+
+namespace nrc {
+
+// Byte offsets inside a cache workspace.
+struct CacheLayout {
+    size_t w, m, v, t, ffr, bfr, total;
+};
+
+// Byte offsets inside the scratch of one training step / backward pass.
+struct ScratchLayout {
+    int64_t tiles;
+    size_t partials, loss_part, grad, flags, loss, skipped, total;
+};
+
+CacheLayout cache_layout(const nrc_config& c);
+ScratchLayout scratch_layout(const nrc_config& c, int64_t n);
+int validate_config(const nrc_config* c);
+bool aligned16(const void* p);
+
+int fail(int code, const char* fmt, ...);
+int ok();
+int device_fail(hipError_t e, const char* what);
+
+}  // namespace nrc
+
+struct nrc_cache {
+    nrc_config cfg;
+    nrc::CacheLayout lay;
+    char* ws;
+    int parity;  // which step-count slot holds the current count
+    int device;
+    float* w() { return (float*)(ws + lay.w); }
+    float* m() { return (float*)(ws + lay.m); }
+    float* v() { return (float*)(ws + lay.v); }
+    int32_t* tslots() { return (int32_t*)(ws + lay.t); }
+    void* ffr() { return cfg.precision == NRC_FP32 ? nullptr : (void*)(ws + lay.ffr); }
+    void* bfr() { return cfg.precision == NRC_FP32 ? nullptr : (void*)(ws + lay.bfr); }
+};
+
+namespace nrc {
+int enqueue_train_step(nrc_cache* c, const void* enc, const float* target, int64_t n, char* scratch,
+                       float* loss_dev, int32_t* skipped_dev, hipStream_t s);
+int enqueue_forward(nrc_cache* c, const void* enc, int64_t n, float* rgb, hipStream_t s);
+}  // namespace nrc

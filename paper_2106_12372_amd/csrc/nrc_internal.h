@@ -1,0 +1,130 @@
+// Internal declarations of the MI355X radiance-cache library: network
+// dimensions, weight-fragment layout for the gfx950 matrix cores, and the host
+// launch wrappers each kernel source file provides.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "../../include/nrc.h"
+
+namespace nrc {
+
+constexpr int kMaxLayers = 9;   // up to 8 hidden layers + output
+constexpr int kEncWidth = 64;   // encoded input width (Sec. 3.6)
+constexpr int kNOut = 3;        // RGB
+constexpr int kTrainTile = 64;  // training samples per workgroup
+
+// One matrix-core operand fragment: 64 lanes x 8 16-bit elements.
+constexpr int kFragElems = 64 * 8;
+
+// Shapes and offsets of the network (Sec. 5 "Architecture"), computed
+// arithmetically so that kernels never index an array by a runtime layer.
+//   Layer l maps h_l (cols(l) features) to z_{l+1} (rows(l) features):
+//   l = 0: [W][64]; l = 1..H-1: [W][W]; l = H (output): [3][W].
+// Weights are one flat FP32 array, layer after layer, each row-major [out][in].
+// Forward fragments of layer l: A operand of z = W_l h (M = rows, K = cols),
+//   fwd_mb(l) blocks of 16 rows x fwd_kc(l) chunks of 32 columns.
+// Backward fragments of layer l: A operand of g = W_l^T delta (M = cols,
+//   K = rows), bwd_mb(l) x bwd_kc(l).
+struct Geo {
+    int W, H;
+    __host__ __device__ Geo(int width, int n_hidden) : W(width), H(n_hidden) {}
+    __host__ __device__ int MB() const { return W >> 4; }
+    __host__ __device__ int KC() const { return W >> 5; }
+    __host__ __device__ int rows(int l) const { return l == H ? kNOut : W; }
+    __host__ __device__ int cols(int l) const { return l == 0 ? kEncWidth : W; }
+    __host__ __device__ int w_off(int l) const { return l == 0 ? 0 : kEncWidth * W + (l - 1) * W * W; }
+    __host__ __device__ int n_params() const { return w_off(H) + kNOut * W; }
+    __host__ __device__ int fwd_kc(int l) const { return l == 0 ? 2 : KC(); }
+    __host__ __device__ int fwd_mb(int l) const { return l == H ? 1 : MB(); }
+    __host__ __device__ int fwd_base(int l) const { return l == 0 ? 0 : 2 * MB() + (l - 1) * MB() * KC(); }
+    __host__ __device__ int n_fwd_frags() const { return fwd_base(H) + KC(); }
+    __host__ __device__ int bwd_kc(int l) const { return l == H ? 1 : KC(); }
+    __host__ __device__ int bwd_mb(int l) const { return l == 0 ? 4 : MB(); }
+    __host__ __device__ int bwd_base(int l) const { return l == 0 ? 0 : 4 * KC() + (l - 1) * MB() * KC(); }
+    __host__ __device__ int n_bwd_frags() const { return bwd_base(H) + MB(); }
+};
+
+// ---------------------------------------------------------------------------
+// Feature <-> operand-slot maps of v_mfma_f32_16x16x32_{f16,bf16}.
+//
+// B operand (K x N = 32 x 16): lane l holds column n = l % 16 and the eight
+// K rows 8*(l/16) .. 8*(l/16)+7.  The accumulator (M x N = 16 x 16): lane l
+// holds column n = l % 16 and rows 4*(l/16) .. 4*(l/16)+3.  A layer's two
+// adjacent 16-row accumulator blocks therefore hand each lane features
+// {4g..4g+3} and {16+4g..16+4g+3} (g = l/16) of one 32-feature chunk, which
+// become that lane's eight B slots of the next product directly if the next
+// weight matrix's K index is permuted the same way ("chained" order).  Inputs
+// read from memory use the natural order 8g..8g+7.
+// ---------------------------------------------------------------------------
+__host__ __device__ inline int chained_feature(int c, int g, int i) {
+    return 32 * c + (i < 4 ? 4 * g + i : 16 + 4 * g + (i - 4));
+}
+__host__ __device__ inline int natural_feature(int c, int g, int i) { return 32 * c + 8 * g + i; }
+__host__ __device__ inline void chained_slot(int k, int& c, int& g, int& i) {
+    c = k >> 5;
+    const int r = k & 31;
+    if (r < 16) { g = r >> 2; i = r & 3; } else { g = (r - 16) >> 2; i = 4 + ((r - 16) & 3); }
+}
+__host__ __device__ inline void natural_slot(int k, int& c, int& g, int& i) {
+    c = k >> 5;
+    const int r = k & 31;
+    g = r >> 3;
+    i = r & 7;
+}
+
+// Position of weight W_l[o][k] in the forward fragment array (element index),
+// and of the same weight in the backward (transposed) fragment array.
+__host__ __device__ inline int64_t fwd_frag_index(const Geo& d, int l, int o, int k) {
+    int c, g, i;
+    if (l == 0) natural_slot(k, c, g, i); else chained_slot(k, c, g, i);
+    const int mb = o >> 4, lane = 16 * g + (o & 15);
+    return ((int64_t)(d.fwd_base(l) + mb * d.fwd_kc(l) + c) * 64 + lane) * 8 + i;
+}
+__host__ __device__ inline int64_t bwd_frag_index(const Geo& d, int l, int o, int k) {
+    int c, g, i;
+    chained_slot(o, c, g, i);  // K index of the transposed product is the row o
+    const int mb = k >> 4, lane = 16 * g + (k & 15);
+    return ((int64_t)(d.bwd_base(l) + mb * d.bwd_kc(l) + c) * 64 + lane) * 8 + i;
+}
+
+struct AdamHyper {
+    float lr, beta1, beta2, eps;
+};
+
+// ---------------------------------------------------------------------------
+// Host launch wrappers (return hipError_t of the launch).
+// ---------------------------------------------------------------------------
+// encode.hip
+hipError_t launch_encode(int precision, int preset, int layout, const float* raw, int64_t n,
+                         void* enc, hipStream_t s);
+// mlp_fp32.hip
+hipError_t launch_fwd_fp32(const Geo& d, const float* w, const float* enc, int64_t n, float* rgb,
+                           hipStream_t s);
+hipError_t launch_train_fp32(const Geo& d, const float* w, const float* enc, const float* tgt,
+                             int64_t n, bool upstream, float loss_eps, float grad_scale,
+                             float* partials, float* loss_part, float* genc, hipStream_t s);
+// mlp_mfma.hip
+hipError_t launch_fwd_mfma(int precision, const Geo& d, const void* ffr, const void* enc,
+                           int64_t n, float* rgb, hipStream_t s);
+hipError_t launch_train_mfma(int precision, const Geo& d, const void* ffr, const void* bfr,
+                             const void* enc, const float* tgt, int64_t n, bool upstream,
+                             float loss_eps, float grad_scale, float* partials, float* loss_part,
+                             float* genc, hipStream_t s);
+size_t fp32_train_lds_bytes(int n_hidden);
+size_t mfma_train_lds_bytes(int width, int n_hidden);
+size_t mfma_fwd_lds_bytes(int width, int n_hidden);
+// optim.hip
+int reduce_blocks(int n_params);
+hipError_t launch_reduce(const float* partials, int n_tiles, int n_params, float inv_scale,
+                         float* grad, int32_t* flags, const float* loss_part, float inv_count,
+                         float* loss_out, hipStream_t s);
+hipError_t launch_adam(int precision, const Geo& d, float* w, float* m, float* v, int32_t* tslots,
+                       int parity, const float* grad, const int32_t* flags, int n_flags,
+                       AdamHyper hp, int32_t* skipped_out, void* ffr, void* bfr, hipStream_t s);
+hipError_t launch_build_frags(int precision, const Geo& d, const float* w, void* ffr, void* bfr,
+                              hipStream_t s);
+
+}  // namespace nrc

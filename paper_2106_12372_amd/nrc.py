@@ -1,0 +1,305 @@
+"""Python binding of the C ABI in include/nrc.h (argument marshalling only).
+
+Every function named ``nrc_*`` here calls the C entry point of the same name
+with device pointers taken from torch tensors and the current HIP stream; all
+arithmetic happens in the HIP kernels of libnrc.so.  PyTorch only provides
+device memory and streams.  Importing this module fails loudly when the
+library has not been built (``python -m paper_2106_12372_amd.build``).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_double, c_float, c_int, c_int32, c_int64, c_size_t, c_uint64, c_void_p
+from typing import Optional
+
+import numpy as np
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libnrc.so")
+if not os.path.exists(_LIB_PATH):
+    raise ImportError(f"{_LIB_PATH} is missing: build it with `python -m paper_2106_12372_amd.build`")
+lib = ctypes.CDLL(_LIB_PATH)
+
+# Status codes, precisions, presets and layouts (same values as nrc.h).
+NRC_OK, NRC_PENDING, NRC_EINVAL, NRC_ENOMEM, NRC_EDEVICE, NRC_EBUSY, NRC_ENOTFOUND = 0, 1, -1, -2, -3, -4, -5
+NRC_FP32, NRC_FP16, NRC_BF16 = 0, 1, 2
+NRC_PRESET_CONFIG, NRC_PRESET_PAPER = 0, 1
+NRC_RAW14, NRC_RAW16 = 0, 1
+NRC_REQ_INFER, NRC_REQ_TRAIN = 0, 1
+ENC_WIDTH = 64
+PRECISIONS = {"fp32": NRC_FP32, "fp16": NRC_FP16, "bf16": NRC_BF16}
+
+
+class NrcError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"nrc error {code}: {msg}")
+        self.code = code
+
+
+class nrc_config(ctypes.Structure):
+    _fields_ = [("width", c_int32), ("n_hidden", c_int32), ("n_out", c_int32),
+                ("precision", c_int32), ("enc_preset", c_int32), ("lr", c_float),
+                ("beta1", c_float), ("beta2", c_float), ("adam_eps", c_float),
+                ("loss_eps", c_float), ("loss_scale", c_float), ("seed", c_uint64)]
+
+
+class nrc_serve_config(ctypes.Structure):
+    _fields_ = [("n_caches", c_int32), ("cache_cfg", nrc_config), ("arena", c_void_p),
+                ("arena_bytes", c_size_t), ("n_streams", c_int32), ("max_inflight", c_int32)]
+
+
+class nrc_request(ctypes.Structure):
+    _fields_ = [("kind", c_int32), ("enc", c_void_p), ("target", c_void_p), ("rgb", c_void_p),
+                ("n", c_int64)]
+
+
+class nrc_result(ctypes.Structure):
+    _fields_ = [("status", c_int32), ("skipped", c_int32), ("loss", c_float),
+                ("t_submit", c_double), ("t_start", c_double), ("t_done", c_double)]
+
+
+def _decl(name, restype, *argtypes):
+    if not hasattr(lib, name):
+        return None
+    fn = getattr(lib, name)
+    fn.restype = restype
+    fn.argtypes = list(argtypes)
+    return fn
+
+
+_P = c_void_p
+_decl("nrc_config_default", c_int, POINTER(nrc_config))
+_decl("nrc_last_error", ctypes.c_char_p)
+_decl("nrc_param_count", c_int64, POINTER(nrc_config))
+_decl("nrc_cache_bytes", c_size_t, POINTER(nrc_config))
+_decl("nrc_train_scratch_bytes", c_size_t, POINTER(nrc_config), c_int64)
+_decl("nrc_enc_elem_bytes", c_int, POINTER(nrc_config))
+_decl("nrc_cache_create", c_int, POINTER(nrc_config), _P, c_size_t, _P, POINTER(_P))
+_decl("nrc_cache_destroy", c_int, _P)
+_decl("nrc_cache_config", c_int, _P, POINTER(nrc_config))
+_decl("nrc_set_weights", c_int, _P, POINTER(c_float), c_int64, _P)
+_decl("nrc_get_weights", c_int, _P, POINTER(c_float), c_int64, _P)
+_decl("nrc_set_weights_device", c_int, _P, _P, c_int64, _P)
+_decl("nrc_get_state", c_int, _P, POINTER(c_float), POINTER(c_float), POINTER(c_float), c_int64,
+      POINTER(c_int64), _P)
+_decl("nrc_set_state", c_int, _P, POINTER(c_float), POINTER(c_float), POINTER(c_float), c_int64,
+      c_int64, _P)
+_decl("nrc_encode", c_int, _P, _P, c_int, c_int64, _P, _P)
+_decl("nrc_forward", c_int, _P, _P, c_int64, _P, _P)
+_decl("nrc_train_step", c_int, _P, _P, _P, c_int64, _P, c_size_t, _P, _P, _P)
+_decl("nrc_backward", c_int, _P, _P, _P, c_int64, _P, c_size_t, _P, _P, _P)
+_decl("nrc_serve_create", c_int, POINTER(nrc_serve_config), POINTER(_P))
+_decl("nrc_serve_set_weights", c_int, _P, c_int, POINTER(c_float), c_int64)
+_decl("nrc_serve_get_weights", c_int, _P, c_int, POINTER(c_float), c_int64)
+_decl("nrc_serve_submit", c_int, _P, c_int, POINTER(nrc_request), POINTER(c_uint64))
+_decl("nrc_serve_poll", c_int, _P, c_uint64, POINTER(nrc_result))
+_decl("nrc_serve_drain", c_int, _P)
+_decl("nrc_serve_destroy", c_int, _P)
+
+EXPORTED = ["nrc_config_default", "nrc_last_error", "nrc_param_count", "nrc_cache_bytes",
+            "nrc_train_scratch_bytes", "nrc_enc_elem_bytes", "nrc_cache_create", "nrc_cache_destroy",
+            "nrc_cache_config", "nrc_set_weights", "nrc_get_weights", "nrc_set_weights_device",
+            "nrc_get_state", "nrc_set_state", "nrc_encode", "nrc_forward", "nrc_train_step",
+            "nrc_backward", "nrc_serve_create", "nrc_serve_set_weights", "nrc_serve_get_weights",
+            "nrc_serve_submit", "nrc_serve_poll", "nrc_serve_drain", "nrc_serve_destroy"]
+
+
+def last_error() -> str:
+    return lib.nrc_last_error().decode()
+
+
+def check(rc: int) -> int:
+    if rc < 0:
+        raise NrcError(rc, last_error())
+    return rc
+
+
+# ---------------------------------------------------------------------------
+# Configuration
+# ---------------------------------------------------------------------------
+def make_config(width: int = 64, n_hidden: int = 5, precision="fp16", enc_preset: int = NRC_PRESET_CONFIG,
+                lr: float = 1e-2, beta1: float = 0.9, beta2: float = 0.99, adam_eps: float = 1e-8,
+                loss_eps: float = 0.01, loss_scale: Optional[float] = None) -> nrc_config:
+    cfg = nrc_config()
+    check(lib.nrc_config_default(ctypes.byref(cfg)))
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    cfg.width, cfg.n_hidden, cfg.precision, cfg.enc_preset = width, n_hidden, prec, enc_preset
+    cfg.lr, cfg.beta1, cfg.beta2, cfg.adam_eps, cfg.loss_eps = lr, beta1, beta2, adam_eps, loss_eps
+    cfg.loss_scale = (1.0 if prec == NRC_FP32 else 128.0) if loss_scale is None else loss_scale
+    return cfg
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def enc_dtype(cfg: nrc_config):
+    torch = _torch()
+    return {NRC_FP32: torch.float32, NRC_FP16: torch.float16, NRC_BF16: torch.bfloat16}[cfg.precision]
+
+
+def _stream(stream) -> c_void_p:
+    if stream is None:
+        return c_void_p(_torch().cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return c_void_p(stream)
+    return c_void_p(stream.cuda_stream)
+
+
+def _ptr(t) -> c_void_p:
+    return c_void_p(0 if t is None else t.data_ptr())
+
+
+def _need(t, dtype, shape_tail, name):
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if tuple(t.shape[1:]) != tuple(shape_tail):
+        raise ValueError(f"{name} must have shape [n]{list(shape_tail)}, got {list(t.shape)}")
+
+
+# ---------------------------------------------------------------------------
+# Entry points (same names as the C ABI)
+# ---------------------------------------------------------------------------
+def nrc_param_count(cfg: nrc_config) -> int:
+    return check(lib.nrc_param_count(ctypes.byref(cfg)))
+
+
+def nrc_cache_bytes(cfg: nrc_config) -> int:
+    b = lib.nrc_cache_bytes(ctypes.byref(cfg))
+    if b == 0:
+        raise NrcError(NRC_EINVAL, last_error())
+    return b
+
+
+def nrc_train_scratch_bytes(cfg: nrc_config, n: int) -> int:
+    b = lib.nrc_train_scratch_bytes(ctypes.byref(cfg), n)
+    if b == 0:
+        raise NrcError(NRC_EINVAL, last_error())
+    return b
+
+
+class Cache:
+    """One radiance cache: a handle plus its device workspace (a torch tensor)."""
+
+    def __init__(self, cfg: nrc_config, device=None, stream=None):
+        torch = _torch()
+        self.cfg = cfg
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        nbytes = nrc_cache_bytes(cfg)
+        # 256 bytes of slack so the workspace can be aligned to 256
+        self._ws_t = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-self._ws_t.data_ptr()) % 256
+        self.ws = self._ws_t[off:off + nbytes]
+        handle = c_void_p()
+        check(lib.nrc_cache_create(ctypes.byref(cfg), c_void_p(self.ws.data_ptr()), nbytes,
+                                   _stream(stream), ctypes.byref(handle)))
+        self.handle = handle
+        self.n_params = nrc_param_count(cfg)
+        self._scratch = None
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            lib.nrc_cache_destroy(h)
+            self.handle = None
+
+    @property
+    def enc_dtype(self):
+        return enc_dtype(self.cfg)
+
+    def scratch(self, n: int):
+        torch = _torch()
+        need = nrc_train_scratch_bytes(self.cfg, n)
+        if self._scratch is None or self._scratch[1] < need:
+            t = torch.empty(need + 256, dtype=torch.uint8, device=self.device)
+            off = (-t.data_ptr()) % 256
+            self._scratch = (t, need, off)
+        t, size, off = self._scratch
+        return t[off:off + size], size
+
+    # weights and state ------------------------------------------------------
+    def set_weights(self, w, stream=None):
+        w = np.ascontiguousarray(np.asarray(w, dtype=np.float32).reshape(-1))
+        check(lib.nrc_set_weights(self.handle, w.ctypes.data_as(POINTER(c_float)), w.size, _stream(stream)))
+
+    def set_weights_device(self, w, stream=None):
+        _need(w.reshape(-1, 1), _torch().float32, (1,), "weights")
+        check(lib.nrc_set_weights_device(self.handle, _ptr(w), w.numel(), _stream(stream)))
+
+    def get_weights(self, stream=None) -> np.ndarray:
+        out = np.empty(self.n_params, dtype=np.float32)
+        check(lib.nrc_get_weights(self.handle, out.ctypes.data_as(POINTER(c_float)), out.size, _stream(stream)))
+        return out
+
+    def get_state(self, stream=None):
+        w, m, v = (np.empty(self.n_params, dtype=np.float32) for _ in range(3))
+        t = c_int64()
+        fp = lambda a: a.ctypes.data_as(POINTER(c_float))
+        check(lib.nrc_get_state(self.handle, fp(w), fp(m), fp(v), self.n_params, ctypes.byref(t), _stream(stream)))
+        return w, m, v, t.value
+
+    def set_state(self, w, m, v, t, stream=None):
+        arrs = [np.ascontiguousarray(np.asarray(a, dtype=np.float32).reshape(-1)) for a in (w, m, v)]
+        fp = lambda a: a.ctypes.data_as(POINTER(c_float))
+        check(lib.nrc_set_state(self.handle, fp(arrs[0]), fp(arrs[1]), fp(arrs[2]), self.n_params, int(t),
+                                _stream(stream)))
+
+
+def nrc_encode(cache: Cache, raw, layout: int = NRC_RAW14, enc=None, stream=None):
+    torch = _torch()
+    width = 14 if layout == NRC_RAW14 else 16
+    _need(raw, torch.float32, (width,), "raw")
+    n = raw.shape[0]
+    if enc is None:
+        enc = torch.empty((n, ENC_WIDTH), dtype=cache.enc_dtype, device=raw.device)
+    _need(enc, cache.enc_dtype, (ENC_WIDTH,), "enc")
+    check(lib.nrc_encode(cache.handle, _ptr(raw), layout, n, _ptr(enc), _stream(stream)))
+    return enc
+
+
+def nrc_forward(cache: Cache, enc, rgb=None, stream=None):
+    torch = _torch()
+    _need(enc, cache.enc_dtype, (ENC_WIDTH,), "enc")
+    n = enc.shape[0]
+    if rgb is None:
+        rgb = torch.empty((n, 3), dtype=torch.float32, device=enc.device)
+    _need(rgb, torch.float32, (3,), "rgb")
+    check(lib.nrc_forward(cache.handle, _ptr(enc), n, _ptr(rgb), _stream(stream)))
+    return rgb
+
+
+def nrc_train_step(cache: Cache, enc, target, loss=None, skipped=None, scratch=None, stream=None):
+    """One Adam step on (enc, target); returns the device scalars (loss, skipped)."""
+    torch = _torch()
+    _need(enc, cache.enc_dtype, (ENC_WIDTH,), "enc")
+    _need(target, torch.float32, (3,), "target")
+    n = enc.shape[0]
+    if target.shape[0] != n:
+        raise ValueError("enc and target differ in length")
+    if loss is None:
+        loss = torch.empty(1, dtype=torch.float32, device=enc.device)
+    if skipped is None:
+        skipped = torch.empty(1, dtype=torch.int32, device=enc.device)
+    sc, size = cache.scratch(n) if scratch is None else (scratch, scratch.numel())
+    check(lib.nrc_train_step(cache.handle, _ptr(enc), _ptr(target), n, _ptr(sc), size, _ptr(loss),
+                             _ptr(skipped), _stream(stream)))
+    return loss, skipped
+
+
+def nrc_backward(cache: Cache, enc, grad_rgb, want_grad_enc: bool = True, scratch=None, stream=None):
+    """Gradients of sum(grad_rgb * network(enc)) w.r.t. the weights and (optionally) enc."""
+    torch = _torch()
+    _need(enc, cache.enc_dtype, (ENC_WIDTH,), "enc")
+    _need(grad_rgb, torch.float32, (3,), "grad_rgb")
+    n = enc.shape[0]
+    grad_w = torch.empty(cache.n_params, dtype=torch.float32, device=enc.device)
+    grad_enc = torch.empty((n, ENC_WIDTH), dtype=torch.float32, device=enc.device) if want_grad_enc else None
+    sc, size = cache.scratch(n) if scratch is None else (scratch, scratch.numel())
+    check(lib.nrc_backward(cache.handle, _ptr(enc), _ptr(grad_rgb), n, _ptr(sc), size, _ptr(grad_w),
+                           _ptr(grad_enc), _stream(stream)))
+    return grad_w, grad_enc
