@@ -303,3 +303,88 @@ def nrc_backward(cache: Cache, enc, grad_rgb, want_grad_enc: bool = True, scratc
     check(lib.nrc_backward(cache.handle, _ptr(enc), _ptr(grad_rgb), n, _ptr(sc), size, _ptr(grad_w),
                            _ptr(grad_enc), _stream(stream)))
     return grad_w, grad_enc
+
+
+# ---------------------------------------------------------------------------
+# Serving
+# ---------------------------------------------------------------------------
+class Server:
+    """Continuous-batching server over `n_caches` resident caches (nrc_serve_*).
+
+    The arena (caches + per-request scratch) is one device tensor of
+    `arena_bytes`.  Request tensors are kept alive here until their ticket has
+    been collected by poll().
+    """
+
+    def __init__(self, n_caches: int, cfg: nrc_config, arena_bytes: int, n_streams: int = 4,
+                 max_inflight: int = 64, device=None):
+        torch = _torch()
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        self.cfg = cfg
+        self._arena_t = torch.empty(arena_bytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-self._arena_t.data_ptr()) % 256
+        sc = nrc_serve_config()
+        sc.n_caches, sc.cache_cfg = n_caches, cfg
+        sc.arena, sc.arena_bytes = self._arena_t.data_ptr() + off, arena_bytes
+        sc.n_streams, sc.max_inflight = n_streams, max_inflight
+        torch.cuda.synchronize(self.device)
+        h = c_void_p()
+        check(lib.nrc_serve_create(ctypes.byref(sc), ctypes.byref(h)))
+        self.handle = h
+        self.n_params = nrc_param_count(cfg)
+        self._live = {}
+
+    def set_weights(self, cache_id: int, w):
+        w = np.ascontiguousarray(np.asarray(w, dtype=np.float32).reshape(-1))
+        check(lib.nrc_serve_set_weights(self.handle, cache_id, w.ctypes.data_as(POINTER(c_float)), w.size))
+
+    def get_weights(self, cache_id: int) -> np.ndarray:
+        out = np.empty(self.n_params, dtype=np.float32)
+        check(lib.nrc_serve_get_weights(self.handle, cache_id, out.ctypes.data_as(POINTER(c_float)), out.size))
+        return out
+
+    def _submit(self, cache_id, req, keep):
+        t = c_uint64()
+        check(lib.nrc_serve_submit(self.handle, cache_id, ctypes.byref(req), ctypes.byref(t)))
+        self._live[t.value] = keep
+        return t.value
+
+    def submit_infer(self, cache_id: int, enc, rgb) -> int:
+        torch = _torch()
+        _need(enc, enc_dtype(self.cfg), (ENC_WIDTH,), "enc")
+        _need(rgb, torch.float32, (3,), "rgb")
+        req = nrc_request(NRC_REQ_INFER, enc.data_ptr(), None, rgb.data_ptr(), enc.shape[0])
+        return self._submit(cache_id, req, (enc, rgb))
+
+    def submit_train(self, cache_id: int, enc, target) -> int:
+        torch = _torch()
+        _need(enc, enc_dtype(self.cfg), (ENC_WIDTH,), "enc")
+        _need(target, torch.float32, (3,), "target")
+        req = nrc_request(NRC_REQ_TRAIN, enc.data_ptr(), target.data_ptr(), None, enc.shape[0])
+        return self._submit(cache_id, req, (enc, target))
+
+    def poll(self, ticket: int):
+        """None while pending, else a dict with status, loss, skipped and timestamps."""
+        res = nrc_result()
+        rc = lib.nrc_serve_poll(self.handle, ticket, ctypes.byref(res))
+        if rc == NRC_PENDING:
+            return None
+        self._live.pop(ticket, None)
+        check(rc)
+        return dict(status=res.status, loss=res.loss, skipped=res.skipped, t_submit=res.t_submit,
+                    t_start=res.t_start, t_done=res.t_done)
+
+    def drain(self):
+        check(lib.nrc_serve_drain(self.handle))
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            check(lib.nrc_serve_drain(self.handle))
+            check(lib.nrc_serve_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,85 @@
+"""Rounding model of the reduced-precision (FP16/BF16) forms, for tests only.
+
+The FP64 oracle defines what the cache computes.  The matrix-core forms round
+at fixed points: the weights and every activation and backward delta are
+stored in FP16/BF16 (round to nearest even), products accumulate in FP32, the
+loss gradient is scaled before rounding and unscaled after the weight-gradient
+sum.  This model evaluates the method in float64 with exactly those rounding
+points, so the distance between the GPU and this model measures the kernels'
+own arithmetic (accumulation order only), while the distance between this
+model and the oracle is the precision loss the format itself causes.
+"""
+import numpy as np
+import torch
+
+import synthdata as sd
+
+
+def quantiser(prec):
+    if prec == "fp16":
+        return lambda x: np.asarray(x, np.float32).astype(np.float16).astype(np.float64)
+    if prec == "bf16":
+        return lambda x: torch.from_numpy(np.ascontiguousarray(np.asarray(x, np.float32))).bfloat16().float().numpy().astype(np.float64)
+    return lambda x: np.asarray(x, np.float64)
+
+
+def forward(mats, x, q):
+    h = q(x)
+    hs = [h]
+    qm = [q(m) for m in mats]
+    for l, w in enumerate(qm):
+        z = h @ w.T
+        if l == len(qm) - 1:
+            return z, hs, qm
+        h = q(np.maximum(z, 0.0))
+        hs.append(h)
+
+
+def backward(qm, hs, d_out, q):
+    grads = [None] * len(qm)
+    d = q(d_out)
+    for l in range(len(qm) - 1, -1, -1):
+        grads[l] = d.T @ hs[l]
+        g = d @ qm[l]
+        if l == 0:
+            return grads, g
+        d = q(g * (hs[l] > 0.0))
+
+
+class TrainModel:
+    """FP32 master weights and Adam state, reduced-precision network arithmetic."""
+
+    def __init__(self, w, prec, width=64, n_hidden=5, loss_scale=128.0, lr=1e-2, b1=0.9, b2=0.99,
+                 eps=1e-8, loss_eps=0.01):
+        self.w = np.asarray(w, np.float32).copy()
+        self.m = np.zeros_like(self.w)
+        self.v = np.zeros_like(self.w)
+        self.t = 0
+        self.q = quantiser(prec)
+        self.width, self.n_hidden = width, n_hidden
+        self.scale, self.lr, self.b1, self.b2, self.eps, self.loss_eps = loss_scale, lr, b1, b2, eps, loss_eps
+
+    def mats(self):
+        return [m.astype(np.float64) for m in sd.split_weights(self.w, self.width, self.n_hidden)]
+
+    def predict(self, x):
+        return forward(self.mats(), x, self.q)[0]
+
+    def step(self, x, y):
+        n = x.shape[0]
+        z, hs, qm = forward(self.mats(), x, self.q)
+        lum = z.mean(axis=1, keepdims=True)
+        den = lum * lum + self.loss_eps
+        diff = z - y
+        loss = float((diff * diff / den).sum() / (3 * n))
+        d_out = 2.0 * diff / den * (self.scale / (3 * n))
+        grads, _ = backward(qm, hs, d_out, self.q)
+        g = (np.concatenate([gg.reshape(-1) for gg in grads]) / self.scale).astype(np.float32)
+        self.t += 1
+        f = np.float32
+        self.m = (f(self.b1) * self.m + f(1 - self.b1) * g).astype(np.float32)
+        self.v = (f(self.b2) * self.v + f(1 - self.b2) * g * g).astype(np.float32)
+        mh = self.m / f(1 - self.b1 ** self.t)
+        vh = self.v / f(1 - self.b2 ** self.t)
+        self.w = (self.w - f(self.lr) * mh / (np.sqrt(vh) + f(self.eps))).astype(np.float32)
+        return loss

@@ -1,0 +1,75 @@
+"""Differentiation form: the fused kernels behind torch.autograd.Function.
+
+Widths 64 and 128, 5 hidden layers, batch 2^16, FP16 (and FP32 at width 64).
+L = sum(R * network(enc)) with a seeded R ~ N(0,1), so dL/dy = R.  Gradients
+of the weights and of the encoded inputs are compared with the FP64 oracle
+(whose own gradients are pinned by central finite differences) and with the
+rounding model; tolerances as in test_gpu_parity.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import synthdata as sd
+from oracle import nrc_oracle as O
+from tests import rounding_model as RM
+from tests.test_gpu_parity import BWD_TOL, MODEL_TOL, l2_err
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def AG():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2106_12372_amd import autograd
+    return autograd
+
+
+@pytest.mark.parametrize("prec,width,n", [("fp16", 64, 65536), ("fp16", 128, 65536), ("fp32", 64, 4096),
+                                          ("bf16", 64, 65536)])
+def test_autograd_gradients(AG, prec, width, n):
+    mod = AG.NRCModule(width=width, n_hidden=5, precision=prec)
+    dt = mod.cache.enc_dtype
+    x = torch.from_numpy(sd.uniform_features(n, 64, 51)).to("cuda").to(dt).requires_grad_(True)
+    r = sd.gaussian((n, 3), sd.SEED_FD)
+    y = mod(x)
+    (y * torch.from_numpy(r).to("cuda")).sum().backward()
+    gw = mod.weights.grad.cpu().numpy().astype(np.float64)
+    gx = x.grad.float().cpu().numpy().astype(np.float64)
+    x64 = x.detach().float().cpu().numpy().astype(np.float64)
+    w = mod.weights.detach().cpu().numpy()
+    st = O.CacheState(w, width=width)
+    yref, hs = O.forward(st.mats(), x64)
+    assert np.all(l2_err(y.detach().cpu().numpy(), yref) <= (1e-5 if prec == "fp32" else 1e-2))
+    grads, gin = O.backward(st.mats(), hs, r.astype(np.float64))
+    ref_w = np.concatenate([g.reshape(-1) for g in grads])
+    assert np.linalg.norm(gw - ref_w) / np.linalg.norm(ref_w) <= BWD_TOL[prec]
+    # grad_enc comes back in the input dtype, so compare it at that rounding
+    q = RM.quantiser(prec)
+    assert np.linalg.norm(gx - q(gin)) / np.linalg.norm(gin) <= BWD_TOL[prec]
+    if prec != "fp32":
+        _, mhs, qm = RM.forward(st.mats(), x64, q)
+        mg, mgin = RM.backward(qm, mhs, r.astype(np.float64), q)
+        mref = np.concatenate([g.reshape(-1) for g in mg])
+        assert np.linalg.norm(gw - mref) / np.linalg.norm(mref) <= MODEL_TOL[prec]
+        assert np.linalg.norm(gx - q(mgin)) / np.linalg.norm(mgin) <= MODEL_TOL[prec]
+
+
+def test_autograd_drives_torch_optimizer(AG):
+    mod = AG.NRCModule(precision="fp16")
+    raw = sd.raw_records(4096, 52)
+    from paper_2106_12372_amd import nrc as N
+    enc = N.nrc_encode(mod.cache, torch.from_numpy(raw).to("cuda"))
+    y = torch.from_numpy(sd.targets(raw)).to("cuda")
+    opt = torch.optim.Adam(mod.parameters(), lr=1e-2, betas=(0.9, 0.99))
+    losses = []
+    for _ in range(30):
+        opt.zero_grad()
+        pred = mod(enc)
+        loss = ((pred - y) ** 2 / (pred.detach().mean(1, keepdim=True) ** 2 + 0.01)).mean()
+        loss.backward()
+        opt.step()
+        losses.append(loss.item())
+    assert losses[-1] < 0.05 * losses[0]

@@ -1,14 +1,24 @@
 """Parity of the HIP path with the FP64 oracle, element by element, through the C ABI.
 
-Tolerances (derived in the design notes):
-* encode: FP32 output 2e-6 absolute (libm-grade sinpi/cospi, acos, atan2 in
-  FP32); FP16/BF16 output additionally one rounding of the stored value
-  (relative 2^-11 / 2^-8).
-* forward, FP32: 1e-5 normwise per channel (max |err| / max |ref|).
-* forward, FP16: 1e-2 normwise per channel.  BF16 on untrained Glorot weights:
-  3e-2 (rounding 2^-8 per operand over six layers); 1e-2 after training.
-* training, FP32: trained outputs 1e-5, loss 1e-5 relative; FP16/BF16: trained
-  outputs 1e-2 (BF16 2e-2 for a single step from Glorot weights), loss 1%.
+Per-channel relative error of a batch of outputs is normwise: "l2" is
+||got_c - ref_c||_2 / ||ref_c||_2, "max" is max_i |got - ref| / max_i |ref|.
+
+Tolerances (derivations in the design notes):
+* encode: FP32 output 2e-6 absolute (FP32 sinpi/cospi, acos, atan2); FP16/BF16
+  output additionally one rounding of the stored value (2^-11 / 2^-8 relative).
+* forward: FP32 1e-5 (l2 and max); FP16 and BF16 1e-2 l2; max-norm 1e-2 FP16,
+  3e-2 BF16 (untrained Glorot weights: 2^-8 rounding of operands over 6 layers).
+* training, FP32: loss 1e-5 relative, trained outputs 1e-5.  FP16/BF16: loss 1%,
+  trained outputs 1e-2 l2 after the frame schedule (4 x 16384).  A single step
+  is Adam's first step, which moves every weight by about lr * sign(g): any
+  gradient component whose rounding error exceeds its size moves by 2 lr, so
+  one step from Glorot weights on a small batch gets 3e-2 (FP16) / 8e-2 (BF16)
+  l2.
+* backward with a random upstream gradient: FP32 1e-5; FP16/BF16 are dominated
+  by cancellation in sums of random-sign terms (6e-2 / 2e-1 l2 per layer).
+* every reduced-precision result is also checked against the rounding model
+  (tests/rounding_model.py: the method in FP64 with the kernels' rounding
+  points), which isolates the kernels' own arithmetic: 5e-3 (FP16), 2e-2 (BF16).
 """
 import numpy as np
 import pytest
@@ -17,12 +27,28 @@ torch = pytest.importorskip("torch")
 
 import synthdata as sd
 from oracle import nrc_oracle as O
+from tests import rounding_model as RM
 
 pytestmark = pytest.mark.gpu
 
 PRECS = ["fp32", "fp16", "bf16"]
 ENC_REL = {"fp32": 0.0, "fp16": 2.0 ** -11, "bf16": 2.0 ** -8}
-FWD_TOL = {"fp32": 1e-5, "fp16": 1e-2, "bf16": 3e-2}
+FWD_TOL = {"fp32": 1e-5, "fp16": 1e-2, "bf16": 1e-2}          # l2
+FWD_TOL_MAX = {"fp32": 1e-5, "fp16": 1e-2, "bf16": 3e-2}
+MODEL_TOL = {"fp32": 1e-5, "fp16": 5e-3, "bf16": 2e-2}         # l2 against the rounding model
+
+
+def l2_err(got, ref):
+    got = np.asarray(got, np.float64)
+    ref = np.asarray(ref, np.float64)
+    den = np.linalg.norm(ref, axis=0)
+    return np.linalg.norm(got - ref, axis=0) / np.where(den == 0, 1.0, den)
+
+
+def check_outputs(got, ref, tol_l2, tol_max):
+    e2, em = l2_err(got, ref), O.channel_rel_error(got, ref)
+    assert np.all(e2 <= tol_l2) and np.all(em <= tol_max), f"l2 {e2} max {em}"
+    return e2, em
 
 
 @pytest.fixture(scope="module")
@@ -87,7 +113,9 @@ def test_encode_dyadic_one_blob_exact(N):
     for prec in PRECS:
         c, _ = make_cache(N, prec)
         enc = N.nrc_encode(c, dev(raw), 0).float().cpu().numpy().astype(np.float64)
-        assert np.array_equal(enc[:, 36:40], O.one_blob(s)), prec
+        # exact in FP32 and FP16; BF16 (8 significant bits) rounds 459/512 to 460/512
+        want = RM.quantiser(prec)(O.one_blob(s))
+        assert np.array_equal(enc[:, 36:40], want), prec
 
 
 # ---------------------------------------------------------------------------
@@ -99,9 +127,9 @@ def test_forward_matches_oracle(N, prec, n):
     c, w = make_cache(N, prec)
     x, x64 = rounded_input(sd.uniform_features(n, 64, 7 + n), prec)
     rgb = N.nrc_forward(c, x).cpu().numpy()
-    ref = O.predict(state_of(w), x64)
-    err = O.channel_rel_error(rgb, ref)
-    assert np.all(err <= FWD_TOL[prec]), err
+    check_outputs(rgb, O.predict(state_of(w), x64), FWD_TOL[prec], FWD_TOL_MAX[prec])
+    model = RM.forward(state_of(w).mats(), x64, RM.quantiser(prec))[0]
+    assert np.all(l2_err(rgb, model) <= MODEL_TOL[prec])
 
 
 @pytest.mark.parametrize("prec", ["fp16", "bf16"])
@@ -109,8 +137,9 @@ def test_forward_width128(N, prec):
     c, w = make_cache(N, prec, width=128)
     x, x64 = rounded_input(sd.uniform_features(3000, 64, 8), prec)
     rgb = N.nrc_forward(c, x).cpu().numpy()
-    ref = O.predict(state_of(w, 128), x64)
-    assert np.all(O.channel_rel_error(rgb, ref) <= FWD_TOL[prec])
+    check_outputs(rgb, O.predict(state_of(w, 128), x64), FWD_TOL[prec], FWD_TOL_MAX[prec])
+    model = RM.forward(state_of(w, 128).mats(), x64, RM.quantiser(prec))[0]
+    assert np.all(l2_err(rgb, model) <= MODEL_TOL[prec])
 
 
 @pytest.mark.parametrize("prec", PRECS)
@@ -119,8 +148,7 @@ def test_forward_other_depths(N, prec, n_hidden):
     c, w = make_cache(N, prec, n_hidden=n_hidden)
     x, x64 = rounded_input(sd.uniform_features(777, 64, 9), prec)
     rgb = N.nrc_forward(c, x).cpu().numpy()
-    ref = O.predict(state_of(w, 64, n_hidden), x64)
-    assert np.all(O.channel_rel_error(rgb, ref) <= FWD_TOL[prec])
+    check_outputs(rgb, O.predict(state_of(w, 64, n_hidden), x64), FWD_TOL[prec], FWD_TOL_MAX[prec])
 
 
 @pytest.mark.parametrize("prec", PRECS)
@@ -128,8 +156,7 @@ def test_forward_encoded_records_end_to_end(N, prec):
     c, w = make_cache(N, prec)
     raw = sd.raw_records(5000, sd.SEED_QUERIES)
     rgb = N.nrc_forward(c, N.nrc_encode(c, dev(raw), 0)).cpu().numpy()
-    ref = O.predict(state_of(w), O.encode(raw))
-    assert np.all(O.channel_rel_error(rgb, ref) <= FWD_TOL[prec])
+    check_outputs(rgb, O.predict(state_of(w), O.encode(raw)), FWD_TOL[prec], FWD_TOL_MAX[prec])
 
 
 @pytest.mark.parametrize("prec", PRECS)
@@ -162,6 +189,7 @@ def test_forward_empty(N):
 # Training (Eq. 5, Sec. 5 optimizer, Sec. 3.4-3.5 schedule)
 # ---------------------------------------------------------------------------
 def _train_parity(N, prec, n, steps, seed, out_tol, loss_tol, width=64):
+    """Train on the GPU, in the oracle and in the rounding model; compare held-out outputs."""
     c, w = make_cache(N, prec, width=width)
     raw = sd.raw_records(n * steps, seed)
     enc = N.nrc_encode(c, dev(raw), 0)
@@ -169,17 +197,22 @@ def _train_parity(N, prec, n, steps, seed, out_tol, loss_tol, width=64):
     y = sd.targets(raw)
     yd = dev(y)
     st = state_of(w, width)
+    model = RM.TrainModel(w, prec, width=width, loss_scale=c.cfg.loss_scale)
     for s in range(steps):
         sl = slice(s * n, (s + 1) * n)
         loss, skipped = N.nrc_train_step(c, enc[sl].contiguous(), yd[sl].contiguous())
         ref_loss, ref_skip = O.train_step(st, enc64[sl], y[sl].astype(np.float64))
+        model.step(enc64[sl], y[sl].astype(np.float64))
         assert int(skipped.item()) == 0 and not ref_skip
         assert abs(loss.item() - ref_loss) <= loss_tol * abs(ref_loss), (s, loss.item(), ref_loss)
     q, q64 = rounded_input(O.encode(sd.raw_records(4096, sd.SEED_HELDOUT)), prec)
     got = N.nrc_forward(c, q).cpu().numpy()
     ref = O.predict(st, q64)
-    err = O.channel_rel_error(got, ref)
-    assert np.all(err <= out_tol), err
+    err = l2_err(got, ref)
+    assert np.all(err <= out_tol), f"l2 {err} max {O.channel_rel_error(got, ref)}"
+    if prec != "fp32":
+        e_model = l2_err(got, model.predict(q64))
+        assert np.all(e_model <= MODEL_TOL[prec]), f"against the rounding model: {e_model}"
     wt = c.get_weights().astype(np.float64)
     rel_w = np.linalg.norm(wt - st.w) / np.linalg.norm(st.w)
     return err, rel_w
@@ -195,9 +228,12 @@ def test_train_fp32_four_steps_frame_schedule(N):
     assert rel_w < 1e-5
 
 
+SINGLE_STEP_TOL = {"fp32": 1e-5, "fp16": 3e-2, "bf16": 8e-2}
+
+
 @pytest.mark.parametrize("prec", ["fp16", "bf16"])
 def test_train_mfma_one_step(N, prec):
-    _train_parity(N, prec, 1024, 1, sd.SEED_RECORDS, 1e-2 if prec == "fp16" else 2e-2, 1e-2)
+    _train_parity(N, prec, 1024, 1, sd.SEED_RECORDS, SINGLE_STEP_TOL[prec], 1e-2)
 
 
 @pytest.mark.parametrize("prec", ["fp16", "bf16"])
@@ -206,11 +242,15 @@ def test_train_mfma_four_steps_frame_schedule(N, prec):
     assert rel_w < 2e-2
 
 
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+def test_train_width128_one_step(N, prec):
+    _train_parity(N, prec, 2048, 1, 21, SINGLE_STEP_TOL[prec], 1e-2, width=128)
+
+
 @pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("n", [1, 63, 65, 1000])
 def test_train_ragged_batches(N, prec, n):
-    tol = 1e-5 if prec == "fp32" else 3e-2
-    _train_parity(N, prec, n, 1, 40 + n, tol, 1e-5 if prec == "fp32" else 1e-2)
+    _train_parity(N, prec, n, 1, 40 + n, SINGLE_STEP_TOL[prec], 1e-5 if prec == "fp32" else 1e-2)
 
 
 @pytest.mark.parametrize("prec", PRECS)
@@ -262,27 +302,53 @@ def test_train_is_deterministic_and_resumable(N, prec):
 # ---------------------------------------------------------------------------
 # Backward with an upstream gradient (autograd form)
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("prec,width", [("fp32", 64), ("fp16", 64), ("bf16", 64), ("fp16", 128)])
+BWD_TOL = {"fp32": 1e-5, "fp16": 6e-2, "bf16": 2e-1}
+
+
+@pytest.mark.parametrize("prec,width", [("fp32", 64), ("fp16", 64), ("bf16", 64), ("fp16", 128),
+                                        ("bf16", 128)])
 def test_backward_matches_oracle(N, prec, width):
     c, w = make_cache(N, prec, width=width)
     n = 1000
     x, x64 = rounded_input(sd.uniform_features(n, 64, 14), prec)
     r = sd.gaussian((n, 3), sd.SEED_FD)
     gw, genc = N.nrc_backward(c, x, dev(r))
+    gw, genc = gw.cpu().numpy().astype(np.float64), genc.cpu().numpy().astype(np.float64)
     st = state_of(w, width)
     y, hs = O.forward(st.mats(), x64)
     grads, gin = O.backward(st.mats(), hs, r.astype(np.float64))
-    ref_w = np.concatenate([g.reshape(-1) for g in grads])
-    gw = gw.cpu().numpy()
-    tol = 1e-5 if prec == "fp32" else (1e-2 if prec == "fp16" else 3e-2)
+    q = RM.quantiser(prec)
+    _, mhs, qm = RM.forward(st.mats(), x64, q)
+    mgrads, mgin = RM.backward(qm, mhs, r.astype(np.float64), q)
     off = 0
     for l, g in enumerate(grads):
-        sz = g.size
-        e = np.max(np.abs(gw[off:off + sz] - ref_w[off:off + sz])) / np.max(np.abs(ref_w[off:off + sz]))
-        assert e <= tol, (l, e)
-        off += sz
-    e_in = np.max(np.abs(genc.cpu().numpy() - gin)) / np.max(np.abs(gin))
-    assert e_in <= tol, e_in
+        got = gw[off:off + g.size]
+        e = np.linalg.norm(got - g.reshape(-1)) / np.linalg.norm(g)
+        assert e <= BWD_TOL[prec], ("oracle", l, e)
+        if prec != "fp32":
+            em = np.linalg.norm(got - mgrads[l].reshape(-1)) / np.linalg.norm(mgrads[l])
+            assert em <= MODEL_TOL[prec], ("rounding model", l, em)
+        off += g.size
+    e_in = np.linalg.norm(genc - gin) / np.linalg.norm(gin)
+    assert e_in <= BWD_TOL[prec], e_in
+    if prec != "fp32":
+        assert np.linalg.norm(genc - mgin) / np.linalg.norm(mgin) <= MODEL_TOL[prec]
+
+
+def test_backward_loss_gradient_matches_train_step_direction(N):
+    """With dL/dy of Eq. 5 as the upstream gradient, nrc_backward's weight
+    gradient equals the oracle's loss gradient (FP32 form)."""
+    c, w = make_cache(N, "fp32")
+    raw = sd.raw_records(777, 31)
+    enc = N.nrc_encode(c, dev(raw), 0)
+    e64 = enc.cpu().numpy().astype(np.float64)
+    y = sd.targets(raw).astype(np.float64)
+    st = state_of(w)
+    yhat = O.predict(st, e64)
+    _, d_out = O.relative_l2(yhat, y)
+    gw, _ = N.nrc_backward(c, enc, dev(d_out), want_grad_enc=False)
+    _, g_ref = O.gradient(st, e64, y)
+    assert np.linalg.norm(gw.cpu().numpy() - g_ref) / np.linalg.norm(g_ref) <= 1e-5
 
 
 # ---------------------------------------------------------------------------
@@ -297,5 +363,4 @@ def test_full_frame_sampled(N, prec):
     idx = np.random.Generator(np.random.PCG64(99)).choice(n, 4096, replace=False)
     idx = np.concatenate([idx, [0, n - 1]])
     got = rgb.cpu().numpy()[idx]
-    ref = O.predict(state_of(w), O.encode(raw[idx]))
-    assert np.all(O.channel_rel_error(got, ref) <= FWD_TOL[prec])
+    check_outputs(got, O.predict(state_of(w), O.encode(raw[idx])), FWD_TOL[prec], FWD_TOL_MAX[prec])

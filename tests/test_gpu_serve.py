@@ -1,0 +1,137 @@
+"""Serving loop on the GPU: a mix of queries and training steps over several
+resident caches gives, for every request, exactly (bitwise) the result of the
+same request replayed alone in per-cache order; admission by memory never
+drops a request; a request larger than the arena is refused."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import synthdata as sd
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def N():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2106_12372_amd import nrc
+    return nrc
+
+
+def _requests(n_caches, n_req, seed):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for k in range(n_req):
+        cache = int(rng.integers(0, n_caches))
+        if rng.random() < 0.6:
+            out.append(("infer", cache, int(np.exp(rng.uniform(np.log(100), np.log(200000))))))
+        else:
+            out.append(("train", cache, 4096))
+    return out
+
+
+def _inputs(N, cfg, reqs, seed):
+    data = []
+    enc_cache = N.Cache(cfg)
+    for k, (kind, cache, n) in enumerate(reqs):
+        raw = sd.raw_records(n, seed + k)
+        enc = N.nrc_encode(enc_cache, torch.from_numpy(raw).to("cuda"))
+        tgt = torch.from_numpy(sd.targets(raw)).to("cuda") if kind == "train" else None
+        data.append((enc, tgt))
+    torch.cuda.synchronize()
+    return data
+
+
+@pytest.mark.parametrize("prec", ["fp16", "fp32"])
+def test_mix_equals_solo_replay(N, prec):
+    cfg = N.make_config(precision=prec)
+    n_caches = 4
+    reqs = _requests(n_caches, 40, 60)
+    data = _inputs(N, cfg, reqs, 600)
+    weights = [sd.glorot_weights(seed=70 + i) for i in range(n_caches)]
+
+    srv = N.Server(n_caches, cfg, arena_bytes=1 << 30, n_streams=4, max_inflight=16)
+    for i, w in enumerate(weights):
+        srv.set_weights(i, w)
+    outs, tickets = [], []
+    for (kind, cache, n), (enc, tgt) in zip(reqs, data):
+        if kind == "infer":
+            rgb = torch.full((n, 3), float("nan"), device="cuda")
+            outs.append(rgb)
+            tickets.append(srv.submit_infer(cache, enc, rgb))
+        else:
+            outs.append(None)
+            tickets.append(srv.submit_train(cache, enc, tgt))
+    results = []
+    for t in tickets:
+        r = srv.poll(t)
+        while r is None:
+            r = srv.poll(t)
+        results.append(r)
+    srv.drain()
+    final_w = [srv.get_weights(i) for i in range(n_caches)]
+    srv.close()
+
+    # solo replay, one request at a time, per-cache order
+    caches = []
+    for w in weights:
+        c = N.Cache(cfg)
+        c.set_weights(w)
+        caches.append(c)
+    for (kind, cache, n), (enc, tgt), out, res in zip(reqs, data, outs, results):
+        assert res["status"] == 0
+        assert res["t_submit"] <= res["t_start"] <= res["t_done"]
+        if kind == "infer":
+            solo = N.nrc_forward(caches[cache], enc)
+            torch.cuda.synchronize()
+            assert torch.equal(solo, out), "query result differs between the mix and the solo replay"
+        else:
+            loss, skipped = N.nrc_train_step(caches[cache], enc, tgt)
+            torch.cuda.synchronize()
+            assert loss.item() == res["loss"] and int(skipped.item()) == res["skipped"] == 0
+    for i, c in enumerate(caches):
+        assert np.array_equal(c.get_weights(), final_w[i])
+
+
+def test_admission_by_memory_never_drops(N):
+    cfg = N.make_config(precision="fp16")
+    cache_bytes = N.nrc_cache_bytes(cfg)
+    step_scratch = N.nrc_train_scratch_bytes(cfg, 4096)
+    # room for two caches and exactly one training step's scratch at a time
+    arena = 2 * ((cache_bytes + 255) // 256 * 256) + step_scratch + 256
+    srv = N.Server(2, cfg, arena_bytes=arena, n_streams=2, max_inflight=8)
+    for i in range(2):
+        srv.set_weights(i, sd.glorot_weights(seed=80 + i))
+    raw = sd.raw_records(4096, 81)
+    c0 = N.Cache(cfg)
+    enc = N.nrc_encode(c0, torch.from_numpy(raw).to("cuda"))
+    tgt = torch.from_numpy(sd.targets(raw)).to("cuda")
+    tickets = [srv.submit_train(k % 2, enc, tgt) for k in range(12)]
+    rgb = torch.empty((4096, 3), device="cuda")
+    tickets.append(srv.submit_infer(0, enc, rgb))
+    done = 0
+    for t in tickets:
+        r = srv.poll(t)
+        while r is None:
+            r = srv.poll(t)
+        assert r["status"] == 0
+        done += 1
+    assert done == 13
+    # a step whose scratch can never fit is refused at submission
+    big = sd.raw_records(65536, 82)
+    enc_big = N.nrc_encode(c0, torch.from_numpy(big).to("cuda"))
+    with pytest.raises(N.NrcError) as e:
+        srv.submit_train(0, enc_big, torch.from_numpy(sd.targets(big)).to("cuda"))
+    assert e.value.code == N.NRC_ENOMEM
+    srv.close()
+
+
+def test_poll_unknown_ticket_and_destroy_busy(N):
+    cfg = N.make_config(precision="fp16")
+    srv = N.Server(1, cfg, arena_bytes=64 << 20)
+    import ctypes
+    res = N.nrc_result()
+    assert N.lib.nrc_serve_poll(srv.handle, 12345, ctypes.byref(res)) == N.NRC_ENOTFOUND
+    srv.close()
