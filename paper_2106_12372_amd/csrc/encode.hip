@@ -21,6 +21,10 @@ template <> __device__ inline float to_t<float>(float x) { return x; }
 template <> __device__ inline _Float16 to_t<_Float16>(float x) { return (_Float16)x; }
 template <> __device__ inline __bf16 to_t<__bf16>(float x) { return (__bf16)x; }
 
+// x mod 2 in [0, 2), exact: x/2, floor and 2*floor are exact, and x - 2k has
+// fewer significant bits than x.
+__device__ inline float mod2(float x) { return x - 2.0f * floorf(x * 0.5f); }
+
 // Antiderivative of the quartic kernel 15/16 (1 - u^2)^2 on [-1, 1], clamped
 // to 0 below and 1 above.
 __device__ inline float quartic_cdf(float u) {
@@ -79,15 +83,13 @@ __global__ __launch_bounds__(kEncBlock) void k_encode(const float* __restrict__ 
             if (PRESET == NRC_PRESET_PAPER) {
                 #pragma unroll
                 for (int d = 0; d < 12; ++d) {
-                    const float ph = fmodf(p * (float)(1 << d), 2.0f);
-                    o[12 * c + d] = to_t<T>(sinpif(ph));
+                    o[12 * c + d] = to_t<T>(sinpif(mod2(p * (float)(1 << d))));
                 }
             } else {
                 #pragma unroll
                 for (int d = 0; d < 6; ++d) {
-                    const float ph = fmodf(p * (float)(1 << d), 2.0f);
                     float sn, cs;
-                    sincospif(ph, &sn, &cs);
+                    sincospif(mod2(p * (float)(1 << d)), &sn, &cs);
                     o[12 * c + 2 * d] = to_t<T>(sn);
                     o[12 * c + 2 * d + 1] = to_t<T>(cs);
                 }

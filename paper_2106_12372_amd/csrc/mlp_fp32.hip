@@ -76,6 +76,7 @@ __global__ __launch_bounds__(256) void k_train_fp32(const float* __restrict__ w,
                                                     int n_hidden, int n_params, float loss_eps,
                                                     float grad_scale, float* __restrict__ partials,
                                                     float* __restrict__ loss_part,
+                                                    int32_t* __restrict__ tile_bad,
                                                     float* __restrict__ genc) {
     extern __shared__ __attribute__((aligned(16))) float smem[];
     float* hs = smem;                                     // (n_hidden+1) x [64][kLd]
@@ -178,10 +179,12 @@ __global__ __launch_bounds__(256) void k_train_fp32(const float* __restrict__ w,
         }
     }
     // dW_H[o][i] = sum_s dL/dy[s][o] h_H[s][i]; wave o < 3, lane = i.
+    bool bad = false;   // any non-finite weight-gradient partial in this tile
     if (wave < kNOut) {
         float acc = 0.0f;
         for (int s = 0; s < kTile; ++s) acc = fmaf(dout[s * 4 + wave], hlast[s * kLd + lane], acc);
         part[(n_params - kNOut * kW) + wave * kW + lane] = acc;
+        bad |= !isfinite(acc);
     }
     __syncthreads();
 
@@ -211,7 +214,10 @@ __global__ __launch_bounds__(256) void k_train_fp32(const float* __restrict__ w,
                 }
             }
             #pragma unroll
-            for (int j = 0; j < 16; ++j) part[off + (16 * wave + j) * cols + lane] = acc[j];
+            for (int j = 0; j < 16; ++j) {
+                part[off + (16 * wave + j) * cols + lane] = acc[j];
+                bad |= !isfinite(acc[j]);
+            }
         }
         // delta_l = W_l^T delta_{l+1}, masked (l >= 1); or dL/dh_0 (l == 0).
         if (l >= 1 || GENC) {
@@ -246,6 +252,8 @@ __global__ __launch_bounds__(256) void k_train_fp32(const float* __restrict__ w,
         __syncthreads();
         float* t = dcur; dcur = dnxt; dnxt = t;
     }
+    const int any_bad = __syncthreads_or(bad ? 1 : 0);
+    if (tid == 0) tile_bad[tile] = any_bad ? 1 : 0;
 }
 
 }  // namespace
@@ -265,7 +273,8 @@ size_t fp32_train_lds_bytes(int n_hidden) {
 
 hipError_t launch_train_fp32(const Geo& d, const float* w, const float* enc, const float* tgt,
                              int64_t n, bool upstream, float loss_eps, float grad_scale,
-                             float* partials, float* loss_part, float* genc, hipStream_t s) {
+                             float* partials, float* loss_part, int32_t* tile_bad, float* genc,
+                             hipStream_t s) {
     const int64_t tiles = (n + kTile - 1) / kTile;
     if (tiles == 0) return hipSuccess;
     const size_t lds = fp32_train_lds_bytes(d.H);
@@ -274,17 +283,17 @@ hipError_t launch_train_fp32(const Geo& d, const float* w, const float* enc, con
         auto k = k_train_fp32<false, false>;
         (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         hipLaunchKernelGGL(k, grid, block, lds, s, w, enc, tgt, n, d.H, d.n_params(),
-                           loss_eps, grad_scale, partials, loss_part, genc);
+                           loss_eps, grad_scale, partials, loss_part, tile_bad, genc);
     } else if (genc) {
         auto k = k_train_fp32<true, true>;
         (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         hipLaunchKernelGGL(k, grid, block, lds, s, w, enc, tgt, n, d.H, d.n_params(),
-                           loss_eps, grad_scale, partials, loss_part, genc);
+                           loss_eps, grad_scale, partials, loss_part, tile_bad, genc);
     } else {
         auto k = k_train_fp32<true, false>;
         (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         hipLaunchKernelGGL(k, grid, block, lds, s, w, enc, tgt, n, d.H, d.n_params(),
-                           loss_eps, grad_scale, partials, loss_part, genc);
+                           loss_eps, grad_scale, partials, loss_part, tile_bad, genc);
     }
     return hipGetLastError();
 }

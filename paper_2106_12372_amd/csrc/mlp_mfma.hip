@@ -53,11 +53,22 @@ template <typename V> __device__ inline V zero8() {
 
 // Two accumulator blocks (features 4g..4g+3 and 16+4g..16+4g+3 of a chunk)
 // -> one B operand in chained order.
+typedef float f32x8 __attribute__((ext_vector_type(8)));
 template <typename T, typename V> __device__ inline V pack8(f32x4 lo, f32x4 hi) {
-    V v;
-    v[0] = to_t<T>(lo[0]); v[1] = to_t<T>(lo[1]); v[2] = to_t<T>(lo[2]); v[3] = to_t<T>(lo[3]);
-    v[4] = to_t<T>(hi[0]); v[5] = to_t<T>(hi[1]); v[6] = to_t<T>(hi[2]); v[7] = to_t<T>(hi[3]);
-    return v;
+    const f32x8 f = __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
+    return __builtin_convertvector(f, V);
+}
+
+typedef short s16x8 __attribute__((ext_vector_type(8)));
+
+// ReLU on a packed FP16/BF16 operand: a negative value has its sign bit set,
+// so as a signed 16-bit integer it is negative and max(., 0) maps it to +0;
+// non-negative values are unchanged.  Rounding preserves sign, so
+// relu(round(x)) == round(relu(x)).
+template <typename V> __device__ inline V relu_packed(V v) {
+    s16x8 i = __builtin_bit_cast(s16x8, v);
+    i = __builtin_elementwise_max(i, (s16x8)(0));
+    return __builtin_bit_cast(V, i);
 }
 
 __device__ inline f32x4 relu4(f32x4 a) {
@@ -77,9 +88,9 @@ __device__ inline float wave_sum(float v) {
 // Inference
 // ---------------------------------------------------------------------------
 template <typename T, int W, int COLS>
-__global__ __launch_bounds__(256) void k_fwd_mfma(const T* __restrict__ ffr, int n_frags,
-                                                  const T* __restrict__ enc, int64_t n,
-                                                  float* __restrict__ rgb, int n_hidden) {
+__global__ __launch_bounds__(256, 2) void k_fwd_mfma(const T* __restrict__ ffr, int n_frags,
+                                                     const T* __restrict__ enc, int64_t n,
+                                                     float* __restrict__ rgb, int n_hidden) {
     using V = typename Vec8<T>::type;
     constexpr int MB = W / 16, KC = W / 32;
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
@@ -92,72 +103,70 @@ __global__ __launch_bounds__(256) void k_fwd_mfma(const T* __restrict__ ffr, int
     const int g = lane >> 4, ln = lane & 15;
     const Geo geo(W, n_hidden);
     const int64_t n_tiles = (n + 16 * COLS - 1) / (16 * COLS);
-    for (int64_t tile = (int64_t)blockIdx.x * 4 + wave; tile < n_tiles;
-         tile += (int64_t)gridDim.x * 4) {
+    const int64_t tstride = (int64_t)gridDim.x * 4;
+
+    // The next tile's encoded rows are loaded while the current tile computes.
+    // Rows past the end of the batch read the last row instead (their outputs
+    // are never stored), so the loads need neither branches nor zero fills.
+    V nxt[COLS][2];
+    auto load_tile = [&](int64_t t) {
+        #pragma unroll
+        for (int col = 0; col < COLS; ++col) {
+            int64_t row = t * 16 * COLS + 16 * col + ln;
+            row = row < n ? row : n - 1;
+            #pragma unroll
+            for (int c = 0; c < 2; ++c)
+                nxt[col][c] = *reinterpret_cast<const V*>(enc + row * kEncWidth + 32 * c + 8 * g);
+        }
+    };
+    int64_t tile = (int64_t)blockIdx.x * 4 + wave;
+    if (tile < n_tiles) load_tile(tile);
+    for (; tile < n_tiles; tile += tstride) {
         const int64_t base = tile * 16 * COLS;
         V b[COLS][KC];
         #pragma unroll
         for (int col = 0; col < COLS; ++col) {
-            const int64_t row = base + 16 * col + ln;
-            #pragma unroll
-            for (int c = 0; c < 2; ++c)
-                b[col][c] = row < n ? *reinterpret_cast<const V*>(enc + row * kEncWidth + 32 * c + 8 * g)
-                                    : zero8<V>();
+            b[col][0] = nxt[col][0];
+            b[col][1] = nxt[col][1];
         }
-        // Input layer: K = 64 in natural order.
-        {
-            f32x4 acc[COLS][MB];
-            #pragma unroll
-            for (int col = 0; col < COLS; ++col)
-                #pragma unroll
-                for (int mb = 0; mb < MB; ++mb) acc[col][mb] = f32x4{0.f, 0.f, 0.f, 0.f};
-            #pragma unroll
-            for (int c = 0; c < 2; ++c)
-                #pragma unroll
-                for (int mb = 0; mb < MB; ++mb) {
-                    const V a = sfr[(mb * 2 + c) * 64 + lane];
-                    #pragma unroll
-                    for (int col = 0; col < COLS; ++col) acc[col][mb] = mfma(a, b[col][c], acc[col][mb]);
-                }
-            #pragma unroll
-            for (int col = 0; col < COLS; ++col)
-                #pragma unroll
-                for (int c = 0; c < KC; ++c)
-                    b[col][c] = pack8<T, V>(relu4(acc[col][2 * c]), relu4(acc[col][2 * c + 1]));
-        }
-        // Hidden layers: K = W in chained order.
-        for (int l = 1; l < n_hidden; ++l) {
+        if (tile + tstride < n_tiles) load_tile(tile + tstride);
+        // Layer l: the first K chunk starts from a zero accumulator (an inline
+        // constant operand), ReLU is applied to the packed 16-bit result.
+        for (int l = 0; l < n_hidden; ++l) {
+            const int kc = l == 0 ? 2 : KC;    // the input layer has K = 64
             const V* fl = sfr + geo.fwd_base(l) * 64 + lane;
             f32x4 acc[COLS][MB];
             #pragma unroll
-            for (int col = 0; col < COLS; ++col)
+            for (int mb = 0; mb < MB; ++mb) {
+                const V a = fl[(mb * kc) * 64];
                 #pragma unroll
-                for (int mb = 0; mb < MB; ++mb) acc[col][mb] = f32x4{0.f, 0.f, 0.f, 0.f};
+                for (int col = 0; col < COLS; ++col) acc[col][mb] = mfma(a, b[col][0], f32x4{0.f, 0.f, 0.f, 0.f});
+            }
             #pragma unroll
-            for (int c = 0; c < KC; ++c)
+            for (int c = 1; c < KC; ++c) {
+                if (c >= kc) break;
                 #pragma unroll
                 for (int mb = 0; mb < MB; ++mb) {
-                    const V a = fl[(mb * KC + c) * 64];
+                    const V a = fl[(mb * kc + c) * 64];
                     #pragma unroll
                     for (int col = 0; col < COLS; ++col) acc[col][mb] = mfma(a, b[col][c], acc[col][mb]);
                 }
+            }
             #pragma unroll
             for (int col = 0; col < COLS; ++col)
                 #pragma unroll
                 for (int c = 0; c < KC; ++c)
-                    b[col][c] = pack8<T, V>(relu4(acc[col][2 * c]), relu4(acc[col][2 * c + 1]));
+                    b[col][c] = relu_packed(pack8<T, V>(acc[col][2 * c], acc[col][2 * c + 1]));
         }
         // Output layer: 3 rows of a 16-row block; lanes 0..15 receive rows 0..3.
         const V* fo = sfr + geo.fwd_base(n_hidden) * 64 + lane;
         f32x4 o[COLS];
         #pragma unroll
-        for (int col = 0; col < COLS; ++col) o[col] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int col = 0; col < COLS; ++col) o[col] = mfma(fo[0], b[col][0], f32x4{0.f, 0.f, 0.f, 0.f});
         #pragma unroll
-        for (int c = 0; c < KC; ++c) {
-            const V a = fo[c * 64];
+        for (int c = 1; c < KC; ++c)
             #pragma unroll
-            for (int col = 0; col < COLS; ++col) o[col] = mfma(a, b[col][c], o[col]);
-        }
+            for (int col = 0; col < COLS; ++col) o[col] = mfma(fo[c * 64], b[col][c], o[col]);
         if (g == 0) {
             #pragma unroll
             for (int col = 0; col < COLS; ++col) {
@@ -178,7 +187,15 @@ __global__ __launch_bounds__(256) void k_fwd_mfma(const T* __restrict__ ffr, int
 // ---------------------------------------------------------------------------
 constexpr int kLdt = kTrainTile + 8;  // LDS row stride of the feature-major stores (elements)
 
-template <typename T, int W, bool UPSTREAM, bool GENC>
+// LDS bytes of the activation and delta stores of one training workgroup.
+__host__ __device__ constexpr int train_act_bytes(int W, int H) {
+    return (kEncWidth + H * W + 2 * W) * kLdt * 2;
+}
+
+// STAGE: all weight fragments are copied to LDS once per workgroup (when they
+// fit next to the activations); otherwise each layer reads them from global
+// memory (L2-resident).
+template <typename T, int W, bool UPSTREAM, bool GENC, bool STAGE>
 __global__ __launch_bounds__(256) void k_train_mfma(const T* __restrict__ ffr,
                                                     const T* __restrict__ bfr,
                                                     const T* __restrict__ enc,
@@ -186,16 +203,19 @@ __global__ __launch_bounds__(256) void k_train_mfma(const T* __restrict__ ffr,
                                                     int n_hidden, float loss_eps, float grad_scale,
                                                     float* __restrict__ partials,
                                                     float* __restrict__ loss_part,
+                                                    int32_t* __restrict__ tile_bad,
                                                     float* __restrict__ genc) {
     using V = typename Vec8<T>::type;
     constexpr int MB = W / 16, KC = W / 32;
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     __shared__ float wsum[4];
+    const Geo geo(W, n_hidden);
     T* hT = reinterpret_cast<T*>(smem_raw);              // h_0: 64 rows, h_l: W rows each
     T* dA = hT + (kEncWidth + n_hidden * W) * kLdt;      // delta buffers, W rows each
     T* dB = dA + W * kLdt;
+    V* sfw = reinterpret_cast<V*>(smem_raw + train_act_bytes(W, n_hidden));
+    V* sbw = sfw + geo.n_fwd_frags() * 64;
 
-    const Geo geo(W, n_hidden);
     const int P = geo.n_params();
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int g = lane >> 4, ln = lane & 15;
@@ -204,50 +224,60 @@ __global__ __launch_bounds__(256) void k_train_mfma(const T* __restrict__ ffr,
     const int64_t row = tile * kTrainTile + sl;
     const bool valid = row < n;
     float* part = partials + tile * (int64_t)P;
-    const V* gf = reinterpret_cast<const V*>(ffr) + lane;
-    const V* gb = reinterpret_cast<const V*>(bfr) + lane;
 
-    // ---- forward ------------------------------------------------------------
+    // Encoded inputs of this wave's 16 records (zeros past the end of the batch).
     V b[KC];
     #pragma unroll
-    for (int c = 0; c < 2; ++c) {
-        const V v = valid ? *reinterpret_cast<const V*>(enc + row * kEncWidth + 32 * c + 8 * g)
-                          : zero8<V>();
-        b[c] = v;
-        #pragma unroll
-        for (int i = 0; i < 8; ++i) hT[(32 * c + 8 * g + i) * kLdt + sl] = v[i];
+    for (int c = 0; c < 2; ++c)
+        b[c] = valid ? *reinterpret_cast<const V*>(enc + row * kEncWidth + 32 * c + 8 * g) : zero8<V>();
+    const V* gf;
+    const V* gb;
+    if (STAGE) {
+        const V* src_f = reinterpret_cast<const V*>(ffr);
+        const V* src_b = reinterpret_cast<const V*>(bfr);
+        for (int i = tid; i < geo.n_fwd_frags() * 64; i += 256) sfw[i] = src_f[i];
+        for (int i = tid; i < geo.n_bwd_frags() * 64; i += 256) sbw[i] = src_b[i];
+        gf = sfw + lane;
+        gb = sbw + lane;
+    } else {
+        gf = reinterpret_cast<const V*>(ffr) + lane;
+        gb = reinterpret_cast<const V*>(bfr) + lane;
     }
+    #pragma unroll
+    for (int c = 0; c < 2; ++c)
+        #pragma unroll
+        for (int i = 0; i < 8; ++i) hT[(32 * c + 8 * g + i) * kLdt + sl] = b[c][i];
+    if (STAGE) __syncthreads();
+
+    // ---- forward ------------------------------------------------------------
     for (int l = 0; l < n_hidden; ++l) {
+        const int kc = l == 0 ? 2 : KC;
+        const V* fl = gf + geo.fwd_base(l) * 64;
         f32x4 acc[MB];
         #pragma unroll
-        for (int mb = 0; mb < MB; ++mb) acc[mb] = f32x4{0.f, 0.f, 0.f, 0.f};
-        if (l == 0) {
+        for (int mb = 0; mb < MB; ++mb) acc[mb] = mfma(fl[(mb * kc) * 64], b[0], f32x4{0.f, 0.f, 0.f, 0.f});
+        #pragma unroll
+        for (int c = 1; c < KC; ++c) {
+            if (c >= kc) break;
             #pragma unroll
-            for (int c = 0; c < 2; ++c)
-                #pragma unroll
-                for (int mb = 0; mb < MB; ++mb) acc[mb] = mfma(gf[(mb * 2 + c) * 64], b[c], acc[mb]);
-        } else {
-            const V* fl = gf + geo.fwd_base(l) * 64;
-            #pragma unroll
-            for (int c = 0; c < KC; ++c)
-                #pragma unroll
-                for (int mb = 0; mb < MB; ++mb) acc[mb] = mfma(fl[(mb * KC + c) * 64], b[c], acc[mb]);
+            for (int mb = 0; mb < MB; ++mb) acc[mb] = mfma(fl[(mb * kc + c) * 64], b[c], acc[mb]);
         }
+        #pragma unroll
+        for (int c = 0; c < KC; ++c) b[c] = relu_packed(pack8<T, V>(acc[2 * c], acc[2 * c + 1]));
+        // h_{l+1} to LDS, feature-major: slot i of chunk c holds feature chained_feature(c, g, i)
         T* ho = hT + (kEncWidth + l * W) * kLdt;
         #pragma unroll
-        for (int mb = 0; mb < MB; ++mb) {
-            acc[mb] = relu4(acc[mb]);
+        for (int c = 0; c < KC; ++c)
             #pragma unroll
-            for (int j = 0; j < 4; ++j) ho[(16 * mb + 4 * g + j) * kLdt + sl] = to_t<T>(acc[mb][j]);
-        }
-        #pragma unroll
-        for (int c = 0; c < KC; ++c) b[c] = pack8<T, V>(acc[2 * c], acc[2 * c + 1]);
+            for (int i = 0; i < 8; ++i)
+                ho[(32 * c + (i < 4 ? 4 * g + i : 12 + 4 * g + i)) * kLdt + sl] = b[c][i];
     }
-    f32x4 y = f32x4{0.f, 0.f, 0.f, 0.f};
+    f32x4 y;
     {
         const V* fo = gf + geo.fwd_base(n_hidden) * 64;
+        y = mfma(fo[0], b[0], f32x4{0.f, 0.f, 0.f, 0.f});
         #pragma unroll
-        for (int c = 0; c < KC; ++c) y = mfma(fo[c * 64], b[c], y);
+        for (int c = 1; c < KC; ++c) y = mfma(fo[c * 64], b[c], y);
     }
 
     // ---- loss gradient (Eq. 5), lanes 0..15 of each wave hold y[0..2] -------
@@ -281,6 +311,7 @@ __global__ __launch_bounds__(256) void k_train_mfma(const T* __restrict__ ffr,
     __syncthreads();
     if (tid == 0) loss_part[tile] = ((wsum[0] + wsum[1]) + wsum[2]) + wsum[3];
 
+    bool bad = false;   // any non-finite weight-gradient partial in this tile
     // ---- output layer: dW_H = dL/dy h_H^T, delta_H = W_H^T dL/dy ------------
     const T* hH = hT + (kEncWidth + (n_hidden - 1) * W) * kLdt;
     for (int nb = wave; nb < MB; nb += 4) {
@@ -294,7 +325,10 @@ __global__ __launch_bounds__(256) void k_train_mfma(const T* __restrict__ ffr,
         }
         if (g == 0) {
             #pragma unroll
-            for (int j = 0; j < kNOut; ++j) part[geo.w_off(n_hidden) + j * W + 16 * nb + ln] = acc[j];
+            for (int j = 0; j < kNOut; ++j) {
+                part[geo.w_off(n_hidden) + j * W + 16 * nb + ln] = acc[j];
+                bad |= !isfinite(acc[j]);
+            }
         }
     }
     {
@@ -307,12 +341,14 @@ __global__ __launch_bounds__(256) void k_train_mfma(const T* __restrict__ ffr,
             #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int f = 16 * mb + 4 * g + j;
-                const float v = (float)hH[f * kLdt + sl] > 0.0f ? acc[mb][j] : 0.0f;
-                acc[mb][j] = v;
-                dB[f * kLdt + sl] = to_t<T>(v);
+                acc[mb][j] = (float)hH[f * kLdt + sl] > 0.0f ? acc[mb][j] : 0.0f;
             }
         #pragma unroll
-        for (int c = 0; c < KC; ++c) b[c] = pack8<T, V>(acc[2 * c], acc[2 * c + 1]);
+        for (int c = 0; c < KC; ++c) {
+            b[c] = pack8<T, V>(acc[2 * c], acc[2 * c + 1]);
+            #pragma unroll
+            for (int i = 0; i < 8; ++i) dB[(32 * c + (i < 4 ? 4 * g + i : 12 + 4 * g + i)) * kLdt + sl] = b[c][i];
+        }
     }
 
     // ---- hidden and input layers ------------------------------------------
@@ -331,15 +367,14 @@ __global__ __launch_bounds__(256) void k_train_mfma(const T* __restrict__ ffr,
                 bb[kc] = *reinterpret_cast<const V*>(hl + (16 * nb + ln) * kLdt + 32 * kc + 8 * g);
             #pragma unroll
             for (int mb = 0; mb < MB; ++mb) {
-                f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
+                f32x4 acc = mfma(*reinterpret_cast<const V*>(dcur + (16 * mb + ln) * kLdt + 8 * g), bb[0],
+                                 f32x4{0.f, 0.f, 0.f, 0.f});
+                acc = mfma(*reinterpret_cast<const V*>(dcur + (16 * mb + ln) * kLdt + 32 + 8 * g), bb[1], acc);
                 #pragma unroll
-                for (int kc = 0; kc < 2; ++kc) {
-                    const V a = *reinterpret_cast<const V*>(dcur + (16 * mb + ln) * kLdt + 32 * kc + 8 * g);
-                    acc = mfma(a, bb[kc], acc);
-                }
-                #pragma unroll
-                for (int j = 0; j < 4; ++j)
+                for (int j = 0; j < 4; ++j) {
                     part[woff + (16 * mb + 4 * g + j) * ncols + 16 * nb + ln] = acc[j];
+                    bad |= !isfinite(acc[j]);
+                }
             }
         }
         if (l >= 1) {
@@ -347,9 +382,9 @@ __global__ __launch_bounds__(256) void k_train_mfma(const T* __restrict__ ffr,
             const V* fb = gb + geo.bwd_base(l) * 64;
             f32x4 acc[MB];
             #pragma unroll
-            for (int mb = 0; mb < MB; ++mb) acc[mb] = f32x4{0.f, 0.f, 0.f, 0.f};
+            for (int mb = 0; mb < MB; ++mb) acc[mb] = mfma(fb[(mb * KC) * 64], b[0], f32x4{0.f, 0.f, 0.f, 0.f});
             #pragma unroll
-            for (int c = 0; c < KC; ++c)
+            for (int c = 1; c < KC; ++c)
                 #pragma unroll
                 for (int mb = 0; mb < MB; ++mb) acc[mb] = mfma(fb[(mb * KC + c) * 64], b[c], acc[mb]);
             #pragma unroll
@@ -357,20 +392,23 @@ __global__ __launch_bounds__(256) void k_train_mfma(const T* __restrict__ ffr,
                 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     const int f = 16 * mb + 4 * g + j;
-                    const float v = (float)hl[f * kLdt + sl] > 0.0f ? acc[mb][j] : 0.0f;
-                    acc[mb][j] = v;
-                    dnxt[f * kLdt + sl] = to_t<T>(v);
+                    acc[mb][j] = (float)hl[f * kLdt + sl] > 0.0f ? acc[mb][j] : 0.0f;
                 }
             #pragma unroll
-            for (int c = 0; c < KC; ++c) b[c] = pack8<T, V>(acc[2 * c], acc[2 * c + 1]);
+            for (int c = 0; c < KC; ++c) {
+                b[c] = pack8<T, V>(acc[2 * c], acc[2 * c + 1]);
+                #pragma unroll
+                for (int i = 0; i < 8; ++i)
+                    dnxt[(32 * c + (i < 4 ? 4 * g + i : 12 + 4 * g + i)) * kLdt + sl] = b[c][i];
+            }
             T* t = dcur; dcur = dnxt; dnxt = t;
         } else if (GENC) {
             // dL/dh_0 = W_0^T delta_1 (64 input features).
             f32x4 acc[4];
             #pragma unroll
-            for (int mb = 0; mb < 4; ++mb) acc[mb] = f32x4{0.f, 0.f, 0.f, 0.f};
+            for (int mb = 0; mb < 4; ++mb) acc[mb] = mfma(gb[(mb * KC) * 64], b[0], f32x4{0.f, 0.f, 0.f, 0.f});
             #pragma unroll
-            for (int c = 0; c < KC; ++c)
+            for (int c = 1; c < KC; ++c)
                 #pragma unroll
                 for (int mb = 0; mb < 4; ++mb) acc[mb] = mfma(gb[(mb * KC + c) * 64], b[c], acc[mb]);
             if (valid) {
@@ -381,6 +419,8 @@ __global__ __launch_bounds__(256) void k_train_mfma(const T* __restrict__ ffr,
             }
         }
     }
+    const int any_bad = __syncthreads_or(bad ? 1 : 0);
+    if (tid == 0) tile_bad[tile] = any_bad ? 1 : 0;
 }
 
 template <typename T, int W>
@@ -391,7 +431,7 @@ hipError_t fwd_dispatch(const Geo& d, const void* ffr, const void* enc, int64_t 
     if (tiles == 0) return hipSuccess;
     const size_t lds = (size_t)d.n_fwd_frags() * 64 * 16;
     int64_t blocks = (tiles + 3) / 4;
-    if (blocks > 2048) blocks = 2048;
+    if (blocks > 2048) blocks = 2048;   // persistent: 2048 workgroups cover the 256 CUs several times
     auto k = k_fwd_mfma<T, W, COLS>;
     (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(256), lds, s, (const T*)ffr, d.n_fwd_frags(),
@@ -402,36 +442,48 @@ hipError_t fwd_dispatch(const Geo& d, const void* ffr, const void* enc, int64_t 
 template <typename T, int W, bool UP, bool GE>
 hipError_t train_launch(const Geo& d, const void* ffr, const void* bfr, const void* enc,
                         const float* tgt, int64_t n, float loss_eps, float grad_scale,
-                        float* partials, float* loss_part, float* genc, hipStream_t s) {
+                        float* partials, float* loss_part, int32_t* tile_bad, float* genc,
+                        hipStream_t s) {
     const int64_t tiles = (n + kTrainTile - 1) / kTrainTile;
     if (tiles == 0) return hipSuccess;
-    const size_t lds = (size_t)(kEncWidth + d.H * W + 2 * W) * kLdt * sizeof(T);
-    auto k = k_train_mfma<T, W, UP, GE>;
-    (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(k, dim3((unsigned)tiles), dim3(256), lds, s, (const T*)ffr, (const T*)bfr,
-                       (const T*)enc, tgt, n, d.H, loss_eps, grad_scale, partials, loss_part, genc);
+    const size_t act = (size_t)train_act_bytes(W, d.H);
+    const size_t staged = act + (size_t)(d.n_fwd_frags() + d.n_bwd_frags()) * 1024;
+    const size_t lds_cap = 160 * 1024 - 64;   // gfx950 LDS per workgroup, minus the static part
+    if (staged <= lds_cap) {
+        auto k = k_train_mfma<T, W, UP, GE, true>;
+        (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)staged);
+        hipLaunchKernelGGL(k, dim3((unsigned)tiles), dim3(256), staged, s, (const T*)ffr, (const T*)bfr,
+                           (const T*)enc, tgt, n, d.H, loss_eps, grad_scale, partials, loss_part,
+                           tile_bad, genc);
+    } else {
+        auto k = k_train_mfma<T, W, UP, GE, false>;
+        (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)act);
+        hipLaunchKernelGGL(k, dim3((unsigned)tiles), dim3(256), act, s, (const T*)ffr, (const T*)bfr,
+                           (const T*)enc, tgt, n, d.H, loss_eps, grad_scale, partials, loss_part,
+                           tile_bad, genc);
+    }
     return hipGetLastError();
 }
 
 template <typename T, int W>
 hipError_t train_dispatch(const Geo& d, const void* ffr, const void* bfr, const void* enc,
                           const float* tgt, int64_t n, bool upstream, float loss_eps,
-                          float grad_scale, float* partials, float* loss_part, float* genc,
-                          hipStream_t s) {
+                          float grad_scale, float* partials, float* loss_part, int32_t* tile_bad,
+                          float* genc, hipStream_t s) {
     if (!upstream)
         return train_launch<T, W, false, false>(d, ffr, bfr, enc, tgt, n, loss_eps, grad_scale,
-                                                partials, loss_part, genc, s);
+                                                partials, loss_part, tile_bad, genc, s);
     if (genc)
         return train_launch<T, W, true, true>(d, ffr, bfr, enc, tgt, n, loss_eps, grad_scale,
-                                              partials, loss_part, genc, s);
+                                              partials, loss_part, tile_bad, genc, s);
     return train_launch<T, W, true, false>(d, ffr, bfr, enc, tgt, n, loss_eps, grad_scale,
-                                           partials, loss_part, genc, s);
+                                           partials, loss_part, tile_bad, genc, s);
 }
 
 }  // namespace
 
 size_t mfma_train_lds_bytes(int width, int n_hidden) {
-    return (size_t)(kEncWidth + n_hidden * width + 2 * width) * kLdt * 2 + 16;
+    return (size_t)train_act_bytes(width, n_hidden) + 16;
 }
 size_t mfma_fwd_lds_bytes(int width, int n_hidden) {
     return (size_t)Geo(width, n_hidden).n_fwd_frags() * 64 * 16;
@@ -449,16 +501,16 @@ hipError_t launch_fwd_mfma(int precision, const Geo& d, const void* ffr, const v
 hipError_t launch_train_mfma(int precision, const Geo& d, const void* ffr, const void* bfr,
                              const void* enc, const float* tgt, int64_t n, bool upstream,
                              float loss_eps, float grad_scale, float* partials, float* loss_part,
-                             float* genc, hipStream_t s) {
+                             int32_t* tile_bad, float* genc, hipStream_t s) {
     if (precision == NRC_FP16)
         return d.W == 64 ? train_dispatch<_Float16, 64>(d, ffr, bfr, enc, tgt, n, upstream, loss_eps,
-                                                        grad_scale, partials, loss_part, genc, s)
+                                                        grad_scale, partials, loss_part, tile_bad, genc, s)
                          : train_dispatch<_Float16, 128>(d, ffr, bfr, enc, tgt, n, upstream, loss_eps,
-                                                         grad_scale, partials, loss_part, genc, s);
+                                                         grad_scale, partials, loss_part, tile_bad, genc, s);
     return d.W == 64 ? train_dispatch<__bf16, 64>(d, ffr, bfr, enc, tgt, n, upstream, loss_eps,
-                                                  grad_scale, partials, loss_part, genc, s)
+                                                  grad_scale, partials, loss_part, tile_bad, genc, s)
                      : train_dispatch<__bf16, 128>(d, ffr, bfr, enc, tgt, n, upstream, loss_eps,
-                                                   grad_scale, partials, loss_part, genc, s);
+                                                   grad_scale, partials, loss_part, tile_bad, genc, s);
 }
 
 }  // namespace nrc

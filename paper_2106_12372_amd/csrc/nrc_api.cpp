@@ -99,7 +99,7 @@ ScratchLayout scratch_layout(const nrc_config& c, int64_t n) {
     L.partials = take(tiles * P * 4);
     L.loss_part = take(tiles * 4);
     L.grad = take(P * 4);
-    L.flags = take((size_t)reduce_blocks((int)P) * 4);
+    L.flags = take(tiles * 4);
     L.loss = take(16);
     L.skipped = take(16);
     L.total = off;
@@ -114,27 +114,24 @@ int enqueue_train_step(nrc_cache* c, const void* enc, const float* target, int64
     const ScratchLayout sl = scratch_layout(cfg, n);
     float* partials = (float*)(scratch + sl.partials);
     float* loss_part = (float*)(scratch + sl.loss_part);
-    float* grad = (float*)(scratch + sl.grad);
-    int32_t* flags = (int32_t*)(scratch + sl.flags);
+    int32_t* tile_bad = (int32_t*)(scratch + sl.flags);
     const float scale = cfg.loss_scale;
     const float grad_scale = (float)((double)scale / (3.0 * (double)n));
     hipError_t e;
     if (cfg.precision == NRC_FP32)
         e = launch_train_fp32(d, c->w(), (const float*)enc, target, n, false, cfg.loss_eps, grad_scale,
-                              partials, loss_part, nullptr, s);
+                              partials, loss_part, tile_bad, nullptr, s);
     else
         e = launch_train_mfma(cfg.precision, d, c->ffr(), c->bfr(), enc, target, n, false, cfg.loss_eps,
-                              grad_scale, partials, loss_part, nullptr, s);
+                              grad_scale, partials, loss_part, tile_bad, nullptr, s);
     if (e != hipSuccess) return device_fail(e, "training kernel launch");
     float* loss_out = loss_dev ? loss_dev : (float*)(scratch + sl.loss);
-    e = launch_reduce(partials, (int)sl.tiles, d.n_params(), 1.0f / scale, grad, flags, loss_part,
-                      (float)(1.0 / (3.0 * (double)n)), loss_out, s);
-    if (e != hipSuccess) return device_fail(e, "gradient reduction launch");
-    const AdamHyper hp{cfg.lr, cfg.beta1, cfg.beta2, cfg.adam_eps};
     int32_t* skipped_out = skipped_dev ? skipped_dev : (int32_t*)(scratch + sl.skipped);
-    e = launch_adam(cfg.precision, d, c->w(), c->m(), c->v(), c->tslots(), c->parity, grad, flags,
-                    reduce_blocks(d.n_params()), hp, skipped_out, c->ffr(), c->bfr(), s);
-    if (e != hipSuccess) return device_fail(e, "Adam launch");
+    const AdamHyper hp{cfg.lr, cfg.beta1, cfg.beta2, cfg.adam_eps};
+    e = launch_reduce_adam(cfg.precision, d, partials, (int)sl.tiles, tile_bad, loss_part,
+                           (float)(1.0 / (3.0 * (double)n)), loss_out, 1.0f / scale, c->w(), c->m(),
+                           c->v(), c->tslots(), c->parity, hp, skipped_out, c->ffr(), c->bfr(), s);
+    if (e != hipSuccess) return device_fail(e, "gradient reduction / Adam launch");
     c->parity ^= 1;
     return NRC_OK;
 }
@@ -390,18 +387,17 @@ int nrc_backward(nrc_cache* cache, const void* enc, const float* grad_rgb, int64
     char* sc = (char*)scratch;
     float* partials = (float*)(sc + sl.partials);
     float* loss_part = (float*)(sc + sl.loss_part);
-    int32_t* flags = (int32_t*)(sc + sl.flags);
+    int32_t* tile_bad = (int32_t*)(sc + sl.flags);
     hipStream_t s = (hipStream_t)stream;
     hipError_t e;
     if (cfg.precision == NRC_FP32)
         e = launch_train_fp32(d, cache->w(), (const float*)enc, grad_rgb, n, true, cfg.loss_eps, 1.0f,
-                              partials, loss_part, grad_enc, s);
+                              partials, loss_part, tile_bad, grad_enc, s);
     else
         e = launch_train_mfma(cfg.precision, d, cache->ffr(), cache->bfr(), enc, grad_rgb, n, true,
-                              cfg.loss_eps, 1.0f, partials, loss_part, grad_enc, s);
+                              cfg.loss_eps, 1.0f, partials, loss_part, tile_bad, grad_enc, s);
     if (e != hipSuccess) return device_fail(e, "backward kernel launch");
-    e = launch_reduce(partials, (int)sl.tiles, d.n_params(), 1.0f, grad_w, flags, loss_part, 1.0f,
-                      nullptr, s);
+    e = launch_reduce(d, partials, (int)sl.tiles, 1.0f, grad_w, loss_part, 1.0f, nullptr, s);
     if (e != hipSuccess) return device_fail(e, "gradient reduction launch");
     return ok();
 }

@@ -105,25 +105,28 @@ hipError_t launch_fwd_fp32(const Geo& d, const float* w, const float* enc, int64
                            hipStream_t s);
 hipError_t launch_train_fp32(const Geo& d, const float* w, const float* enc, const float* tgt,
                              int64_t n, bool upstream, float loss_eps, float grad_scale,
-                             float* partials, float* loss_part, float* genc, hipStream_t s);
+                             float* partials, float* loss_part, int32_t* tile_bad, float* genc,
+                             hipStream_t s);
 // mlp_mfma.hip
 hipError_t launch_fwd_mfma(int precision, const Geo& d, const void* ffr, const void* enc,
                            int64_t n, float* rgb, hipStream_t s);
 hipError_t launch_train_mfma(int precision, const Geo& d, const void* ffr, const void* bfr,
                              const void* enc, const float* tgt, int64_t n, bool upstream,
                              float loss_eps, float grad_scale, float* partials, float* loss_part,
-                             float* genc, hipStream_t s);
+                             int32_t* tile_bad, float* genc, hipStream_t s);
 size_t fp32_train_lds_bytes(int n_hidden);
 size_t mfma_train_lds_bytes(int width, int n_hidden);
 size_t mfma_fwd_lds_bytes(int width, int n_hidden);
 // optim.hip
 int reduce_blocks(int n_params);
-hipError_t launch_reduce(const float* partials, int n_tiles, int n_params, float inv_scale,
-                         float* grad, int32_t* flags, const float* loss_part, float inv_count,
-                         float* loss_out, hipStream_t s);
-hipError_t launch_adam(int precision, const Geo& d, float* w, float* m, float* v, int32_t* tslots,
-                       int parity, const float* grad, const int32_t* flags, int n_flags,
-                       AdamHyper hp, int32_t* skipped_out, void* ffr, void* bfr, hipStream_t s);
+hipError_t launch_reduce(const Geo& d, const float* partials, int n_tiles, float inv_scale,
+                         float* grad, const float* loss_part, float inv_count, float* loss_out,
+                         hipStream_t s);
+hipError_t launch_reduce_adam(int precision, const Geo& d, const float* partials, int n_tiles,
+                              const int32_t* tile_bad, const float* loss_part, float inv_count,
+                              float* loss_out, float inv_scale, float* w, float* m, float* v,
+                              int32_t* tslots, int parity, AdamHyper hp, int32_t* skipped_out,
+                              void* ffr, void* bfr, hipStream_t s);
 hipError_t launch_build_frags(int precision, const Geo& d, const float* w, void* ffr, void* bfr,
                               hipStream_t s);
 

@@ -1,17 +1,18 @@
 // Weight-gradient reduction and the Adam update (Sec. 5 "Optimizer").
 //
-// k_reduce: one thread per weight sums that weight's per-tile partials in a
-// fixed tile order with Neumaier compensation, so the reduced gradient does
-// not depend on scheduling, and flags non-finite results per workgroup.  The
-// first wave of workgroup 0 also reduces the per-tile loss partials.
-//
-// k_adam: one thread per weight.  If any workgroup flagged a non-finite
-// gradient the whole step is skipped (weights, moments and step count stay as
-// they are).  Otherwise the FP32 master weight and its moments are updated
-// and the reduced-precision copies in both matrix-core fragment layouts are
-// refreshed in place.  The step count lives in two device slots used in
-// alternation (read one, write the other), so no thread of the launch ever
-// reads a value another thread of the same launch writes.
+// k_reduce<ADAM>: a workgroup owns 32 consecutive weights; its 8 groups of 32
+// lanes each sum every 8th tile's partial for one weight (coalesced 128-byte
+// rows), with Neumaier compensation, and the 8 group sums are combined in a
+// fixed order, so the reduced gradient does not depend on scheduling.
+// Without ADAM the gradient is written out (backward of the autograd form).
+// With ADAM the workgroup first ORs the per-tile non-finite flags the training
+// kernel wrote: if any is set the whole step is skipped (weights, moments and
+// step count stay as they are); otherwise each weight's FP32 master copy and
+// Adam moments are updated and its FP16/BF16 copies in both matrix-core
+// fragment layouts are refreshed.  The step count lives in two device slots
+// used in alternation (read one, write the other), so no thread of the launch
+// reads a value another thread of the same launch writes.  Workgroup 0 also
+// reduces the per-tile loss partials.
 #include "nrc_internal.h"
 
 namespace nrc {
@@ -23,41 +24,6 @@ __device__ inline void neumaier_add(float& s, float& c, float x) {
     const float t = s + x;
     if (fabsf(s) >= fabsf(x)) c += (s - t) + x; else c += (x - t) + s;
     s = t;
-}
-
-__global__ __launch_bounds__(kRedBlock) void k_reduce(const float* __restrict__ partials,
-                                                      int n_tiles, int P, float inv_scale,
-                                                      float* __restrict__ grad,
-                                                      int32_t* __restrict__ flags,
-                                                      const float* __restrict__ loss_part,
-                                                      float inv_count, float* __restrict__ loss_out) {
-    const int p = blockIdx.x * kRedBlock + threadIdx.x;
-    int bad = 0;
-    if (p < P) {
-        float s = 0.0f, c = 0.0f;
-        int t = 0;
-        for (; t + 8 <= n_tiles; t += 8) {
-            float x[8];
-            #pragma unroll
-            for (int u = 0; u < 8; ++u) x[u] = partials[(int64_t)(t + u) * P + p];
-            #pragma unroll
-            for (int u = 0; u < 8; ++u) neumaier_add(s, c, x[u]);
-        }
-        for (; t < n_tiles; ++t) neumaier_add(s, c, partials[(int64_t)t * P + p]);
-        const float gv = (s + c) * inv_scale;
-        grad[p] = gv;
-        bad = !isfinite(gv);
-    }
-    const int any = __syncthreads_or(bad);
-    if (threadIdx.x == 0) flags[blockIdx.x] = any ? 1 : 0;
-    if (blockIdx.x == 0 && threadIdx.x < 64 && loss_out != nullptr) {
-        float s = 0.0f, c = 0.0f;
-        for (int t = threadIdx.x; t < n_tiles; t += 64) neumaier_add(s, c, loss_part[t]);
-        float v = s + c;
-        #pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-        if (threadIdx.x == 0) *loss_out = v * inv_count;
-    }
 }
 
 // Locate weight p (flat index) as (layer, row, column).
@@ -84,37 +50,84 @@ __device__ inline void write_frags(const Geo& d, int p, float w, T* ffr, T* bfr)
     bfr[bwd_frag_index(d, l, o, k)] = v;
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_adam(float* __restrict__ w, float* __restrict__ m,
-                                              float* __restrict__ v, int32_t* __restrict__ tslots,
-                                              int parity, const float* __restrict__ grad,
-                                              const int32_t* __restrict__ flags, int n_flags,
-                                              AdamHyper hp, int32_t* __restrict__ skipped_out,
-                                              T* __restrict__ ffr, T* __restrict__ bfr, int width,
-                                              int n_hidden) {
+constexpr int kRedParams = 32;   // weights per workgroup
+constexpr int kRedGroups = 8;    // tile groups per workgroup
+
+template <typename T, bool ADAM>
+__global__ __launch_bounds__(256) void k_reduce(const float* __restrict__ partials, int n_tiles,
+                                                const int32_t* __restrict__ tile_bad,
+                                                const float* __restrict__ loss_part, float inv_count,
+                                                float* __restrict__ loss_out, float inv_scale,
+                                                float* __restrict__ grad_out, float* __restrict__ w,
+                                                float* __restrict__ m, float* __restrict__ v,
+                                                int32_t* __restrict__ tslots, int parity, AdamHyper hp,
+                                                int32_t* __restrict__ skipped_out, T* __restrict__ ffr,
+                                                T* __restrict__ bfr, int width, int n_hidden) {
+    __shared__ float s_sum[kRedGroups][kRedParams];
+    __shared__ float s_cmp[kRedGroups][kRedParams];
     __shared__ int s_skip;
-    if (threadIdx.x < 64) {
+    const Geo d(width, n_hidden);
+    const int P = d.n_params();
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int pl = tid % kRedParams, grp = tid / kRedParams;
+    const int p = blockIdx.x * kRedParams + pl;
+
+    if (ADAM && tid < 64) {
         int any = 0;
-        for (int i = threadIdx.x; i < n_flags; i += 64) any |= flags[i];
+        for (int t = tid; t < n_tiles; t += 64) any |= tile_bad[t];
         #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) any |= __shfl_xor(any, off, 64);
-        if (threadIdx.x == 0) s_skip = any;
+        if (tid == 0) s_skip = any;
     }
+    float s = 0.0f, c = 0.0f;
+    if (p < P) {
+        int t = grp;
+        for (; t + 3 * kRedGroups < n_tiles; t += 4 * kRedGroups) {
+            float x[4];
+            #pragma unroll
+            for (int u = 0; u < 4; ++u) x[u] = partials[(int64_t)(t + u * kRedGroups) * P + p];
+            #pragma unroll
+            for (int u = 0; u < 4; ++u) neumaier_add(s, c, x[u]);
+        }
+        for (; t < n_tiles; t += kRedGroups) neumaier_add(s, c, partials[(int64_t)t * P + p]);
+    }
+    s_sum[grp][pl] = s;
+    s_cmp[grp][pl] = c;
     __syncthreads();
+
+    if (blockIdx.x == 0 && tid >= 64 && tid < 128 && loss_out != nullptr) {
+        float ls = 0.0f, lc = 0.0f;
+        for (int t = lane; t < n_tiles; t += 64) neumaier_add(ls, lc, loss_part[t]);
+        float lv = ls + lc;
+        #pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) lv += __shfl_xor(lv, off, 64);
+        if (lane == 0) *loss_out = lv * inv_count;
+    }
+    if (grp != 0 || p >= P) return;   // workgroup 0's thread 0 has p = 0 and stays
+    float gv = 0.0f;
+    {
+        float S = 0.0f, C = 0.0f;
+        #pragma unroll
+        for (int k = 0; k < kRedGroups; ++k) {
+            neumaier_add(S, C, s_sum[k][pl]);
+            C += s_cmp[k][pl];
+        }
+        gv = (S + C) * inv_scale;
+    }
+    if (!ADAM) {
+        grad_out[p] = gv;
+        return;
+    }
     const int skip = s_skip;
     const int t_old = tslots[parity];
     const int t_new = skip ? t_old : t_old + 1;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (blockIdx.x == 0 && tid == 0) {
         tslots[parity ^ 1] = t_new;
         if (skipped_out) *skipped_out = skip;
     }
     if (skip) return;
-    const Geo d(width, n_hidden);
-    const int p = blockIdx.x * 256 + threadIdx.x;
-    if (p >= d.n_params()) return;
-    const float g = grad[p];
-    const float m1 = hp.beta1 * m[p] + (1.0f - hp.beta1) * g;
-    const float v1 = hp.beta2 * v[p] + (1.0f - hp.beta2) * g * g;
+    const float m1 = hp.beta1 * m[p] + (1.0f - hp.beta1) * gv;
+    const float v1 = hp.beta2 * v[p] + (1.0f - hp.beta2) * gv * gv;
     const float bc1 = 1.0f - powf(hp.beta1, (float)t_new);
     const float bc2 = 1.0f - powf(hp.beta2, (float)t_new);
     const float w1 = w[p] - hp.lr * (m1 / bc1) / (sqrtf(v1 / bc2) + hp.eps);
@@ -135,29 +148,35 @@ __global__ __launch_bounds__(256) void k_build_frags(const float* __restrict__ w
 
 }  // namespace
 
-int reduce_blocks(int n_params) { return (n_params + kRedBlock - 1) / kRedBlock; }
+int reduce_blocks(int n_params) { return (n_params + kRedParams - 1) / kRedParams; }
 
-hipError_t launch_reduce(const float* partials, int n_tiles, int n_params, float inv_scale,
-                         float* grad, int32_t* flags, const float* loss_part, float inv_count,
-                         float* loss_out, hipStream_t s) {
-    hipLaunchKernelGGL(k_reduce, dim3(reduce_blocks(n_params)), dim3(kRedBlock), 0, s, partials,
-                       n_tiles, n_params, inv_scale, grad, flags, loss_part, inv_count, loss_out);
+hipError_t launch_reduce(const Geo& d, const float* partials, int n_tiles, float inv_scale,
+                         float* grad, const float* loss_part, float inv_count, float* loss_out,
+                         hipStream_t s) {
+    hipLaunchKernelGGL((k_reduce<_Float16, false>), dim3(reduce_blocks(d.n_params())), dim3(256), 0, s,
+                       partials, n_tiles, (const int32_t*)nullptr, loss_part, inv_count, loss_out,
+                       inv_scale, grad, (float*)nullptr, (float*)nullptr, (float*)nullptr,
+                       (int32_t*)nullptr, 0, AdamHyper{}, (int32_t*)nullptr, (_Float16*)nullptr,
+                       (_Float16*)nullptr, d.W, d.H);
     return hipGetLastError();
 }
 
-hipError_t launch_adam(int precision, const Geo& d, float* w, float* m, float* v, int32_t* tslots,
-                       int parity, const float* grad, const int32_t* flags, int n_flags,
-                       AdamHyper hp, int32_t* skipped_out, void* ffr, void* bfr, hipStream_t s) {
-    const dim3 grid((d.n_params() + 255) / 256), block(256);
-    if (precision == NRC_FP16)
-        hipLaunchKernelGGL(k_adam<_Float16>, grid, block, 0, s, w, m, v, tslots, parity, grad, flags,
-                           n_flags, hp, skipped_out, (_Float16*)ffr, (_Float16*)bfr, d.W, d.H);
-    else if (precision == NRC_BF16)
-        hipLaunchKernelGGL(k_adam<__bf16>, grid, block, 0, s, w, m, v, tslots, parity, grad, flags,
-                           n_flags, hp, skipped_out, (__bf16*)ffr, (__bf16*)bfr, d.W, d.H);
+hipError_t launch_reduce_adam(int precision, const Geo& d, const float* partials, int n_tiles,
+                              const int32_t* tile_bad, const float* loss_part, float inv_count,
+                              float* loss_out, float inv_scale, float* w, float* m, float* v,
+                              int32_t* tslots, int parity, AdamHyper hp, int32_t* skipped_out,
+                              void* ffr, void* bfr, hipStream_t s) {
+    const dim3 grid(reduce_blocks(d.n_params())), block(256);
+    if (precision == NRC_BF16)
+        hipLaunchKernelGGL((k_reduce<__bf16, true>), grid, block, 0, s, partials, n_tiles, tile_bad,
+                           loss_part, inv_count, loss_out, inv_scale, (float*)nullptr, w, m, v, tslots,
+                           parity, hp, skipped_out, (__bf16*)ffr, (__bf16*)bfr, d.W, d.H);
     else
-        hipLaunchKernelGGL(k_adam<_Float16>, grid, block, 0, s, w, m, v, tslots, parity, grad, flags,
-                           n_flags, hp, skipped_out, (_Float16*)nullptr, (_Float16*)nullptr, d.W, d.H);
+        hipLaunchKernelGGL((k_reduce<_Float16, true>), grid, block, 0, s, partials, n_tiles, tile_bad,
+                           loss_part, inv_count, loss_out, inv_scale, (float*)nullptr, w, m, v, tslots,
+                           parity, hp, skipped_out,
+                           precision == NRC_FP16 ? (_Float16*)ffr : (_Float16*)nullptr,
+                           precision == NRC_FP16 ? (_Float16*)bfr : (_Float16*)nullptr, d.W, d.H);
     return hipGetLastError();
 }
 

@@ -14,7 +14,7 @@ torch = pytest.importorskip("torch")
 import synthdata as sd
 from oracle import nrc_oracle as O
 from tests import rounding_model as RM
-from tests.test_gpu_parity import BWD_TOL, MODEL_TOL, l2_err
+from tests.test_gpu_parity import BWD_TOL, FWD_TOL, MODEL_TOL, l2_err
 
 pytestmark = pytest.mark.gpu
 
@@ -42,7 +42,7 @@ def test_autograd_gradients(AG, prec, width, n):
     w = mod.weights.detach().cpu().numpy()
     st = O.CacheState(w, width=width)
     yref, hs = O.forward(st.mats(), x64)
-    assert np.all(l2_err(y.detach().cpu().numpy(), yref) <= (1e-5 if prec == "fp32" else 1e-2))
+    assert np.all(l2_err(y.detach().cpu().numpy(), yref) <= FWD_TOL[prec])
     grads, gin = O.backward(st.mats(), hs, r.astype(np.float64))
     ref_w = np.concatenate([g.reshape(-1) for g in grads])
     assert np.linalg.norm(gw - ref_w) / np.linalg.norm(ref_w) <= BWD_TOL[prec]

@@ -6,8 +6,10 @@ Per-channel relative error of a batch of outputs is normwise: "l2" is
 Tolerances (derivations in the design notes):
 * encode: FP32 output 2e-6 absolute (FP32 sinpi/cospi, acos, atan2); FP16/BF16
   output additionally one rounding of the stored value (2^-11 / 2^-8 relative).
-* forward: FP32 1e-5 (l2 and max); FP16 and BF16 1e-2 l2; max-norm 1e-2 FP16,
-  3e-2 BF16 (untrained Glorot weights: 2^-8 rounding of operands over 6 layers).
+* forward: FP32 1e-5 (l2 and max); FP16 1e-2.  BF16 on untrained Glorot
+  weights 3e-2: their outputs are near zero, so the output layer cancels
+  (|W_5| |h_5| is 2-3x |W_5 h_5|) and amplifies BF16's 2^-8 operand rounding
+  over six layers; on a trained cache BF16 meets 1e-2 (frame-schedule test).
 * training, FP32: loss 1e-5 relative, trained outputs 1e-5.  FP16/BF16: loss 1%,
   trained outputs 1e-2 l2 after the frame schedule (4 x 16384).  A single step
   is Adam's first step, which moves every weight by about lr * sign(g): any
@@ -33,7 +35,7 @@ pytestmark = pytest.mark.gpu
 
 PRECS = ["fp32", "fp16", "bf16"]
 ENC_REL = {"fp32": 0.0, "fp16": 2.0 ** -11, "bf16": 2.0 ** -8}
-FWD_TOL = {"fp32": 1e-5, "fp16": 1e-2, "bf16": 1e-2}          # l2
+FWD_TOL = {"fp32": 1e-5, "fp16": 1e-2, "bf16": 3e-2}          # l2, untrained weights
 FWD_TOL_MAX = {"fp32": 1e-5, "fp16": 1e-2, "bf16": 3e-2}
 MODEL_TOL = {"fp32": 1e-5, "fp16": 5e-3, "bf16": 2e-2}         # l2 against the rounding model
 
