@@ -129,6 +129,89 @@ def frame_bench(form: str, steps: int, warmup: int):
     return out
 
 
+def serve_bench(form: str, n_requests: int, serial: bool, load: float = 0.8, capacity_rps=None):
+    """Serving form: 8 resident caches, a Poisson stream mixing inference requests
+    (log-uniform 1k..2M queries) and 16,384-record training steps 60:40, admission
+    against a 64 GB device arena.  First the closed-loop capacity (every request
+    submitted at once), then an open-loop run at `load` x capacity with
+    Poisson arrivals; latency is submit -> completion observed by the server.
+    `serial` serves one request at a time on one stream."""
+    import torch
+    from paper_2106_12372_amd import nrc as N
+
+    dev = torch.device("cuda", 0)
+    n_caches = 8
+    cfg = N.make_config(width=WIDTH, n_hidden=N_HIDDEN, precision=form)
+    trace = sd.serve_trace(n_requests, n_caches=n_caches, seed=sd.SEED_SERVE)
+    enc_cache = N.Cache(cfg, device=dev)
+    enc_pool = N.nrc_encode(enc_cache, torch.from_numpy(sd.raw_records(2_000_000, sd.SEED_QUERIES)).to(dev))
+    train_enc, train_tgt = [], []
+    for c in range(n_caches):
+        raw = sd.raw_records(TRAIN_BATCH, 1000 + c)
+        train_enc.append(N.nrc_encode(enc_cache, torch.from_numpy(raw).to(dev)))
+        train_tgt.append(torch.from_numpy(sd.targets(raw)).to(dev))
+    rgb_out = [torch.empty((2_000_000, 3), dtype=torch.float32, device=dev) for _ in range(n_caches)]
+    torch.cuda.synchronize()
+    arena = 64 << 30
+    srv = N.Server(n_caches, cfg, arena_bytes=arena, n_streams=1 if serial else 4,
+                   max_inflight=1 if serial else 64, device=dev)
+    for c in range(n_caches):
+        srv.set_weights(c, sd.glorot_weights(WIDTH, N_HIDDEN, seed=100 + c))
+
+    def submit(r):
+        c = r["cache"]
+        if r["kind"] == "infer":
+            n = min(r["n"], 2_000_000)
+            return srv.submit_infer(c, enc_pool[:n], rgb_out[c][:n])
+        return srv.submit_train(c, train_enc[c], train_tgt[c])
+
+    def collect(tickets):
+        res = []
+        for t in tickets:
+            r = srv.poll(t)
+            while r is None:
+                r = srv.poll(t)
+            res.append(r)
+        return res
+
+    n_q = sum(min(r["n"], 2_000_000) for r in trace if r["kind"] == "infer")
+    n_s = sum(r["n"] for r in trace if r["kind"] == "train")
+    # warm-up, then closed-loop capacity
+    collect([submit(r) for r in trace[:50]])
+    t0 = time.perf_counter()
+    res = collect([submit(r) for r in trace])
+    makespan = max(x["t_done"] for x in res) - min(x["t_submit"] for x in res)
+    cap_rps = len(trace) / makespan
+    # open loop at load x capacity (of the reference server when given)
+    rate = load * (capacity_rps if capacity_rps else cap_rps)
+    gaps = np.diff([0.0] + [r["t_arrive"] for r in trace])
+    arrivals = np.cumsum(gaps / gaps.mean() / rate)
+    tickets = []
+    t0 = time.perf_counter()
+    for k, r in enumerate(trace):
+        while time.perf_counter() - t0 < arrivals[k]:
+            pass
+        tickets.append(submit(r))
+    res = collect(tickets)
+    srv.close()
+    lat = np.array([x["t_done"] - x["t_submit"] for x in res]) * 1e3
+    lat_inf = np.array([x["t_done"] - x["t_submit"] for x, r in zip(res, trace) if r["kind"] == "infer"]) * 1e3
+    lat_tr = np.array([x["t_done"] - x["t_submit"] for x, r in zip(res, trace) if r["kind"] == "train"]) * 1e3
+    span = max(x["t_done"] for x in res) - min(x["t_submit"] for x in res)
+    return {
+        "form": form, "serial": serial, "requests": len(trace), "caches": n_caches,
+        "arena_gb": arena / 2 ** 30,
+        "capacity": {"requests_per_s": cap_rps, "queries_per_s": n_q / makespan,
+                     "train_samples_per_s": n_s / makespan, "makespan_ms": makespan * 1e3},
+        "offered_requests_per_s": rate,
+        "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+        "p50_infer_ms": float(np.percentile(lat_inf, 50)), "p99_infer_ms": float(np.percentile(lat_inf, 99)),
+        "p50_train_ms": float(np.percentile(lat_tr, 50)), "p99_train_ms": float(np.percentile(lat_tr, 99)),
+        "queries_per_s": n_q / span, "train_samples_per_s": n_s / span,
+        "failed": int(sum(1 for x in res if x["status"] != 0)),
+    }
+
+
 def cpu_baseline():
     """The FP64 oracle on the host cores: one full frame (encode + inference of
     2,073,600 queries, encode of 65,536 records, four training steps)."""
@@ -164,6 +247,10 @@ def main():
     ap.add_argument("--form", default="fp32", choices=["fp32", "fp16", "bf16"])
     ap.add_argument("--no-forms", action="store_true", help="skip the other precision forms")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run a plain 256 MiB device copy (reference for HBM byte counters)")
+    ap.add_argument("--serve-requests", type=int, default=2000,
+                    help="requests in the serving trace (0 skips the serving run)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (the cache is a "
@@ -175,6 +262,13 @@ def main():
         sys.exit(2)
     torch.cuda.set_device(0)
 
+    if args.calib_copy:
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     log(f"frame bench: form {args.form}, {args.warmup} warmup + {args.steps} timed steps")
     main_res = frame_bench(args.form, args.steps, args.warmup)
     forms = {}
@@ -184,6 +278,15 @@ def main():
                 continue
             log(f"frame bench: form {f}")
             forms[f] = frame_bench(f, args.steps, args.warmup)
+    serve = None
+    if args.serve_requests > 0:
+        log(f"serving: 8 caches, fp16, {args.serve_requests} requests")
+        mix = serve_bench("fp16", args.serve_requests, serial=False)
+        log("serving: serial plain fp32, same trace and offered load")
+        ser = serve_bench("fp32", args.serve_requests, serial=True,
+                          capacity_rps=mix["capacity"]["requests_per_s"])
+        serve = {"continuous_fp16": mix, "serial_fp32": ser,
+                 "p50_ms": mix["p50_ms"], "p99_ms": mix["p99_ms"]}
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle on one frame")
@@ -213,6 +316,7 @@ def main():
         "roofline": main_res["roofline"],
         "cpu_baseline": cpu,
         "forms": forms,
+        "serve": serve,
     }
     print(json.dumps(res), flush=True)
 

@@ -84,7 +84,9 @@ __global__ __launch_bounds__(256) void k_train_fp32(const float* __restrict__ w,
     float* dbuf1 = dbuf0 + kTile * kLd;
     float* dout = dbuf1 + kTile * kLd;                    // [64][4]
 
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    // The wave index is uniform across the wave; saying so lets weight
+    // addresses that depend on it use scalar loads.
+    const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int64_t tile = blockIdx.x;
     const int64_t row = tile * kTile + lane;
     const bool valid = row < n;

@@ -96,7 +96,19 @@ __global__ __launch_bounds__(256, 2) void k_fwd_mfma(const T* __restrict__ ffr, 
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     V* sfr = reinterpret_cast<V*>(smem_raw);
     const V* gfr = reinterpret_cast<const V*>(ffr);
-    for (int i = threadIdx.x; i < n_frags * 64; i += 256) sfr[i] = gfr[i];
+    for (int base = 0; base < n_frags * 64; base += 12 * 256) {
+        V tmp[12];
+        #pragma unroll
+        for (int u = 0; u < 12; ++u) {
+            const int i = base + u * 256 + (int)threadIdx.x;
+            if (i < n_frags * 64) tmp[u] = gfr[i];
+        }
+        #pragma unroll
+        for (int u = 0; u < 12; ++u) {
+            const int i = base + u * 256 + (int)threadIdx.x;
+            if (i < n_frags * 64) sfr[i] = tmp[u];
+        }
+    }
     __syncthreads();
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -233,10 +245,25 @@ __global__ __launch_bounds__(256) void k_train_mfma(const T* __restrict__ ffr,
     const V* gf;
     const V* gb;
     if (STAGE) {
+        // Forward and backward fragments are contiguous in LDS (sbw follows
+        // sfw); copy them in rounds of 12 loads per thread, all in flight
+        // before the first LDS store.
+        const int nf = geo.n_fwd_frags() * 64, total = nf + geo.n_bwd_frags() * 64;
         const V* src_f = reinterpret_cast<const V*>(ffr);
         const V* src_b = reinterpret_cast<const V*>(bfr);
-        for (int i = tid; i < geo.n_fwd_frags() * 64; i += 256) sfw[i] = src_f[i];
-        for (int i = tid; i < geo.n_bwd_frags() * 64; i += 256) sbw[i] = src_b[i];
+        for (int base = 0; base < total; base += 12 * 256) {
+            V tmp[12];
+            #pragma unroll
+            for (int u = 0; u < 12; ++u) {
+                const int i = base + u * 256 + tid;
+                if (i < total) tmp[u] = i < nf ? src_f[i] : src_b[i - nf];
+            }
+            #pragma unroll
+            for (int u = 0; u < 12; ++u) {
+                const int i = base + u * 256 + tid;
+                if (i < total) sfw[i] = tmp[u];
+            }
+        }
         gf = sfw + lane;
         gb = sbw + lane;
     } else {
