@@ -1,8 +1,9 @@
 """Benchmark of the radiance-cache hot path on one MI355X.
 
 A step is one 1920x1080 frame of the cache: encode 2,073,600 synthetic query
-records and run inference on them, encode 65,536 training records, and take
-four Adam steps of 16,384 records each (Sec. 3.4-3.5 of the paper).  Inputs
+records and run inference on them (one fused kernel), encode 65,536 training
+records, and take four Adam steps of 16,384 records each (Sec. 3.4-3.5 of the
+paper).  Inputs
 are resident in HBM before the timed region.  The default form is plain FP32
 (vector ALUs); the FP16 and BF16 matrix-core forms run the same frame and are
 reported under "forms".  Prints one JSON line.
@@ -62,54 +63,67 @@ def frame_bench(form: str, steps: int, warmup: int):
     y_b = [y[s * TRAIN_BATCH:(s + 1) * TRAIN_BATCH] for s in range(N_TRAIN_BATCHES)]
     e_b = [enc_r[s * TRAIN_BATCH:(s + 1) * TRAIN_BATCH] for s in range(N_TRAIN_BATCHES)]
     stream = torch.cuda.current_stream(dev)
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
 
     def step(record: bool):
         if record:
             ev[0].record(stream)
-        N.nrc_encode(cache, raw_q, enc=enc_q)
+        N.nrc_forward_raw(cache, raw_q, rgb=rgb)           # encode + inference, one kernel
         if record:
             ev[1].record(stream)
-        N.nrc_forward(cache, enc_q, rgb=rgb)
-        if record:
-            ev[2].record(stream)
         N.nrc_encode(cache, raw_r, enc=enc_r)
         if record:
-            ev[3].record(stream)
+            ev[2].record(stream)
         for s in range(N_TRAIN_BATCHES):
             N.nrc_train_step(cache, e_b[s], y_b[s], loss=loss[s:s + 1], skipped=skipped[s:s + 1],
                              scratch=scratch)
         if record:
-            ev[4].record(stream)
+            ev[3].record(stream)
 
     for _ in range(warmup):
         step(False)
     torch.cuda.synchronize()
-    comp = np.zeros(4)
+    comp = np.zeros(3)
     t0 = time.perf_counter()
     for _ in range(steps):
         step(True)
-        ev[4].synchronize()
-        comp += [ev[i].elapsed_time(ev[i + 1]) for i in range(4)]
+        ev[3].synchronize()
+        comp += [ev[i].elapsed_time(ev[i + 1]) for i in range(3)]
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     comp /= steps
     ms = elapsed * 1e3 / steps
-    t_fwd_s = comp[1] * 1e-3
-    achieved = N_QUERIES * FLOP_PER_QUERY / t_fwd_s / 1e12
+
+    # The same queries through the two-kernel path (encode to HBM, then inference).
+    ue = np.zeros(2)
+    for it in range(steps + 2):
+        ev[0].record(stream)
+        N.nrc_encode(cache, raw_q, enc=enc_q)
+        ev[1].record(stream)
+        N.nrc_forward(cache, enc_q, rgb=rgb)
+        ev[2].record(stream)
+        ev[2].synchronize()
+        if it >= 2:
+            ue += [ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2])]
+    ue /= steps
+
+    t_q = comp[0] * 1e-3
+    achieved = N_QUERIES * FLOP_PER_QUERY / t_q / 1e12
     enc_bytes = 2 if form != "fp32" else 4
+    t_fwd = ue[1] * 1e-3
     out = {
         "form": form,
         "ms_per_step": ms,
         "queries_per_s": N_QUERIES / (ms * 1e-3),
         "train_samples_per_s": N_TRAIN_BATCHES * TRAIN_BATCH / (ms * 1e-3),
-        "components_ms": {"encode_queries": comp[0], "forward": comp[1], "encode_records": comp[2],
-                          "train_4_steps": comp[3]},
-        "query_pass_queries_per_s": N_QUERIES / ((comp[0] + comp[1]) * 1e-3),
-        "mlp_only_queries_per_s": N_QUERIES / t_fwd_s,
-        "train_only_samples_per_s": N_TRAIN_BATCHES * TRAIN_BATCH / (comp[3] * 1e-3),
+        "components_ms": {"query_pass_fused": comp[0], "encode_records": comp[1],
+                          "train_4_steps": comp[2]},
+        "unfused_ms": {"encode_queries": ue[0], "forward": ue[1]},
+        "query_pass_queries_per_s": N_QUERIES / t_q,
+        "mlp_only_queries_per_s": N_QUERIES / t_fwd,
+        "train_only_samples_per_s": N_TRAIN_BATCHES * TRAIN_BATCH / (comp[2] * 1e-3),
         "roofline": {
-            "kernel": "k_fwd_mfma" if form != "fp32" else "k_fwd_fp32",
+            "kernel": "k_fwd_raw_mfma" if form != "fp32" else "k_fwd_raw_fp32",
             "bound": BOUND[form],
             "achieved": achieved,
             "peak": PEAK_TFLOPS[form],
@@ -118,8 +132,18 @@ def frame_bench(form: str, steps: int, warmup: int):
             "traffic": None,
             "flop_per_query": FLOP_PER_QUERY,
             "queries_per_launch": N_QUERIES,
-            "avg_launch_ms": comp[1],
-            "hbm_gbs_algorithmic": N_QUERIES * (64 * enc_bytes + 12) / t_fwd_s / 1e9,
+            "avg_launch_ms": comp[0],
+            "hbm_gbs_algorithmic": N_QUERIES * (56 + 12) / t_q / 1e9,
+        },
+        "mlp_only_roofline": {
+            "kernel": "k_fwd_mfma" if form != "fp32" else "k_fwd_fp32",
+            "bound": BOUND[form],
+            "achieved": N_QUERIES * FLOP_PER_QUERY / t_fwd / 1e12,
+            "peak": PEAK_TFLOPS[form],
+            "unit": "TFLOP/s",
+            "frac": N_QUERIES * FLOP_PER_QUERY / t_fwd / 1e12 / PEAK_TFLOPS[form],
+            "avg_launch_ms": ue[1],
+            "hbm_gbs_algorithmic": N_QUERIES * (64 * enc_bytes + 12) / t_fwd / 1e9,
         },
         "final_loss": float(loss[-1].item()),
         "skipped_steps": int(skipped.sum().item()),
@@ -310,6 +334,7 @@ def main():
                    "train_batches": N_TRAIN_BATCHES, "train_batch": TRAIN_BATCH, "form": args.form},
         "train_samples_per_s": main_res["train_samples_per_s"],
         "components_ms": main_res["components_ms"],
+        "unfused_ms": main_res["unfused_ms"],
         "mlp_only_queries_per_s": main_res["mlp_only_queries_per_s"],
         "train_only_samples_per_s": main_res["train_only_samples_per_s"],
         "frame_tflops": main_res["frame_tflops"],

@@ -66,6 +66,12 @@ extern "C" {
  * Adam (Sec. 5 Optimizer): lr, beta1, beta2, adam_eps; loss_eps is the eps of
  * Eq. 5; loss_scale multiplies the loss gradient before the reduced-precision
  * backward pass and is divided out before Adam (use 1 for FP32).
+ * ema_alpha > 0 keeps the exponential moving average of the weights of Eq. 2
+ * (Sec. 3.4), bias-corrected: W_bar_t = E_t / (1 - alpha^t) with
+ * E_t = alpha E_{t-1} + (1 - alpha) W_t, advanced by every applied Adam step;
+ * the query entry points (nrc_forward, nrc_forward_raw) then use W_bar, as the
+ * paper does for rendering, while training and nrc_backward use W.  Before the
+ * first step W_bar equals the weights that were set.
  */
 typedef struct nrc_config {
     int32_t width;
@@ -79,13 +85,14 @@ typedef struct nrc_config {
     float adam_eps;
     float loss_eps;
     float loss_scale;
-    uint64_t seed; /* reserved; weights are always set explicitly */
+    float ema_alpha; /* EMA of the weights (Eq. 2); 0 disables, the paper uses 0.99 */
+    uint64_t seed;   /* reserved; weights are always set explicitly */
 } nrc_config;
 
 typedef struct nrc_cache nrc_cache;
 
 /* Fills *cfg with the defaults: 64, 5, 3, FP16, CONFIG, 1e-2, 0.9, 0.99, 1e-8,
- * 0.01, 128, 0.  Returns NRC_EINVAL on NULL. */
+ * 0.01, 128, 0 (no EMA), 0.  Returns NRC_EINVAL on NULL. */
 int nrc_config_default(nrc_config* cfg);
 
 /* Message describing the last failure on the calling thread ("" if none).
@@ -144,6 +151,16 @@ int nrc_set_state(nrc_cache* cache, const float* host_w, const float* host_m,
                   const float* host_v, int64_t n, int64_t t, void* stream);
 
 /*
+ * EMA weight set (caches with ema_alpha > 0): W_bar (the weights queries use)
+ * and the running sum E, each n floats on the host, for inspection and
+ * checkpoint/resume.  nrc_set_ema must follow nrc_set_state (which resets the
+ * EMA to W_bar = W, E = 0).  Synchronises `stream`.
+ */
+int nrc_get_ema(const nrc_cache* cache, float* host_w_bar, float* host_e, int64_t n, void* stream);
+int nrc_set_ema(nrc_cache* cache, const float* host_w_bar, const float* host_e, int64_t n,
+                void* stream);
+
+/*
  * Input encoding (Sec. 3.6, Table "parameters"): raw device records
  * [n][14] (NRC_RAW14) or [n][16] (NRC_RAW16) FP32 -> enc [n][64] at the cache
  * precision (FP32 for NRC_FP32, else FP16/BF16), using the cache's preset.
@@ -159,6 +176,16 @@ int nrc_encode(const nrc_cache* cache, const float* raw, int raw_layout, int64_t
  * (FP32, device) = network(enc[n][64]) with the current weights.  Any n >= 0.
  */
 int nrc_forward(nrc_cache* cache, const void* enc, int64_t n, float* rgb, void* stream);
+
+/*
+ * Inference straight from raw records (Sec. 3.6 encodings + Sec. 4 network in
+ * one kernel): rgb[n][3] = network(encode(raw[n][14 or 16])), the encoded
+ * features never touching device memory.  Same result as nrc_encode followed by
+ * nrc_forward (the features are rounded to the cache precision in both).
+ * Width 64 only.  Any n >= 0.
+ */
+int nrc_forward_raw(nrc_cache* cache, const float* raw, int raw_layout, int64_t n, float* rgb,
+                    void* stream);
 
 /*
  * One optimisation step (Sec. 3.4-3.5, Eq. 5, Sec. 5): forward over the batch

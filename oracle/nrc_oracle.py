@@ -37,6 +37,11 @@ notes):
   finite is skipped (t unchanged).
 * Loss scaling is a rounding device of reduced-precision arithmetic; in FP64
   it cancels exactly, so the oracle has no scale.
+* EMA of the weights (Eq. 2): as printed its two coefficients do not sum to
+  one; it is read as the bias-corrected average
+  W_bar_t = [(1 - a) W_t + a eta_{t-1} W_bar_{t-1}] / eta_t, eta_t = 1 - a^t,
+  i.e. W_bar_t = E_t / eta_t with E_t = a E_{t-1} + (1 - a) W_t, E_0 = 0.  It
+  advances only on steps that update the weights and never feeds back.
 """
 from __future__ import annotations
 
@@ -224,6 +229,8 @@ class CacheState:
     t: int = 0
     adam: AdamConfig = field(default_factory=AdamConfig)
     loss_eps: float = LOSS_EPS
+    ema_alpha: float = 0.0      # Sec. 3.4 uses 0.99; 0 disables the EMA set
+    w_bar: np.ndarray = None
 
     def __post_init__(self):
         self.w = np.asarray(self.w, dtype=np.float64).copy()
@@ -244,6 +251,13 @@ def predict(state: CacheState, enc: np.ndarray) -> np.ndarray:
     return forward(state.mats(), enc)[0]
 
 
+def ema_step(w_bar_prev: np.ndarray, w: np.ndarray, t: int, alpha: float) -> np.ndarray:
+    """One step of Eq. 2 (bias-corrected reading): W_bar_t from W_bar_{t-1} and W_t."""
+    eta_t = 1.0 - alpha ** t
+    eta_prev = 1.0 - alpha ** (t - 1)
+    return ((1.0 - alpha) * w + alpha * eta_prev * w_bar_prev) / eta_t
+
+
 def gradient(state: CacheState, enc: np.ndarray, y: np.ndarray):
     """Loss and flat weight gradient of one batch (Eq. 5 through the network)."""
     mats = state.mats()
@@ -254,12 +268,22 @@ def gradient(state: CacheState, enc: np.ndarray, y: np.ndarray):
 
 
 def train_step(state: CacheState, enc: np.ndarray, y: np.ndarray):
-    """One optimisation step on one batch; returns (loss, skipped)."""
+    """One optimisation step on one batch; returns (loss, skipped).  With
+    state.ema_alpha > 0 the EMA weight set (Eq. 2) follows the new weights."""
     loss, g = gradient(state, enc, y)
     if not np.all(np.isfinite(g)):
         return loss, True
     state.w, state.m, state.v, state.t = adam(state.w, state.m, state.v, state.t, g, state.adam)
+    if state.ema_alpha > 0.0:
+        prev = state.w_bar if state.w_bar is not None else np.zeros_like(state.w)
+        state.w_bar = ema_step(prev, state.w, state.t, state.ema_alpha)
     return loss, False
+
+
+def predict_ema(state: CacheState, enc: np.ndarray) -> np.ndarray:
+    """Cache query with the EMA weights (Sec. 3.4): the set used for rendering."""
+    w = state.w_bar if state.w_bar is not None else state.w
+    return forward(CacheState(w, width=state.width, n_hidden=state.n_hidden).mats(), enc)[0]
 
 
 def frame(state: CacheState, query_enc: np.ndarray, record_enc: np.ndarray,

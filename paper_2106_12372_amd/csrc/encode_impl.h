@@ -1,0 +1,116 @@
+// Device-side input encoding of one path vertex (Sec. 3.6 "Input Encoding",
+// Table "parameters", Sec. 5 "High-performance primitives for encoding"),
+// shared by the stand-alone encoding kernel and the fused raw-record
+// inference kernels.
+#pragma once
+
+#include "nrc_internal.h"
+
+namespace nrc {
+
+constexpr float kInvPi = 0.318309886183790671538f;
+constexpr float kPi = 3.14159265358979323846f;
+
+// x mod 2 in [0, 2), exact: x/2, floor and 2*floor are exact, and x - 2k has
+// fewer significant bits than x.
+__device__ inline float mod2(float x) { return x - 2.0f * floorf(x * 0.5f); }
+
+// Antiderivative of the quartic kernel 15/16 (1 - u^2)^2 on [-1, 1], clamped
+// to 0 below and 1 above.
+__device__ inline float quartic_cdf(float u) {
+    if (u <= -1.0f) return 0.0f;
+    if (u >= 1.0f) return 1.0f;
+    const float u2 = u * u;
+    return 0.5f + u * (0.9375f + u2 * (-0.625f + 0.1875f * u2));
+}
+
+// One-blob encoding with 4 bins on [0,1]: mass of a quartic blob of half-width
+// one bin centred at 4s over each bin; the edge bins also take the tails.
+__device__ inline void one_blob4(float s, float* e) {
+    const float c = 4.0f * s;
+    const float f1 = quartic_cdf(1.0f - c);
+    const float f2 = quartic_cdf(2.0f - c);
+    const float f3 = quartic_cdf(3.0f - c);
+    e[0] = f1;
+    e[1] = f2 - f1;
+    e[2] = f3 - f2;
+    e[3] = 1.0f - f3;
+}
+
+// Unit vector -> spherical coordinates normalised to [0,1]^2.
+__device__ inline void sph(float x, float y, float z, float& u, float& w) {
+    u = acosf(fminf(fmaxf(z, -1.0f), 1.0f)) * kInvPi;
+    w = (atan2f(y, x) + kPi) * (0.5f * kInvPi);
+}
+
+// sin and cos of pi * 2^d * p for d = 0 .. NOCT-1.  Octaves 0, 3, 6, 9 are
+// evaluated directly (sincospi of the exactly reduced phase); the two octaves
+// after each come from the double-angle identities sin 2a = 2 sin a cos a,
+// cos 2a = (cos a - sin a)(cos a + sin a), which at most quadruple the
+// absolute rounding error (a few 1e-7).
+template <int NOCT>
+__device__ inline void octaves(float p, float* sn, float* cs) {
+    #pragma unroll
+    for (int d = 0; d < NOCT; ++d) {
+        if (d % 3 == 0) {
+            sincospif(mod2(p * (float)(1 << d)), &sn[d], &cs[d]);
+        } else {
+            const float s0 = sn[d - 1], c0 = cs[d - 1];
+            sn[d] = 2.0f * s0 * c0;
+            cs[d] = (c0 - s0) * (c0 + s0);
+        }
+    }
+}
+
+// The 64 encoded features of one raw record (14 or 16 floats).
+//   config preset: per position coordinate sin, cos of 6 octaves (36), one-blob
+//   of the direction and normal angles (16), roughness, diffuse and specular
+//   albedo (7), five zeros.
+//   paper preset: 12 sines per coordinate (36), one-blob of the angles (16),
+//   one-blob of 1 - exp(-roughness) (4), albedos (6), two ones.
+template <int PRESET, int LAYOUT>
+__device__ inline void encode_record(const float* x, float* o) {
+    #pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        if (PRESET == NRC_PRESET_PAPER) {
+            float sn[12], cs[12];
+            octaves<12>(x[c], sn, cs);
+            #pragma unroll
+            for (int d = 0; d < 12; ++d) o[12 * c + d] = sn[d];
+        } else {
+            float sn[6], cs[6];
+            octaves<6>(x[c], sn, cs);
+            #pragma unroll
+            for (int d = 0; d < 6; ++d) {
+                o[12 * c + 2 * d] = sn[d];
+                o[12 * c + 2 * d + 1] = cs[d];
+            }
+        }
+    }
+    float ang[4];
+    const float* rest;
+    if (LAYOUT == NRC_RAW14) {
+        ang[0] = x[3]; ang[1] = x[4]; ang[2] = x[5]; ang[3] = x[6];
+        rest = x + 7;
+    } else {
+        sph(x[3], x[4], x[5], ang[0], ang[1]);
+        sph(x[6], x[7], x[8], ang[2], ang[3]);
+        rest = x + 9;
+    }
+    #pragma unroll
+    for (int a = 0; a < 4; ++a) one_blob4(ang[a], o + 36 + 4 * a);
+    if (PRESET == NRC_PRESET_PAPER) {
+        one_blob4(1.0f - expf(-rest[0]), o + 52);
+        #pragma unroll
+        for (int j = 0; j < 6; ++j) o[56 + j] = rest[1 + j];
+        o[62] = 1.0f;
+        o[63] = 1.0f;
+    } else {
+        #pragma unroll
+        for (int j = 0; j < 7; ++j) o[52 + j] = rest[j];
+        #pragma unroll
+        for (int j = 59; j < 64; ++j) o[j] = 0.0f;
+    }
+}
+
+}  // namespace nrc

@@ -12,6 +12,7 @@
 // dW_l for all 64 input features (lane = input feature), summing over the
 // tile's samples.  Each tile writes its dW partial; a separate fixed-order
 // reduction sums the partials (no atomics, so results are reproducible).
+#include "encode_impl.h"
 #include "nrc_internal.h"
 
 namespace nrc {
@@ -19,20 +20,12 @@ namespace {
 
 constexpr int kW = 64;      // the FP32 form supports width 64
 constexpr int kLd = 68;     // padded LDS row stride (floats)
-constexpr int kTile = kTrainTile;
+constexpr int kTile = 64;       // training records per workgroup
 
-__global__ __launch_bounds__(256) void k_fwd_fp32(const float* __restrict__ w,
-                                                  const float* __restrict__ enc, int64_t n,
-                                                  float* __restrict__ rgb, int n_hidden) {
-    const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (s >= n) return;
-    float h[kW];
-    const float4* row = reinterpret_cast<const float4*>(enc + s * kEncWidth);
-    #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-        const float4 v = row[q];
-        h[4 * q] = v.x; h[4 * q + 1] = v.y; h[4 * q + 2] = v.z; h[4 * q + 3] = v.w;
-    }
+// The network on one record whose 64 input features are in h (VGPRs); every
+// weight is a wave-uniform operand fetched with scalar loads.
+__device__ inline void mlp_fp32(float (&h)[kW], const float* __restrict__ w, int n_hidden,
+                                float (&y)[kNOut]) {
     const float* wl = w;
     for (int l = 0; l < n_hidden; ++l) {
         float z[kW];
@@ -47,7 +40,6 @@ __global__ __launch_bounds__(256) void k_fwd_fp32(const float* __restrict__ w,
         for (int o = 0; o < kW; ++o) h[o] = fmaxf(z[o], 0.0f);
         wl += kW * kW;
     }
-    float y[kNOut];
     #pragma unroll
     for (int o = 0; o < kNOut; ++o) {
         float acc = 0.0f;
@@ -55,6 +47,47 @@ __global__ __launch_bounds__(256) void k_fwd_fp32(const float* __restrict__ w,
         for (int k = 0; k < kW; ++k) acc = fmaf(wl[o * kW + k], h[k], acc);
         y[o] = acc;
     }
+}
+
+__global__ __launch_bounds__(256) void k_fwd_fp32(const float* __restrict__ w,
+                                                  const float* __restrict__ enc, int64_t n,
+                                                  float* __restrict__ rgb, int n_hidden) {
+    const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (s >= n) return;
+    float h[kW];
+    const float4* row = reinterpret_cast<const float4*>(enc + s * kEncWidth);
+    #pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const float4 v = row[q];
+        h[4 * q] = v.x; h[4 * q + 1] = v.y; h[4 * q + 2] = v.z; h[4 * q + 3] = v.w;
+    }
+    float y[kNOut];
+    mlp_fp32(h, w, n_hidden, y);
+    rgb[s * 3 + 0] = y[0];
+    rgb[s * 3 + 1] = y[1];
+    rgb[s * 3 + 2] = y[2];
+}
+
+// Inference from raw records with the encoding fused in: each lane encodes its
+// record straight into the VGPRs of the first layer's input.
+template <int PRESET, int LAYOUT>
+__global__ __launch_bounds__(256) void k_fwd_raw_fp32(const float* __restrict__ w,
+                                                      const float* __restrict__ raw, int64_t n,
+                                                      float* __restrict__ rgb, int n_hidden) {
+    constexpr int RW = LAYOUT == NRC_RAW14 ? 14 : 16;
+    const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (s >= n) return;
+    float x[RW];
+    const float2* src = reinterpret_cast<const float2*>(raw + s * RW);
+    #pragma unroll
+    for (int q = 0; q < RW / 2; ++q) {
+        const float2 v = src[q];
+        x[2 * q] = v.x; x[2 * q + 1] = v.y;
+    }
+    float h[kW];
+    encode_record<PRESET, LAYOUT>(x, h);
+    float y[kNOut];
+    mlp_fp32(h, w, n_hidden, y);
     rgb[s * 3 + 0] = y[0];
     rgb[s * 3 + 1] = y[1];
     rgb[s * 3 + 2] = y[2];
@@ -266,6 +299,25 @@ hipError_t launch_fwd_fp32(const Geo& d, const float* w, const float* enc, int64
     if (blocks == 0) return hipSuccess;
     hipLaunchKernelGGL(k_fwd_fp32, dim3((unsigned)blocks), dim3(256), 0, s, w, enc, n, rgb,
                        d.H);
+    return hipGetLastError();
+}
+
+hipError_t launch_fwd_raw_fp32(const Geo& d, int preset, int layout, const float* w, const float* raw,
+                               int64_t n, float* rgb, hipStream_t s) {
+    const int64_t blocks = (n + 255) / 256;
+    if (blocks == 0) return hipSuccess;
+    const dim3 grid((unsigned)blocks), block(256);
+    if (preset == NRC_PRESET_PAPER) {
+        if (layout == NRC_RAW14)
+            hipLaunchKernelGGL((k_fwd_raw_fp32<NRC_PRESET_PAPER, NRC_RAW14>), grid, block, 0, s, w, raw, n, rgb, d.H);
+        else
+            hipLaunchKernelGGL((k_fwd_raw_fp32<NRC_PRESET_PAPER, NRC_RAW16>), grid, block, 0, s, w, raw, n, rgb, d.H);
+    } else {
+        if (layout == NRC_RAW14)
+            hipLaunchKernelGGL((k_fwd_raw_fp32<NRC_PRESET_CONFIG, NRC_RAW14>), grid, block, 0, s, w, raw, n, rgb, d.H);
+        else
+            hipLaunchKernelGGL((k_fwd_raw_fp32<NRC_PRESET_CONFIG, NRC_RAW16>), grid, block, 0, s, w, raw, n, rgb, d.H);
+    }
     return hipGetLastError();
 }
 

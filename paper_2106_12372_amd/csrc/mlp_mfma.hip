@@ -22,6 +22,7 @@
 // a contraction over the tile's 64 records, reads delta and h back from LDS
 // with the record index contiguous.  Each tile writes its weight-gradient
 // partial sums; a fixed-order reduction follows (no atomics).
+#include "encode_impl.h"
 #include "nrc_internal.h"
 
 namespace nrc {
@@ -87,37 +88,107 @@ __device__ inline float wave_sum(float v) {
 // ---------------------------------------------------------------------------
 // Inference
 // ---------------------------------------------------------------------------
+// Copy n_frags operand fragments (1 KB each) from global memory to LDS; every
+// thread issues up to 12 loads before its first store.
+template <typename V>
+__device__ inline void stage_frags(V* dst, const V* src, int n_frags) {
+    const int total = n_frags * 64;
+    for (int base = 0; base < total; base += 12 * 256) {
+        V tmp[12];
+        #pragma unroll
+        for (int u = 0; u < 12; ++u) {
+            const int i = base + u * 256 + (int)threadIdx.x;
+            if (i < total) tmp[u] = src[i];
+        }
+        #pragma unroll
+        for (int u = 0; u < 12; ++u) {
+            const int i = base + u * 256 + (int)threadIdx.x;
+            if (i < total) dst[i] = tmp[u];
+        }
+    }
+}
+
+// The whole network on 16*COLS records held as B operands (b[col][0..1] =
+// encoded features, natural order); returns the output accumulators (lanes
+// 0..15 hold rows 0..3, i.e. the RGB values and a zero row).  Each layer's
+// first K chunk starts from a zero accumulator (an inline constant operand)
+// and ReLU is applied to the packed 16-bit result.
+template <typename T, int W, int COLS>
+__device__ inline void mlp_tile(const typename Vec8<T>::type* sfr, typename Vec8<T>::type (&b)[COLS][W / 32],
+                                int n_hidden, int lane, f32x4 (&o)[COLS]) {
+    using V = typename Vec8<T>::type;
+    constexpr int MB = W / 16, KC = W / 32;
+    const Geo geo(W, n_hidden);
+    for (int l = 0; l < n_hidden; ++l) {
+        const int kc = l == 0 ? 2 : KC;    // the input layer has K = 64
+        const V* fl = sfr + geo.fwd_base(l) * 64 + lane;
+        f32x4 acc[COLS][MB];
+        #pragma unroll
+        for (int mb = 0; mb < MB; ++mb) {
+            const V a = fl[(mb * kc) * 64];
+            #pragma unroll
+            for (int col = 0; col < COLS; ++col) acc[col][mb] = mfma(a, b[col][0], f32x4{0.f, 0.f, 0.f, 0.f});
+        }
+        #pragma unroll
+        for (int c = 1; c < KC; ++c) {
+            if (c >= kc) break;
+            #pragma unroll
+            for (int mb = 0; mb < MB; ++mb) {
+                const V a = fl[(mb * kc + c) * 64];
+                #pragma unroll
+                for (int col = 0; col < COLS; ++col) acc[col][mb] = mfma(a, b[col][c], acc[col][mb]);
+            }
+        }
+        #pragma unroll
+        for (int col = 0; col < COLS; ++col)
+            #pragma unroll
+            for (int c = 0; c < KC; ++c)
+                b[col][c] = relu_packed(pack8<T, V>(acc[col][2 * c], acc[col][2 * c + 1]));
+    }
+    const V* fo = sfr + geo.fwd_base(n_hidden) * 64 + lane;
+    #pragma unroll
+    for (int col = 0; col < COLS; ++col) o[col] = mfma(fo[0], b[col][0], f32x4{0.f, 0.f, 0.f, 0.f});
+    #pragma unroll
+    for (int c = 1; c < KC; ++c)
+        #pragma unroll
+        for (int col = 0; col < COLS; ++col) o[col] = mfma(fo[c * 64], b[col][c], o[col]);
+}
+
+template <int COLS>
+__device__ inline void store_rgb(const f32x4 (&o)[COLS], int64_t base, int64_t n, int g, int ln,
+                                 float* __restrict__ rgb) {
+    if (g != 0) return;
+    #pragma unroll
+    for (int col = 0; col < COLS; ++col) {
+        const int64_t row = base + 16 * col + ln;
+        if (row < n) {
+            float* dst = rgb + row * 3;
+            dst[0] = o[col][0];
+            dst[1] = o[col][1];
+            dst[2] = o[col][2];
+        }
+    }
+}
+
+// Inference from encoded rows.  A persistent workgroup stages the forward
+// weight fragments in LDS once; each wave streams tiles of 16*COLS records and
+// loads the next tile's rows while the current one computes.
 template <typename T, int W, int COLS>
 __global__ __launch_bounds__(256, 2) void k_fwd_mfma(const T* __restrict__ ffr, int n_frags,
                                                      const T* __restrict__ enc, int64_t n,
                                                      float* __restrict__ rgb, int n_hidden) {
     using V = typename Vec8<T>::type;
-    constexpr int MB = W / 16, KC = W / 32;
+    constexpr int KC = W / 32;
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     V* sfr = reinterpret_cast<V*>(smem_raw);
-    const V* gfr = reinterpret_cast<const V*>(ffr);
-    for (int base = 0; base < n_frags * 64; base += 12 * 256) {
-        V tmp[12];
-        #pragma unroll
-        for (int u = 0; u < 12; ++u) {
-            const int i = base + u * 256 + (int)threadIdx.x;
-            if (i < n_frags * 64) tmp[u] = gfr[i];
-        }
-        #pragma unroll
-        for (int u = 0; u < 12; ++u) {
-            const int i = base + u * 256 + (int)threadIdx.x;
-            if (i < n_frags * 64) sfr[i] = tmp[u];
-        }
-    }
+    stage_frags(sfr, reinterpret_cast<const V*>(ffr), n_frags);
     __syncthreads();
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int g = lane >> 4, ln = lane & 15;
-    const Geo geo(W, n_hidden);
     const int64_t n_tiles = (n + 16 * COLS - 1) / (16 * COLS);
     const int64_t tstride = (int64_t)gridDim.x * 4;
 
-    // The next tile's encoded rows are loaded while the current tile computes.
     // Rows past the end of the batch read the last row instead (their outputs
     // are never stored), so the loads need neither branches nor zero fills.
     V nxt[COLS][2];
@@ -134,7 +205,6 @@ __global__ __launch_bounds__(256, 2) void k_fwd_mfma(const T* __restrict__ ffr, 
     int64_t tile = (int64_t)blockIdx.x * 4 + wave;
     if (tile < n_tiles) load_tile(tile);
     for (; tile < n_tiles; tile += tstride) {
-        const int64_t base = tile * 16 * COLS;
         V b[COLS][KC];
         #pragma unroll
         for (int col = 0; col < COLS; ++col) {
@@ -142,72 +212,106 @@ __global__ __launch_bounds__(256, 2) void k_fwd_mfma(const T* __restrict__ ffr, 
             b[col][1] = nxt[col][1];
         }
         if (tile + tstride < n_tiles) load_tile(tile + tstride);
-        // Layer l: the first K chunk starts from a zero accumulator (an inline
-        // constant operand), ReLU is applied to the packed 16-bit result.
-        for (int l = 0; l < n_hidden; ++l) {
-            const int kc = l == 0 ? 2 : KC;    // the input layer has K = 64
-            const V* fl = sfr + geo.fwd_base(l) * 64 + lane;
-            f32x4 acc[COLS][MB];
-            #pragma unroll
-            for (int mb = 0; mb < MB; ++mb) {
-                const V a = fl[(mb * kc) * 64];
-                #pragma unroll
-                for (int col = 0; col < COLS; ++col) acc[col][mb] = mfma(a, b[col][0], f32x4{0.f, 0.f, 0.f, 0.f});
-            }
-            #pragma unroll
-            for (int c = 1; c < KC; ++c) {
-                if (c >= kc) break;
-                #pragma unroll
-                for (int mb = 0; mb < MB; ++mb) {
-                    const V a = fl[(mb * kc + c) * 64];
-                    #pragma unroll
-                    for (int col = 0; col < COLS; ++col) acc[col][mb] = mfma(a, b[col][c], acc[col][mb]);
-                }
-            }
-            #pragma unroll
-            for (int col = 0; col < COLS; ++col)
-                #pragma unroll
-                for (int c = 0; c < KC; ++c)
-                    b[col][c] = relu_packed(pack8<T, V>(acc[col][2 * c], acc[col][2 * c + 1]));
-        }
-        // Output layer: 3 rows of a 16-row block; lanes 0..15 receive rows 0..3.
-        const V* fo = sfr + geo.fwd_base(n_hidden) * 64 + lane;
         f32x4 o[COLS];
-        #pragma unroll
-        for (int col = 0; col < COLS; ++col) o[col] = mfma(fo[0], b[col][0], f32x4{0.f, 0.f, 0.f, 0.f});
-        #pragma unroll
-        for (int c = 1; c < KC; ++c)
+        mlp_tile<T, W, COLS>(sfr, b, n_hidden, lane, o);
+        store_rgb<COLS>(o, tile * 16 * COLS, n, g, ln, rgb);
+    }
+}
+
+// Inference from raw records with the encoding fused in (Sec. 3.6 encodings,
+// Sec. 4 network).  Each wave owns a 64-record tile: lane r encodes record r
+// (the next tile's raw floats are loaded while the current tile computes),
+// writes its 64 features to the wave's own LDS rows, and the wave reads them
+// back as B operands.  HBM traffic per query: the raw record in, RGB out.
+template <typename T, int W, int PRESET, int LAYOUT>
+__global__ __launch_bounds__(256, 2) void k_fwd_raw_mfma(const T* __restrict__ ffr, int n_frags,
+                                                         const float* __restrict__ raw, int64_t n,
+                                                         float* __restrict__ rgb, int n_hidden) {
+    using V = typename Vec8<T>::type;
+    constexpr int COLS = 4, KC = W / 32;
+    constexpr int RW = LAYOUT == NRC_RAW14 ? 14 : 16;
+    constexpr int ROW = 72;                     // LDS row stride of an encoded record, elements
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+    V* sfr = reinterpret_cast<V*>(smem_raw);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane >> 4, ln = lane & 15;
+    T* senc = reinterpret_cast<T*>(smem_raw + n_frags * 1024) + wave * 64 * ROW;
+    stage_frags(sfr, reinterpret_cast<const V*>(ffr), n_frags);
+    __syncthreads();
+
+    const int64_t n_tiles = (n + 63) / 64;
+    const int64_t tstride = (int64_t)gridDim.x * 4;
+    float x[RW];
+    auto load_raw = [&](int64_t t) {
+        int64_t row = t * 64 + lane;
+        row = row < n ? row : n - 1;
+        const float* src = raw + row * RW;
+        if (RW == 16) {
             #pragma unroll
-            for (int col = 0; col < COLS; ++col) o[col] = mfma(fo[c * 64], b[col][c], o[col]);
-        if (g == 0) {
+            for (int q = 0; q < 4; ++q) {
+                const float4 v = reinterpret_cast<const float4*>(src)[q];
+                x[4 * q] = v.x; x[4 * q + 1] = v.y; x[4 * q + 2] = v.z; x[4 * q + 3] = v.w;
+            }
+        } else {
             #pragma unroll
-            for (int col = 0; col < COLS; ++col) {
-                const int64_t row = base + 16 * col + ln;
-                if (row < n) {
-                    float* dst = rgb + row * 3;
-                    dst[0] = o[col][0];
-                    dst[1] = o[col][1];
-                    dst[2] = o[col][2];
-                }
+            for (int q = 0; q < RW / 2; ++q) {
+                const float2 v = reinterpret_cast<const float2*>(src)[q];
+                x[2 * q] = v.x; x[2 * q + 1] = v.y;
             }
         }
+    };
+    int64_t tile = (int64_t)blockIdx.x * 4 + wave;
+    if (tile < n_tiles) load_raw(tile);
+    for (; tile < n_tiles; tile += tstride) {
+        {
+            float f[64];
+            encode_record<PRESET, LAYOUT>(x, f);
+            T* dst = senc + lane * ROW;
+            #pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const f32x4 lo = f32x4{f[8 * q], f[8 * q + 1], f[8 * q + 2], f[8 * q + 3]};
+                const f32x4 hi = f32x4{f[8 * q + 4], f[8 * q + 5], f[8 * q + 6], f[8 * q + 7]};
+                *reinterpret_cast<V*>(dst + 8 * q) = pack8<T, V>(lo, hi);
+            }
+        }
+        if (tile + tstride < n_tiles) load_raw(tile + tstride);
+        // LDS writes of all lanes complete before any lane reads another's row.
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        V b[COLS][KC];
+        #pragma unroll
+        for (int col = 0; col < COLS; ++col)
+            #pragma unroll
+            for (int c = 0; c < 2; ++c)
+                b[col][c] = *reinterpret_cast<const V*>(senc + (16 * col + ln) * ROW + 32 * c + 8 * g);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        f32x4 o[COLS];
+        mlp_tile<T, W, COLS>(sfr, b, n_hidden, lane, o);
+        store_rgb<COLS>(o, tile * 64, n, g, ln, rgb);
     }
 }
 
 // ---------------------------------------------------------------------------
 // Training: forward + loss gradient + data backward + per-tile weight gradient
 // ---------------------------------------------------------------------------
-constexpr int kLdt = kTrainTile + 8;  // LDS row stride of the feature-major stores (elements)
+// Records per workgroup: 64 at width 64 (4 waves), 32 at width 128 (2 waves),
+// so that every layer's activations and deltas of the tile fit in LDS.
+template <int W> struct TrainShape {
+    static constexpr int TS = W == 64 ? 64 : 32;   // records per tile
+    static constexpr int NW = TS / 16;             // waves per workgroup
+    static constexpr int LDT = TS + 8;             // LDS row stride, elements
+};
 
-// LDS bytes of the activation and delta stores of one training workgroup.
-__host__ __device__ constexpr int train_act_bytes(int W, int H) {
-    return (kEncWidth + H * W + 2 * W) * kLdt * 2;
+// LDS bytes of one training workgroup: h_0 (64 rows), h_1..h_H and
+// delta_1..delta_H (W rows each), dL/dy (16 rows), all [feature][record].
+__host__ __device__ constexpr int train_lds_bytes(int W, int H) {
+    return (kEncWidth + 2 * H * W + 16) * (W == 64 ? 72 : 40) * 2;
 }
 
-// STAGE: all weight fragments are copied to LDS once per workgroup (when they
-// fit next to the activations); otherwise each layer reads them from global
-// memory (L2-resident).
-template <typename T, int W, bool UPSTREAM, bool GENC, bool STAGE>
+template <typename T, int W, bool UPSTREAM, bool GENC>
 __global__ __launch_bounds__(256) void k_train_mfma(const T* __restrict__ ffr,
                                                     const T* __restrict__ bfr,
                                                     const T* __restrict__ enc,
@@ -218,65 +322,43 @@ __global__ __launch_bounds__(256) void k_train_mfma(const T* __restrict__ ffr,
                                                     int32_t* __restrict__ tile_bad,
                                                     float* __restrict__ genc) {
     using V = typename Vec8<T>::type;
-    constexpr int MB = W / 16, KC = W / 32;
+    using S = TrainShape<W>;
+    constexpr int MB = W / 16, KC = W / 32, TS = S::TS, NW = S::NW, LDT = S::LDT, TK = TS / 32;
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     __shared__ float wsum[4];
     const Geo geo(W, n_hidden);
-    T* hT = reinterpret_cast<T*>(smem_raw);              // h_0: 64 rows, h_l: W rows each
-    T* dA = hT + (kEncWidth + n_hidden * W) * kLdt;      // delta buffers, W rows each
-    T* dB = dA + W * kLdt;
-    V* sfw = reinterpret_cast<V*>(smem_raw + train_act_bytes(W, n_hidden));
-    V* sbw = sfw + geo.n_fwd_frags() * 64;
+    T* hT = reinterpret_cast<T*>(smem_raw);                  // h_0 .. h_H
+    T* dT = hT + (kEncWidth + n_hidden * W) * LDT;           // delta_1 .. delta_H
+    T* dO = dT + n_hidden * W * LDT;                         // dL/dy, rows 0..2
+    auto hrow = [&](int l) { return hT + (l == 0 ? 0 : kEncWidth + (l - 1) * W) * LDT; };
+    auto drow = [&](int l) { return dT + (l - 1) * W * LDT; };
 
     const int P = geo.n_params();
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int g = lane >> 4, ln = lane & 15;
     const int64_t tile = blockIdx.x;
-    const int sl = 16 * wave + ln;                       // record within the tile
-    const int64_t row = tile * kTrainTile + sl;
+    const int sl = 16 * wave + ln;                           // record within the tile
+    const int64_t row = tile * TS + sl;
     const bool valid = row < n;
     float* part = partials + tile * (int64_t)P;
+    const V* gf = reinterpret_cast<const V*>(ffr) + lane;
+    const V* gb = reinterpret_cast<const V*>(bfr) + lane;
 
-    // Encoded inputs of this wave's 16 records (zeros past the end of the batch).
+    // Scatter a chained-order operand (features of chunk c) into a [feature][record] store.
+    auto put = [&](T* base, const V& v, int c) {
+        #pragma unroll
+        for (int i = 0; i < 8; ++i) base[(32 * c + (i < 4 ? 4 * g + i : 12 + 4 * g + i)) * LDT + sl] = v[i];
+    };
+
+    // ---- forward (each wave: its 16 records, activations in VGPRs) ----------
     V b[KC];
     #pragma unroll
-    for (int c = 0; c < 2; ++c)
+    for (int c = 0; c < 2; ++c) {
         b[c] = valid ? *reinterpret_cast<const V*>(enc + row * kEncWidth + 32 * c + 8 * g) : zero8<V>();
-    const V* gf;
-    const V* gb;
-    if (STAGE) {
-        // Forward and backward fragments are contiguous in LDS (sbw follows
-        // sfw); copy them in rounds of 12 loads per thread, all in flight
-        // before the first LDS store.
-        const int nf = geo.n_fwd_frags() * 64, total = nf + geo.n_bwd_frags() * 64;
-        const V* src_f = reinterpret_cast<const V*>(ffr);
-        const V* src_b = reinterpret_cast<const V*>(bfr);
-        for (int base = 0; base < total; base += 12 * 256) {
-            V tmp[12];
-            #pragma unroll
-            for (int u = 0; u < 12; ++u) {
-                const int i = base + u * 256 + tid;
-                if (i < total) tmp[u] = i < nf ? src_f[i] : src_b[i - nf];
-            }
-            #pragma unroll
-            for (int u = 0; u < 12; ++u) {
-                const int i = base + u * 256 + tid;
-                if (i < total) sfw[i] = tmp[u];
-            }
-        }
-        gf = sfw + lane;
-        gb = sbw + lane;
-    } else {
-        gf = reinterpret_cast<const V*>(ffr) + lane;
-        gb = reinterpret_cast<const V*>(bfr) + lane;
-    }
-    #pragma unroll
-    for (int c = 0; c < 2; ++c)
         #pragma unroll
-        for (int i = 0; i < 8; ++i) hT[(32 * c + 8 * g + i) * kLdt + sl] = b[c][i];
-    if (STAGE) __syncthreads();
-
-    // ---- forward ------------------------------------------------------------
+        for (int i = 0; i < 8; ++i) hT[(32 * c + 8 * g + i) * LDT + sl] = b[c][i];
+    }
     for (int l = 0; l < n_hidden; ++l) {
         const int kc = l == 0 ? 2 : KC;
         const V* fl = gf + geo.fwd_base(l) * 64;
@@ -289,15 +371,12 @@ __global__ __launch_bounds__(256) void k_train_mfma(const T* __restrict__ ffr,
             #pragma unroll
             for (int mb = 0; mb < MB; ++mb) acc[mb] = mfma(fl[(mb * kc + c) * 64], b[c], acc[mb]);
         }
+        T* ho = hrow(l + 1);
         #pragma unroll
-        for (int c = 0; c < KC; ++c) b[c] = relu_packed(pack8<T, V>(acc[2 * c], acc[2 * c + 1]));
-        // h_{l+1} to LDS, feature-major: slot i of chunk c holds feature chained_feature(c, g, i)
-        T* ho = hT + (kEncWidth + l * W) * kLdt;
-        #pragma unroll
-        for (int c = 0; c < KC; ++c)
-            #pragma unroll
-            for (int i = 0; i < 8; ++i)
-                ho[(32 * c + (i < 4 ? 4 * g + i : 12 + 4 * g + i)) * kLdt + sl] = b[c][i];
+        for (int c = 0; c < KC; ++c) {
+            b[c] = relu_packed(pack8<T, V>(acc[2 * c], acc[2 * c + 1]));
+            put(ho, b[c], c);
+        }
     }
     f32x4 y;
     {
@@ -307,7 +386,7 @@ __global__ __launch_bounds__(256) void k_train_mfma(const T* __restrict__ ffr,
         for (int c = 1; c < KC; ++c) y = mfma(fo[c * 64], b[c], y);
     }
 
-    // ---- loss gradient (Eq. 5), lanes 0..15 of each wave hold y[0..2] -------
+    // ---- loss gradient (Eq. 5); lanes 0..15 of each wave hold y[0..2] -------
     float d0 = 0.f, d1 = 0.f, d2 = 0.f, lterm = 0.f;
     if (g == 0 && valid) {
         if (UPSTREAM) {
@@ -329,120 +408,112 @@ __global__ __launch_bounds__(256) void k_train_mfma(const T* __restrict__ ffr,
     V bd = zero8<V>();
     if (g == 0) {
         bd[0] = to_t<T>(d0); bd[1] = to_t<T>(d1); bd[2] = to_t<T>(d2);
-        dA[0 * kLdt + sl] = bd[0];
-        dA[1 * kLdt + sl] = bd[1];
-        dA[2 * kLdt + sl] = bd[2];
+        dO[0 * LDT + sl] = bd[0];
+        dO[1 * LDT + sl] = bd[1];
+        dO[2 * LDT + sl] = bd[2];
     }
     const float wl = wave_sum(lterm);
     if (lane == 0) wsum[wave] = wl;
-    __syncthreads();
-    if (tid == 0) loss_part[tile] = ((wsum[0] + wsum[1]) + wsum[2]) + wsum[3];
 
-    bool bad = false;   // any non-finite weight-gradient partial in this tile
-    // ---- output layer: dW_H = dL/dy h_H^T, delta_H = W_H^T dL/dy ------------
-    const T* hH = hT + (kEncWidth + (n_hidden - 1) * W) * kLdt;
-    for (int nb = wave; nb < MB; nb += 4) {
-        f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
-        #pragma unroll
-        for (int kc = 0; kc < 2; ++kc) {
-            const V a = ln < kNOut ? *reinterpret_cast<const V*>(dA + ln * kLdt + 32 * kc + 8 * g)
-                                   : zero8<V>();
-            const V bb = *reinterpret_cast<const V*>(hH + (16 * nb + ln) * kLdt + 32 * kc + 8 * g);
-            acc = mfma(a, bb, acc);
-        }
-        if (g == 0) {
-            #pragma unroll
-            for (int j = 0; j < kNOut; ++j) {
-                part[geo.w_off(n_hidden) + j * W + 16 * nb + ln] = acc[j];
-                bad |= !isfinite(acc[j]);
-            }
-        }
-    }
-    {
-        const V* fb = gb + geo.bwd_base(n_hidden) * 64;
+    // ---- data backward: the whole delta chain in VGPRs, each delta kept in LDS
+    // delta_l = (W_l^T delta_{l+1}) masked by ReLU'(z_l); W_H^T acts on dL/dy.
+    for (int l = n_hidden; l >= 1; --l) {
+        const T* hl = hrow(l);
         f32x4 acc[MB];
-        #pragma unroll
-        for (int mb = 0; mb < MB; ++mb) acc[mb] = mfma(fb[mb * 64], bd, f32x4{0.f, 0.f, 0.f, 0.f});
-        #pragma unroll
-        for (int mb = 0; mb < MB; ++mb)
+        if (l == n_hidden) {
+            const V* fb = gb + geo.bwd_base(n_hidden) * 64;
             #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int f = 16 * mb + 4 * g + j;
-                acc[mb][j] = (float)hH[f * kLdt + sl] > 0.0f ? acc[mb][j] : 0.0f;
-            }
-        #pragma unroll
-        for (int c = 0; c < KC; ++c) {
-            b[c] = pack8<T, V>(acc[2 * c], acc[2 * c + 1]);
-            #pragma unroll
-            for (int i = 0; i < 8; ++i) dB[(32 * c + (i < 4 ? 4 * g + i : 12 + 4 * g + i)) * kLdt + sl] = b[c][i];
-        }
-    }
-
-    // ---- hidden and input layers ------------------------------------------
-    T* dcur = dB;
-    T* dnxt = dA;
-    for (int l = n_hidden - 1; l >= 0; --l) {
-        __syncthreads();
-        const int ncols = l == 0 ? kEncWidth : W;
-        const int woff = geo.w_off(l);
-        const T* hl = hT + (l == 0 ? 0 : (kEncWidth + (l - 1) * W)) * kLdt;
-        // dW_l = delta_{l+1} h_l^T, a contraction over the tile's 64 records.
-        for (int nb = wave; nb < ncols / 16; nb += 4) {
-            V bb[2];
-            #pragma unroll
-            for (int kc = 0; kc < 2; ++kc)
-                bb[kc] = *reinterpret_cast<const V*>(hl + (16 * nb + ln) * kLdt + 32 * kc + 8 * g);
-            #pragma unroll
-            for (int mb = 0; mb < MB; ++mb) {
-                f32x4 acc = mfma(*reinterpret_cast<const V*>(dcur + (16 * mb + ln) * kLdt + 8 * g), bb[0],
-                                 f32x4{0.f, 0.f, 0.f, 0.f});
-                acc = mfma(*reinterpret_cast<const V*>(dcur + (16 * mb + ln) * kLdt + 32 + 8 * g), bb[1], acc);
-                #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    part[woff + (16 * mb + 4 * g + j) * ncols + 16 * nb + ln] = acc[j];
-                    bad |= !isfinite(acc[j]);
-                }
-            }
-        }
-        if (l >= 1) {
-            // delta_l = W_l^T delta_{l+1}, masked by ReLU'(z_l).
+            for (int mb = 0; mb < MB; ++mb) acc[mb] = mfma(fb[mb * 64], bd, f32x4{0.f, 0.f, 0.f, 0.f});
+        } else {
             const V* fb = gb + geo.bwd_base(l) * 64;
-            f32x4 acc[MB];
             #pragma unroll
             for (int mb = 0; mb < MB; ++mb) acc[mb] = mfma(fb[(mb * KC) * 64], b[0], f32x4{0.f, 0.f, 0.f, 0.f});
             #pragma unroll
             for (int c = 1; c < KC; ++c)
                 #pragma unroll
                 for (int mb = 0; mb < MB; ++mb) acc[mb] = mfma(fb[(mb * KC + c) * 64], b[c], acc[mb]);
+        }
+        #pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
             #pragma unroll
-            for (int mb = 0; mb < MB; ++mb)
+            for (int j = 0; j < 4; ++j)
+                acc[mb][j] = (float)hl[(16 * mb + 4 * g + j) * LDT + sl] > 0.0f ? acc[mb][j] : 0.0f;
+        T* dl = drow(l);
+        #pragma unroll
+        for (int c = 0; c < KC; ++c) {
+            b[c] = pack8<T, V>(acc[2 * c], acc[2 * c + 1]);
+            put(dl, b[c], c);
+        }
+    }
+    if (GENC) {
+        // dL/dh_0 = W_0^T delta_1 (64 input features).
+        f32x4 acc[4];
+        #pragma unroll
+        for (int mb = 0; mb < 4; ++mb) acc[mb] = mfma(gb[(mb * KC) * 64], b[0], f32x4{0.f, 0.f, 0.f, 0.f});
+        #pragma unroll
+        for (int c = 1; c < KC; ++c)
+            #pragma unroll
+            for (int mb = 0; mb < 4; ++mb) acc[mb] = mfma(gb[(mb * KC + c) * 64], b[c], acc[mb]);
+        if (valid) {
+            #pragma unroll
+            for (int mb = 0; mb < 4; ++mb)
+                *reinterpret_cast<float4*>(genc + row * kEncWidth + 16 * mb + 4 * g) =
+                    make_float4(acc[mb][0], acc[mb][1], acc[mb][2], acc[mb][3]);
+        }
+    }
+    __syncthreads();
+    if (tid == 0) {
+        float t = 0.0f;
+        for (int w = 0; w < NW; ++w) t += wsum[w];
+        loss_part[tile] = t;
+    }
+
+    // ---- weight gradients: dW_l = delta_{l+1} h_l^T over the tile's records --
+    // All layers at once (no dependence between them).  The 16x16 result
+    // blocks are stored in the accumulator's own layout, one float4 per lane:
+    // slot w_off(l) + ((mb * NB + nb) * 64 + lane) * 4 + j holds
+    // dW_l[16 mb + 4 g + j][16 nb + ln].  The output layer is row-major.
+    bool bad = false;
+    for (int l = 0; l <= n_hidden; ++l) {
+        const int ncols = l == 0 ? kEncWidth : W;
+        const int NB = ncols / 16;
+        const T* hl = hrow(l);
+        const T* dl = l == n_hidden ? dO : drow(l + 1);
+        const int woff = geo.w_off(l);
+        for (int nb = wave; nb < NB; nb += NW) {
+            V bb[TK];
+            #pragma unroll
+            for (int kc = 0; kc < TK; ++kc)
+                bb[kc] = *reinterpret_cast<const V*>(hl + (16 * nb + ln) * LDT + 32 * kc + 8 * g);
+            if (l == n_hidden) {
+                f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
                 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const int f = 16 * mb + 4 * g + j;
-                    acc[mb][j] = (float)hl[f * kLdt + sl] > 0.0f ? acc[mb][j] : 0.0f;
+                for (int kc = 0; kc < TK; ++kc) {
+                    const V a = ln < kNOut ? *reinterpret_cast<const V*>(dl + ln * LDT + 32 * kc + 8 * g)
+                                           : zero8<V>();
+                    acc = mfma(a, bb[kc], acc);
                 }
-            #pragma unroll
-            for (int c = 0; c < KC; ++c) {
-                b[c] = pack8<T, V>(acc[2 * c], acc[2 * c + 1]);
+                if (g == 0) {
+                    #pragma unroll
+                    for (int j = 0; j < kNOut; ++j) {
+                        part[woff + j * W + 16 * nb + ln] = acc[j];
+                        bad |= !isfinite(acc[j]);
+                    }
+                }
+            } else {
                 #pragma unroll
-                for (int i = 0; i < 8; ++i)
-                    dnxt[(32 * c + (i < 4 ? 4 * g + i : 12 + 4 * g + i)) * kLdt + sl] = b[c][i];
-            }
-            T* t = dcur; dcur = dnxt; dnxt = t;
-        } else if (GENC) {
-            // dL/dh_0 = W_0^T delta_1 (64 input features).
-            f32x4 acc[4];
-            #pragma unroll
-            for (int mb = 0; mb < 4; ++mb) acc[mb] = mfma(gb[(mb * KC) * 64], b[0], f32x4{0.f, 0.f, 0.f, 0.f});
-            #pragma unroll
-            for (int c = 1; c < KC; ++c)
-                #pragma unroll
-                for (int mb = 0; mb < 4; ++mb) acc[mb] = mfma(gb[(mb * KC + c) * 64], b[c], acc[mb]);
-            if (valid) {
-                #pragma unroll
-                for (int mb = 0; mb < 4; ++mb)
-                    *reinterpret_cast<float4*>(genc + row * kEncWidth + 16 * mb + 4 * g) =
-                        make_float4(acc[mb][0], acc[mb][1], acc[mb][2], acc[mb][3]);
+                for (int mb = 0; mb < MB; ++mb) {
+                    f32x4 acc = mfma(*reinterpret_cast<const V*>(dl + (16 * mb + ln) * LDT + 8 * g), bb[0],
+                                     f32x4{0.f, 0.f, 0.f, 0.f});
+                    #pragma unroll
+                    for (int kc = 1; kc < TK; ++kc)
+                        acc = mfma(*reinterpret_cast<const V*>(dl + (16 * mb + ln) * LDT + 32 * kc + 8 * g),
+                                   bb[kc], acc);
+                    *reinterpret_cast<float4*>(part + woff + ((mb * NB + nb) * 64 + lane) * 4) =
+                        make_float4(acc[0], acc[1], acc[2], acc[3]);
+                    #pragma unroll
+                    for (int j = 0; j < 4; ++j) bad |= !isfinite(acc[j]);
+                }
             }
         }
     }
@@ -466,29 +537,45 @@ hipError_t fwd_dispatch(const Geo& d, const void* ffr, const void* enc, int64_t 
     return hipGetLastError();
 }
 
+template <typename T, int W, int PRESET, int LAYOUT>
+hipError_t fwd_raw_launch(const Geo& d, const void* ffr, const float* raw, int64_t n, float* rgb,
+                          hipStream_t s) {
+    const int64_t tiles = (n + 63) / 64;
+    if (tiles == 0) return hipSuccess;
+    const size_t lds = (size_t)d.n_fwd_frags() * 1024 + 4 * 64 * 72 * sizeof(T);
+    int64_t blocks = (tiles + 3) / 4;
+    if (blocks > 2048) blocks = 2048;
+    auto k = k_fwd_raw_mfma<T, W, PRESET, LAYOUT>;
+    (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(256), lds, s, (const T*)ffr, d.n_fwd_frags(), raw,
+                       n, rgb, d.H);
+    return hipGetLastError();
+}
+
+template <typename T, int W>
+hipError_t fwd_raw_dispatch(const Geo& d, int preset, int layout, const void* ffr, const float* raw,
+                            int64_t n, float* rgb, hipStream_t s) {
+    if (preset == NRC_PRESET_PAPER)
+        return layout == NRC_RAW14 ? fwd_raw_launch<T, W, NRC_PRESET_PAPER, NRC_RAW14>(d, ffr, raw, n, rgb, s)
+                                   : fwd_raw_launch<T, W, NRC_PRESET_PAPER, NRC_RAW16>(d, ffr, raw, n, rgb, s);
+    return layout == NRC_RAW14 ? fwd_raw_launch<T, W, NRC_PRESET_CONFIG, NRC_RAW14>(d, ffr, raw, n, rgb, s)
+                               : fwd_raw_launch<T, W, NRC_PRESET_CONFIG, NRC_RAW16>(d, ffr, raw, n, rgb, s);
+}
+
 template <typename T, int W, bool UP, bool GE>
 hipError_t train_launch(const Geo& d, const void* ffr, const void* bfr, const void* enc,
                         const float* tgt, int64_t n, float loss_eps, float grad_scale,
                         float* partials, float* loss_part, int32_t* tile_bad, float* genc,
                         hipStream_t s) {
-    const int64_t tiles = (n + kTrainTile - 1) / kTrainTile;
+    using S = TrainShape<W>;
+    const int64_t tiles = (n + S::TS - 1) / S::TS;
     if (tiles == 0) return hipSuccess;
-    const size_t act = (size_t)train_act_bytes(W, d.H);
-    const size_t staged = act + (size_t)(d.n_fwd_frags() + d.n_bwd_frags()) * 1024;
-    const size_t lds_cap = 160 * 1024 - 64;   // gfx950 LDS per workgroup, minus the static part
-    if (staged <= lds_cap) {
-        auto k = k_train_mfma<T, W, UP, GE, true>;
-        (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)staged);
-        hipLaunchKernelGGL(k, dim3((unsigned)tiles), dim3(256), staged, s, (const T*)ffr, (const T*)bfr,
-                           (const T*)enc, tgt, n, d.H, loss_eps, grad_scale, partials, loss_part,
-                           tile_bad, genc);
-    } else {
-        auto k = k_train_mfma<T, W, UP, GE, false>;
-        (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)act);
-        hipLaunchKernelGGL(k, dim3((unsigned)tiles), dim3(256), act, s, (const T*)ffr, (const T*)bfr,
-                           (const T*)enc, tgt, n, d.H, loss_eps, grad_scale, partials, loss_part,
-                           tile_bad, genc);
-    }
+    const size_t lds = (size_t)train_lds_bytes(W, d.H);
+    auto k = k_train_mfma<T, W, UP, GE>;
+    (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k, dim3((unsigned)tiles), dim3(64 * S::NW), lds, s, (const T*)ffr, (const T*)bfr,
+                       (const T*)enc, tgt, n, d.H, loss_eps, grad_scale, partials, loss_part, tile_bad,
+                       genc);
     return hipGetLastError();
 }
 
@@ -510,7 +597,7 @@ hipError_t train_dispatch(const Geo& d, const void* ffr, const void* bfr, const 
 }  // namespace
 
 size_t mfma_train_lds_bytes(int width, int n_hidden) {
-    return (size_t)train_act_bytes(width, n_hidden) + 16;
+    return (size_t)train_lds_bytes(width, n_hidden) + 16;
 }
 size_t mfma_fwd_lds_bytes(int width, int n_hidden) {
     return (size_t)Geo(width, n_hidden).n_fwd_frags() * 64 * 16;
@@ -523,6 +610,14 @@ hipError_t launch_fwd_mfma(int precision, const Geo& d, const void* ffr, const v
                          : fwd_dispatch<_Float16, 128>(d, ffr, enc, n, rgb, s);
     return d.W == 64 ? fwd_dispatch<__bf16, 64>(d, ffr, enc, n, rgb, s)
                      : fwd_dispatch<__bf16, 128>(d, ffr, enc, n, rgb, s);
+}
+
+// Width 64 only: the fused kernel keeps the weights and four 64-record encode
+// buffers in LDS side by side.
+hipError_t launch_fwd_raw_mfma(int precision, const Geo& d, int preset, int layout, const void* ffr,
+                               const float* raw, int64_t n, float* rgb, hipStream_t s) {
+    if (precision == NRC_FP16) return fwd_raw_dispatch<_Float16, 64>(d, preset, layout, ffr, raw, n, rgb, s);
+    return fwd_raw_dispatch<__bf16, 64>(d, preset, layout, ffr, raw, n, rgb, s);
 }
 
 hipError_t launch_train_mfma(int precision, const Geo& d, const void* ffr, const void* bfr,

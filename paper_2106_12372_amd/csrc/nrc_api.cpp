@@ -65,6 +65,7 @@ int validate_config(const nrc_config* c) {
     if (!(c->adam_eps >= 0.0f) || !std::isfinite(c->adam_eps)) return fail(NRC_EINVAL, "adam_eps must be >= 0");
     if (!(c->loss_eps > 0.0f) || !std::isfinite(c->loss_eps)) return fail(NRC_EINVAL, "loss_eps must be positive");
     if (!(c->loss_scale > 0.0f) || !std::isfinite(c->loss_scale)) return fail(NRC_EINVAL, "loss_scale must be positive");
+    if (!(c->ema_alpha >= 0.0f && c->ema_alpha < 1.0f)) return fail(NRC_EINVAL, "ema_alpha must be in [0, 1)");
     return NRC_OK;
 }
 
@@ -84,6 +85,12 @@ CacheLayout cache_layout(const nrc_config& c) {
     } else {
         L.ffr = L.bfr = 0;
     }
+    L.e = L.wbar = L.effr = 0;
+    if (c.ema_alpha > 0.0f) {
+        L.e = take(P * 4);
+        L.wbar = take(P * 4);
+        if (c.precision != NRC_FP32) L.effr = take((size_t)d.n_fwd_frags() * kFragElems * 2);
+    }
     L.total = off;
     return L;
 }
@@ -91,7 +98,8 @@ CacheLayout cache_layout(const nrc_config& c) {
 ScratchLayout scratch_layout(const nrc_config& c, int64_t n) {
     const Geo d(c.width, c.n_hidden);
     const size_t P = (size_t)d.n_params();
-    const size_t tiles = (size_t)((n + kTrainTile - 1) / kTrainTile);
+    const int ts = train_tile(c.precision, c.width);
+    const size_t tiles = (size_t)((n + ts - 1) / ts);
     ScratchLayout L{};
     size_t off = 0;
     auto take = [&](size_t bytes) { const size_t o = off; off = align256(off + bytes); return o; };
@@ -128,9 +136,11 @@ int enqueue_train_step(nrc_cache* c, const void* enc, const float* target, int64
     float* loss_out = loss_dev ? loss_dev : (float*)(scratch + sl.loss);
     int32_t* skipped_out = skipped_dev ? skipped_dev : (int32_t*)(scratch + sl.skipped);
     const AdamHyper hp{cfg.lr, cfg.beta1, cfg.beta2, cfg.adam_eps};
-    e = launch_reduce_adam(cfg.precision, d, partials, (int)sl.tiles, tile_bad, loss_part,
-                           (float)(1.0 / (3.0 * (double)n)), loss_out, 1.0f / scale, c->w(), c->m(),
-                           c->v(), c->tslots(), c->parity, hp, skipped_out, c->ffr(), c->bfr(), s);
+    const EmaArgs ema{c->ema() ? cfg.ema_alpha : 0.0f, c->e(), c->wbar(), c->effr()};
+    e = launch_reduce_adam(cfg.precision, d, cfg.precision != NRC_FP32, partials, (int)sl.tiles,
+                           tile_bad, loss_part, (float)(1.0 / (3.0 * (double)n)), loss_out,
+                           1.0f / scale, c->w(), c->m(), c->v(), c->tslots(), c->parity, hp, ema,
+                           skipped_out, c->ffr(), c->bfr(), s);
     if (e != hipSuccess) return device_fail(e, "gradient reduction / Adam launch");
     c->parity ^= 1;
     return NRC_OK;
@@ -140,9 +150,9 @@ int enqueue_forward(nrc_cache* c, const void* enc, int64_t n, float* rgb, hipStr
     const Geo d(c->cfg.width, c->cfg.n_hidden);
     hipError_t e;
     if (c->cfg.precision == NRC_FP32)
-        e = launch_fwd_fp32(d, c->w(), (const float*)enc, n, rgb, s);
+        e = launch_fwd_fp32(d, c->query_w(), (const float*)enc, n, rgb, s);
     else
-        e = launch_fwd_mfma(c->cfg.precision, d, c->ffr(), enc, n, rgb, s);
+        e = launch_fwd_mfma(c->cfg.precision, d, c->query_ffr(), enc, n, rgb, s);
     if (e != hipSuccess) return device_fail(e, "forward launch");
     return NRC_OK;
 }
@@ -167,6 +177,7 @@ int nrc_config_default(nrc_config* cfg) {
     cfg->adam_eps = 1e-8f;
     cfg->loss_eps = 0.01f;
     cfg->loss_scale = 128.0f;
+    cfg->ema_alpha = 0.0f;
     cfg->seed = 0;
     return ok();
 }
@@ -241,6 +252,27 @@ int nrc_cache_config(const nrc_cache* cache, nrc_config* out) {
     return ok();
 }
 
+// Rebuild the reduced-precision weight copies from the master weights and
+// restart the EMA set at W_bar = W, E = 0 (enqueued on s).
+static hipError_t reset_ema_and_frags(nrc_cache* c, hipStream_t s) {
+    const Geo d(c->cfg.width, c->cfg.n_hidden);
+    const size_t bytes = (size_t)d.n_params() * 4;
+    hipError_t e = hipSuccess;
+    if (c->ema()) {
+        e = hipMemsetAsync(c->e(), 0, bytes, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(c->wbar(), c->w(), bytes, hipMemcpyDeviceToDevice, s);
+    }
+    if (e == hipSuccess && c->cfg.precision != NRC_FP32) {
+        e = hipMemsetAsync(c->ffr(), 0, (size_t)d.n_fwd_frags() * kFragElems * 2, s);
+        if (e == hipSuccess) e = hipMemsetAsync(c->bfr(), 0, (size_t)d.n_bwd_frags() * kFragElems * 2, s);
+        if (e == hipSuccess && c->ema())
+            e = hipMemsetAsync(c->effr(), 0, (size_t)d.n_fwd_frags() * kFragElems * 2, s);
+        if (e == hipSuccess)
+            e = launch_build_frags(c->cfg.precision, d, c->w(), c->ffr(), c->bfr(), c->effr(), s);
+    }
+    return e;
+}
+
 static int upload_state(nrc_cache* c, const float* w, const float* m, const float* v, int64_t t,
                         hipStream_t s) {
     const Geo d(c->cfg.width, c->cfg.n_hidden);
@@ -252,11 +284,7 @@ static int upload_state(nrc_cache* c, const float* w, const float* m, const floa
         e = v ? hipMemcpyAsync(c->v(), v, bytes, hipMemcpyHostToDevice, s) : hipMemsetAsync(c->v(), 0, bytes, s);
     int32_t ts[4] = {(int32_t)t, (int32_t)t, 0, 0};
     if (e == hipSuccess) e = hipMemcpyAsync(c->tslots(), ts, sizeof ts, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess && c->cfg.precision != NRC_FP32) {
-        e = hipMemsetAsync(c->ffr(), 0, (size_t)d.n_fwd_frags() * kFragElems * 2, s);
-        if (e == hipSuccess) e = hipMemsetAsync(c->bfr(), 0, (size_t)d.n_bwd_frags() * kFragElems * 2, s);
-        if (e == hipSuccess) e = launch_build_frags(c->cfg.precision, d, c->w(), c->ffr(), c->bfr(), s);
-    }
+    if (e == hipSuccess) e = reset_ema_and_frags(c, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return device_fail(e, "state upload");
     c->parity = 0;
@@ -283,8 +311,7 @@ int nrc_set_weights_device(nrc_cache* cache, const float* dev_w, int64_t n, void
     if (e == hipSuccess) e = hipMemsetAsync(cache->m(), 0, bytes, s);
     if (e == hipSuccess) e = hipMemsetAsync(cache->v(), 0, bytes, s);
     if (e == hipSuccess) e = hipMemsetAsync(cache->tslots(), 0, 16, s);
-    if (e == hipSuccess && cache->cfg.precision != NRC_FP32)
-        e = launch_build_frags(cache->cfg.precision, d, cache->w(), cache->ffr(), cache->bfr(), s);
+    if (e == hipSuccess) e = reset_ema_and_frags(cache, s);
     if (e != hipSuccess) return device_fail(e, "device weight upload");
     cache->parity = 0;
     return ok();
@@ -328,6 +355,36 @@ int nrc_set_state(nrc_cache* cache, const float* host_w, const float* host_m, co
     return upload_state(cache, host_w, host_m, host_v, t, (hipStream_t)stream);
 }
 
+int nrc_get_ema(const nrc_cache* cache, float* host_w_bar, float* host_e, int64_t n, void* stream) {
+    if (!cache || !host_w_bar || !host_e) return fail(NRC_EINVAL, "NULL argument");
+    nrc_cache* c = const_cast<nrc_cache*>(cache);
+    if (!c->ema()) return fail(NRC_EINVAL, "the cache keeps no EMA weights (ema_alpha = 0)");
+    const int64_t P = Geo(c->cfg.width, c->cfg.n_hidden).n_params();
+    if (n != P) return fail(NRC_EINVAL, "expected %lld weights, got %lld", (long long)P, (long long)n);
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipMemcpyAsync(host_w_bar, c->wbar(), (size_t)P * 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(host_e, c->e(), (size_t)P * 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return device_fail(e, "EMA download");
+    return ok();
+}
+
+int nrc_set_ema(nrc_cache* cache, const float* host_w_bar, const float* host_e, int64_t n, void* stream) {
+    if (!cache || !host_w_bar || !host_e) return fail(NRC_EINVAL, "NULL argument");
+    if (!cache->ema()) return fail(NRC_EINVAL, "the cache keeps no EMA weights (ema_alpha = 0)");
+    const Geo d(cache->cfg.width, cache->cfg.n_hidden);
+    if (n != d.n_params()) return fail(NRC_EINVAL, "expected %d weights, got %lld", d.n_params(), (long long)n);
+    hipStream_t s = (hipStream_t)stream;
+    const size_t bytes = (size_t)d.n_params() * 4;
+    hipError_t e = hipMemcpyAsync(cache->wbar(), host_w_bar, bytes, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(cache->e(), host_e, bytes, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && cache->cfg.precision != NRC_FP32)
+        e = launch_build_frags(cache->cfg.precision, d, cache->wbar(), cache->effr(), nullptr, nullptr, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return device_fail(e, "EMA upload");
+    return ok();
+}
+
 int nrc_encode(const nrc_cache* cache, const float* raw, int raw_layout, int64_t n, void* enc,
                void* stream) {
     if (!cache) return fail(NRC_EINVAL, "cache is NULL");
@@ -350,6 +407,27 @@ int nrc_forward(nrc_cache* cache, const void* enc, int64_t n, float* rgb, void* 
     if (!aligned16(enc) || ((uintptr_t)rgb & 3)) return fail(NRC_EINVAL, "misaligned buffer");
     const int rc = enqueue_forward(cache, enc, n, rgb, (hipStream_t)stream);
     return rc == NRC_OK ? ok() : rc;
+}
+
+int nrc_forward_raw(nrc_cache* cache, const float* raw, int raw_layout, int64_t n, float* rgb,
+                    void* stream) {
+    if (!cache) return fail(NRC_EINVAL, "cache is NULL");
+    if (raw_layout != NRC_RAW14 && raw_layout != NRC_RAW16) return fail(NRC_EINVAL, "unknown raw layout %d", raw_layout);
+    if (cache->cfg.width != 64) return fail(NRC_EINVAL, "the fused raw-record path supports width 64");
+    if (n < 0) return fail(NRC_EINVAL, "n must be >= 0");
+    if (n == 0) return ok();
+    if (!raw || !rgb) return fail(NRC_EINVAL, "NULL buffer");
+    if (!aligned16(raw) || ((uintptr_t)rgb & 3)) return fail(NRC_EINVAL, "misaligned buffer");
+    const Geo d(cache->cfg.width, cache->cfg.n_hidden);
+    hipError_t e;
+    if (cache->cfg.precision == NRC_FP32)
+        e = launch_fwd_raw_fp32(d, cache->cfg.enc_preset, raw_layout, cache->query_w(), raw, n, rgb,
+                                (hipStream_t)stream);
+    else
+        e = launch_fwd_raw_mfma(cache->cfg.precision, d, cache->cfg.enc_preset, raw_layout,
+                                cache->query_ffr(), raw, n, rgb, (hipStream_t)stream);
+    if (e != hipSuccess) return device_fail(e, "fused forward launch");
+    return ok();
 }
 
 int nrc_train_step(nrc_cache* cache, const void* enc, const float* target, int64_t n,
@@ -397,7 +475,8 @@ int nrc_backward(nrc_cache* cache, const void* enc, const float* grad_rgb, int64
         e = launch_train_mfma(cfg.precision, d, cache->ffr(), cache->bfr(), enc, grad_rgb, n, true,
                               cfg.loss_eps, 1.0f, partials, loss_part, tile_bad, grad_enc, s);
     if (e != hipSuccess) return device_fail(e, "backward kernel launch");
-    e = launch_reduce(d, partials, (int)sl.tiles, 1.0f, grad_w, loss_part, 1.0f, nullptr, s);
+    e = launch_reduce(d, cfg.precision != NRC_FP32, partials, (int)sl.tiles, 1.0f, grad_w, loss_part,
+                      1.0f, nullptr, s);
     if (e != hipSuccess) return device_fail(e, "gradient reduction launch");
     return ok();
 }

@@ -11,7 +11,7 @@ namespace nrc {
 
 // Byte offsets inside a cache workspace.
 struct CacheLayout {
-    size_t w, m, v, t, ffr, bfr, total;
+    size_t w, m, v, t, ffr, bfr, e, wbar, effr, total;
 };
 
 // Byte offsets inside the scratch of one training step / backward pass.
@@ -43,6 +43,13 @@ struct nrc_cache {
     int32_t* tslots() { return (int32_t*)(ws + lay.t); }
     void* ffr() { return cfg.precision == NRC_FP32 ? nullptr : (void*)(ws + lay.ffr); }
     void* bfr() { return cfg.precision == NRC_FP32 ? nullptr : (void*)(ws + lay.bfr); }
+    bool ema() const { return cfg.ema_alpha > 0.0f; }
+    float* e() { return ema() ? (float*)(ws + lay.e) : nullptr; }
+    float* wbar() { return ema() ? (float*)(ws + lay.wbar) : nullptr; }
+    void* effr() { return (ema() && cfg.precision != NRC_FP32) ? (void*)(ws + lay.effr) : nullptr; }
+    // Weights the query entry points use: the EMA set when it is kept.
+    const float* query_w() { return ema() ? wbar() : w(); }
+    const void* query_ffr() { return ema() ? effr() : ffr(); }
 };
 
 namespace nrc {

@@ -14,7 +14,11 @@ namespace nrc {
 constexpr int kMaxLayers = 9;   // up to 8 hidden layers + output
 constexpr int kEncWidth = 64;   // encoded input width (Sec. 3.6)
 constexpr int kNOut = 3;        // RGB
-constexpr int kTrainTile = 64;  // training samples per workgroup
+// Training records per workgroup tile: 64, except 32 for the width-128
+// matrix-core form (its activations and deltas must fit in LDS).
+__host__ __device__ inline int train_tile(int precision, int width) {
+    return (precision != NRC_FP32 && width == 128) ? 32 : 64;
+}
 
 // One matrix-core operand fragment: 64 lanes x 8 16-bit elements.
 constexpr int kFragElems = 64 * 8;
@@ -94,6 +98,15 @@ struct AdamHyper {
     float lr, beta1, beta2, eps;
 };
 
+// EMA weight set (Eq. 2): alpha = 0 disables it.  e: running sum E,
+// wbar: bias-corrected W_bar (FP32), effr: W_bar's forward fragments.
+struct EmaArgs {
+    float alpha;
+    float* e;
+    float* wbar;
+    void* effr;
+};
+
 // ---------------------------------------------------------------------------
 // Host launch wrappers (return hipError_t of the launch).
 // ---------------------------------------------------------------------------
@@ -107,7 +120,11 @@ hipError_t launch_train_fp32(const Geo& d, const float* w, const float* enc, con
                              int64_t n, bool upstream, float loss_eps, float grad_scale,
                              float* partials, float* loss_part, int32_t* tile_bad, float* genc,
                              hipStream_t s);
+hipError_t launch_fwd_raw_fp32(const Geo& d, int preset, int layout, const float* w, const float* raw,
+                               int64_t n, float* rgb, hipStream_t s);
 // mlp_mfma.hip
+hipError_t launch_fwd_raw_mfma(int precision, const Geo& d, int preset, int layout, const void* ffr,
+                               const float* raw, int64_t n, float* rgb, hipStream_t s);
 hipError_t launch_fwd_mfma(int precision, const Geo& d, const void* ffr, const void* enc,
                            int64_t n, float* rgb, hipStream_t s);
 hipError_t launch_train_mfma(int precision, const Geo& d, const void* ffr, const void* bfr,
@@ -119,15 +136,19 @@ size_t mfma_train_lds_bytes(int width, int n_hidden);
 size_t mfma_fwd_lds_bytes(int width, int n_hidden);
 // optim.hip
 int reduce_blocks(int n_params);
-hipError_t launch_reduce(const Geo& d, const float* partials, int n_tiles, float inv_scale,
-                         float* grad, const float* loss_part, float inv_count, float* loss_out,
-                         hipStream_t s);
-hipError_t launch_reduce_adam(int precision, const Geo& d, const float* partials, int n_tiles,
+// `native`: the partials use the matrix-core accumulator layout (see
+// k_train_mfma) instead of row-major [out][in].
+hipError_t launch_reduce(const Geo& d, bool native, const float* partials, int n_tiles,
+                         float inv_scale, float* grad, const float* loss_part, float inv_count,
+                         float* loss_out, hipStream_t s);
+hipError_t launch_reduce_adam(int precision, const Geo& d, bool native, const float* partials, int n_tiles,
                               const int32_t* tile_bad, const float* loss_part, float inv_count,
                               float* loss_out, float inv_scale, float* w, float* m, float* v,
-                              int32_t* tslots, int parity, AdamHyper hp, int32_t* skipped_out,
-                              void* ffr, void* bfr, hipStream_t s);
+                              int32_t* tslots, int parity, AdamHyper hp, EmaArgs ema,
+                              int32_t* skipped_out, void* ffr, void* bfr, hipStream_t s);
+// Writes W's forward fragments to ffr and ffr2 (each may be NULL) and its
+// backward fragments to bfr (may be NULL).
 hipError_t launch_build_frags(int precision, const Geo& d, const float* w, void* ffr, void* bfr,
-                              hipStream_t s);
+                              void* ffr2, hipStream_t s);
 
 }  // namespace nrc

@@ -26,15 +26,30 @@ __device__ inline void neumaier_add(float& s, float& c, float x) {
     s = t;
 }
 
+// Layer holding flat index p (weights and partial slots share the ranges).
+__device__ inline int layer_of(const Geo& d, int p) {
+    if (p < d.w_off(1)) return 0;
+    if (p >= d.w_off(d.H)) return d.H;
+    return 1 + (p - d.w_off(1)) / (d.W * d.W);
+}
+
+// Weight index held by partial slot s in the matrix-core accumulator layout:
+// slot w_off(l) + ((mb * NB + nb) * 64 + lane) * 4 + j holds
+// dW_l[16 mb + 4 (lane / 16) + j][16 nb + lane % 16]; the output layer is
+// row-major.
+__device__ inline int param_of_slot(const Geo& d, int s) {
+    const int l = layer_of(d, s);
+    if (l == d.H) return s;
+    const int r = s - d.w_off(l);
+    const int cols = d.cols(l), NB = cols >> 4;
+    const int j = r & 3, lane = (r >> 2) & 63, blk = r >> 8;
+    const int mb = blk / NB, nb = blk - mb * NB;
+    return d.w_off(l) + (16 * mb + 4 * (lane >> 4) + j) * cols + 16 * nb + (lane & 15);
+}
+
 // Locate weight p (flat index) as (layer, row, column).
 __device__ inline void locate(const Geo& d, int p, int& l, int& o, int& k) {
-    if (p < d.w_off(1)) {
-        l = 0;
-    } else if (p >= d.w_off(d.H)) {
-        l = d.H;
-    } else {
-        l = 1 + (p - d.w_off(1)) / (d.W * d.W);
-    }
+    l = layer_of(d, p);
     const int r = p - d.w_off(l);
     const int cols = d.cols(l);
     o = r / cols;
@@ -46,14 +61,14 @@ __device__ inline void write_frags(const Geo& d, int p, float w, T* ffr, T* bfr)
     int l, o, k;
     locate(d, p, l, o, k);
     const T v = (T)w;
-    ffr[fwd_frag_index(d, l, o, k)] = v;
-    bfr[bwd_frag_index(d, l, o, k)] = v;
+    if (ffr) ffr[fwd_frag_index(d, l, o, k)] = v;
+    if (bfr) bfr[bwd_frag_index(d, l, o, k)] = v;
 }
 
 constexpr int kRedParams = 32;   // weights per workgroup
 constexpr int kRedGroups = 8;    // tile groups per workgroup
 
-template <typename T, bool ADAM>
+template <typename T, bool ADAM, bool NATIVE>
 __global__ __launch_bounds__(256) void k_reduce(const float* __restrict__ partials, int n_tiles,
                                                 const int32_t* __restrict__ tile_bad,
                                                 const float* __restrict__ loss_part, float inv_count,
@@ -61,8 +76,9 @@ __global__ __launch_bounds__(256) void k_reduce(const float* __restrict__ partia
                                                 float* __restrict__ grad_out, float* __restrict__ w,
                                                 float* __restrict__ m, float* __restrict__ v,
                                                 int32_t* __restrict__ tslots, int parity, AdamHyper hp,
-                                                int32_t* __restrict__ skipped_out, T* __restrict__ ffr,
-                                                T* __restrict__ bfr, int width, int n_hidden) {
+                                                EmaArgs ema, int32_t* __restrict__ skipped_out,
+                                                T* __restrict__ ffr, T* __restrict__ bfr, int width,
+                                                int n_hidden) {
     __shared__ float s_sum[kRedGroups][kRedParams];
     __shared__ float s_cmp[kRedGroups][kRedParams];
     __shared__ int s_skip;
@@ -70,7 +86,7 @@ __global__ __launch_bounds__(256) void k_reduce(const float* __restrict__ partia
     const int P = d.n_params();
     const int tid = threadIdx.x, lane = tid & 63;
     const int pl = tid % kRedParams, grp = tid / kRedParams;
-    const int p = blockIdx.x * kRedParams + pl;
+    const int sidx = blockIdx.x * kRedParams + pl;          // partial slot (coalesced across lanes)
 
     if (ADAM && tid < 64) {
         int any = 0;
@@ -80,16 +96,16 @@ __global__ __launch_bounds__(256) void k_reduce(const float* __restrict__ partia
         if (tid == 0) s_skip = any;
     }
     float s = 0.0f, c = 0.0f;
-    if (p < P) {
+    if (sidx < P) {
         int t = grp;
         for (; t + 3 * kRedGroups < n_tiles; t += 4 * kRedGroups) {
             float x[4];
             #pragma unroll
-            for (int u = 0; u < 4; ++u) x[u] = partials[(int64_t)(t + u * kRedGroups) * P + p];
+            for (int u = 0; u < 4; ++u) x[u] = partials[(int64_t)(t + u * kRedGroups) * P + sidx];
             #pragma unroll
             for (int u = 0; u < 4; ++u) neumaier_add(s, c, x[u]);
         }
-        for (; t < n_tiles; t += kRedGroups) neumaier_add(s, c, partials[(int64_t)t * P + p]);
+        for (; t < n_tiles; t += kRedGroups) neumaier_add(s, c, partials[(int64_t)t * P + sidx]);
     }
     s_sum[grp][pl] = s;
     s_cmp[grp][pl] = c;
@@ -103,7 +119,8 @@ __global__ __launch_bounds__(256) void k_reduce(const float* __restrict__ partia
         for (int off = 32; off >= 1; off >>= 1) lv += __shfl_xor(lv, off, 64);
         if (lane == 0) *loss_out = lv * inv_count;
     }
-    if (grp != 0 || p >= P) return;   // workgroup 0's thread 0 has p = 0 and stays
+    if (grp != 0 || sidx >= P) return;   // workgroup 0's thread 0 has slot 0 and stays
+    const int p = NATIVE ? param_of_slot(d, sidx) : sidx;
     float gv = 0.0f;
     {
         float S = 0.0f, C = 0.0f;
@@ -135,60 +152,73 @@ __global__ __launch_bounds__(256) void k_reduce(const float* __restrict__ partia
     m[p] = m1;
     v[p] = v1;
     if (ffr != nullptr) write_frags<T>(d, p, w1, ffr, bfr);
+    if (ema.alpha > 0.0f) {
+        // Eq. 2, bias-corrected: E_t = a E_{t-1} + (1 - a) W_t, W_bar_t = E_t / (1 - a^t).
+        const float e1 = ema.alpha * ema.e[p] + (1.0f - ema.alpha) * w1;
+        const float wb = e1 / (1.0f - powf(ema.alpha, (float)t_new));
+        ema.e[p] = e1;
+        ema.wbar[p] = wb;
+        if (ema.effr != nullptr) write_frags<T>(d, p, wb, (T*)ema.effr, (T*)nullptr);
+    }
 }
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_build_frags(const float* __restrict__ w, T* __restrict__ ffr,
-                                                     T* __restrict__ bfr, int width, int n_hidden) {
+                                                     T* __restrict__ bfr, T* __restrict__ ffr2,
+                                                     int width, int n_hidden) {
     const Geo d(width, n_hidden);
     const int p = blockIdx.x * 256 + threadIdx.x;
     if (p >= d.n_params()) return;
     write_frags<T>(d, p, w[p], ffr, bfr);
+    if (ffr2) write_frags<T>(d, p, w[p], ffr2, (T*)nullptr);
 }
 
 }  // namespace
 
 int reduce_blocks(int n_params) { return (n_params + kRedParams - 1) / kRedParams; }
 
-hipError_t launch_reduce(const Geo& d, const float* partials, int n_tiles, float inv_scale,
-                         float* grad, const float* loss_part, float inv_count, float* loss_out,
-                         hipStream_t s) {
-    hipLaunchKernelGGL((k_reduce<_Float16, false>), dim3(reduce_blocks(d.n_params())), dim3(256), 0, s,
-                       partials, n_tiles, (const int32_t*)nullptr, loss_part, inv_count, loss_out,
-                       inv_scale, grad, (float*)nullptr, (float*)nullptr, (float*)nullptr,
-                       (int32_t*)nullptr, 0, AdamHyper{}, (int32_t*)nullptr, (_Float16*)nullptr,
-                       (_Float16*)nullptr, d.W, d.H);
+hipError_t launch_reduce(const Geo& d, bool native, const float* partials, int n_tiles,
+                         float inv_scale, float* grad, const float* loss_part, float inv_count,
+                         float* loss_out, hipStream_t s) {
+    const dim3 grid(reduce_blocks(d.n_params())), block(256);
+    auto k = native ? k_reduce<_Float16, false, true> : k_reduce<_Float16, false, false>;
+    hipLaunchKernelGGL(k, grid, block, 0, s, partials, n_tiles, (const int32_t*)nullptr, loss_part,
+                       inv_count, loss_out, inv_scale, grad, (float*)nullptr, (float*)nullptr,
+                       (float*)nullptr, (int32_t*)nullptr, 0, AdamHyper{}, EmaArgs{},
+                       (int32_t*)nullptr, (_Float16*)nullptr, (_Float16*)nullptr, d.W, d.H);
     return hipGetLastError();
 }
 
-hipError_t launch_reduce_adam(int precision, const Geo& d, const float* partials, int n_tiles,
-                              const int32_t* tile_bad, const float* loss_part, float inv_count,
-                              float* loss_out, float inv_scale, float* w, float* m, float* v,
-                              int32_t* tslots, int parity, AdamHyper hp, int32_t* skipped_out,
-                              void* ffr, void* bfr, hipStream_t s) {
+hipError_t launch_reduce_adam(int precision, const Geo& d, bool native, const float* partials,
+                              int n_tiles, const int32_t* tile_bad, const float* loss_part,
+                              float inv_count, float* loss_out, float inv_scale, float* w, float* m,
+                              float* v, int32_t* tslots, int parity, AdamHyper hp, EmaArgs ema,
+                              int32_t* skipped_out, void* ffr, void* bfr, hipStream_t s) {
     const dim3 grid(reduce_blocks(d.n_params())), block(256);
-    if (precision == NRC_BF16)
-        hipLaunchKernelGGL((k_reduce<__bf16, true>), grid, block, 0, s, partials, n_tiles, tile_bad,
-                           loss_part, inv_count, loss_out, inv_scale, (float*)nullptr, w, m, v, tslots,
-                           parity, hp, skipped_out, (__bf16*)ffr, (__bf16*)bfr, d.W, d.H);
-    else
-        hipLaunchKernelGGL((k_reduce<_Float16, true>), grid, block, 0, s, partials, n_tiles, tile_bad,
-                           loss_part, inv_count, loss_out, inv_scale, (float*)nullptr, w, m, v, tslots,
-                           parity, hp, skipped_out,
-                           precision == NRC_FP16 ? (_Float16*)ffr : (_Float16*)nullptr,
-                           precision == NRC_FP16 ? (_Float16*)bfr : (_Float16*)nullptr, d.W, d.H);
+    if (precision == NRC_BF16) {
+        auto k = native ? k_reduce<__bf16, true, true> : k_reduce<__bf16, true, false>;
+        hipLaunchKernelGGL(k, grid, block, 0, s, partials, n_tiles, tile_bad, loss_part, inv_count,
+                           loss_out, inv_scale, (float*)nullptr, w, m, v, tslots, parity, hp, ema,
+                           skipped_out, (__bf16*)ffr, (__bf16*)bfr, d.W, d.H);
+    } else {
+        // FP32 caches have no reduced-precision copies (ffr, bfr, ema.effr are NULL).
+        auto k = native ? k_reduce<_Float16, true, true> : k_reduce<_Float16, true, false>;
+        hipLaunchKernelGGL(k, grid, block, 0, s, partials, n_tiles, tile_bad, loss_part, inv_count,
+                           loss_out, inv_scale, (float*)nullptr, w, m, v, tslots, parity, hp, ema,
+                           skipped_out, (_Float16*)ffr, (_Float16*)bfr, d.W, d.H);
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_build_frags(int precision, const Geo& d, const float* w, void* ffr, void* bfr,
-                              hipStream_t s) {
+                              void* ffr2, hipStream_t s) {
     const dim3 grid((d.n_params() + 255) / 256), block(256);
     if (precision == NRC_FP16)
         hipLaunchKernelGGL(k_build_frags<_Float16>, grid, block, 0, s, w, (_Float16*)ffr,
-                           (_Float16*)bfr, d.W, d.H);
+                           (_Float16*)bfr, (_Float16*)ffr2, d.W, d.H);
     else if (precision == NRC_BF16)
         hipLaunchKernelGGL(k_build_frags<__bf16>, grid, block, 0, s, w, (__bf16*)ffr, (__bf16*)bfr,
-                           d.W, d.H);
+                           (__bf16*)ffr2, d.W, d.H);
     return hipGetLastError();
 }
 

@@ -40,7 +40,8 @@ class nrc_config(ctypes.Structure):
     _fields_ = [("width", c_int32), ("n_hidden", c_int32), ("n_out", c_int32),
                 ("precision", c_int32), ("enc_preset", c_int32), ("lr", c_float),
                 ("beta1", c_float), ("beta2", c_float), ("adam_eps", c_float),
-                ("loss_eps", c_float), ("loss_scale", c_float), ("seed", c_uint64)]
+                ("loss_eps", c_float), ("loss_scale", c_float), ("ema_alpha", c_float),
+                ("seed", c_uint64)]
 
 
 class nrc_serve_config(ctypes.Structure):
@@ -84,8 +85,11 @@ _decl("nrc_get_state", c_int, _P, POINTER(c_float), POINTER(c_float), POINTER(c_
       POINTER(c_int64), _P)
 _decl("nrc_set_state", c_int, _P, POINTER(c_float), POINTER(c_float), POINTER(c_float), c_int64,
       c_int64, _P)
+_decl("nrc_get_ema", c_int, _P, POINTER(c_float), POINTER(c_float), c_int64, _P)
+_decl("nrc_set_ema", c_int, _P, POINTER(c_float), POINTER(c_float), c_int64, _P)
 _decl("nrc_encode", c_int, _P, _P, c_int, c_int64, _P, _P)
 _decl("nrc_forward", c_int, _P, _P, c_int64, _P, _P)
+_decl("nrc_forward_raw", c_int, _P, _P, c_int, c_int64, _P, _P)
 _decl("nrc_train_step", c_int, _P, _P, _P, c_int64, _P, c_size_t, _P, _P, _P)
 _decl("nrc_backward", c_int, _P, _P, _P, c_int64, _P, c_size_t, _P, _P, _P)
 _decl("nrc_serve_create", c_int, POINTER(nrc_serve_config), POINTER(_P))
@@ -99,7 +103,7 @@ _decl("nrc_serve_destroy", c_int, _P)
 EXPORTED = ["nrc_config_default", "nrc_last_error", "nrc_param_count", "nrc_cache_bytes",
             "nrc_train_scratch_bytes", "nrc_enc_elem_bytes", "nrc_cache_create", "nrc_cache_destroy",
             "nrc_cache_config", "nrc_set_weights", "nrc_get_weights", "nrc_set_weights_device",
-            "nrc_get_state", "nrc_set_state", "nrc_encode", "nrc_forward", "nrc_train_step",
+            "nrc_get_state", "nrc_set_state", "nrc_get_ema", "nrc_set_ema", "nrc_encode", "nrc_forward", "nrc_forward_raw", "nrc_train_step",
             "nrc_backward", "nrc_serve_create", "nrc_serve_set_weights", "nrc_serve_get_weights",
             "nrc_serve_submit", "nrc_serve_poll", "nrc_serve_drain", "nrc_serve_destroy"]
 
@@ -119,13 +123,15 @@ def check(rc: int) -> int:
 # ---------------------------------------------------------------------------
 def make_config(width: int = 64, n_hidden: int = 5, precision="fp16", enc_preset: int = NRC_PRESET_CONFIG,
                 lr: float = 1e-2, beta1: float = 0.9, beta2: float = 0.99, adam_eps: float = 1e-8,
-                loss_eps: float = 0.01, loss_scale: Optional[float] = None) -> nrc_config:
+                loss_eps: float = 0.01, loss_scale: Optional[float] = None,
+                ema_alpha: float = 0.0) -> nrc_config:
     cfg = nrc_config()
     check(lib.nrc_config_default(ctypes.byref(cfg)))
     prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     cfg.width, cfg.n_hidden, cfg.precision, cfg.enc_preset = width, n_hidden, prec, enc_preset
     cfg.lr, cfg.beta1, cfg.beta2, cfg.adam_eps, cfg.loss_eps = lr, beta1, beta2, adam_eps, loss_eps
     cfg.loss_scale = (1.0 if prec == NRC_FP32 else 128.0) if loss_scale is None else loss_scale
+    cfg.ema_alpha = ema_alpha
     return cfg
 
 
@@ -243,6 +249,18 @@ class Cache:
         check(lib.nrc_get_state(self.handle, fp(w), fp(m), fp(v), self.n_params, ctypes.byref(t), _stream(stream)))
         return w, m, v, t.value
 
+    def get_ema(self, stream=None):
+        """(W_bar, E) of a cache created with ema_alpha > 0."""
+        wb, e = (np.empty(self.n_params, dtype=np.float32) for _ in range(2))
+        fp = lambda a: a.ctypes.data_as(POINTER(c_float))
+        check(lib.nrc_get_ema(self.handle, fp(wb), fp(e), self.n_params, _stream(stream)))
+        return wb, e
+
+    def set_ema(self, w_bar, e, stream=None):
+        arrs = [np.ascontiguousarray(np.asarray(a, dtype=np.float32).reshape(-1)) for a in (w_bar, e)]
+        fp = lambda a: a.ctypes.data_as(POINTER(c_float))
+        check(lib.nrc_set_ema(self.handle, fp(arrs[0]), fp(arrs[1]), self.n_params, _stream(stream)))
+
     def set_state(self, w, m, v, t, stream=None):
         arrs = [np.ascontiguousarray(np.asarray(a, dtype=np.float32).reshape(-1)) for a in (w, m, v)]
         fp = lambda a: a.ctypes.data_as(POINTER(c_float))
@@ -270,6 +288,19 @@ def nrc_forward(cache: Cache, enc, rgb=None, stream=None):
         rgb = torch.empty((n, 3), dtype=torch.float32, device=enc.device)
     _need(rgb, torch.float32, (3,), "rgb")
     check(lib.nrc_forward(cache.handle, _ptr(enc), n, _ptr(rgb), _stream(stream)))
+    return rgb
+
+
+def nrc_forward_raw(cache: Cache, raw, layout: int = NRC_RAW14, rgb=None, stream=None):
+    """Fused encode + inference on raw records."""
+    torch = _torch()
+    width = 14 if layout == NRC_RAW14 else 16
+    _need(raw, torch.float32, (width,), "raw")
+    n = raw.shape[0]
+    if rgb is None:
+        rgb = torch.empty((n, 3), dtype=torch.float32, device=raw.device)
+    _need(rgb, torch.float32, (3,), "rgb")
+    check(lib.nrc_forward_raw(cache.handle, _ptr(raw), layout, n, _ptr(rgb), _stream(stream)))
     return rgb
 
 

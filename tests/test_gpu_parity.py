@@ -162,6 +162,30 @@ def test_forward_encoded_records_end_to_end(N, prec):
 
 
 @pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("preset", [0, 1])
+@pytest.mark.parametrize("layout", [0, 1])
+@pytest.mark.parametrize("n", [5000, 4097, 64, 63, 1])
+def test_forward_raw_equals_encode_then_forward(N, prec, preset, layout, n):
+    # The fused kernel rounds the features to the cache precision exactly where
+    # nrc_encode stores them, and each record's products are independent of the
+    # others, so the two paths agree bitwise.
+    c, w = make_cache(N, prec, preset=preset)
+    raw = dev(sd.raw_records(n, 200 + n, layout))
+    fused = N.nrc_forward_raw(c, raw, layout)
+    two_step = N.nrc_forward(c, N.nrc_encode(c, raw, layout))
+    assert torch.equal(fused, two_step)
+    ref = O.predict(state_of(w), O.encode(raw.cpu().numpy(), layout, preset))
+    check_outputs(fused.cpu().numpy(), ref, FWD_TOL[prec], FWD_TOL_MAX[prec])
+
+
+def test_forward_raw_rejects_width128(N):
+    c, _ = make_cache(N, "fp16", width=128)
+    with pytest.raises(N.NrcError) as e:
+        N.nrc_forward_raw(c, dev(sd.raw_records(10, 1)))
+    assert e.value.code == N.NRC_EINVAL
+
+
+@pytest.mark.parametrize("prec", PRECS)
 def test_forward_positive_homogeneity(N, prec):
     # No biases and ReLU: f(2x) = 2 f(x).  Exact in FP32 and BF16 (no subnormals
     # in range); FP16 can round subnormal activations differently.
@@ -362,7 +386,76 @@ def test_full_frame_sampled(N, prec):
     c, w = make_cache(N, prec)
     raw = sd.raw_records(n, sd.SEED_QUERIES)
     rgb = N.nrc_forward(c, N.nrc_encode(c, dev(raw), 0))
+    assert torch.equal(N.nrc_forward_raw(c, dev(raw), 0), rgb)
     idx = np.random.Generator(np.random.PCG64(99)).choice(n, 4096, replace=False)
     idx = np.concatenate([idx, [0, n - 1]])
     got = rgb.cpu().numpy()[idx]
     check_outputs(got, O.predict(state_of(w), O.encode(raw[idx])), FWD_TOL[prec], FWD_TOL_MAX[prec])
+
+
+# ---------------------------------------------------------------------------
+# EMA weight set (Eq. 2), used by the query entry points
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("prec", PRECS)
+def test_ema_queries_follow_oracle(N, prec):
+    c, w = make_cache(N, prec, ema_alpha=0.99)
+    q, q64 = rounded_input(O.encode(sd.raw_records(2048, sd.SEED_HELDOUT)), prec)
+    # before any step the EMA set is the weights that were set
+    st = O.CacheState(w.astype(np.float64), ema_alpha=0.99)
+    check_outputs(N.nrc_forward(c, q).cpu().numpy(), O.predict(st, q64), FWD_TOL[prec], FWD_TOL_MAX[prec])
+    n, steps = 4096, 4
+    raw = sd.raw_records(n * steps, 61)
+    enc = N.nrc_encode(c, dev(raw), 0)
+    e64 = enc.float().cpu().numpy().astype(np.float64)
+    y = sd.targets(raw)
+    yd = dev(y)
+    for s in range(steps):
+        sl = slice(s * n, (s + 1) * n)
+        N.nrc_train_step(c, enc[sl].contiguous(), yd[sl].contiguous())
+        O.train_step(st, e64[sl], y[sl].astype(np.float64))
+    wb, e = c.get_ema()
+    tol_w = 1e-5 if prec == "fp32" else 2e-2
+    assert np.linalg.norm(wb - st.w_bar) / np.linalg.norm(st.w_bar) <= tol_w
+    got = N.nrc_forward(c, q).cpu().numpy()
+    tol = 1e-5 if prec == "fp32" else 1e-2
+    assert np.all(l2_err(got, O.predict_ema(st, q64)) <= tol)
+    # the fused raw path queries the same EMA set
+    rq = dev(sd.raw_records(3000, 62))
+    assert torch.equal(N.nrc_forward_raw(c, rq), N.nrc_forward(c, N.nrc_encode(c, rq)))
+    # training weights are untouched by the EMA: same as a cache without it
+    c2, _ = make_cache(N, prec)
+    for s in range(steps):
+        sl = slice(s * n, (s + 1) * n)
+        N.nrc_train_step(c2, enc[sl].contiguous(), yd[sl].contiguous())
+    assert np.array_equal(c2.get_weights(), c.get_weights())
+
+
+def test_ema_checkpoint_resume_and_skip(N):
+    raw = sd.raw_records(4 * 1024, 63)
+    y = sd.targets(raw)
+
+    def run(c, ks, bad=None):
+        enc = N.nrc_encode(c, dev(raw), 0)
+        for k in ks:
+            yy = y[k * 1024:(k + 1) * 1024].copy()
+            if bad == k:
+                yy[5, 0] = np.inf
+            N.nrc_train_step(c, enc[k * 1024:(k + 1) * 1024], dev(yy))
+        torch.cuda.synchronize()
+
+    a, _ = make_cache(N, "fp16", ema_alpha=0.99)
+    run(a, range(4))
+    b, _ = make_cache(N, "fp16", ema_alpha=0.99)
+    run(b, range(2))
+    st, ema = b.get_state(), b.get_ema()
+    d, _ = make_cache(N, "fp16", ema_alpha=0.99)
+    d.set_state(*st)
+    d.set_ema(*ema)
+    run(d, range(2, 4))
+    for x, z in zip(a.get_ema(), d.get_ema()):
+        assert np.array_equal(x, z)
+    # a skipped step leaves the EMA set unchanged
+    before = d.get_ema()
+    run(d, [1], bad=1)
+    for x, z in zip(before, d.get_ema()):
+        assert np.array_equal(x, z)

@@ -437,3 +437,43 @@ def test_frame_queries_use_start_of_frame_weights_and_disjoint_batches():
     swap[[0, 1023]] = swap[[1023, 0]]
     O.frame(st_b, q, x[swap], y[swap])
     assert not np.allclose(st_b.w, st.w, rtol=1e-9, atol=1e-12)
+
+
+# ----------------------------------------------------------------------------
+# EMA of the weights (Eq. 2)
+# ----------------------------------------------------------------------------
+def test_ema_matches_explicit_weighted_average():
+    # Closed form of the bias-corrected average of W_1..W_t with weights
+    # (1 - a) a^(t-i), normalised by their sum 1 - a^t.
+    a = 0.99
+    rng = np.random.Generator(np.random.PCG64(41))
+    ws = [rng.standard_normal(7) for _ in range(12)]
+    w_bar = np.zeros(7)
+    for t in range(1, 13):
+        w_bar = O.ema_step(w_bar, ws[t - 1], t, a)
+        coef = np.array([(1 - a) * a ** (t - i) for i in range(1, t + 1)])
+        want = (coef[:, None] * np.array(ws[:t])).sum(axis=0) / coef.sum()
+        assert np.allclose(w_bar, want, rtol=1e-12, atol=1e-14)
+        assert coef.sum() == pytest.approx(1 - a ** t, rel=1e-12)
+
+
+def test_ema_first_step_and_constant_weights():
+    w = np.array([0.3, -2.0, 5.0])
+    assert np.allclose(O.ema_step(np.zeros(3), w, 1, 0.99), w, rtol=1e-14)
+    w_bar = np.zeros(3)
+    for t in range(1, 50):
+        w_bar = O.ema_step(w_bar, w, t, 0.99)
+        assert np.allclose(w_bar, w, rtol=1e-12)
+
+
+def test_ema_does_not_feed_back_into_training():
+    raw = sd.raw_records(2048, 3)
+    x, y = O.encode(raw), sd.targets(raw).astype(np.float64)
+    plain = O.CacheState(sd.glorot_weights())
+    ema = O.CacheState(sd.glorot_weights(), ema_alpha=0.99)
+    for k in range(3):
+        O.train_step(plain, x[k * 512:(k + 1) * 512], y[k * 512:(k + 1) * 512])
+        O.train_step(ema, x[k * 512:(k + 1) * 512], y[k * 512:(k + 1) * 512])
+    assert np.array_equal(plain.w, ema.w)
+    assert not np.allclose(ema.w_bar, ema.w)
+    assert np.allclose(O.predict_ema(plain, x[:8]), O.predict(plain, x[:8]))
