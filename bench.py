@@ -42,6 +42,32 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+KERNEL_SOURCES = {"k_fwd_raw_mfma": ["mlp_mfma.hip", "encode_impl.h", "nrc_internal.h"],
+                  "k_fwd_raw_fp32": ["mlp_fp32.hip", "encode_impl.h", "nrc_internal.h"]}
+
+
+def measured_traffic(kernel: str, form: str):
+    """HBM bytes per launch from the rocprofv3 FETCH_SIZE / WRITE_SIZE summary in
+    profiles/, scaled by the copy-kernel calibration recorded there; None when
+    there is none or the kernel's sources changed since it was taken."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES.get(kernel, []):
+        with open(os.path.join(ROOT, "paper_2106_12372_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    digest = h.hexdigest()
+    for path in glob.glob(os.path.join(ROOT, "profiles", "*.md")):
+        with open(path) as fh:
+            for line in fh:
+                if not line.startswith("traffic:"):
+                    continue
+                kv = dict(tok.split("=", 1) for tok in line.split()[1:])
+                if kv.get("kernel") == kernel and kv.get("form") == form and kv.get("src_sha256") == digest:
+                    return float(kv["bytes_per_launch"])
+    return None
+
+
 def frame_bench(form: str, steps: int, warmup: int):
     import torch
     from paper_2106_12372_amd import nrc as N
@@ -129,7 +155,8 @@ def frame_bench(form: str, steps: int, warmup: int):
             "peak": PEAK_TFLOPS[form],
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_TFLOPS[form],
-            "traffic": None,
+            "traffic": measured_traffic("k_fwd_raw_mfma" if form != "fp32" else "k_fwd_raw_fp32", form),
+            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "flop_per_query": FLOP_PER_QUERY,
             "queries_per_launch": N_QUERIES,
             "avg_launch_ms": comp[0],

@@ -15,13 +15,32 @@ constexpr float kPi = 3.14159265358979323846f;
 // fewer significant bits than x.
 __device__ inline float mod2(float x) { return x - 2.0f * floorf(x * 0.5f); }
 
-// Antiderivative of the quartic kernel 15/16 (1 - u^2)^2 on [-1, 1], clamped
-// to 0 below and 1 above.
+// Antiderivative of the quartic kernel 15/16 (1 - u^2)^2 on [-1, 1], 0 below
+// and 1 above.  Clamping u first is branch-free and exact at the ends: with
+// u = +-1 every partial sum of the (dyadic) coefficients is exact, giving 1 and 0.
 __device__ inline float quartic_cdf(float u) {
-    if (u <= -1.0f) return 0.0f;
-    if (u >= 1.0f) return 1.0f;
-    const float u2 = u * u;
-    return 0.5f + u * (0.9375f + u2 * (-0.625f + 0.1875f * u2));
+    const float uc = fminf(fmaxf(u, -1.0f), 1.0f);
+    const float u2 = uc * uc;
+    return 0.5f + uc * (0.9375f + u2 * (-0.625f + 0.1875f * u2));
+}
+
+// sin(pi r) and cos(pi r) for r in [0, 2), branch-free.  r = q/2 + x with
+// q = rint(2r) and |x| <= 1/4 (x exact by Sterbenz); sin and cos of t = pi x
+// come from their Taylor series truncated after t^9 and t^10, whose remainders
+// at |t| <= pi/4 are below 2e-9 and 1.2e-10; the quadrant q mod 4 then swaps
+// and negates them.
+__device__ inline void sincospi_r(float r, float* sn, float* cs) {
+    const float q = rintf(2.0f * r);
+    const float x = r - 0.5f * q;
+    const float t = kPi * x;
+    const float t2 = t * t;
+    const float s = t * (1.0f + t2 * (-1.0f / 6.0f + t2 * (1.0f / 120.0f + t2 * (-1.0f / 5040.0f + t2 * (1.0f / 362880.0f)))));
+    const float c = 1.0f + t2 * (-0.5f + t2 * (1.0f / 24.0f + t2 * (-1.0f / 720.0f + t2 * (1.0f / 40320.0f + t2 * (-1.0f / 3628800.0f)))));
+    const int k = (int)q & 3;
+    const float ss = (k & 1) ? c : s;      // quadrants 1, 3 swap sin and cos
+    const float cc = (k & 1) ? s : c;
+    *sn = (k & 2) ? -ss : ss;              // quadrants 2, 3 negate sin
+    *cs = (k == 1 || k == 2) ? -cc : cc;   // quadrants 1, 2 negate cos
 }
 
 // One-blob encoding with 4 bins on [0,1]: mass of a quartic blob of half-width
@@ -44,7 +63,7 @@ __device__ inline void sph(float x, float y, float z, float& u, float& w) {
 }
 
 // sin and cos of pi * 2^d * p for d = 0 .. NOCT-1.  Octaves 0, 3, 6, 9 are
-// evaluated directly (sincospi of the exactly reduced phase); the two octaves
+// evaluated directly (sincospi_r of the exactly reduced phase); the two octaves
 // after each come from the double-angle identities sin 2a = 2 sin a cos a,
 // cos 2a = (cos a - sin a)(cos a + sin a), which at most quadruple the
 // absolute rounding error (a few 1e-7).
@@ -53,7 +72,7 @@ __device__ inline void octaves(float p, float* sn, float* cs) {
     #pragma unroll
     for (int d = 0; d < NOCT; ++d) {
         if (d % 3 == 0) {
-            sincospif(mod2(p * (float)(1 << d)), &sn[d], &cs[d]);
+            sincospi_r(mod2(p * (float)(1 << d)), &sn[d], &cs[d]);
         } else {
             const float s0 = sn[d - 1], c0 = cs[d - 1];
             sn[d] = 2.0f * s0 * c0;
