@@ -22,29 +22,31 @@ constexpr int kW = 64;      // the FP32 form supports width 64
 constexpr int kLd = 68;     // padded LDS row stride (floats)
 constexpr int kTile = 64;       // training records per workgroup
 
-// The network on one record whose 64 input features are in h (VGPRs); every
-// weight is a wave-uniform operand fetched with scalar loads.
+// One 64 -> 64 ReLU layer on the activations in h (VGPRs); every weight is a
+// wave-uniform operand fetched with scalar loads.
+__device__ inline void layer_fp32(float (&h)[kW], const float* __restrict__ wl) {
+    float z[kW];
+    #pragma unroll
+    for (int o = 0; o < kW; ++o) {
+        float acc = 0.0f;
+        #pragma unroll
+        for (int k = 0; k < kW; ++k) acc = fmaf(wl[o * kW + k], h[k], acc);
+        z[o] = acc;
+    }
+    #pragma unroll
+    for (int o = 0; o < kW; ++o) h[o] = fmaxf(z[o], 0.0f);
+}
+
+// The network on one record whose 64 input features are in h.
 __device__ inline void mlp_fp32(float (&h)[kW], const float* __restrict__ w, int n_hidden,
                                 float (&y)[kNOut]) {
-    const float* wl = w;
-    for (int l = 0; l < n_hidden; ++l) {
-        float z[kW];
-        #pragma unroll
-        for (int o = 0; o < kW; ++o) {
-            float acc = 0.0f;
-            #pragma unroll
-            for (int k = 0; k < kW; ++k) acc = fmaf(wl[o * kW + k], h[k], acc);
-            z[o] = acc;
-        }
-        #pragma unroll
-        for (int o = 0; o < kW; ++o) h[o] = fmaxf(z[o], 0.0f);
-        wl += kW * kW;
-    }
+    for (int l = 0; l < n_hidden; ++l) layer_fp32(h, w + l * kW * kW);
+    const float* wo = w + n_hidden * kW * kW;
     #pragma unroll
     for (int o = 0; o < kNOut; ++o) {
         float acc = 0.0f;
         #pragma unroll
-        for (int k = 0; k < kW; ++k) acc = fmaf(wl[o * kW + k], h[k], acc);
+        for (int k = 0; k < kW; ++k) acc = fmaf(wo[o * kW + k], h[k], acc);
         y[o] = acc;
     }
 }
@@ -136,8 +138,11 @@ __global__ __launch_bounds__(256) void k_train_fp32(const float* __restrict__ w,
     __syncthreads();
 
     // Forward: wave w writes features 16w..16w+15 of every sample (lane = sample).
-    const float* wl = w;
+    // Layer l's weights start at w + l * 64 * 64 (the input layer is 64 x 64
+    // too); addressing them from the base pointer, not a running one, keeps the
+    // scalar register file from spilling.
     for (int l = 0; l < n_hidden; ++l) {
+        const float* wl = w + l * kW * kW;
         const float* hin = hs + l * kTile * kLd + lane * kLd;
         float* hout = hs + (l + 1) * kTile * kLd + lane * kLd;
         float acc[16];
@@ -160,10 +165,9 @@ __global__ __launch_bounds__(256) void k_train_fp32(const float* __restrict__ w,
             *reinterpret_cast<float4*>(hout + 16 * wave + 4 * j4) =
                 make_float4(fmaxf(acc[4 * j4], 0.f), fmaxf(acc[4 * j4 + 1], 0.f),
                             fmaxf(acc[4 * j4 + 2], 0.f), fmaxf(acc[4 * j4 + 3], 0.f));
-        wl += kW * (l == 0 ? kEncWidth : kW);
         __syncthreads();
     }
-    const float* wout = wl;                               // [3][64]
+    const float* wout = w + n_hidden * kW * kW;           // [3][64]
     const float* hlast = hs + n_hidden * kTile * kLd;
 
     // Output layer, loss and dL/dy (wave 0, lane = sample).
