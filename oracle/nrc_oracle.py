@@ -27,6 +27,9 @@ notes):
   tails, so the k values sum to one.
 * Padding (Sec. 3.6): the config preset pads with 0 (roughness enters as is);
   the paper preset encodes 1 - exp(-r) with one-blob and pads with 1.
+* Cheap primitives (Sec. 5): the one-blob kernel is the quartic throughout;
+  the "paper-tri" preset also replaces each sine sin(2^d pi p) by the triangle
+  wave tri(2^d p) of the same period, tri(x) = 2|x mod 2 - 1| - 1 as printed.
 * Architecture (Sec. 5 Architecture): 6 weight matrices, no biases, ReLU after
   each hidden layer, linear output.  ReLU'(0) = 0.
 * Loss (Eq. 5, Sec. 5 Relative loss): per channel (y_hat - y)^2 / (lum^2 + eps)
@@ -63,6 +66,7 @@ RAW14 = 0
 RAW16 = 1
 PRESET_CONFIG = 0
 PRESET_PAPER = 1
+PRESET_PAPER_TRI = 2   # paper preset with the triangle wave in place of sin (Sec. 5)
 
 
 # ---------------------------------------------------------------------------
@@ -76,13 +80,23 @@ def sph(v: np.ndarray) -> np.ndarray:
     return np.stack([theta / np.pi, (phi + np.pi) / (2.0 * np.pi)], axis=1)
 
 
+def tri(x: np.ndarray) -> np.ndarray:
+    """Triangle wave of Sec. 5 (figure "cheap_primitives") standing in for sin(pi x):
+    period 2, in phase with the sine, 2 |(x - 1/2) mod 2 - 1| - 1."""
+    return 2.0 * np.abs(np.mod(x - 0.5, 2.0) - 1.0) - 1.0
+
+
 def freq(p: np.ndarray, preset: int = PRESET_CONFIG) -> np.ndarray:
     """Frequency encoding of positions [n][3] (Sec. 3.6): 12 features per coordinate."""
     p = np.asarray(p, dtype=np.float64)
     n = p.shape[0]
     cols = []
     for c in range(3):
-        if preset == PRESET_PAPER:
+        if preset == PRESET_PAPER_TRI:
+            # the sine of frequency 2^d replaced by the triangle wave of the same period
+            for d in range(PAPER_OCTAVES):
+                cols.append(tri(p[:, c] * 2.0 ** d))
+        elif preset == PRESET_PAPER:
             for d in range(PAPER_OCTAVES):
                 r = np.mod(p[:, c] * 2.0 ** d, 2.0)
                 cols.append(np.sin(np.pi * r))
@@ -129,13 +143,14 @@ def encode(raw: np.ndarray, layout: int = RAW14, preset: int = PRESET_CONFIG) ->
     parts = [freq(pos, preset),
              one_blob(d_sph).reshape(n, 8),
              one_blob(n_sph).reshape(n, 8)]
-    if preset == PRESET_PAPER:
+    paper = preset in (PRESET_PAPER, PRESET_PAPER_TRI)
+    if paper:
         parts.append(one_blob(1.0 - np.exp(-rough[:, 0])).reshape(n, 4))
     else:
         parts.append(rough)
     parts += [diffuse, specular]
     body = np.concatenate(parts, axis=1)
-    pad_value = 1.0 if preset == PRESET_PAPER else 0.0
+    pad_value = 1.0 if paper else 0.0
     pad = np.full((n, ENC_WIDTH - body.shape[1]), pad_value)
     return np.concatenate([body, pad], axis=1)
 

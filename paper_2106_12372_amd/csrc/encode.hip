@@ -62,17 +62,17 @@ hipError_t dispatch_encode(int preset, int layout, const float* raw, int64_t n, 
     const int64_t blocks = (n + kEncBlock - 1) / kEncBlock;
     if (blocks == 0) return hipSuccess;
     const dim3 grid((unsigned)blocks), block(kEncBlock);
-    if (preset == NRC_PRESET_PAPER) {
-        if (layout == NRC_RAW14)
-            hipLaunchKernelGGL((k_encode<T, NRC_PRESET_PAPER, NRC_RAW14>), grid, block, 0, s, raw, n, enc);
-        else
-            hipLaunchKernelGGL((k_encode<T, NRC_PRESET_PAPER, NRC_RAW16>), grid, block, 0, s, raw, n, enc);
+#define NRC_ENC_LAUNCH(PR, LA) \
+    hipLaunchKernelGGL((k_encode<T, PR, LA>), grid, block, 0, s, raw, n, enc)
+    const bool r14 = layout == NRC_RAW14;
+    if (preset == NRC_PRESET_PAPER_TRI) {
+        if (r14) NRC_ENC_LAUNCH(NRC_PRESET_PAPER_TRI, NRC_RAW14); else NRC_ENC_LAUNCH(NRC_PRESET_PAPER_TRI, NRC_RAW16);
+    } else if (preset == NRC_PRESET_PAPER) {
+        if (r14) NRC_ENC_LAUNCH(NRC_PRESET_PAPER, NRC_RAW14); else NRC_ENC_LAUNCH(NRC_PRESET_PAPER, NRC_RAW16);
     } else {
-        if (layout == NRC_RAW14)
-            hipLaunchKernelGGL((k_encode<T, NRC_PRESET_CONFIG, NRC_RAW14>), grid, block, 0, s, raw, n, enc);
-        else
-            hipLaunchKernelGGL((k_encode<T, NRC_PRESET_CONFIG, NRC_RAW16>), grid, block, 0, s, raw, n, enc);
+        if (r14) NRC_ENC_LAUNCH(NRC_PRESET_CONFIG, NRC_RAW14); else NRC_ENC_LAUNCH(NRC_PRESET_CONFIG, NRC_RAW16);
     }
+#undef NRC_ENC_LAUNCH
     return hipGetLastError();
 }
 

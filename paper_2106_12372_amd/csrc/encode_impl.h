@@ -62,6 +62,11 @@ __device__ inline void sph(float x, float y, float z, float& u, float& w) {
     w = (atan2f(y, x) + kPi) * (0.5f * kInvPi);
 }
 
+// Triangle wave of Sec. 5 ("cheap primitives") in place of sin(pi x): period 2,
+// in phase with the sine, 2 |(x - 1/2) mod 2 - 1| - 1.  For the positions used
+// here x - 1/2 is exact unless |x| < 1/4, where its rounding is below 2^-26.
+__device__ inline float tri(float x) { return 2.0f * fabsf(mod2(x - 0.5f) - 1.0f) - 1.0f; }
+
 // sin and cos of pi * 2^d * p for d = 0 .. NOCT-1.  Octaves 0, 3, 6, 9 are
 // evaluated directly (sincospi_r of the exactly reduced phase); the two octaves
 // after each come from the double-angle identities sin 2a = 2 sin a cos a,
@@ -87,11 +92,16 @@ __device__ inline void octaves(float p, float* sn, float* cs) {
 //   albedo (7), five zeros.
 //   paper preset: 12 sines per coordinate (36), one-blob of the angles (16),
 //   one-blob of 1 - exp(-roughness) (4), albedos (6), two ones.
+//   paper-tri preset: as paper with tri(2^d p) in place of sin(2^d pi p).
 template <int PRESET, int LAYOUT>
 __device__ inline void encode_record(const float* x, float* o) {
+    constexpr bool paper = PRESET == NRC_PRESET_PAPER || PRESET == NRC_PRESET_PAPER_TRI;
     #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        if (PRESET == NRC_PRESET_PAPER) {
+        if (PRESET == NRC_PRESET_PAPER_TRI) {
+            #pragma unroll
+            for (int d = 0; d < 12; ++d) o[12 * c + d] = tri(x[c] * (float)(1 << d));
+        } else if (PRESET == NRC_PRESET_PAPER) {
             float sn[12], cs[12];
             octaves<12>(x[c], sn, cs);
             #pragma unroll
@@ -118,7 +128,7 @@ __device__ inline void encode_record(const float* x, float* o) {
     }
     #pragma unroll
     for (int a = 0; a < 4; ++a) one_blob4(ang[a], o + 36 + 4 * a);
-    if (PRESET == NRC_PRESET_PAPER) {
+    if (paper) {
         one_blob4(1.0f - expf(-rest[0]), o + 52);
         #pragma unroll
         for (int j = 0; j < 6; ++j) o[56 + j] = rest[1 + j];

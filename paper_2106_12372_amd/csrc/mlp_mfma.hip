@@ -555,6 +555,9 @@ hipError_t fwd_raw_launch(const Geo& d, const void* ffr, const float* raw, int64
 template <typename T, int W>
 hipError_t fwd_raw_dispatch(const Geo& d, int preset, int layout, const void* ffr, const float* raw,
                             int64_t n, float* rgb, hipStream_t s) {
+    if (preset == NRC_PRESET_PAPER_TRI)
+        return layout == NRC_RAW14 ? fwd_raw_launch<T, W, NRC_PRESET_PAPER_TRI, NRC_RAW14>(d, ffr, raw, n, rgb, s)
+                                   : fwd_raw_launch<T, W, NRC_PRESET_PAPER_TRI, NRC_RAW16>(d, ffr, raw, n, rgb, s);
     if (preset == NRC_PRESET_PAPER)
         return layout == NRC_RAW14 ? fwd_raw_launch<T, W, NRC_PRESET_PAPER, NRC_RAW14>(d, ffr, raw, n, rgb, s)
                                    : fwd_raw_launch<T, W, NRC_PRESET_PAPER, NRC_RAW16>(d, ffr, raw, n, rgb, s);

@@ -477,3 +477,42 @@ def test_ema_does_not_feed_back_into_training():
     assert np.array_equal(plain.w, ema.w)
     assert not np.allclose(ema.w_bar, ema.w)
     assert np.allclose(O.predict_ema(plain, x[:8]), O.predict(plain, x[:8]))
+
+
+# ----------------------------------------------------------------------------
+# Triangle wave (Sec. 5, cheap primitives)
+# ----------------------------------------------------------------------------
+def test_triangle_wave_closed_form():
+    # The triangle wave through the extrema and zeros of sin(pi x): period 2,
+    # tri(0) = 0, tri(1/2) = 1, tri(1) = 0, tri(3/2) = -1, linear in between
+    # (slope +2 on [-1/2, 1/2], -2 on [1/2, 3/2]).
+    x = np.array([0.0, 0.25, 0.5, 0.75, 1.0, 1.5, 2.0, 2.25, -0.5, 7.0, 7.5])
+    want = np.array([0.0, 0.5, 1.0, 0.5, 0.0, -1.0, 0.0, 0.5, -1.0, 0.0, -1.0])
+    assert np.allclose(O.tri(x), want, atol=1e-15)
+    t = np.linspace(-0.5, 0.5, 101)
+    assert np.allclose(O.tri(t), 2.0 * t, atol=1e-14)
+    assert np.allclose(O.tri(t + 1.0), -2.0 * t, atol=1e-14)
+    # agrees with sin(pi x) at every multiple of 1/2 and has its sign everywhere
+    h = np.arange(-8, 9) * 0.5
+    assert np.allclose(O.tri(h), np.round(np.sin(np.pi * h), 12), atol=1e-15)
+    y = np.linspace(-3.0, 3.0, 6001)
+    s = np.round(np.sin(np.pi * y), 12)
+    assert np.array_equal(np.sign(np.round(O.tri(y), 12)), np.sign(s))
+    assert np.all(np.abs(O.tri(y)) <= np.abs(s) + 1e-12)   # sin lies above its chords (concave)
+
+
+def test_encode_paper_tri_preset_layout():
+    raw = sd.raw_records(64, 90)
+    a = O.encode(raw, preset=O.PRESET_PAPER)
+    b = O.encode(raw, preset=O.PRESET_PAPER_TRI)
+    r = raw.astype(np.float64)
+    for c in range(3):
+        for d in range(12):
+            x = 2 ** d * r[:, c]
+            # with k the nearest integer to x: rising edge 2 (x - k) for even k,
+            # falling edge -2 (x - k) for odd k
+            k = np.floor(x + 0.5)                      # nearest integer
+            frac = x - k                               # in [-1/2, 1/2)
+            want = np.where(np.mod(k, 2) == 0, 2 * frac, -2 * frac)
+            assert np.allclose(b[:, 12 * c + d], want, atol=1e-12)
+    assert np.array_equal(a[:, 36:], b[:, 36:])          # everything after the position is shared
