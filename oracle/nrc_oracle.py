@@ -29,7 +29,8 @@ notes):
   the paper preset encodes 1 - exp(-r) with one-blob and pads with 1.
 * Cheap primitives (Sec. 5): the one-blob kernel is the quartic throughout;
   the "paper-tri" preset also replaces each sine sin(2^d pi p) by the triangle
-  wave tri(2^d p) of the same period, tri(x) = 2|x mod 2 - 1| - 1 as printed.
+  wave of the same period and phase, tri(x) = 2|(x - 1/2) mod 2 - 1| - 1, which
+  meets sin(pi x) at every multiple of 1/2.
 * Architecture (Sec. 5 Architecture): 6 weight matrices, no biases, ReLU after
   each hidden layer, linear output.  ReLU'(0) = 0.
 * Loss (Eq. 5, Sec. 5 Relative loss): per channel (y_hat - y)^2 / (lum^2 + eps)
@@ -45,6 +46,11 @@ notes):
   W_bar_t = [(1 - a) W_t + a eta_{t-1} W_bar_{t-1}] / eta_t, eta_t = 1 - a^t,
   i.e. W_bar_t = E_t / eta_t with E_t = a E_{t-1} + (1 - a) W_t, E_0 = 0.  It
   advances only on steps that update the weights and never feeds back.
+* Reflectance factorisation (Sec. 5): the cache's prediction is the network
+  output times alpha + beta, per channel; alpha and beta are the identity-
+  encoded diffuse and specular albedo columns of the network input itself, so
+  the factor is a function of the input row.  The loss (Eq. 5, luminance of
+  the factorised prediction) and its gradient act on the factorised value.
 """
 from __future__ import annotations
 
@@ -67,6 +73,13 @@ RAW16 = 1
 PRESET_CONFIG = 0
 PRESET_PAPER = 1
 PRESET_PAPER_TRI = 2   # paper preset with the triangle wave in place of sin (Sec. 5)
+
+
+def albedo_columns(preset: int):
+    """Columns of the diffuse and specular albedo in the encoded row (Sec. 3.6
+    concatenation order): after roughness at 52 (config), after the roughness
+    one-blob at 52..55 (paper)."""
+    return (56, 59) if preset in (PRESET_PAPER, PRESET_PAPER_TRI) else (53, 56)
 
 
 # ---------------------------------------------------------------------------
@@ -246,6 +259,8 @@ class CacheState:
     loss_eps: float = LOSS_EPS
     ema_alpha: float = 0.0      # Sec. 3.4 uses 0.99; 0 disables the EMA set
     w_bar: np.ndarray = None
+    factorize: bool = False     # Sec. 5 reflectance factorisation
+    preset: int = PRESET_CONFIG  # encoding preset: where the albedo columns sit
 
     def __post_init__(self):
         self.w = np.asarray(self.w, dtype=np.float64).copy()
@@ -262,8 +277,19 @@ class CacheState:
         return out
 
 
+def reflectance(enc: np.ndarray, preset: int) -> np.ndarray:
+    """alpha + beta per channel (Sec. 5 Reflectance factorization), [n][3]."""
+    enc = np.asarray(enc, dtype=np.float64)
+    a, b = albedo_columns(preset)
+    return enc[:, a:a + 3] + enc[:, b:b + 3]
+
+
 def predict(state: CacheState, enc: np.ndarray) -> np.ndarray:
-    return forward(state.mats(), enc)[0]
+    """Cache query: the network output, times alpha + beta when factorised."""
+    out = forward(state.mats(), enc)[0]
+    if state.factorize:
+        out = out * reflectance(enc, state.preset)
+    return out
 
 
 def ema_step(w_bar_prev: np.ndarray, w: np.ndarray, t: int, alpha: float) -> np.ndarray:
@@ -274,12 +300,32 @@ def ema_step(w_bar_prev: np.ndarray, w: np.ndarray, t: int, alpha: float) -> np.
 
 
 def gradient(state: CacheState, enc: np.ndarray, y: np.ndarray):
-    """Loss and flat weight gradient of one batch (Eq. 5 through the network)."""
+    """Loss and flat weight gradient of one batch (Eq. 5 through the network).
+    Factorised: y_hat = f * R with R = alpha + beta, so dL/df = dL/dy_hat * R."""
     mats = state.mats()
-    y_hat, hs = forward(mats, enc)
-    loss, d_out = relative_l2(y_hat, y, state.loss_eps)
-    grads, _ = backward(mats, hs, d_out)
+    f, hs = forward(mats, enc)
+    r = reflectance(enc, state.preset) if state.factorize else 1.0
+    loss, d_out = relative_l2(f * r, y, state.loss_eps)
+    grads, _ = backward(mats, hs, d_out * r)
     return loss, np.concatenate([g.reshape(-1) for g in grads])
+
+
+def query_gradient(state: CacheState, enc: np.ndarray, grad_out: np.ndarray):
+    """Gradients of a scalar whose gradient with respect to the cache's
+    prediction is `grad_out` [n][3]: (flat weight gradient, input gradient
+    [n][64]).  Factorised, the input gradient also takes d(f R)/dR = f on each
+    albedo column."""
+    mats = state.mats()
+    f, hs = forward(mats, enc)
+    grad_out = np.asarray(grad_out, dtype=np.float64)
+    if not state.factorize:
+        grads, g_in = backward(mats, hs, grad_out)
+    else:
+        grads, g_in = backward(mats, hs, grad_out * reflectance(enc, state.preset))
+        a, b = albedo_columns(state.preset)
+        g_in[:, a:a + 3] += grad_out * f
+        g_in[:, b:b + 3] += grad_out * f
+    return np.concatenate([g.reshape(-1) for g in grads]), g_in
 
 
 def train_step(state: CacheState, enc: np.ndarray, y: np.ndarray):
@@ -298,7 +344,8 @@ def train_step(state: CacheState, enc: np.ndarray, y: np.ndarray):
 def predict_ema(state: CacheState, enc: np.ndarray) -> np.ndarray:
     """Cache query with the EMA weights (Sec. 3.4): the set used for rendering."""
     w = state.w_bar if state.w_bar is not None else state.w
-    return forward(CacheState(w, width=state.width, n_hidden=state.n_hidden).mats(), enc)[0]
+    return predict(CacheState(w, width=state.width, n_hidden=state.n_hidden,
+                              factorize=state.factorize, preset=state.preset), enc)
 
 
 def frame(state: CacheState, query_enc: np.ndarray, record_enc: np.ndarray,

@@ -67,6 +67,27 @@ def _adam_no_bias_correction(w, m, v, t, g, cfg):
     return w - cfg.lr * m / (np.sqrt(v) + cfg.eps), m, v, t
 
 
+def _reflectance_shifted_columns(enc, preset):
+    a, b = O.albedo_columns(preset)
+    enc = np.asarray(enc, float)
+    return enc[:, a - 1:a + 2] + enc[:, b - 1:b + 2]
+
+
+def _query_gradient_no_albedo_term(state, enc, grad_out):
+    f, hs = O.forward(state.mats(), enc)
+    grads, g_in = O.backward(state.mats(), hs, np.asarray(grad_out) * O.reflectance(enc, state.preset))
+    return np.concatenate([g.reshape(-1) for g in grads]), g_in
+
+
+def _gradient_factor_dropped(state, enc, y):
+    # the loss sees f R but the gradient ignores R on the way back
+    f, hs = O.forward(state.mats(), enc)
+    r = O.reflectance(enc, state.preset) if state.factorize else 1.0
+    loss, d_out = O.relative_l2(f * r, y, state.loss_eps)
+    grads, _ = O.backward(state.mats(), hs, d_out)
+    return loss, np.concatenate([g.reshape(-1) for g in grads])
+
+
 MUTANTS = [
     ("freq", _freq_no_pi, [P.test_freq_matches_libm_closed_form, P.test_freq_dyadic_points_exact]),
     ("one_blob", _one_blob_no_tails, [P.test_one_blob_exact_dyadic_fixture, P.test_one_blob_invariants]),
@@ -77,6 +98,9 @@ MUTANTS = [
     ("backward", _backward_no_mask, [P.test_backward_central_differences_weights_and_inputs]),
     ("adam", _adam_swapped_betas, [P.test_adam_matches_torch_optim_fp64]),
     ("adam", _adam_no_bias_correction, [P.test_adam_constant_gradient_closed_form]),
+    ("reflectance", _reflectance_shifted_columns, [P.test_factorised_prediction_scales_by_raw_albedos]),
+    ("query_gradient", _query_gradient_no_albedo_term, [P.test_factorised_query_gradient_central_differences]),
+    ("gradient", _gradient_factor_dropped, [P.test_factorised_train_gradient_central_differences]),
 ]
 
 

@@ -516,3 +516,112 @@ def test_encode_paper_tri_preset_layout():
             want = np.where(np.mod(k, 2) == 0, 2 * frac, -2 * frac)
             assert np.allclose(b[:, 12 * c + d], want, atol=1e-12)
     assert np.array_equal(a[:, 36:], b[:, 36:])          # everything after the position is shared
+
+
+# ----------------------------------------------------------------------------
+# Reflectance factorisation (Sec. 5): prediction = network output * (alpha + beta)
+# ----------------------------------------------------------------------------
+def _small_state(factorize, preset=O.PRESET_CONFIG, seed=0):
+    return O.CacheState(sd.glorot_weights(width=8, n_hidden=2, seed=seed), width=8, n_hidden=2,
+                        factorize=factorize, preset=preset)
+
+
+def test_factorised_prediction_scales_by_raw_albedos():
+    # The factor comes from the raw record's diffuse (fields 8..10) and specular
+    # (11..13) albedo, whichever columns the preset puts them in.
+    raw = sd.raw_records(64, 91)
+    r = raw[:, 8:11].astype(np.float64) + raw[:, 11:14].astype(np.float64)
+    for preset in (O.PRESET_CONFIG, O.PRESET_PAPER, O.PRESET_PAPER_TRI):
+        x = O.encode(raw, preset=preset)
+        plain = O.predict(_small_state(False, preset), x)
+        fact = O.predict(_small_state(True, preset), x)
+        assert np.allclose(fact, plain * r, rtol=1e-14, atol=0)
+        assert np.array_equal(O.reflectance(x, preset), r)
+
+
+def test_factorisation_with_unit_reflectance_is_the_identity():
+    raw = sd.raw_records(32, 92).copy()
+    raw[:, 8:11] = 0.25
+    raw[:, 11:14] = 0.75
+    x = O.encode(raw)
+    y = sd.targets(raw).astype(np.float64)
+    assert np.array_equal(O.predict(_small_state(True), x), O.predict(_small_state(False), x))
+    la, ga = O.gradient(_small_state(True), x, y)
+    lb, gb = O.gradient(_small_state(False), x, y)
+    assert la == lb and np.array_equal(ga, gb)
+
+
+def _masks(st, x):
+    return [hh > 0 for hh in O.forward(st.mats(), x)[1][1:]]
+
+
+def test_factorised_query_gradient_central_differences():
+    # L = sum G * y_hat.  Along any one weight or input coordinate (ReLU masks
+    # fixed) y_hat = f R is at most quadratic, so central differences are exact
+    # up to rounding, albedo columns included.
+    raw = sd.raw_records(12, 93)
+    x = O.encode(raw)
+    g_out = np.random.Generator(np.random.PCG64(94)).standard_normal((12, 3))
+    st = _small_state(True)
+    gw, gx = O.query_gradient(st, x, g_out)
+    h = 1e-3
+    base = _masks(st, x)
+
+    def lossf(s, xx):
+        return float((g_out * O.predict(s, xx)).sum())
+
+    rng = np.random.Generator(np.random.PCG64(95))
+    ok = 0
+    for k in rng.choice(gw.size, 80, replace=False):
+        a, b = _small_state(True), _small_state(True)
+        a.w[k] += h
+        b.w[k] -= h
+        if any((p != q).any() for p, q in zip(_masks(a, x), base)) or \
+           any((p != q).any() for p, q in zip(_masks(b, x), base)):
+            continue
+        assert gw[k] == pytest.approx((lossf(a, x) - lossf(b, x)) / (2 * h), rel=1e-7, abs=1e-10)
+        ok += 1
+    assert ok > 40
+    cols = list(range(36, 64))   # one-blob, roughness, both albedos, padding
+    ok = 0
+    for i in range(12):
+        for j in cols:
+            xp, xm = x.copy(), x.copy()
+            xp[i, j] += h
+            xm[i, j] -= h
+            if any((p != q).any() for p, q in zip(_masks(st, xp), base)) or \
+               any((p != q).any() for p, q in zip(_masks(st, xm), base)):
+                continue
+            fd = (lossf(st, xp) - lossf(st, xm)) / (2 * h)
+            assert gx[i, j] == pytest.approx(fd, rel=1e-7, abs=1e-10)
+            ok += 1
+    assert ok > 200
+
+
+def test_factorised_train_gradient_central_differences():
+    # Eq. 5 on the factorised prediction, denominator held at its unperturbed value.
+    raw = sd.raw_records(16, 96)
+    x, y = O.encode(raw), sd.targets(raw).astype(np.float64)
+    st = _small_state(True)
+    loss, g = O.gradient(st, x, y)
+    yh = O.predict(st, x)
+    den = yh.mean(axis=1, keepdims=True) ** 2 + 0.01
+    assert loss == pytest.approx(float(((yh - y) ** 2 / den).mean()), rel=1e-13)
+    h = 1e-3
+    base = _masks(st, x)
+
+    def frozen(s):
+        return float(((O.predict(s, x) - y) ** 2 / den).sum() / (3 * x.shape[0]))
+
+    rng = np.random.Generator(np.random.PCG64(97))
+    ok = 0
+    for k in rng.choice(g.size, 60, replace=False):
+        a, b = _small_state(True), _small_state(True)
+        a.w[k] += h
+        b.w[k] -= h
+        if any((p != q).any() for p, q in zip(_masks(a, x), base)) or \
+           any((p != q).any() for p, q in zip(_masks(b, x), base)):
+            continue
+        assert g[k] == pytest.approx((frozen(a) - frozen(b)) / (2 * h), rel=1e-7, abs=1e-10)
+        ok += 1
+    assert ok > 30
