@@ -87,13 +87,18 @@ typedef struct nrc_config {
     float loss_eps;
     float loss_scale;
     float ema_alpha; /* EMA of the weights (Eq. 2); 0 disables, the paper uses 0.99 */
+    int32_t factorize; /* 1: reflectance factorisation (Sec. 5): the prediction is the
+                        * network output times (diffuse + specular albedo), per channel,
+                        * both read from the encoded row (config preset: columns 53..55
+                        * and 56..58; paper presets: 56..58 and 59..61).  Training,
+                        * the loss and the gradients then act on the factorised value. */
     uint64_t seed;   /* reserved; weights are always set explicitly */
 } nrc_config;
 
 typedef struct nrc_cache nrc_cache;
 
 /* Fills *cfg with the defaults: 64, 5, 3, FP16, CONFIG, 1e-2, 0.9, 0.99, 1e-8,
- * 0.01, 128, 0 (no EMA), 0.  Returns NRC_EINVAL on NULL. */
+ * 0.01, 128, 0 (no EMA), 0 (no factorisation), 0.  Returns NRC_EINVAL on NULL. */
 int nrc_config_default(nrc_config* cfg);
 
 /* Message describing the last failure on the calling thread ("" if none).

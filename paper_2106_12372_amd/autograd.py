@@ -43,9 +43,11 @@ class NRCModule(torch.nn.Module):
     """The cache network as a torch module: weights are one flat Parameter."""
 
     def __init__(self, width: int = 64, n_hidden: int = 5, precision: str = "fp16",
-                 weights: np.ndarray | None = None, device=None):
+                 weights: np.ndarray | None = None, device=None, **config):
+        """config: further nrc_config fields (enc_preset, factorize, ...)."""
         super().__init__()
-        self.cache = N.Cache(N.make_config(width=width, n_hidden=n_hidden, precision=precision), device=device)
+        self.cache = N.Cache(N.make_config(width=width, n_hidden=n_hidden, precision=precision, **config),
+                             device=device)
         w = sd.glorot_weights(width, n_hidden) if weights is None else np.asarray(weights, np.float32)
         self.weights = torch.nn.Parameter(torch.from_numpy(w.copy()).to(self.cache.device))
 

@@ -51,9 +51,17 @@ __device__ inline void mlp_fp32(float (&h)[kW], const float* __restrict__ w, int
     }
 }
 
+// Output of one query: the network output times the reflectance factor.
+__device__ inline void store_query(float* __restrict__ rgb, int64_t s, const float (&y)[kNOut],
+                                   const float (&r)[kNOut]) {
+    rgb[s * 3 + 0] = y[0] * r[0];
+    rgb[s * 3 + 1] = y[1] * r[1];
+    rgb[s * 3 + 2] = y[2] * r[2];
+}
+
 __global__ __launch_bounds__(256) void k_fwd_fp32(const float* __restrict__ w,
                                                   const float* __restrict__ enc, int64_t n,
-                                                  float* __restrict__ rgb, int n_hidden) {
+                                                  float* __restrict__ rgb, int n_hidden, int fcol) {
     const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (s >= n) return;
     float h[kW];
@@ -63,11 +71,10 @@ __global__ __launch_bounds__(256) void k_fwd_fp32(const float* __restrict__ w,
         const float4 v = row[q];
         h[4 * q] = v.x; h[4 * q + 1] = v.y; h[4 * q + 2] = v.z; h[4 * q + 3] = v.w;
     }
-    float y[kNOut];
+    float r[kNOut], y[kNOut];
+    reflectance_row(h, fcol, r);
     mlp_fp32(h, w, n_hidden, y);
-    rgb[s * 3 + 0] = y[0];
-    rgb[s * 3 + 1] = y[1];
-    rgb[s * 3 + 2] = y[2];
+    store_query(rgb, s, y, r);
 }
 
 // Inference from raw records with the encoding fused in: each lane encodes its
@@ -75,7 +82,7 @@ __global__ __launch_bounds__(256) void k_fwd_fp32(const float* __restrict__ w,
 template <int PRESET, int LAYOUT>
 __global__ __launch_bounds__(256) void k_fwd_raw_fp32(const float* __restrict__ w,
                                                       const float* __restrict__ raw, int64_t n,
-                                                      float* __restrict__ rgb, int n_hidden) {
+                                                      float* __restrict__ rgb, int n_hidden, int fcol) {
     constexpr int RW = LAYOUT == NRC_RAW14 ? 14 : 16;
     const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (s >= n) return;
@@ -88,11 +95,10 @@ __global__ __launch_bounds__(256) void k_fwd_raw_fp32(const float* __restrict__ 
     }
     float h[kW];
     encode_record<PRESET, LAYOUT>(x, h);
-    float y[kNOut];
+    float r[kNOut], y[kNOut];
+    reflectance_row(h, fcol, r);
     mlp_fp32(h, w, n_hidden, y);
-    rgb[s * 3 + 0] = y[0];
-    rgb[s * 3 + 1] = y[1];
-    rgb[s * 3 + 2] = y[2];
+    store_query(rgb, s, y, r);
 }
 
 // Fixed-order sum over the 64 lanes of a wave (same tree on every call).
@@ -104,6 +110,9 @@ __device__ inline float wave_sum(float v) {
 
 // UPSTREAM = false: targets given, relative L2 loss (Eq. 5) produces dL/dy.
 // UPSTREAM = true : tgt holds an upstream gradient dL/dy directly.
+// With the reflectance factorisation (fcol != 0) y is the network output times
+// R = alpha + beta; the network's output gradient is dL/dy * R, and dL/denc
+// also takes dL/dy_c * f_c on both albedo columns of channel c.
 template <bool UPSTREAM, bool GENC>
 __global__ __launch_bounds__(256) void k_train_fp32(const float* __restrict__ w,
                                                     const float* __restrict__ enc,
@@ -112,12 +121,13 @@ __global__ __launch_bounds__(256) void k_train_fp32(const float* __restrict__ w,
                                                     float grad_scale, float* __restrict__ partials,
                                                     float* __restrict__ loss_part,
                                                     int32_t* __restrict__ tile_bad,
-                                                    float* __restrict__ genc) {
+                                                    float* __restrict__ genc, int fcol) {
     extern __shared__ __attribute__((aligned(16))) float smem[];
     float* hs = smem;                                     // (n_hidden+1) x [64][kLd]
     float* dbuf0 = hs + (n_hidden + 1) * kTile * kLd;     // 2 x [64][kLd]
     float* dbuf1 = dbuf0 + kTile * kLd;
-    float* dout = dbuf1 + kTile * kLd;                    // [64][4]
+    float* dout = dbuf1 + kTile * kLd;                    // [64][4]: dL/d(network output)
+    float* fout = dout + kTile * 4;                       // [64][4]: network output
 
     // The wave index is uniform across the wave; saying so lets weight
     // addresses that depend on it use scalar loads.
@@ -172,32 +182,42 @@ __global__ __launch_bounds__(256) void k_train_fp32(const float* __restrict__ w,
 
     // Output layer, loss and dL/dy (wave 0, lane = sample).
     if (wave == 0) {
-        float y[kNOut] = {0.f, 0.f, 0.f};
+        float f[kNOut] = {0.f, 0.f, 0.f};
         const float* hr = hlast + lane * kLd;
         #pragma unroll
         for (int k = 0; k < kW; ++k) {
             const float hv = hr[k];
             #pragma unroll
-            for (int o = 0; o < kNOut; ++o) y[o] = fmaf(wout[o * kW + k], hv, y[o]);
+            for (int o = 0; o < kNOut; ++o) f[o] = fmaf(wout[o * kW + k], hv, f[o]);
+        }
+        float r[kNOut] = {1.f, 1.f, 1.f};
+        if (fcol) {
+            const float* h0 = hs + lane * kLd;
+            #pragma unroll
+            for (int o = 0; o < kNOut; ++o) r[o] = h0[fcol + o] + h0[fcol + 3 + o];
         }
         float d[kNOut] = {0.f, 0.f, 0.f};
         float lterm = 0.0f;
         if (valid) {
             if (UPSTREAM) {
                 #pragma unroll
-                for (int o = 0; o < kNOut; ++o) d[o] = tgt[row * 3 + o] * grad_scale;
+                for (int o = 0; o < kNOut; ++o) d[o] = tgt[row * 3 + o] * grad_scale * r[o];
             } else {
+                float y[kNOut];
+                #pragma unroll
+                for (int o = 0; o < kNOut; ++o) y[o] = f[o] * r[o];
                 const float lum = (y[0] + y[1] + y[2]) * (1.0f / 3.0f);
                 const float inv_den = 1.0f / (lum * lum + loss_eps);
                 #pragma unroll
                 for (int o = 0; o < kNOut; ++o) {
                     const float diff = y[o] - tgt[row * 3 + o];
                     lterm = fmaf(diff * diff, inv_den, lterm);
-                    d[o] = 2.0f * diff * inv_den * grad_scale;
+                    d[o] = 2.0f * diff * inv_den * grad_scale * r[o];
                 }
             }
         }
         *reinterpret_cast<float4*>(dout + lane * 4) = make_float4(d[0], d[1], d[2], 0.f);
+        if (GENC) *reinterpret_cast<float4*>(fout + lane * 4) = make_float4(f[0], f[1], f[2], 0.f);
         const float tot = wave_sum(lterm);
         if (lane == 0) loss_part[tile] = tot;
     }
@@ -282,6 +302,17 @@ __global__ __launch_bounds__(256) void k_train_fp32(const float* __restrict__ w,
                 #pragma unroll
                 for (int j = 0; j < 16; ++j) dst[j] = hr[j] > 0.0f ? acc[j] : 0.0f;
             } else if (valid) {
+                if (fcol) {
+                    // d(f_c R_c)/d(albedo column) = f_c on the diffuse and specular column.
+                    #pragma unroll
+                    for (int j = 0; j < 16; ++j) {
+                        int c = 16 * wave + j - fcol;
+                        if (c >= 0 && c < 6) {
+                            c = c >= 3 ? c - 3 : c;
+                            acc[j] = fmaf(tgt[row * 3 + c], fout[lane * 4 + c], acc[j]);
+                        }
+                    }
+                }
                 #pragma unroll
                 for (int j4 = 0; j4 < 4; ++j4)
                     *reinterpret_cast<float4*>(genc + row * kEncWidth + 16 * wave + 4 * j4) =
@@ -302,7 +333,7 @@ hipError_t launch_fwd_fp32(const Geo& d, const float* w, const float* enc, int64
     const int64_t blocks = (n + 255) / 256;
     if (blocks == 0) return hipSuccess;
     hipLaunchKernelGGL(k_fwd_fp32, dim3((unsigned)blocks), dim3(256), 0, s, w, enc, n, rgb,
-                       d.H);
+                       d.H, d.F);
     return hipGetLastError();
 }
 
@@ -313,25 +344,25 @@ hipError_t launch_fwd_raw_fp32(const Geo& d, int preset, int layout, const float
     const dim3 grid((unsigned)blocks), block(256);
     if (preset == NRC_PRESET_PAPER_TRI) {
         if (layout == NRC_RAW14)
-            hipLaunchKernelGGL((k_fwd_raw_fp32<NRC_PRESET_PAPER_TRI, NRC_RAW14>), grid, block, 0, s, w, raw, n, rgb, d.H);
+            hipLaunchKernelGGL((k_fwd_raw_fp32<NRC_PRESET_PAPER_TRI, NRC_RAW14>), grid, block, 0, s, w, raw, n, rgb, d.H, d.F);
         else
-            hipLaunchKernelGGL((k_fwd_raw_fp32<NRC_PRESET_PAPER_TRI, NRC_RAW16>), grid, block, 0, s, w, raw, n, rgb, d.H);
+            hipLaunchKernelGGL((k_fwd_raw_fp32<NRC_PRESET_PAPER_TRI, NRC_RAW16>), grid, block, 0, s, w, raw, n, rgb, d.H, d.F);
     } else if (preset == NRC_PRESET_PAPER) {
         if (layout == NRC_RAW14)
-            hipLaunchKernelGGL((k_fwd_raw_fp32<NRC_PRESET_PAPER, NRC_RAW14>), grid, block, 0, s, w, raw, n, rgb, d.H);
+            hipLaunchKernelGGL((k_fwd_raw_fp32<NRC_PRESET_PAPER, NRC_RAW14>), grid, block, 0, s, w, raw, n, rgb, d.H, d.F);
         else
-            hipLaunchKernelGGL((k_fwd_raw_fp32<NRC_PRESET_PAPER, NRC_RAW16>), grid, block, 0, s, w, raw, n, rgb, d.H);
+            hipLaunchKernelGGL((k_fwd_raw_fp32<NRC_PRESET_PAPER, NRC_RAW16>), grid, block, 0, s, w, raw, n, rgb, d.H, d.F);
     } else {
         if (layout == NRC_RAW14)
-            hipLaunchKernelGGL((k_fwd_raw_fp32<NRC_PRESET_CONFIG, NRC_RAW14>), grid, block, 0, s, w, raw, n, rgb, d.H);
+            hipLaunchKernelGGL((k_fwd_raw_fp32<NRC_PRESET_CONFIG, NRC_RAW14>), grid, block, 0, s, w, raw, n, rgb, d.H, d.F);
         else
-            hipLaunchKernelGGL((k_fwd_raw_fp32<NRC_PRESET_CONFIG, NRC_RAW16>), grid, block, 0, s, w, raw, n, rgb, d.H);
+            hipLaunchKernelGGL((k_fwd_raw_fp32<NRC_PRESET_CONFIG, NRC_RAW16>), grid, block, 0, s, w, raw, n, rgb, d.H, d.F);
     }
     return hipGetLastError();
 }
 
 size_t fp32_train_lds_bytes(int n_hidden) {
-    return ((size_t)(n_hidden + 1) * kTile * kLd + 2 * kTile * kLd + kTile * 4) * sizeof(float);
+    return ((size_t)(n_hidden + 1) * kTile * kLd + 2 * kTile * kLd + 2 * kTile * 4) * sizeof(float);
 }
 
 hipError_t launch_train_fp32(const Geo& d, const float* w, const float* enc, const float* tgt,
@@ -346,17 +377,17 @@ hipError_t launch_train_fp32(const Geo& d, const float* w, const float* enc, con
         auto k = k_train_fp32<false, false>;
         (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         hipLaunchKernelGGL(k, grid, block, lds, s, w, enc, tgt, n, d.H, d.n_params(),
-                           loss_eps, grad_scale, partials, loss_part, tile_bad, genc);
+                           loss_eps, grad_scale, partials, loss_part, tile_bad, genc, d.F);
     } else if (genc) {
         auto k = k_train_fp32<true, true>;
         (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         hipLaunchKernelGGL(k, grid, block, lds, s, w, enc, tgt, n, d.H, d.n_params(),
-                           loss_eps, grad_scale, partials, loss_part, tile_bad, genc);
+                           loss_eps, grad_scale, partials, loss_part, tile_bad, genc, d.F);
     } else {
         auto k = k_train_fp32<true, false>;
         (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         hipLaunchKernelGGL(k, grid, block, lds, s, w, enc, tgt, n, d.H, d.n_params(),
-                           loss_eps, grad_scale, partials, loss_part, tile_bad, genc);
+                           loss_eps, grad_scale, partials, loss_part, tile_bad, genc, d.F);
     }
     return hipGetLastError();
 }

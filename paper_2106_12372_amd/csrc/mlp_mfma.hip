@@ -154,18 +154,37 @@ __device__ inline void mlp_tile(const typename Vec8<T>::type* sfr, typename Vec8
         for (int col = 0; col < COLS; ++col) o[col] = mfma(fo[c * 64], b[col][c], o[col]);
 }
 
+// Reflectance factor alpha + beta (Sec. 5) of record ln from the B operand
+// holding input features 32..63 in natural order (lane 16g + ln: features
+// 32 + 8g .. 32 + 8g + 7); valid in lanes 0..15, 1 when fcol == 0.  Config
+// preset: diffuse 53..55 sit in lane 32 + ln, slots 5..7, and specular 56..58
+// in lane 48 + ln, slots 0..2; paper presets: both in lane 48 + ln, slots 0..5.
+template <typename V>
+__device__ inline void reflectance_operand(const V& b1, int fcol, int ln, float (&r)[3]) {
+    if (fcol == kAlbedoColConfig) {
+        #pragma unroll
+        for (int c = 0; c < 3; ++c)
+            r[c] = __shfl((float)b1[5 + c], 32 + ln, 64) + __shfl((float)b1[c], 48 + ln, 64);
+    } else if (fcol == kAlbedoColPaper) {
+        #pragma unroll
+        for (int c = 0; c < 3; ++c) r[c] = __shfl((float)b1[c] + (float)b1[3 + c], 48 + ln, 64);
+    } else {
+        r[0] = r[1] = r[2] = 1.0f;
+    }
+}
+
 template <int COLS>
-__device__ inline void store_rgb(const f32x4 (&o)[COLS], int64_t base, int64_t n, int g, int ln,
-                                 float* __restrict__ rgb) {
+__device__ inline void store_rgb(const f32x4 (&o)[COLS], const float (&r)[COLS][3], int64_t base,
+                                 int64_t n, int g, int ln, float* __restrict__ rgb) {
     if (g != 0) return;
     #pragma unroll
     for (int col = 0; col < COLS; ++col) {
         const int64_t row = base + 16 * col + ln;
         if (row < n) {
             float* dst = rgb + row * 3;
-            dst[0] = o[col][0];
-            dst[1] = o[col][1];
-            dst[2] = o[col][2];
+            dst[0] = o[col][0] * r[col][0];
+            dst[1] = o[col][1] * r[col][1];
+            dst[2] = o[col][2] * r[col][2];
         }
     }
 }
@@ -176,7 +195,7 @@ __device__ inline void store_rgb(const f32x4 (&o)[COLS], int64_t base, int64_t n
 template <typename T, int W, int COLS>
 __global__ __launch_bounds__(256, 2) void k_fwd_mfma(const T* __restrict__ ffr, int n_frags,
                                                      const T* __restrict__ enc, int64_t n,
-                                                     float* __restrict__ rgb, int n_hidden) {
+                                                     float* __restrict__ rgb, int n_hidden, int fcol) {
     using V = typename Vec8<T>::type;
     constexpr int KC = W / 32;
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
@@ -212,9 +231,12 @@ __global__ __launch_bounds__(256, 2) void k_fwd_mfma(const T* __restrict__ ffr, 
             b[col][1] = nxt[col][1];
         }
         if (tile + tstride < n_tiles) load_tile(tile + tstride);
+        float r[COLS][3];
+        #pragma unroll
+        for (int col = 0; col < COLS; ++col) reflectance_operand(b[col][1], fcol, ln, r[col]);
         f32x4 o[COLS];
         mlp_tile<T, W, COLS>(sfr, b, n_hidden, lane, o);
-        store_rgb<COLS>(o, tile * 16 * COLS, n, g, ln, rgb);
+        store_rgb<COLS>(o, r, tile * 16 * COLS, n, g, ln, rgb);
     }
 }
 
@@ -226,7 +248,7 @@ __global__ __launch_bounds__(256, 2) void k_fwd_mfma(const T* __restrict__ ffr, 
 template <typename T, int W, int PRESET, int LAYOUT>
 __global__ __launch_bounds__(256, 2) void k_fwd_raw_mfma(const T* __restrict__ ffr, int n_frags,
                                                          const float* __restrict__ raw, int64_t n,
-                                                         float* __restrict__ rgb, int n_hidden) {
+                                                         float* __restrict__ rgb, int n_hidden, int fcol) {
     using V = typename Vec8<T>::type;
     constexpr int COLS = 4, KC = W / 32;
     constexpr int RW = LAYOUT == NRC_RAW14 ? 14 : 16;
@@ -288,9 +310,12 @@ __global__ __launch_bounds__(256, 2) void k_fwd_raw_mfma(const T* __restrict__ f
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        float r[COLS][3];
+        #pragma unroll
+        for (int col = 0; col < COLS; ++col) reflectance_operand(b[col][1], fcol, ln, r[col]);
         f32x4 o[COLS];
         mlp_tile<T, W, COLS>(sfr, b, n_hidden, lane, o);
-        store_rgb<COLS>(o, tile * 64, n, g, ln, rgb);
+        store_rgb<COLS>(o, r, tile * 64, n, g, ln, rgb);
     }
 }
 
@@ -320,7 +345,7 @@ __global__ __launch_bounds__(256) void k_train_mfma(const T* __restrict__ ffr,
                                                     float* __restrict__ partials,
                                                     float* __restrict__ loss_part,
                                                     int32_t* __restrict__ tile_bad,
-                                                    float* __restrict__ genc) {
+                                                    float* __restrict__ genc, int fcol) {
     using V = typename Vec8<T>::type;
     using S = TrainShape<W>;
     constexpr int MB = W / 16, KC = W / 32, TS = S::TS, NW = S::NW, LDT = S::LDT, TK = TS / 32;
@@ -359,6 +384,8 @@ __global__ __launch_bounds__(256) void k_train_mfma(const T* __restrict__ ffr,
         #pragma unroll
         for (int i = 0; i < 8; ++i) hT[(32 * c + 8 * g + i) * LDT + sl] = b[c][i];
     }
+    float r[3];                      // reflectance factor of record sl (lanes 0..15)
+    reflectance_operand(b[1], fcol, ln, r);
     for (int l = 0; l < n_hidden; ++l) {
         const int kc = l == 0 ? 2 : KC;
         const V* fl = gf + geo.fwd_base(l) * 64;
@@ -387,22 +414,25 @@ __global__ __launch_bounds__(256) void k_train_mfma(const T* __restrict__ ffr,
     }
 
     // ---- loss gradient (Eq. 5); lanes 0..15 of each wave hold y[0..2] -------
+    // The prediction is the network output times r; the network's output
+    // gradient is the prediction's gradient times r.
     float d0 = 0.f, d1 = 0.f, d2 = 0.f, lterm = 0.f;
     if (g == 0 && valid) {
         if (UPSTREAM) {
-            d0 = tgt[row * 3 + 0] * grad_scale;
-            d1 = tgt[row * 3 + 1] * grad_scale;
-            d2 = tgt[row * 3 + 2] * grad_scale;
+            d0 = tgt[row * 3 + 0] * grad_scale * r[0];
+            d1 = tgt[row * 3 + 1] * grad_scale * r[1];
+            d2 = tgt[row * 3 + 2] * grad_scale * r[2];
         } else {
-            const float lum = (y[0] + y[1] + y[2]) * (1.0f / 3.0f);
+            const float p0 = y[0] * r[0], p1 = y[1] * r[1], p2 = y[2] * r[2];
+            const float lum = (p0 + p1 + p2) * (1.0f / 3.0f);
             const float inv_den = 1.0f / (lum * lum + loss_eps);
-            const float e0 = y[0] - tgt[row * 3 + 0];
-            const float e1 = y[1] - tgt[row * 3 + 1];
-            const float e2 = y[2] - tgt[row * 3 + 2];
+            const float e0 = p0 - tgt[row * 3 + 0];
+            const float e1 = p1 - tgt[row * 3 + 1];
+            const float e2 = p2 - tgt[row * 3 + 2];
             lterm = (e0 * e0 + e1 * e1 + e2 * e2) * inv_den;
-            d0 = 2.0f * e0 * inv_den * grad_scale;
-            d1 = 2.0f * e1 * inv_den * grad_scale;
-            d2 = 2.0f * e2 * inv_den * grad_scale;
+            d0 = 2.0f * e0 * inv_den * grad_scale * r[0];
+            d1 = 2.0f * e1 * inv_den * grad_scale * r[1];
+            d2 = 2.0f * e2 * inv_den * grad_scale * r[2];
         }
     }
     V bd = zero8<V>();
@@ -454,6 +484,24 @@ __global__ __launch_bounds__(256) void k_train_mfma(const T* __restrict__ ffr,
         for (int c = 1; c < KC; ++c)
             #pragma unroll
             for (int mb = 0; mb < 4; ++mb) acc[mb] = mfma(gb[(mb * KC + c) * 64], b[c], acc[mb]);
+        if (fcol) {
+            // d(f_c R_c)/d(albedo column) = f_c: lane (g, ln) holds input
+            // features 48 + 4g .. 48 + 4g + 3 of record sl in acc[3].
+            float f[3];
+            #pragma unroll
+            for (int c = 0; c < 3; ++c) f[c] = __shfl(y[c], ln, 64);
+            if (valid) {
+                #pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    int c = 48 + 4 * g + j - fcol;
+                    if (c >= 0 && c < 6) {
+                        c = c >= 3 ? c - 3 : c;
+                        const float fc = c == 0 ? f[0] : c == 1 ? f[1] : f[2];
+                        acc[3][j] = fmaf(tgt[row * 3 + c], fc, acc[3][j]);
+                    }
+                }
+            }
+        }
         if (valid) {
             #pragma unroll
             for (int mb = 0; mb < 4; ++mb)
@@ -533,7 +581,7 @@ hipError_t fwd_dispatch(const Geo& d, const void* ffr, const void* enc, int64_t 
     auto k = k_fwd_mfma<T, W, COLS>;
     (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(256), lds, s, (const T*)ffr, d.n_fwd_frags(),
-                       (const T*)enc, n, rgb, d.H);
+                       (const T*)enc, n, rgb, d.H, d.F);
     return hipGetLastError();
 }
 
@@ -548,7 +596,7 @@ hipError_t fwd_raw_launch(const Geo& d, const void* ffr, const float* raw, int64
     auto k = k_fwd_raw_mfma<T, W, PRESET, LAYOUT>;
     (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(256), lds, s, (const T*)ffr, d.n_fwd_frags(), raw,
-                       n, rgb, d.H);
+                       n, rgb, d.H, d.F);
     return hipGetLastError();
 }
 
@@ -578,7 +626,7 @@ hipError_t train_launch(const Geo& d, const void* ffr, const void* bfr, const vo
     (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL(k, dim3((unsigned)tiles), dim3(64 * S::NW), lds, s, (const T*)ffr, (const T*)bfr,
                        (const T*)enc, tgt, n, d.H, loss_eps, grad_scale, partials, loss_part, tile_bad,
-                       genc);
+                       genc, d.F);
     return hipGetLastError();
 }
 

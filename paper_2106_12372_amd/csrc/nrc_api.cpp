@@ -67,6 +67,7 @@ int validate_config(const nrc_config* c) {
     if (!(c->loss_eps > 0.0f) || !std::isfinite(c->loss_eps)) return fail(NRC_EINVAL, "loss_eps must be positive");
     if (!(c->loss_scale > 0.0f) || !std::isfinite(c->loss_scale)) return fail(NRC_EINVAL, "loss_scale must be positive");
     if (!(c->ema_alpha >= 0.0f && c->ema_alpha < 1.0f)) return fail(NRC_EINVAL, "ema_alpha must be in [0, 1)");
+    if (c->factorize != 0 && c->factorize != 1) return fail(NRC_EINVAL, "factorize must be 0 or 1");
     return NRC_OK;
 }
 
@@ -115,11 +116,18 @@ ScratchLayout scratch_layout(const nrc_config& c, int64_t n) {
     return L;
 }
 
+// Network shape plus the reflectance-factorisation column the kernels use.
+Geo kernel_geo(const nrc_config& c) {
+    Geo d(c.width, c.n_hidden);
+    d.F = c.factorize ? albedo_col(c.enc_preset) : 0;
+    return d;
+}
+
 // Enqueue one training step (forward, loss, backward, reduction, Adam) on s.
 int enqueue_train_step(nrc_cache* c, const void* enc, const float* target, int64_t n, char* scratch,
                        float* loss_dev, int32_t* skipped_dev, hipStream_t s) {
     const nrc_config& cfg = c->cfg;
-    const Geo d(cfg.width, cfg.n_hidden);
+    const Geo d = kernel_geo(cfg);
     const ScratchLayout sl = scratch_layout(cfg, n);
     float* partials = (float*)(scratch + sl.partials);
     float* loss_part = (float*)(scratch + sl.loss_part);
@@ -148,7 +156,7 @@ int enqueue_train_step(nrc_cache* c, const void* enc, const float* target, int64
 }
 
 int enqueue_forward(nrc_cache* c, const void* enc, int64_t n, float* rgb, hipStream_t s) {
-    const Geo d(c->cfg.width, c->cfg.n_hidden);
+    const Geo d = kernel_geo(c->cfg);
     hipError_t e;
     if (c->cfg.precision == NRC_FP32)
         e = launch_fwd_fp32(d, c->query_w(), (const float*)enc, n, rgb, s);
@@ -179,6 +187,7 @@ int nrc_config_default(nrc_config* cfg) {
     cfg->loss_eps = 0.01f;
     cfg->loss_scale = 128.0f;
     cfg->ema_alpha = 0.0f;
+    cfg->factorize = 0;
     cfg->seed = 0;
     return ok();
 }
@@ -419,7 +428,7 @@ int nrc_forward_raw(nrc_cache* cache, const float* raw, int raw_layout, int64_t 
     if (n == 0) return ok();
     if (!raw || !rgb) return fail(NRC_EINVAL, "NULL buffer");
     if (!aligned16(raw) || ((uintptr_t)rgb & 3)) return fail(NRC_EINVAL, "misaligned buffer");
-    const Geo d(cache->cfg.width, cache->cfg.n_hidden);
+    const Geo d = kernel_geo(cache->cfg);
     hipError_t e;
     if (cache->cfg.precision == NRC_FP32)
         e = launch_fwd_raw_fp32(d, cache->cfg.enc_preset, raw_layout, cache->query_w(), raw, n, rgb,
@@ -462,7 +471,7 @@ int nrc_backward(nrc_cache* cache, const void* enc, const float* grad_rgb, int64
     const ScratchLayout sl = scratch_layout(cfg, n);
     if (scratch_bytes < sl.total)
         return fail(NRC_ENOMEM, "scratch of %zu bytes is smaller than the %zu bytes needed", scratch_bytes, sl.total);
-    const Geo d(cfg.width, cfg.n_hidden);
+    const Geo d = kernel_geo(cfg);
     char* sc = (char*)scratch;
     float* partials = (float*)(sc + sl.partials);
     float* loss_part = (float*)(sc + sl.loss_part);

@@ -14,6 +14,14 @@ namespace nrc {
 constexpr int kMaxLayers = 9;   // up to 8 hidden layers + output
 constexpr int kEncWidth = 64;   // encoded input width (Sec. 3.6)
 constexpr int kNOut = 3;        // RGB
+// First column of the diffuse albedo in the encoded row; the specular albedo
+// follows it (Sec. 3.6 concatenation order): after the roughness at 52 in the
+// config preset, after the roughness one-blob at 52..55 in the paper presets.
+constexpr int kAlbedoColConfig = 53;
+constexpr int kAlbedoColPaper = 56;
+__host__ __device__ inline int albedo_col(int preset) {
+    return preset == NRC_PRESET_CONFIG ? kAlbedoColConfig : kAlbedoColPaper;
+}
 // Training records per workgroup tile: 64, except 32 for the width-128
 // matrix-core form (its activations and deltas must fit in LDS).
 __host__ __device__ inline int train_tile(int precision, int width) {
@@ -32,8 +40,11 @@ constexpr int kFragElems = 64 * 8;
 //   fwd_mb(l) blocks of 16 rows x fwd_kc(l) chunks of 32 columns.
 // Backward fragments of layer l: A operand of g = W_l^T delta (M = cols,
 //   K = rows), bwd_mb(l) x bwd_kc(l).
+//   F: reflectance factorisation (Sec. 5): 0 = off, otherwise the albedo
+//   column (kAlbedoColConfig or kAlbedoColPaper); the prediction is the network
+//   output times enc[F + c] + enc[F + 3 + c] per channel c.
 struct Geo {
-    int W, H;
+    int W, H, F = 0;
     __host__ __device__ Geo(int width, int n_hidden) : W(width), H(n_hidden) {}
     __host__ __device__ int MB() const { return W >> 4; }
     __host__ __device__ int KC() const { return W >> 5; }
@@ -92,6 +103,17 @@ __host__ __device__ inline int64_t bwd_frag_index(const Geo& d, int l, int o, in
     chained_slot(o, c, g, i);  // K index of the transposed product is the row o
     const int mb = k >> 4, lane = 16 * g + (k & 15);
     return ((int64_t)(d.bwd_base(l) + mb * d.bwd_kc(l) + c) * 64 + lane) * 8 + i;
+}
+
+// alpha + beta per channel from an encoded row held in registers (one lane per
+// record); fcol is 0 (no factorisation, factor 1), kAlbedoColConfig or
+// kAlbedoColPaper.  The selects keep every register index compile-time.
+__device__ inline void reflectance_row(const float (&h)[kEncWidth], int fcol, float (&r)[kNOut]) {
+    #pragma unroll
+    for (int c = 0; c < kNOut; ++c)
+        r[c] = fcol == kAlbedoColPaper    ? h[kAlbedoColPaper + c] + h[kAlbedoColPaper + 3 + c]
+               : fcol == kAlbedoColConfig ? h[kAlbedoColConfig + c] + h[kAlbedoColConfig + 3 + c]
+                                          : 1.0f;
 }
 
 struct AdamHyper {

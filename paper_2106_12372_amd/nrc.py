@@ -41,6 +41,7 @@ class nrc_config(ctypes.Structure):
                 ("precision", c_int32), ("enc_preset", c_int32), ("lr", c_float),
                 ("beta1", c_float), ("beta2", c_float), ("adam_eps", c_float),
                 ("loss_eps", c_float), ("loss_scale", c_float), ("ema_alpha", c_float),
+                ("factorize", c_int32),
                 ("seed", c_uint64)]
 
 
@@ -124,7 +125,7 @@ def check(rc: int) -> int:
 def make_config(width: int = 64, n_hidden: int = 5, precision="fp16", enc_preset: int = NRC_PRESET_CONFIG,
                 lr: float = 1e-2, beta1: float = 0.9, beta2: float = 0.99, adam_eps: float = 1e-8,
                 loss_eps: float = 0.01, loss_scale: Optional[float] = None,
-                ema_alpha: float = 0.0) -> nrc_config:
+                ema_alpha: float = 0.0, factorize: bool = False) -> nrc_config:
     cfg = nrc_config()
     check(lib.nrc_config_default(ctypes.byref(cfg)))
     prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
@@ -132,6 +133,7 @@ def make_config(width: int = 64, n_hidden: int = 5, precision="fp16", enc_preset
     cfg.lr, cfg.beta1, cfg.beta2, cfg.adam_eps, cfg.loss_eps = lr, beta1, beta2, adam_eps, loss_eps
     cfg.loss_scale = (1.0 if prec == NRC_FP32 else 128.0) if loss_scale is None else loss_scale
     cfg.ema_alpha = ema_alpha
+    cfg.factorize = 1 if factorize else 0
     return cfg
 
 

@@ -46,11 +46,22 @@ def backward(qm, hs, d_out, q):
         d = q(g * (hs[l] > 0.0))
 
 
+def factor(x, fcol):
+    """Reflectance factor of the encoded rows x (values as stored), in FP32
+    arithmetic like the kernels; 1 when fcol is None."""
+    if fcol is None:
+        return 1.0
+    x32 = np.asarray(x, np.float32)
+    return (x32[:, fcol:fcol + 3] + x32[:, fcol + 3:fcol + 6]).astype(np.float64)
+
+
 class TrainModel:
-    """FP32 master weights and Adam state, reduced-precision network arithmetic."""
+    """FP32 master weights and Adam state, reduced-precision network arithmetic.
+    fcol: first albedo column of the reflectance factorisation, or None."""
 
     def __init__(self, w, prec, width=64, n_hidden=5, loss_scale=128.0, lr=1e-2, b1=0.9, b2=0.99,
-                 eps=1e-8, loss_eps=0.01):
+                 eps=1e-8, loss_eps=0.01, fcol=None):
+        self.fcol = fcol
         self.w = np.asarray(w, np.float32).copy()
         self.m = np.zeros_like(self.w)
         self.v = np.zeros_like(self.w)
@@ -63,16 +74,18 @@ class TrainModel:
         return [m.astype(np.float64) for m in sd.split_weights(self.w, self.width, self.n_hidden)]
 
     def predict(self, x):
-        return forward(self.mats(), x, self.q)[0]
+        return forward(self.mats(), x, self.q)[0] * factor(x, self.fcol)
 
     def step(self, x, y):
         n = x.shape[0]
         z, hs, qm = forward(self.mats(), x, self.q)
+        r = factor(x, self.fcol)
+        z = z * r
         lum = z.mean(axis=1, keepdims=True)
         den = lum * lum + self.loss_eps
         diff = z - y
         loss = float((diff * diff / den).sum() / (3 * n))
-        d_out = 2.0 * diff / den * (self.scale / (3 * n))
+        d_out = 2.0 * diff / den * (self.scale / (3 * n)) * r
         grads, _ = backward(qm, hs, d_out, self.q)
         g = (np.concatenate([gg.reshape(-1) for gg in grads]) / self.scale).astype(np.float32)
         self.t += 1

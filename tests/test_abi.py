@@ -43,8 +43,10 @@ def test_config_validation(N):
     bad = [dict(width=96), dict(n_hidden=0), dict(n_hidden=9), dict(precision=7),
            dict(enc_preset=3), dict(lr=-1.0), dict(beta1=1.0), dict(loss_eps=0.0),
            dict(loss_scale=0.0), dict(precision="fp32", width=128), dict(width=128, n_hidden=6)]
-    for kw in bad:
-        cfg = N.make_config(**kw)
+    raw_bad = N.make_config()
+    raw_bad.factorize = 2                         # only 0 and 1 are defined
+    for kw in bad + [raw_bad]:
+        cfg = kw if isinstance(kw, N.nrc_config) else N.make_config(**kw)
         with pytest.raises(N.NrcError) as e:
             N.nrc_cache_bytes(cfg)
         assert e.value.code == N.NRC_EINVAL

@@ -57,6 +57,28 @@ def test_autograd_gradients(AG, prec, width, n):
         assert np.linalg.norm(gx - q(mgin)) / np.linalg.norm(mgin) <= MODEL_TOL[prec]
 
 
+@pytest.mark.parametrize("prec", ["fp16", "fp32"])
+def test_autograd_factorised(AG, prec):
+    # Reflectance factorisation: the input gradient also flows into the albedo
+    # columns (d(f R)/dR = f).
+    from paper_2106_12372_amd import nrc as N
+    mod = AG.NRCModule(precision=prec, factorize=True)
+    raw = sd.raw_records(8192, 53)
+    x = N.nrc_encode(mod.cache, torch.from_numpy(raw).to("cuda")).requires_grad_(True)
+    r = sd.gaussian((8192, 3), sd.SEED_FD)
+    y = mod(x)
+    (y * torch.from_numpy(r).to("cuda")).sum().backward()
+    x64 = x.detach().float().cpu().numpy().astype(np.float64)
+    st = O.CacheState(mod.weights.detach().cpu().numpy(), factorize=True)
+    assert np.all(l2_err(y.detach().cpu().numpy(), O.predict(st, x64)) <= FWD_TOL[prec])
+    ref_w, ref_in = O.query_gradient(st, x64, r.astype(np.float64))
+    gw = mod.weights.grad.cpu().numpy().astype(np.float64)
+    gx = x.grad.float().cpu().numpy().astype(np.float64)
+    q = RM.quantiser(prec)
+    assert np.linalg.norm(gw - ref_w) / np.linalg.norm(ref_w) <= BWD_TOL[prec]
+    assert np.linalg.norm(gx - q(ref_in)) / np.linalg.norm(ref_in) <= BWD_TOL[prec]
+
+
 def test_autograd_drives_torch_optimizer(AG):
     mod = AG.NRCModule(precision="fp16")
     raw = sd.raw_records(4096, 52)

@@ -215,16 +215,18 @@ def test_forward_empty(N):
 # ---------------------------------------------------------------------------
 # Training (Eq. 5, Sec. 5 optimizer, Sec. 3.4-3.5 schedule)
 # ---------------------------------------------------------------------------
-def _train_parity(N, prec, n, steps, seed, out_tol, loss_tol, width=64):
+def _train_parity(N, prec, n, steps, seed, out_tol, loss_tol, width=64, preset=0, factorize=False):
     """Train on the GPU, in the oracle and in the rounding model; compare held-out outputs."""
-    c, w = make_cache(N, prec, width=width)
+    c, w = make_cache(N, prec, width=width, preset=preset, factorize=factorize)
     raw = sd.raw_records(n * steps, seed)
     enc = N.nrc_encode(c, dev(raw), 0)
     enc64 = enc.float().cpu().numpy().astype(np.float64)
     y = sd.targets(raw)
     yd = dev(y)
     st = state_of(w, width)
-    model = RM.TrainModel(w, prec, width=width, loss_scale=c.cfg.loss_scale)
+    st.factorize, st.preset = factorize, preset
+    model = RM.TrainModel(w, prec, width=width, loss_scale=c.cfg.loss_scale,
+                          fcol=O.albedo_columns(preset)[0] if factorize else None)
     for s in range(steps):
         sl = slice(s * n, (s + 1) * n)
         loss, skipped = N.nrc_train_step(c, enc[sl].contiguous(), yd[sl].contiguous())
@@ -232,7 +234,7 @@ def _train_parity(N, prec, n, steps, seed, out_tol, loss_tol, width=64):
         model.step(enc64[sl], y[sl].astype(np.float64))
         assert int(skipped.item()) == 0 and not ref_skip
         assert abs(loss.item() - ref_loss) <= loss_tol * abs(ref_loss), (s, loss.item(), ref_loss)
-    q, q64 = rounded_input(O.encode(sd.raw_records(4096, sd.SEED_HELDOUT)), prec)
+    q, q64 = rounded_input(O.encode(sd.raw_records(4096, sd.SEED_HELDOUT), preset=preset), prec)
     got = N.nrc_forward(c, q).cpu().numpy()
     ref = O.predict(st, q64)
     err = l2_err(got, ref)
@@ -376,6 +378,73 @@ def test_backward_loss_gradient_matches_train_step_direction(N):
     gw, _ = N.nrc_backward(c, enc, dev(d_out), want_grad_enc=False)
     _, g_ref = O.gradient(st, e64, y)
     assert np.linalg.norm(gw.cpu().numpy() - g_ref) / np.linalg.norm(g_ref) <= 1e-5
+
+
+# ---------------------------------------------------------------------------
+# Reflectance factorisation (Sec. 5): prediction = network output * (alpha + beta)
+# ---------------------------------------------------------------------------
+def _torch_factor(enc, preset):
+    a, b = O.albedo_columns(preset)
+    e = enc.float()
+    return e[:, a:a + 3] + e[:, b:b + 3]
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("preset", [0, 1, 2])
+@pytest.mark.parametrize("layout", [0, 1])
+@pytest.mark.parametrize("n", [4097, 1000, 63])
+def test_forward_factorised(N, prec, preset, layout, n):
+    raw = dev(sd.raw_records(n, 300 + n, layout))
+    c, w = make_cache(N, prec, preset=preset, factorize=True)
+    plain, _ = make_cache(N, prec, preset=preset)
+    enc = N.nrc_encode(c, raw, layout)
+    got = N.nrc_forward(c, enc)
+    # the kernels multiply their unfactorised output by alpha + beta formed in
+    # FP32 from the stored features: bitwise what torch computes from the same
+    # tensors
+    assert torch.equal(got, N.nrc_forward(plain, enc) * _torch_factor(enc, preset))
+    assert torch.equal(N.nrc_forward_raw(c, raw, layout), got)
+    if n >= 64:
+        st = O.CacheState(w.astype(np.float64), factorize=True, preset=preset)
+        ref = O.predict(st, O.encode(raw.cpu().numpy(), layout, preset))
+        check_outputs(got.cpu().numpy(), ref, FWD_TOL[prec], FWD_TOL_MAX[prec])
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("preset", [0, 1])
+def test_train_factorised_one_step(N, prec, preset):
+    _train_parity(N, prec, 1024, 1, 71, SINGLE_STEP_TOL[prec], 1e-5 if prec == "fp32" else 1e-2,
+                  preset=preset, factorize=True)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_train_factorised_frame_schedule(N, prec):
+    _, rel_w = _train_parity(N, prec, 16384, 4, 72, 1e-5 if prec == "fp32" else 1e-2,
+                             1e-5 if prec == "fp32" else 1e-2, factorize=True)
+    assert rel_w < (1e-5 if prec == "fp32" else 2e-2)
+
+
+@pytest.mark.parametrize("prec,width", [("fp32", 64), ("fp16", 64), ("bf16", 64), ("fp16", 128)])
+@pytest.mark.parametrize("preset", [0, 1])
+def test_backward_factorised(N, prec, width, preset):
+    c, w = make_cache(N, prec, width=width, preset=preset, factorize=True)
+    n = 1000
+    raw = sd.raw_records(n, 73)
+    enc = N.nrc_encode(c, dev(raw), 0)
+    x64 = enc.float().cpu().numpy().astype(np.float64)
+    r = sd.gaussian((n, 3), sd.SEED_FD)
+    gw, genc = N.nrc_backward(c, enc, dev(r))
+    gw, genc = gw.cpu().numpy().astype(np.float64), genc.cpu().numpy().astype(np.float64)
+    st = state_of(w, width)
+    st.factorize, st.preset = True, preset
+    ref_w, ref_in = O.query_gradient(st, x64, r.astype(np.float64))
+    assert np.linalg.norm(gw - ref_w) / np.linalg.norm(ref_w) <= BWD_TOL[prec]
+    assert np.linalg.norm(genc - ref_in) / np.linalg.norm(ref_in) <= BWD_TOL[prec]
+    # the albedo columns carry the extra term d(f R)/dR = f; FP32 matches it closely
+    a, b = O.albedo_columns(preset)
+    cols = list(range(a, a + 3)) + list(range(b, b + 3))
+    e_cols = np.linalg.norm(genc[:, cols] - ref_in[:, cols]) / np.linalg.norm(ref_in[:, cols])
+    assert e_cols <= BWD_TOL[prec], e_cols
 
 
 # ---------------------------------------------------------------------------
