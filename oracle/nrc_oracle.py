@@ -46,6 +46,17 @@ notes):
   W_bar_t = [(1 - a) W_t + a eta_{t-1} W_bar_{t-1}] / eta_t, eta_t = 1 - a^t,
   i.e. W_bar_t = E_t / eta_t with E_t = a E_{t-1} + (1 - a) W_t, E_0 = 0.  It
   advances only on steps that update the weights and never feeds back.
+* Record shuffle (Sec. 3.5): the paper shuffles the training records with a
+  linear congruential generator but gives no constants.  Read as the orbit of
+  a full-period LCG x_{i+1} = (a x_i + c) mod m on m = 2^ceil(log2 n) (Hull and
+  Dobell: c odd and a = 1 mod 4 give period m), started at x_0 = seed mod m,
+  with values >= n skipped: a permutation of the n records.  a and c are
+  Knuth's MMIX multiplier and increment reduced mod 2^32.  The frame uses the
+  first min(n, s l) shuffled records, cut into s consecutive batches of
+  near-equal size (exactly l each when n >= s l).
+* Self-training (Sec. 3.3, Sec. 5 Self-training): a record's target is the
+  radiance gathered from its vertex to the tail of its path plus the
+  throughput to the tail times the cache's prediction at the tail vertex.
 * Reflectance factorisation (Sec. 5): the cache's prediction is the network
   output times alpha + beta, per channel; alpha and beta are the identity-
   encoded diffuse and specular albedo columns of the network input itself, so
@@ -346,6 +357,65 @@ def predict_ema(state: CacheState, enc: np.ndarray) -> np.ndarray:
     w = state.w_bar if state.w_bar is not None else state.w
     return predict(CacheState(w, width=state.width, n_hidden=state.n_hidden,
                               factorize=state.factorize, preset=state.preset), enc)
+
+
+# ---------------------------------------------------------------------------
+# Training-record pipeline (Sec. 3.5 shuffle, Sec. 3.3 self-training)
+# ---------------------------------------------------------------------------
+LCG_A = 6364136223846793005 % 2 ** 32   # = 5 (mod 8)
+LCG_C = 1442695040888963407 % 2 ** 32   # odd
+
+
+def lcg_modulus(n: int) -> int:
+    m = 1
+    while m < n:
+        m *= 2
+    return m
+
+
+def lcg_permutation(n: int, seed: int) -> np.ndarray:
+    """Shuffled record order: the LCG orbit from seed mod m with values >= n skipped."""
+    m = lcg_modulus(n)
+    x = seed % m
+    out = []
+    for _ in range(m):
+        if x < n:
+            out.append(x)
+        x = (LCG_A * x + LCG_C) % m
+    return np.array(out, dtype=np.int64)
+
+
+def frame_batches(n: int, steps: int, batch: int, seed: int):
+    """Record indices of each of the `steps` training batches of one frame."""
+    perm = lcg_permutation(n, seed)
+    used = min(n, steps * batch)
+    return [perm[s * used // steps:(s + 1) * used // steps] for s in range(steps)]
+
+
+def self_training_targets(radiance: np.ndarray, throughput: np.ndarray, tail_rgb: np.ndarray,
+                          tail_index: np.ndarray) -> np.ndarray:
+    """target_i = radiance_i + throughput_i * tail_rgb[tail_index_i], per channel."""
+    radiance = np.asarray(radiance, dtype=np.float64)
+    throughput = np.asarray(throughput, dtype=np.float64)
+    tail_rgb = np.asarray(tail_rgb, dtype=np.float64)
+    return radiance + throughput * tail_rgb[np.asarray(tail_index)]
+
+
+def frame_shuffled(state: CacheState, query_enc: np.ndarray, record_enc: np.ndarray,
+                   record_y: np.ndarray, steps: int = 4, batch: int = 16384, seed: int = 0):
+    """One frame with the shuffle: queries with the start-of-frame weights, then one
+    step per shuffled batch (Sec. 3.4 footnote, Sec. 3.5)."""
+    rgb = predict(state, query_enc)
+    losses, skips = [], []
+    for idx in frame_batches(record_enc.shape[0], steps, batch, seed):
+        if idx.size == 0:
+            losses.append(0.0)
+            skips.append(True)
+            continue
+        loss, skipped = train_step(state, record_enc[idx], record_y[idx])
+        losses.append(loss)
+        skips.append(skipped)
+    return rgb, losses, skips
 
 
 def frame(state: CacheState, query_enc: np.ndarray, record_enc: np.ndarray,

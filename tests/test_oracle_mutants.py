@@ -88,6 +88,31 @@ def _gradient_factor_dropped(state, enc, y):
     return loss, np.concatenate([g.reshape(-1) for g in grads])
 
 
+def _lcg_even_increment(n, seed):
+    m = O.lcg_modulus(n)
+    x, out = seed % m, []
+    for _ in range(m):
+        if x < n:
+            out.append(x)
+        x = (O.LCG_A * x + O.LCG_C - 1) % m
+    return np.array(out, dtype=np.int64)
+
+
+def _lcg_keeps_n(n, seed):
+    m = O.lcg_modulus(n)
+    x, out = seed % m, []
+    for _ in range(m):
+        if x <= n:
+            out.append(x)
+        x = (O.LCG_A * x + O.LCG_C) % m
+    return np.array(out, dtype=np.int64)
+
+
+def _targets_wrong_tail(radiance, throughput, tail_rgb, tail_index):
+    return np.asarray(radiance, float) + np.asarray(throughput, float) * np.asarray(tail_rgb, float)[
+        (np.asarray(tail_index) + 1) % len(tail_rgb)]
+
+
 MUTANTS = [
     ("freq", _freq_no_pi, [P.test_freq_matches_libm_closed_form, P.test_freq_dyadic_points_exact]),
     ("one_blob", _one_blob_no_tails, [P.test_one_blob_exact_dyadic_fixture, P.test_one_blob_invariants]),
@@ -101,6 +126,9 @@ MUTANTS = [
     ("reflectance", _reflectance_shifted_columns, [P.test_factorised_prediction_scales_by_raw_albedos]),
     ("query_gradient", _query_gradient_no_albedo_term, [P.test_factorised_query_gradient_central_differences]),
     ("gradient", _gradient_factor_dropped, [P.test_factorised_train_gradient_central_differences]),
+    ("lcg_permutation", _lcg_even_increment, [P.test_lcg_full_period_and_permutation]),
+    ("lcg_permutation", _lcg_keeps_n, [P.test_lcg_orbit_matches_hand_derived_fixture]),
+    ("self_training_targets", _targets_wrong_tail, [P.test_self_training_targets]),
 ]
 
 

@@ -625,3 +625,86 @@ def test_factorised_train_gradient_central_differences():
         assert g[k] == pytest.approx((frozen(a) - frozen(b)) / (2 * h), rel=1e-7, abs=1e-10)
         ok += 1
     assert ok > 30
+
+
+# ----------------------------------------------------------------------------
+# Training-record shuffle (Sec. 3.5) and self-training targets (Sec. 3.3)
+# ----------------------------------------------------------------------------
+def _golden_lcg():
+    rows = {}
+    for line in open(os.path.join(GOLDEN, "lcg_orbit_m16.txt")):
+        line = line.strip()
+        if line and not line.startswith("#"):
+            k, *v = line.split()
+            rows[k] = [int(t) for t in v]
+    return rows
+
+
+def test_lcg_orbit_matches_hand_derived_fixture():
+    g = _golden_lcg()
+    assert O.lcg_permutation(16, 0).tolist() == g["orbit"]
+    assert O.lcg_permutation(10, 0).tolist() == g["n10"]
+    assert O.lcg_permutation(10, 7).tolist() == g["n10s7"]
+    assert O.lcg_permutation(10, 7 + 16).tolist() == g["n10s7"]     # the seed acts mod m
+
+
+def test_lcg_full_period_and_permutation():
+    # Hull-Dobell: c odd and a = 1 (mod 4) give the full period 2^k, so every
+    # orbit is a permutation; skipping values >= n keeps one of [0, n).
+    assert O.LCG_C % 2 == 1 and O.LCG_A % 4 == 1
+    for k in range(0, 17):
+        m = 2 ** k
+        assert np.array_equal(np.sort(O.lcg_permutation(m, 12345)), np.arange(m))
+    rng = np.random.Generator(np.random.PCG64(98))
+    for n in [1, 2, 3, 5, 1000, 16385, 50000]:
+        p = O.lcg_permutation(n, int(rng.integers(0, 2 ** 32)))
+        assert p.size == n and np.array_equal(np.sort(p), np.arange(n))
+    assert O.lcg_permutation(0, 5).size == 0
+
+
+def test_frame_batches_are_disjoint_and_spread_over_the_records():
+    n, steps, batch = 65536, 4, 16384
+    bs = O.frame_batches(n, steps, batch, 2)
+    assert [b.size for b in bs] == [batch] * steps
+    allb = np.concatenate(bs)
+    assert np.array_equal(np.sort(allb), np.arange(n))               # disjoint, cover all
+    # not correlated with record position (image region): every batch draws
+    # within 10% of its share from each sixteenth of the record range
+    for b in bs:
+        h = np.bincount(b // (n // 16), minlength=16)
+        assert np.max(np.abs(h - batch / 16)) <= 0.1 * batch / 16
+    # more records than s l: the first s l shuffled ones are used
+    bs = O.frame_batches(70000, steps, batch, 2)
+    assert [b.size for b in bs] == [batch] * steps
+    assert np.array_equal(np.concatenate(bs), O.lcg_permutation(70000, 2)[:steps * batch])
+    # fewer: near-equal batches of all of them
+    bs = O.frame_batches(1001, steps, batch, 2)
+    assert [b.size for b in bs] == [250, 250, 250, 251]
+    assert np.array_equal(np.sort(np.concatenate(bs)), np.arange(1001))
+
+
+def test_frame_shuffled_equals_frame_on_permuted_records():
+    st_a = O.CacheState(sd.glorot_weights())
+    st_b = O.CacheState(sd.glorot_weights())
+    raw = sd.raw_records(4 * 256, 99)
+    x, y = O.encode(raw), sd.targets(raw).astype(np.float64)
+    q = O.encode(sd.raw_records(64, 100))
+    rgb_a, la, sa = O.frame_shuffled(st_a, q, x, y, steps=4, batch=256, seed=9)
+    p = O.lcg_permutation(x.shape[0], 9)
+    rgb_b, lb = O.frame(st_b, q, x[p], y[p], n_steps=4)
+    assert np.array_equal(rgb_a, rgb_b) and la == lb and not any(sa)
+    assert np.array_equal(st_a.w, st_b.w)
+
+
+def test_self_training_targets():
+    rng = np.random.Generator(np.random.PCG64(101))
+    L = rng.random((50, 3))
+    T = rng.random((50, 3))
+    tail = rng.random((7, 3))
+    k = rng.integers(0, 7, 50)
+    got = O.self_training_targets(L, T, tail, k)
+    assert np.array_equal(O.self_training_targets(L, np.zeros_like(T), tail, k), L)   # no tail term
+    assert np.array_equal(O.self_training_targets(np.zeros_like(L), np.ones_like(T), tail, k), tail[k])
+    for i in range(50):                                                           # record by record
+        for c in range(3):
+            assert got[i, c] == L[i, c] + T[i, c] * tail[k[i], c]
