@@ -2,8 +2,8 @@
 
 A step is one 1920x1080 frame of the cache: encode 2,073,600 synthetic query
 records and run inference on them (one fused kernel), encode 65,536 training
-records, and take four Adam steps of 16,384 records each (Sec. 3.4-3.5 of the
-paper).  Inputs
+records, shuffle them with the LCG and take four Adam steps on disjoint
+batches of 16,384 records (Sec. 3.3 and 3.5 of the paper).  Inputs
 are resident in HBM before the timed region.  The default form is plain FP32
 (vector ALUs); the FP16 and BF16 matrix-core forms run the same frame and are
 reported under "forms".  Prints one JSON line.
@@ -83,13 +83,12 @@ def frame_bench(form: str, steps: int, warmup: int):
     enc_q = torch.empty((N_QUERIES, 64), dtype=cache.enc_dtype, device=dev)
     enc_r = torch.empty((N_TRAIN_BATCHES * TRAIN_BATCH, 64), dtype=cache.enc_dtype, device=dev)
     rgb = torch.empty((N_QUERIES, 3), dtype=torch.float32, device=dev)
-    loss = torch.empty(N_TRAIN_BATCHES, dtype=torch.float32, device=dev)
-    skipped = torch.empty(N_TRAIN_BATCHES, dtype=torch.int32, device=dev)
-    scratch, _ = cache.scratch(TRAIN_BATCH)
-    y_b = [y[s * TRAIN_BATCH:(s + 1) * TRAIN_BATCH] for s in range(N_TRAIN_BATCHES)]
-    e_b = [enc_r[s * TRAIN_BATCH:(s + 1) * TRAIN_BATCH] for s in range(N_TRAIN_BATCHES)]
+    n_rec = N_TRAIN_BATCHES * TRAIN_BATCH
+    frame_scratch = N._aligned_bytes(N.nrc_frame_scratch_bytes(cfg, n_rec, N_TRAIN_BATCHES, TRAIN_BATCH), dev)
     stream = torch.cuda.current_stream(dev)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    frame_no = [0]
+    last = {}
 
     def step(record: bool):
         if record:
@@ -100,9 +99,11 @@ def frame_bench(form: str, steps: int, warmup: int):
         N.nrc_encode(cache, raw_r, enc=enc_r)
         if record:
             ev[2].record(stream)
-        for s in range(N_TRAIN_BATCHES):
-            N.nrc_train_step(cache, e_b[s], y_b[s], loss=loss[s:s + 1], skipped=skipped[s:s + 1],
-                             scratch=scratch)
+        # LCG shuffle, then 4 steps on disjoint batches, a new shuffle each frame
+        last["loss"], last["skipped"] = N.nrc_train_frame(cache, enc_r, y, steps=N_TRAIN_BATCHES,
+                                                          batch=TRAIN_BATCH, seed=frame_no[0],
+                                                          scratch=frame_scratch)
+        frame_no[0] += 1
         if record:
             ev[3].record(stream)
 
@@ -143,7 +144,7 @@ def frame_bench(form: str, steps: int, warmup: int):
         "queries_per_s": N_QUERIES / (ms * 1e-3),
         "train_samples_per_s": N_TRAIN_BATCHES * TRAIN_BATCH / (ms * 1e-3),
         "components_ms": {"query_pass_fused": comp[0], "encode_records": comp[1],
-                          "train_4_steps": comp[2]},
+                          "shuffle_and_train_4_steps": comp[2]},
         "unfused_ms": {"encode_queries": ue[0], "forward": ue[1]},
         "query_pass_queries_per_s": N_QUERIES / t_q,
         "mlp_only_queries_per_s": N_QUERIES / t_fwd,
@@ -172,11 +173,39 @@ def frame_bench(form: str, steps: int, warmup: int):
             "avg_launch_ms": ue[1],
             "hbm_gbs_algorithmic": N_QUERIES * (64 * enc_bytes + 12) / t_fwd / 1e9,
         },
-        "final_loss": float(loss[-1].item()),
-        "skipped_steps": int(skipped.sum().item()),
+        "final_loss": float(last["loss"][-1].item()),
+        "skipped_steps": int(last["skipped"].sum().item()),
     }
     frame_flop = N_QUERIES * FLOP_PER_QUERY + N_TRAIN_BATCHES * TRAIN_BATCH * FLOP_PER_TRAIN_SAMPLE
     out["frame_tflops"] = frame_flop / (ms * 1e-3) / 1e12
+    out["query_pass_by_preset_ms"] = preset_bench(form, raw_q, rgb, steps)
+    return out
+
+
+def preset_bench(form: str, raw_q, rgb, steps: int):
+    """The fused query pass under each encoding preset: config (sin and cos of 6
+    octaves), paper (12 sines) and paper-tri (12 triangle waves, the cheap
+    primitive of Sec. 5); average kernel time in ms."""
+    import torch
+    from paper_2106_12372_amd import nrc as N
+
+    stream = torch.cuda.current_stream(raw_q.device)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    out = {}
+    for name, preset in (("config", N.NRC_PRESET_CONFIG), ("paper", N.NRC_PRESET_PAPER),
+                         ("paper_tri", N.NRC_PRESET_PAPER_TRI)):
+        cache = N.Cache(N.make_config(width=WIDTH, n_hidden=N_HIDDEN, precision=form, enc_preset=preset),
+                        device=raw_q.device)
+        cache.set_weights(sd.glorot_weights(WIDTH, N_HIDDEN))
+        t = 0.0
+        for it in range(steps + 2):
+            ev[0].record(stream)
+            N.nrc_forward_raw(cache, raw_q, rgb=rgb)
+            ev[1].record(stream)
+            ev[1].synchronize()
+            if it >= 2:
+                t += ev[0].elapsed_time(ev[1])
+        out[name] = t / steps
     return out
 
 
@@ -265,7 +294,7 @@ def serve_bench(form: str, n_requests: int, serial: bool, load: float = 0.8, cap
 
 def cpu_baseline():
     """The FP64 oracle on the host cores: one full frame (encode + inference of
-    2,073,600 queries, encode of 65,536 records, four training steps)."""
+    2,073,600 queries, encode of 65,536 records, shuffle, four training steps)."""
     from oracle import nrc_oracle as O
     try:
         from threadpoolctl import threadpool_info
@@ -278,15 +307,12 @@ def cpu_baseline():
     st = O.CacheState(sd.glorot_weights(WIDTH, N_HIDDEN))
     t0 = time.perf_counter()
     q_enc = O.encode(raw_q)
-    O.predict(st, q_enc)
     r_enc = O.encode(raw_r)
-    for s in range(N_TRAIN_BATCHES):
-        sl = slice(s * TRAIN_BATCH, (s + 1) * TRAIN_BATCH)
-        O.train_step(st, r_enc[sl], y[sl])
+    O.frame_shuffled(st, q_enc, r_enc, y, N_TRAIN_BATCHES, TRAIN_BATCH, 0)
     t = time.perf_counter() - t0
     return {"value": N_QUERIES / t, "unit": "queries/s", "cores": int(threads), "kind": "oracle",
             "sample": "one full frame: FP64 NumPy encode + inference of 2,073,600 queries, encode of "
-                      "65,536 records, four 16,384-record training steps",
+                      "65,536 records, LCG shuffle, four 16,384-record training steps",
             "seconds": t, "train_samples_per_s": N_TRAIN_BATCHES * TRAIN_BATCH / t}
 
 
@@ -365,6 +391,7 @@ def main():
         "mlp_only_queries_per_s": main_res["mlp_only_queries_per_s"],
         "train_only_samples_per_s": main_res["train_only_samples_per_s"],
         "frame_tflops": main_res["frame_tflops"],
+        "query_pass_by_preset_ms": main_res["query_pass_by_preset_ms"],
         "roofline": main_res["roofline"],
         "cpu_baseline": cpu,
         "forms": forms,

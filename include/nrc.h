@@ -68,7 +68,7 @@ extern "C" {
  * Eq. 5; loss_scale multiplies the loss gradient before the reduced-precision
  * backward pass and is divided out before Adam (use 1 for FP32).
  * ema_alpha > 0 keeps the exponential moving average of the weights of Eq. 2
- * (Sec. 3.4), bias-corrected: W_bar_t = E_t / (1 - alpha^t) with
+ * (Sec. 3.3), bias-corrected: W_bar_t = E_t / (1 - alpha^t) with
  * E_t = alpha E_{t-1} + (1 - alpha) W_t, advanced by every applied Adam step;
  * the query entry points (nrc_forward, nrc_forward_raw) then use W_bar, as the
  * paper does for rendering, while training and nrc_backward use W.  Before the
@@ -194,7 +194,7 @@ int nrc_forward_raw(nrc_cache* cache, const float* raw, int raw_layout, int64_t 
                     void* stream);
 
 /*
- * One optimisation step (Sec. 3.4-3.5, Eq. 5, Sec. 5): forward over the batch
+ * One optimisation step (Sec. 3.3 and 3.5, Eq. 5, Sec. 5): forward over the batch
  * enc[n][64] with targets target[n][3] (FP32), relative L2 loss, backward,
  * weight gradients summed over the batch, then one Adam update of the master
  * weights.  The loss (FP32 scalar) is written to *loss_dev and the skip flag
@@ -220,6 +220,71 @@ int nrc_train_step(nrc_cache* cache, const void* enc, const float* target, int64
 int nrc_backward(nrc_cache* cache, const void* enc, const float* grad_rgb, int64_t n,
                  void* scratch, size_t scratch_bytes, float* grad_w, float* grad_enc,
                  void* stream);
+
+/* ------------------------------------------------------------------------- */
+/* Training-record pipeline of one frame (Sec. 3.3 footnote, Sec. 3.5,       */
+/* Sec. 3.2 self-training).                                                  */
+/* ------------------------------------------------------------------------- */
+
+/* Bytes of device scratch nrc_shuffle needs (a small constant, 4 KiB). */
+size_t nrc_shuffle_scratch_bytes(int64_t n);
+
+/*
+ * Record shuffle of Sec. 3.5 ("shuffle all training records using a linear
+ * congruential generator").  Writes perm[0..n) (int32, device), a permutation
+ * of 0..n-1: the orbit x_0 = seed mod m, x_{i+1} = (a x_i + c) mod m of the
+ * full-period LCG on m = the smallest power of two >= n, with values >= n
+ * skipped; a = 1284865837 and c = 4150755663 (Knuth's MMIX multiplier and
+ * increment reduced mod 2^32).  The same (n, seed) always gives the same
+ * order.  scratch: device, 4-byte aligned, nrc_shuffle_scratch_bytes(n);
+ * overwritten.  0 <= n < 2^31.  Asynchronous on `stream`.
+ */
+int nrc_shuffle(int64_t n, uint64_t seed, int32_t* perm, void* scratch, size_t scratch_bytes,
+                void* stream);
+
+/*
+ * One training step (as nrc_train_step) on the records idx[0..n) of enc and
+ * target: the batch is gathered inside the training kernel.  idx: device int32,
+ * each entry a valid row of enc / target (not checked).  scratch as for
+ * nrc_train_step with this n.
+ */
+int nrc_train_step_indexed(nrc_cache* cache, const void* enc, const float* target,
+                           const int32_t* idx, int64_t n, void* scratch, size_t scratch_bytes,
+                           float* loss_dev, int32_t* skipped_dev, void* stream);
+
+/* Bytes of device scratch nrc_train_frame needs; 0 on invalid arguments. */
+size_t nrc_frame_scratch_bytes(const nrc_config* cfg, int64_t n_records, int steps, int64_t batch);
+
+/*
+ * The cache update of one frame (Sec. 3.3 footnote, Sec. 3.5): shuffle the
+ * n_records training records (nrc_shuffle with `seed`), take the first
+ * used = min(n_records, steps * batch) of them, and run `steps` training
+ * steps, step k on shuffled records [k used / steps, (k+1) used / steps)
+ * (disjoint batches, exactly `batch` records each when n_records >= steps *
+ * batch; the paper uses steps = 4, batch = 16384).  losses_dev[steps] and
+ * skipped_dev[steps] (device) receive each step's loss and skip flag.
+ * enc[n_records][64] at the cache precision, target[n_records][3] FP32, both
+ * device.  steps in [1, 64], n_records in [steps, 2^31).  scratch: device,
+ * 256-byte aligned, nrc_frame_scratch_bytes.  Everything is enqueued on
+ * `stream`; nothing waits for the host.
+ */
+int nrc_train_frame(nrc_cache* cache, const void* enc, const float* target, int64_t n_records,
+                    int steps, int64_t batch, uint64_t seed, void* scratch, size_t scratch_bytes,
+                    float* losses_dev, int32_t* skipped_dev, void* stream);
+
+/*
+ * Self-training targets (Sec. 3.2, Sec. 6 "Self-training"): a training
+ * record's target is the radiance gathered from its vertex to the end of its
+ * path plus the throughput from its vertex to the path's tail times the
+ * cache's prediction at the tail vertex (an nrc_forward / nrc_forward_raw of
+ * the tail queries):
+ *   target[i][c] = radiance[i][c] + throughput[i][c] * tail_rgb[tail_index[i]][c].
+ * All arrays FP32 [.][3] (tail_index int32 [n]), device.  A tail_index outside
+ * [0, n_tail) gives a NaN target, so the training step that uses it skips.
+ */
+int nrc_self_training_targets(const float* radiance, const float* throughput, const float* tail_rgb,
+                              const int32_t* tail_index, int64_t n, int64_t n_tail, float* target,
+                              void* stream);
 
 /* ------------------------------------------------------------------------- */
 /* Serving: continuous batching of inference and training requests over     */

@@ -54,7 +54,7 @@ notes):
   Knuth's MMIX multiplier and increment reduced mod 2^32.  The frame uses the
   first min(n, s l) shuffled records, cut into s consecutive batches of
   near-equal size (exactly l each when n >= s l).
-* Self-training (Sec. 3.3, Sec. 5 Self-training): a record's target is the
+* Self-training (Sec. 3.2, Sec. 6 Self-training): a record's target is the
   radiance gathered from its vertex to the tail of its path plus the
   throughput to the tail times the cache's prediction at the tail vertex.
 * Reflectance factorisation (Sec. 5): the cache's prediction is the network
@@ -251,7 +251,7 @@ def adam(w: np.ndarray, m: np.ndarray, v: np.ndarray, t: int, g: np.ndarray, cfg
 
 
 # ---------------------------------------------------------------------------
-# Cache state, training step, frame (Sec. 3.4 footnote, Sec. 3.5)
+# Cache state, training step, frame (Sec. 3.3 footnote, Sec. 3.5)
 # ---------------------------------------------------------------------------
 def layer_shapes(width: int, n_hidden: int, n_in: int = ENC_WIDTH, n_out: int = 3):
     return [(width, n_in)] + [(width, width)] * (n_hidden - 1) + [(n_out, width)]
@@ -268,7 +268,7 @@ class CacheState:
     t: int = 0
     adam: AdamConfig = field(default_factory=AdamConfig)
     loss_eps: float = LOSS_EPS
-    ema_alpha: float = 0.0      # Sec. 3.4 uses 0.99; 0 disables the EMA set
+    ema_alpha: float = 0.0      # Sec. 3.3 uses 0.99; 0 disables the EMA set
     w_bar: np.ndarray = None
     factorize: bool = False     # Sec. 5 reflectance factorisation
     preset: int = PRESET_CONFIG  # encoding preset: where the albedo columns sit
@@ -353,14 +353,14 @@ def train_step(state: CacheState, enc: np.ndarray, y: np.ndarray):
 
 
 def predict_ema(state: CacheState, enc: np.ndarray) -> np.ndarray:
-    """Cache query with the EMA weights (Sec. 3.4): the set used for rendering."""
+    """Cache query with the EMA weights (Sec. 3.3): the set used for rendering."""
     w = state.w_bar if state.w_bar is not None else state.w
     return predict(CacheState(w, width=state.width, n_hidden=state.n_hidden,
                               factorize=state.factorize, preset=state.preset), enc)
 
 
 # ---------------------------------------------------------------------------
-# Training-record pipeline (Sec. 3.5 shuffle, Sec. 3.3 self-training)
+# Training-record pipeline (Sec. 3.5 shuffle, Sec. 3.2 self-training)
 # ---------------------------------------------------------------------------
 LCG_A = 6364136223846793005 % 2 ** 32   # = 5 (mod 8)
 LCG_C = 1442695040888963407 % 2 ** 32   # odd
@@ -404,7 +404,7 @@ def self_training_targets(radiance: np.ndarray, throughput: np.ndarray, tail_rgb
 def frame_shuffled(state: CacheState, query_enc: np.ndarray, record_enc: np.ndarray,
                    record_y: np.ndarray, steps: int = 4, batch: int = 16384, seed: int = 0):
     """One frame with the shuffle: queries with the start-of-frame weights, then one
-    step per shuffled batch (Sec. 3.4 footnote, Sec. 3.5)."""
+    step per shuffled batch (Sec. 3.3 footnote, Sec. 3.5)."""
     rgb = predict(state, query_enc)
     losses, skips = [], []
     for idx in frame_batches(record_enc.shape[0], steps, batch, seed):
@@ -421,7 +421,7 @@ def frame_shuffled(state: CacheState, query_enc: np.ndarray, record_enc: np.ndar
 def frame(state: CacheState, query_enc: np.ndarray, record_enc: np.ndarray,
           record_y: np.ndarray, n_steps: int = 4):
     """One frame: queries with the start-of-frame weights, then `n_steps` steps on
-    disjoint consecutive slices of the training records (Sec. 3.4 footnote, Sec. 3.5)."""
+    disjoint consecutive slices of the training records (Sec. 3.3 footnote, Sec. 3.5)."""
     rgb = predict(state, query_enc)
     n = record_enc.shape[0]
     per = n // n_steps

@@ -116,7 +116,8 @@ __device__ inline float wave_sum(float v) {
 template <bool UPSTREAM, bool GENC>
 __global__ __launch_bounds__(256) void k_train_fp32(const float* __restrict__ w,
                                                     const float* __restrict__ enc,
-                                                    const float* __restrict__ tgt, int64_t n,
+                                                    const float* __restrict__ tgt,
+                                                    const int32_t* __restrict__ idx, int64_t n,
                                                     int n_hidden, int n_params, float loss_eps,
                                                     float grad_scale, float* __restrict__ partials,
                                                     float* __restrict__ loss_part,
@@ -135,6 +136,8 @@ __global__ __launch_bounds__(256) void k_train_fp32(const float* __restrict__ w,
     const int64_t tile = blockIdx.x;
     const int64_t row = tile * kTile + lane;
     const bool valid = row < n;
+    // record read for this slot: idx[row] for a gathered batch, else row
+    const int64_t src = !valid ? 0 : idx ? (int64_t)idx[row] : row;
     float* part = partials + tile * (int64_t)n_params;
 
     // Stage the tile's inputs as h_0 (zeros past the end of the batch).
@@ -142,7 +145,7 @@ __global__ __launch_bounds__(256) void k_train_fp32(const float* __restrict__ w,
         const int s = i >> 4, q = i & 15;
         const int64_t r = tile * kTile + s;
         float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (r < n) v = reinterpret_cast<const float4*>(enc + r * kEncWidth)[q];
+        if (r < n) v = reinterpret_cast<const float4*>(enc + (idx ? (int64_t)idx[r] : r) * kEncWidth)[q];
         *reinterpret_cast<float4*>(hs + s * kLd + 4 * q) = v;
     }
     __syncthreads();
@@ -201,7 +204,7 @@ __global__ __launch_bounds__(256) void k_train_fp32(const float* __restrict__ w,
         if (valid) {
             if (UPSTREAM) {
                 #pragma unroll
-                for (int o = 0; o < kNOut; ++o) d[o] = tgt[row * 3 + o] * grad_scale * r[o];
+                for (int o = 0; o < kNOut; ++o) d[o] = tgt[src * 3 + o] * grad_scale * r[o];
             } else {
                 float y[kNOut];
                 #pragma unroll
@@ -210,7 +213,7 @@ __global__ __launch_bounds__(256) void k_train_fp32(const float* __restrict__ w,
                 const float inv_den = 1.0f / (lum * lum + loss_eps);
                 #pragma unroll
                 for (int o = 0; o < kNOut; ++o) {
-                    const float diff = y[o] - tgt[row * 3 + o];
+                    const float diff = y[o] - tgt[src * 3 + o];
                     lterm = fmaf(diff * diff, inv_den, lterm);
                     d[o] = 2.0f * diff * inv_den * grad_scale * r[o];
                 }
@@ -309,7 +312,7 @@ __global__ __launch_bounds__(256) void k_train_fp32(const float* __restrict__ w,
                         int c = 16 * wave + j - fcol;
                         if (c >= 0 && c < 6) {
                             c = c >= 3 ? c - 3 : c;
-                            acc[j] = fmaf(tgt[row * 3 + c], fout[lane * 4 + c], acc[j]);
+                            acc[j] = fmaf(tgt[src * 3 + c], fout[lane * 4 + c], acc[j]);
                         }
                     }
                 }
@@ -366,7 +369,7 @@ size_t fp32_train_lds_bytes(int n_hidden) {
 }
 
 hipError_t launch_train_fp32(const Geo& d, const float* w, const float* enc, const float* tgt,
-                             int64_t n, bool upstream, float loss_eps, float grad_scale,
+                             const int32_t* idx, int64_t n, bool upstream, float loss_eps, float grad_scale,
                              float* partials, float* loss_part, int32_t* tile_bad, float* genc,
                              hipStream_t s) {
     const int64_t tiles = (n + kTile - 1) / kTile;
@@ -376,17 +379,17 @@ hipError_t launch_train_fp32(const Geo& d, const float* w, const float* enc, con
     if (!upstream) {
         auto k = k_train_fp32<false, false>;
         (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        hipLaunchKernelGGL(k, grid, block, lds, s, w, enc, tgt, n, d.H, d.n_params(),
+        hipLaunchKernelGGL(k, grid, block, lds, s, w, enc, tgt, idx, n, d.H, d.n_params(),
                            loss_eps, grad_scale, partials, loss_part, tile_bad, genc, d.F);
     } else if (genc) {
         auto k = k_train_fp32<true, true>;
         (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        hipLaunchKernelGGL(k, grid, block, lds, s, w, enc, tgt, n, d.H, d.n_params(),
+        hipLaunchKernelGGL(k, grid, block, lds, s, w, enc, tgt, idx, n, d.H, d.n_params(),
                            loss_eps, grad_scale, partials, loss_part, tile_bad, genc, d.F);
     } else {
         auto k = k_train_fp32<true, false>;
         (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        hipLaunchKernelGGL(k, grid, block, lds, s, w, enc, tgt, n, d.H, d.n_params(),
+        hipLaunchKernelGGL(k, grid, block, lds, s, w, enc, tgt, idx, n, d.H, d.n_params(),
                            loss_eps, grad_scale, partials, loss_part, tile_bad, genc, d.F);
     }
     return hipGetLastError();

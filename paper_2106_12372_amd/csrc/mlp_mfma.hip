@@ -340,7 +340,8 @@ template <typename T, int W, bool UPSTREAM, bool GENC>
 __global__ __launch_bounds__(256) void k_train_mfma(const T* __restrict__ ffr,
                                                     const T* __restrict__ bfr,
                                                     const T* __restrict__ enc,
-                                                    const float* __restrict__ tgt, int64_t n,
+                                                    const float* __restrict__ tgt,
+                                                    const int32_t* __restrict__ idx, int64_t n,
                                                     int n_hidden, float loss_eps, float grad_scale,
                                                     float* __restrict__ partials,
                                                     float* __restrict__ loss_part,
@@ -366,6 +367,8 @@ __global__ __launch_bounds__(256) void k_train_mfma(const T* __restrict__ ffr,
     const int sl = 16 * wave + ln;                           // record within the tile
     const int64_t row = tile * TS + sl;
     const bool valid = row < n;
+    // record read for this slot: idx[row] for a gathered batch, else row
+    const int64_t src = !valid ? 0 : idx ? (int64_t)idx[row] : row;
     float* part = partials + tile * (int64_t)P;
     const V* gf = reinterpret_cast<const V*>(ffr) + lane;
     const V* gb = reinterpret_cast<const V*>(bfr) + lane;
@@ -380,7 +383,7 @@ __global__ __launch_bounds__(256) void k_train_mfma(const T* __restrict__ ffr,
     V b[KC];
     #pragma unroll
     for (int c = 0; c < 2; ++c) {
-        b[c] = valid ? *reinterpret_cast<const V*>(enc + row * kEncWidth + 32 * c + 8 * g) : zero8<V>();
+        b[c] = valid ? *reinterpret_cast<const V*>(enc + src * kEncWidth + 32 * c + 8 * g) : zero8<V>();
         #pragma unroll
         for (int i = 0; i < 8; ++i) hT[(32 * c + 8 * g + i) * LDT + sl] = b[c][i];
     }
@@ -419,16 +422,16 @@ __global__ __launch_bounds__(256) void k_train_mfma(const T* __restrict__ ffr,
     float d0 = 0.f, d1 = 0.f, d2 = 0.f, lterm = 0.f;
     if (g == 0 && valid) {
         if (UPSTREAM) {
-            d0 = tgt[row * 3 + 0] * grad_scale * r[0];
-            d1 = tgt[row * 3 + 1] * grad_scale * r[1];
-            d2 = tgt[row * 3 + 2] * grad_scale * r[2];
+            d0 = tgt[src * 3 + 0] * grad_scale * r[0];
+            d1 = tgt[src * 3 + 1] * grad_scale * r[1];
+            d2 = tgt[src * 3 + 2] * grad_scale * r[2];
         } else {
             const float p0 = y[0] * r[0], p1 = y[1] * r[1], p2 = y[2] * r[2];
             const float lum = (p0 + p1 + p2) * (1.0f / 3.0f);
             const float inv_den = 1.0f / (lum * lum + loss_eps);
-            const float e0 = p0 - tgt[row * 3 + 0];
-            const float e1 = p1 - tgt[row * 3 + 1];
-            const float e2 = p2 - tgt[row * 3 + 2];
+            const float e0 = p0 - tgt[src * 3 + 0];
+            const float e1 = p1 - tgt[src * 3 + 1];
+            const float e2 = p2 - tgt[src * 3 + 2];
             lterm = (e0 * e0 + e1 * e1 + e2 * e2) * inv_den;
             d0 = 2.0f * e0 * inv_den * grad_scale * r[0];
             d1 = 2.0f * e1 * inv_den * grad_scale * r[1];
@@ -497,7 +500,7 @@ __global__ __launch_bounds__(256) void k_train_mfma(const T* __restrict__ ffr,
                     if (c >= 0 && c < 6) {
                         c = c >= 3 ? c - 3 : c;
                         const float fc = c == 0 ? f[0] : c == 1 ? f[1] : f[2];
-                        acc[3][j] = fmaf(tgt[row * 3 + c], fc, acc[3][j]);
+                        acc[3][j] = fmaf(tgt[src * 3 + c], fc, acc[3][j]);
                     }
                 }
             }
@@ -615,7 +618,7 @@ hipError_t fwd_raw_dispatch(const Geo& d, int preset, int layout, const void* ff
 
 template <typename T, int W, bool UP, bool GE>
 hipError_t train_launch(const Geo& d, const void* ffr, const void* bfr, const void* enc,
-                        const float* tgt, int64_t n, float loss_eps, float grad_scale,
+                        const float* tgt, const int32_t* idx, int64_t n, float loss_eps, float grad_scale,
                         float* partials, float* loss_part, int32_t* tile_bad, float* genc,
                         hipStream_t s) {
     using S = TrainShape<W>;
@@ -625,23 +628,23 @@ hipError_t train_launch(const Geo& d, const void* ffr, const void* bfr, const vo
     auto k = k_train_mfma<T, W, UP, GE>;
     (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL(k, dim3((unsigned)tiles), dim3(64 * S::NW), lds, s, (const T*)ffr, (const T*)bfr,
-                       (const T*)enc, tgt, n, d.H, loss_eps, grad_scale, partials, loss_part, tile_bad,
+                       (const T*)enc, tgt, idx, n, d.H, loss_eps, grad_scale, partials, loss_part, tile_bad,
                        genc, d.F);
     return hipGetLastError();
 }
 
 template <typename T, int W>
 hipError_t train_dispatch(const Geo& d, const void* ffr, const void* bfr, const void* enc,
-                          const float* tgt, int64_t n, bool upstream, float loss_eps,
+                          const float* tgt, const int32_t* idx, int64_t n, bool upstream, float loss_eps,
                           float grad_scale, float* partials, float* loss_part, int32_t* tile_bad,
                           float* genc, hipStream_t s) {
     if (!upstream)
-        return train_launch<T, W, false, false>(d, ffr, bfr, enc, tgt, n, loss_eps, grad_scale,
+        return train_launch<T, W, false, false>(d, ffr, bfr, enc, tgt, idx, n, loss_eps, grad_scale,
                                                 partials, loss_part, tile_bad, genc, s);
     if (genc)
-        return train_launch<T, W, true, true>(d, ffr, bfr, enc, tgt, n, loss_eps, grad_scale,
+        return train_launch<T, W, true, true>(d, ffr, bfr, enc, tgt, idx, n, loss_eps, grad_scale,
                                               partials, loss_part, tile_bad, genc, s);
-    return train_launch<T, W, true, false>(d, ffr, bfr, enc, tgt, n, loss_eps, grad_scale,
+    return train_launch<T, W, true, false>(d, ffr, bfr, enc, tgt, idx, n, loss_eps, grad_scale,
                                            partials, loss_part, tile_bad, genc, s);
 }
 
@@ -672,17 +675,17 @@ hipError_t launch_fwd_raw_mfma(int precision, const Geo& d, int preset, int layo
 }
 
 hipError_t launch_train_mfma(int precision, const Geo& d, const void* ffr, const void* bfr,
-                             const void* enc, const float* tgt, int64_t n, bool upstream,
+                             const void* enc, const float* tgt, const int32_t* idx, int64_t n, bool upstream,
                              float loss_eps, float grad_scale, float* partials, float* loss_part,
                              int32_t* tile_bad, float* genc, hipStream_t s) {
     if (precision == NRC_FP16)
-        return d.W == 64 ? train_dispatch<_Float16, 64>(d, ffr, bfr, enc, tgt, n, upstream, loss_eps,
+        return d.W == 64 ? train_dispatch<_Float16, 64>(d, ffr, bfr, enc, tgt, idx, n, upstream, loss_eps,
                                                         grad_scale, partials, loss_part, tile_bad, genc, s)
-                         : train_dispatch<_Float16, 128>(d, ffr, bfr, enc, tgt, n, upstream, loss_eps,
+                         : train_dispatch<_Float16, 128>(d, ffr, bfr, enc, tgt, idx, n, upstream, loss_eps,
                                                          grad_scale, partials, loss_part, tile_bad, genc, s);
-    return d.W == 64 ? train_dispatch<__bf16, 64>(d, ffr, bfr, enc, tgt, n, upstream, loss_eps,
+    return d.W == 64 ? train_dispatch<__bf16, 64>(d, ffr, bfr, enc, tgt, idx, n, upstream, loss_eps,
                                                   grad_scale, partials, loss_part, tile_bad, genc, s)
-                     : train_dispatch<__bf16, 128>(d, ffr, bfr, enc, tgt, n, upstream, loss_eps,
+                     : train_dispatch<__bf16, 128>(d, ffr, bfr, enc, tgt, idx, n, upstream, loss_eps,
                                                    grad_scale, partials, loss_part, tile_bad, genc, s);
 }
 

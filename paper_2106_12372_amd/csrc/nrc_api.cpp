@@ -124,8 +124,8 @@ Geo kernel_geo(const nrc_config& c) {
 }
 
 // Enqueue one training step (forward, loss, backward, reduction, Adam) on s.
-int enqueue_train_step(nrc_cache* c, const void* enc, const float* target, int64_t n, char* scratch,
-                       float* loss_dev, int32_t* skipped_dev, hipStream_t s) {
+int enqueue_train_step(nrc_cache* c, const void* enc, const float* target, const int32_t* idx,
+                       int64_t n, char* scratch, float* loss_dev, int32_t* skipped_dev, hipStream_t s) {
     const nrc_config& cfg = c->cfg;
     const Geo d = kernel_geo(cfg);
     const ScratchLayout sl = scratch_layout(cfg, n);
@@ -136,10 +136,10 @@ int enqueue_train_step(nrc_cache* c, const void* enc, const float* target, int64
     const float grad_scale = (float)((double)scale / (3.0 * (double)n));
     hipError_t e;
     if (cfg.precision == NRC_FP32)
-        e = launch_train_fp32(d, c->w(), (const float*)enc, target, n, false, cfg.loss_eps, grad_scale,
+        e = launch_train_fp32(d, c->w(), (const float*)enc, target, idx, n, false, cfg.loss_eps, grad_scale,
                               partials, loss_part, tile_bad, nullptr, s);
     else
-        e = launch_train_mfma(cfg.precision, d, c->ffr(), c->bfr(), enc, target, n, false, cfg.loss_eps,
+        e = launch_train_mfma(cfg.precision, d, c->ffr(), c->bfr(), enc, target, idx, n, false, cfg.loss_eps,
                               grad_scale, partials, loss_part, tile_bad, nullptr, s);
     if (e != hipSuccess) return device_fail(e, "training kernel launch");
     float* loss_out = loss_dev ? loss_dev : (float*)(scratch + sl.loss);
@@ -453,7 +453,7 @@ int nrc_train_step(nrc_cache* cache, const void* enc, const float* target, int64
     const size_t need = scratch_layout(cache->cfg, n).total;
     if (scratch_bytes < need)
         return fail(NRC_ENOMEM, "scratch of %zu bytes is smaller than the %zu bytes needed", scratch_bytes, need);
-    const int rc = enqueue_train_step(cache, enc, target, n, (char*)scratch, loss_dev, skipped_dev,
+    const int rc = enqueue_train_step(cache, enc, target, nullptr, n, (char*)scratch, loss_dev, skipped_dev,
                                       (hipStream_t)stream);
     return rc == NRC_OK ? ok() : rc;
 }
@@ -479,15 +479,138 @@ int nrc_backward(nrc_cache* cache, const void* enc, const float* grad_rgb, int64
     hipStream_t s = (hipStream_t)stream;
     hipError_t e;
     if (cfg.precision == NRC_FP32)
-        e = launch_train_fp32(d, cache->w(), (const float*)enc, grad_rgb, n, true, cfg.loss_eps, 1.0f,
+        e = launch_train_fp32(d, cache->w(), (const float*)enc, grad_rgb, nullptr, n, true, cfg.loss_eps, 1.0f,
                               partials, loss_part, tile_bad, grad_enc, s);
     else
-        e = launch_train_mfma(cfg.precision, d, cache->ffr(), cache->bfr(), enc, grad_rgb, n, true,
+        e = launch_train_mfma(cfg.precision, d, cache->ffr(), cache->bfr(), enc, grad_rgb, nullptr, n, true,
                               cfg.loss_eps, 1.0f, partials, loss_part, tile_bad, grad_enc, s);
     if (e != hipSuccess) return device_fail(e, "backward kernel launch");
     e = launch_reduce(d, cfg.precision != NRC_FP32, partials, (int)sl.tiles, 1.0f, grad_w, loss_part,
                       1.0f, nullptr, s);
     if (e != hipSuccess) return device_fail(e, "gradient reduction launch");
+    return ok();
+}
+
+// ---------------------------------------------------------------------------
+// Training-record pipeline (Sec. 3.5 shuffle and batches, Sec. 3.2 self-training)
+// ---------------------------------------------------------------------------
+size_t nrc_shuffle_scratch_bytes(int64_t n) {
+    if (n < 0) { fail(NRC_EINVAL, "n must be >= 0"); return 0; }
+    ok();
+    return shuffle_scratch_bytes();
+}
+
+int nrc_shuffle(int64_t n, uint64_t seed, int32_t* perm, void* scratch, size_t scratch_bytes,
+                void* stream) {
+    if (n < 0 || n >= ((int64_t)1 << 31)) return fail(NRC_EINVAL, "n must be in [0, 2^31)");
+    if (n == 0) return ok();
+    if (!perm || !scratch) return fail(NRC_EINVAL, "NULL buffer");
+    if (((uintptr_t)perm & 3) || ((uintptr_t)scratch & 3)) return fail(NRC_EINVAL, "misaligned buffer");
+    if (scratch_bytes < shuffle_scratch_bytes())
+        return fail(NRC_ENOMEM, "shuffle scratch of %zu bytes is smaller than the %zu bytes needed",
+                    scratch_bytes, shuffle_scratch_bytes());
+    const hipError_t e = launch_shuffle(n, seed, perm, (int32_t*)scratch, (hipStream_t)stream);
+    if (e != hipSuccess) return device_fail(e, "shuffle launch");
+    return ok();
+}
+
+int nrc_train_step_indexed(nrc_cache* cache, const void* enc, const float* target, const int32_t* idx,
+                           int64_t n, void* scratch, size_t scratch_bytes, float* loss_dev,
+                           int32_t* skipped_dev, void* stream) {
+    if (!cache) return fail(NRC_EINVAL, "cache is NULL");
+    if (n < 1) return fail(NRC_EINVAL, "a training batch needs n >= 1");
+    if (n > ((int64_t)1 << 31)) return fail(NRC_EINVAL, "training batch too large");
+    if (!enc || !target || !idx || !scratch) return fail(NRC_EINVAL, "NULL buffer");
+    if (!aligned16(enc) || ((uintptr_t)target & 3) || ((uintptr_t)idx & 3) || ((uintptr_t)scratch & 255))
+        return fail(NRC_EINVAL, "misaligned buffer (scratch must be 256-byte aligned)");
+    if (((uintptr_t)loss_dev & 3) || ((uintptr_t)skipped_dev & 3)) return fail(NRC_EINVAL, "misaligned output");
+    const size_t need = scratch_layout(cache->cfg, n).total;
+    if (scratch_bytes < need)
+        return fail(NRC_ENOMEM, "scratch of %zu bytes is smaller than the %zu bytes needed", scratch_bytes, need);
+    const int rc = enqueue_train_step(cache, enc, target, idx, n, (char*)scratch, loss_dev, skipped_dev,
+                                      (hipStream_t)stream);
+    return rc == NRC_OK ? ok() : rc;
+}
+
+namespace {
+// Frame scratch: the permutation, the shuffle's span counts, and one training
+// step's scratch for the largest batch (the steps run one after another).
+struct FrameLayout {
+    size_t perm, counts, step, total;
+    int64_t max_batch;
+};
+
+FrameLayout frame_layout(const nrc_config& c, int64_t n_records, int steps, int64_t batch) {
+    FrameLayout L{};
+    const int64_t used = n_records < steps * batch ? n_records : steps * batch;
+    L.max_batch = (used + steps - 1) / steps;
+    size_t off = 0;
+    auto take = [&](size_t bytes) { const size_t o = off; off = align256(off + bytes); return o; };
+    L.perm = take((size_t)n_records * 4);
+    L.counts = take(shuffle_scratch_bytes());
+    L.step = take(scratch_layout(c, L.max_batch).total);
+    L.total = off;
+    return L;
+}
+
+int check_frame_args(const nrc_config* cfg, int64_t n_records, int steps, int64_t batch) {
+    if (steps < 1 || steps > 64) return fail(NRC_EINVAL, "steps must be in [1, 64]");
+    if (batch < 1 || batch > ((int64_t)1 << 30)) return fail(NRC_EINVAL, "batch must be in [1, 2^30]");
+    if (n_records < steps || n_records >= ((int64_t)1 << 31))
+        return fail(NRC_EINVAL, "n_records must be in [steps, 2^31)");
+    (void)cfg;
+    return NRC_OK;
+}
+}  // namespace
+
+size_t nrc_frame_scratch_bytes(const nrc_config* cfg, int64_t n_records, int steps, int64_t batch) {
+    if (validate_config(cfg) != NRC_OK) return 0;
+    if (check_frame_args(cfg, n_records, steps, batch) != NRC_OK) return 0;
+    ok();
+    return frame_layout(*cfg, n_records, steps, batch).total;
+}
+
+int nrc_train_frame(nrc_cache* cache, const void* enc, const float* target, int64_t n_records, int steps,
+                    int64_t batch, uint64_t seed, void* scratch, size_t scratch_bytes, float* losses_dev,
+                    int32_t* skipped_dev, void* stream) {
+    if (!cache) return fail(NRC_EINVAL, "cache is NULL");
+    const int rc0 = check_frame_args(&cache->cfg, n_records, steps, batch);
+    if (rc0 != NRC_OK) return rc0;
+    if (!enc || !target || !scratch || !losses_dev || !skipped_dev) return fail(NRC_EINVAL, "NULL buffer");
+    if (!aligned16(enc) || ((uintptr_t)target & 3) || ((uintptr_t)scratch & 255) ||
+        ((uintptr_t)losses_dev & 3) || ((uintptr_t)skipped_dev & 3))
+        return fail(NRC_EINVAL, "misaligned buffer (scratch must be 256-byte aligned)");
+    const FrameLayout L = frame_layout(cache->cfg, n_records, steps, batch);
+    if (scratch_bytes < L.total)
+        return fail(NRC_ENOMEM, "scratch of %zu bytes is smaller than the %zu bytes needed", scratch_bytes, L.total);
+    char* sc = (char*)scratch;
+    int32_t* perm = (int32_t*)(sc + L.perm);
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = launch_shuffle(n_records, seed, perm, (int32_t*)(sc + L.counts), s);
+    if (e != hipSuccess) return device_fail(e, "shuffle launch");
+    const int64_t used = n_records < steps * batch ? n_records : steps * batch;
+    for (int k = 0; k < steps; ++k) {
+        const int64_t lo = k * used / steps, hi = (k + 1) * used / steps;
+        const int rc = enqueue_train_step(cache, enc, target, perm + lo, hi - lo, sc + L.step, losses_dev + k,
+                                          skipped_dev + k, s);
+        if (rc != NRC_OK) return rc;
+    }
+    return ok();
+}
+
+int nrc_self_training_targets(const float* radiance, const float* throughput, const float* tail_rgb,
+                              const int32_t* tail_index, int64_t n, int64_t n_tail, float* target,
+                              void* stream) {
+    if (n < 0 || n_tail < 0) return fail(NRC_EINVAL, "n and n_tail must be >= 0");
+    if (n == 0) return ok();
+    if (n_tail < 1) return fail(NRC_EINVAL, "records need at least one tail prediction");
+    if (!radiance || !throughput || !tail_rgb || !tail_index || !target) return fail(NRC_EINVAL, "NULL buffer");
+    if (((uintptr_t)radiance | (uintptr_t)throughput | (uintptr_t)tail_rgb | (uintptr_t)tail_index |
+         (uintptr_t)target) & 3)
+        return fail(NRC_EINVAL, "misaligned buffer");
+    const hipError_t e = launch_self_train(radiance, throughput, tail_rgb, tail_index, n, n_tail, target,
+                                           (hipStream_t)stream);
+    if (e != hipSuccess) return device_fail(e, "self-training target launch");
     return ok();
 }
 

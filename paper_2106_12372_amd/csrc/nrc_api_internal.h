@@ -53,7 +53,8 @@ struct nrc_cache {
 };
 
 namespace nrc {
-int enqueue_train_step(nrc_cache* c, const void* enc, const float* target, int64_t n, char* scratch,
-                       float* loss_dev, int32_t* skipped_dev, hipStream_t s);
+// idx (may be NULL): the batch is records idx[0..n) of enc / target.
+int enqueue_train_step(nrc_cache* c, const void* enc, const float* target, const int32_t* idx,
+                       int64_t n, char* scratch, float* loss_dev, int32_t* skipped_dev, hipStream_t s);
 int enqueue_forward(nrc_cache* c, const void* enc, int64_t n, float* rgb, hipStream_t s);
 }  // namespace nrc

@@ -138,8 +138,9 @@ hipError_t launch_encode(int precision, int preset, int layout, const float* raw
 // mlp_fp32.hip
 hipError_t launch_fwd_fp32(const Geo& d, const float* w, const float* enc, int64_t n, float* rgb,
                            hipStream_t s);
+// idx (may be NULL): the batch is records idx[0..n) of enc / tgt.
 hipError_t launch_train_fp32(const Geo& d, const float* w, const float* enc, const float* tgt,
-                             int64_t n, bool upstream, float loss_eps, float grad_scale,
+                             const int32_t* idx, int64_t n, bool upstream, float loss_eps, float grad_scale,
                              float* partials, float* loss_part, int32_t* tile_bad, float* genc,
                              hipStream_t s);
 hipError_t launch_fwd_raw_fp32(const Geo& d, int preset, int layout, const float* w, const float* raw,
@@ -150,7 +151,7 @@ hipError_t launch_fwd_raw_mfma(int precision, const Geo& d, int preset, int layo
 hipError_t launch_fwd_mfma(int precision, const Geo& d, const void* ffr, const void* enc,
                            int64_t n, float* rgb, hipStream_t s);
 hipError_t launch_train_mfma(int precision, const Geo& d, const void* ffr, const void* bfr,
-                             const void* enc, const float* tgt, int64_t n, bool upstream,
+                             const void* enc, const float* tgt, const int32_t* idx, int64_t n, bool upstream,
                              float loss_eps, float grad_scale, float* partials, float* loss_part,
                              int32_t* tile_bad, float* genc, hipStream_t s);
 size_t fp32_train_lds_bytes(int n_hidden);
@@ -168,6 +169,19 @@ hipError_t launch_reduce_adam(int precision, const Geo& d, bool native, const fl
                               float* loss_out, float inv_scale, float* w, float* m, float* v,
                               int32_t* tslots, int parity, AdamHyper hp, EmaArgs ema,
                               int32_t* skipped_out, void* ffr, void* bfr, hipStream_t s);
+// shuffle.hip: the record shuffle's LCG, x -> (a x + c) mod 2^k, with
+// Knuth's MMIX multiplier and increment reduced mod 2^32 (a = 5 mod 8, c odd:
+// full period 2^k for every k <= 32).
+constexpr uint32_t kLcgA = 1284865837u;
+constexpr uint32_t kLcgC = 4150755663u;
+void shuffle_shape(int64_t n, uint64_t& m, int& rounds, int& spans);
+size_t shuffle_scratch_bytes();
+// perm[0..n) = the orbit from seed mod m with values >= n skipped; counts is
+// shuffle_scratch_bytes() of device scratch.
+hipError_t launch_shuffle(int64_t n, uint64_t seed, int32_t* perm, int32_t* counts, hipStream_t s);
+hipError_t launch_self_train(const float* radiance, const float* throughput, const float* tail_rgb,
+                             const int32_t* tail_index, int64_t n, int64_t n_tail, float* target,
+                             hipStream_t s);
 // Writes W's forward fragments to ffr and ffr2 (each may be NULL) and its
 // backward fragments to bfr (may be NULL).
 hipError_t launch_build_frags(int precision, const Geo& d, const float* w, void* ffr, void* bfr,

@@ -1,6 +1,6 @@
 // Serving loop: continuous batching of cache queries and training steps from
 // several independent resident caches (each cache is the network of Sec. 3-5;
-// queries per Sec. 3.5, training steps per Sec. 3.4-3.5 and Eq. 5).
+// queries per Sec. 3.5, training steps per Sec. 3.3 and 3.5 and Eq. 5).
 //
 // One scheduler thread owns the device work.  Clients submit requests from any
 // thread; a request is admitted as soon as an in-flight slot is free and its
@@ -155,7 +155,7 @@ bool nrc_server::try_launch(Request& r, std::unique_lock<std::mutex>&) {
         for (uint64_t t : dp.reads) wait_on(t);
         char* sc = scratch_base + off;
         const ScratchLayout sl = scratch_layout(c->cfg, r.req.n);
-        rc = enqueue_train_step(c, r.req.enc, r.req.target, r.req.n, sc, (float*)(sc + sl.loss),
+        rc = enqueue_train_step(c, r.req.enc, r.req.target, nullptr, r.req.n, sc, (float*)(sc + sl.loss),
                                 (int32_t*)(sc + sl.skipped), s);
         if (rc == NRC_OK) {
             if (hipMemcpyAsync(&host_out[slot].loss, sc + sl.loss, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||

@@ -93,6 +93,12 @@ _decl("nrc_forward", c_int, _P, _P, c_int64, _P, _P)
 _decl("nrc_forward_raw", c_int, _P, _P, c_int, c_int64, _P, _P)
 _decl("nrc_train_step", c_int, _P, _P, _P, c_int64, _P, c_size_t, _P, _P, _P)
 _decl("nrc_backward", c_int, _P, _P, _P, c_int64, _P, c_size_t, _P, _P, _P)
+_decl("nrc_shuffle_scratch_bytes", c_size_t, c_int64)
+_decl("nrc_shuffle", c_int, c_int64, c_uint64, _P, _P, c_size_t, _P)
+_decl("nrc_train_step_indexed", c_int, _P, _P, _P, _P, c_int64, _P, c_size_t, _P, _P, _P)
+_decl("nrc_frame_scratch_bytes", c_size_t, POINTER(nrc_config), c_int64, c_int, c_int64)
+_decl("nrc_train_frame", c_int, _P, _P, _P, c_int64, c_int, c_int64, c_uint64, _P, c_size_t, _P, _P, _P)
+_decl("nrc_self_training_targets", c_int, _P, _P, _P, _P, c_int64, c_int64, _P, _P)
 _decl("nrc_serve_create", c_int, POINTER(nrc_serve_config), POINTER(_P))
 _decl("nrc_serve_set_weights", c_int, _P, c_int, POINTER(c_float), c_int64)
 _decl("nrc_serve_get_weights", c_int, _P, c_int, POINTER(c_float), c_int64)
@@ -105,7 +111,8 @@ EXPORTED = ["nrc_config_default", "nrc_last_error", "nrc_param_count", "nrc_cach
             "nrc_train_scratch_bytes", "nrc_enc_elem_bytes", "nrc_cache_create", "nrc_cache_destroy",
             "nrc_cache_config", "nrc_set_weights", "nrc_get_weights", "nrc_set_weights_device",
             "nrc_get_state", "nrc_set_state", "nrc_get_ema", "nrc_set_ema", "nrc_encode", "nrc_forward", "nrc_forward_raw", "nrc_train_step",
-            "nrc_backward", "nrc_serve_create", "nrc_serve_set_weights", "nrc_serve_get_weights",
+            "nrc_backward", "nrc_shuffle_scratch_bytes", "nrc_shuffle", "nrc_train_step_indexed",
+            "nrc_frame_scratch_bytes", "nrc_train_frame", "nrc_self_training_targets", "nrc_serve_create", "nrc_serve_set_weights", "nrc_serve_get_weights",
             "nrc_serve_submit", "nrc_serve_poll", "nrc_serve_drain", "nrc_serve_destroy"]
 
 
@@ -322,6 +329,85 @@ def nrc_train_step(cache: Cache, enc, target, loss=None, skipped=None, scratch=N
     check(lib.nrc_train_step(cache.handle, _ptr(enc), _ptr(target), n, _ptr(sc), size, _ptr(loss),
                              _ptr(skipped), _stream(stream)))
     return loss, skipped
+
+
+def _aligned_bytes(nbytes: int, device):
+    """A 256-byte aligned uint8 device buffer of nbytes."""
+    torch = _torch()
+    t = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    off = (-t.data_ptr()) % 256
+    return t[off:off + nbytes]
+
+
+def nrc_shuffle(n: int, seed: int, device="cuda", perm=None, stream=None):
+    """Shuffled record order (Sec. 3.5): int32 device tensor perm[n]."""
+    torch = _torch()
+    if perm is None:
+        perm = torch.empty(n, dtype=torch.int32, device=device)
+    sc = _aligned_bytes(max(1, lib.nrc_shuffle_scratch_bytes(n)), perm.device)
+    check(lib.nrc_shuffle(n, seed & (2 ** 64 - 1), _ptr(perm), _ptr(sc), sc.numel(), _stream(stream)))
+    return perm
+
+
+def nrc_train_step_indexed(cache: Cache, enc, target, idx, loss=None, skipped=None, stream=None):
+    """One Adam step on records idx of (enc, target); returns the device scalars (loss, skipped)."""
+    torch = _torch()
+    _need(enc, cache.enc_dtype, (ENC_WIDTH,), "enc")
+    _need(target, torch.float32, (3,), "target")
+    _need(idx, torch.int32, (), "idx")
+    if target.shape[0] != enc.shape[0]:
+        raise ValueError("enc and target differ in length")
+    n = idx.shape[0]
+    if loss is None:
+        loss = torch.empty(1, dtype=torch.float32, device=enc.device)
+    if skipped is None:
+        skipped = torch.empty(1, dtype=torch.int32, device=enc.device)
+    sc, size = cache.scratch(n)
+    check(lib.nrc_train_step_indexed(cache.handle, _ptr(enc), _ptr(target), _ptr(idx), n, _ptr(sc), size,
+                                     _ptr(loss), _ptr(skipped), _stream(stream)))
+    return loss, skipped
+
+
+def nrc_frame_scratch_bytes(cfg: nrc_config, n_records: int, steps: int, batch: int) -> int:
+    b = lib.nrc_frame_scratch_bytes(ctypes.byref(cfg), n_records, steps, batch)
+    if b == 0:
+        raise NrcError(NRC_EINVAL, last_error())
+    return b
+
+
+def nrc_train_frame(cache: Cache, enc, target, steps: int = 4, batch: int = 16384, seed: int = 0,
+                    scratch=None, stream=None):
+    """Shuffle the frame's records and run `steps` training steps on disjoint
+    batches (Sec. 3.3 and 3.5); returns device tensors (losses[steps], skipped[steps])."""
+    torch = _torch()
+    _need(enc, cache.enc_dtype, (ENC_WIDTH,), "enc")
+    _need(target, torch.float32, (3,), "target")
+    n = enc.shape[0]
+    if target.shape[0] != n:
+        raise ValueError("enc and target differ in length")
+    if scratch is None:
+        scratch = _aligned_bytes(nrc_frame_scratch_bytes(cache.cfg, n, steps, batch), enc.device)
+    losses = torch.empty(steps, dtype=torch.float32, device=enc.device)
+    skipped = torch.empty(steps, dtype=torch.int32, device=enc.device)
+    check(lib.nrc_train_frame(cache.handle, _ptr(enc), _ptr(target), n, steps, batch, seed & (2 ** 64 - 1),
+                              _ptr(scratch), scratch.numel(), _ptr(losses), _ptr(skipped), _stream(stream)))
+    return losses, skipped
+
+
+def nrc_self_training_targets(radiance, throughput, tail_rgb, tail_index, stream=None):
+    """target = radiance + throughput * tail_rgb[tail_index] (Sec. 3.2 self-training)."""
+    torch = _torch()
+    _need(radiance, torch.float32, (3,), "radiance")
+    _need(throughput, torch.float32, (3,), "throughput")
+    _need(tail_rgb, torch.float32, (3,), "tail_rgb")
+    _need(tail_index, torch.int32, (), "tail_index")
+    n = radiance.shape[0]
+    if throughput.shape[0] != n or tail_index.shape[0] != n:
+        raise ValueError("radiance, throughput and tail_index differ in length")
+    target = torch.empty((n, 3), dtype=torch.float32, device=radiance.device)
+    check(lib.nrc_self_training_targets(_ptr(radiance), _ptr(throughput), _ptr(tail_rgb), _ptr(tail_index), n,
+                                        tail_rgb.shape[0], _ptr(target), _stream(stream)))
+    return target
 
 
 def nrc_backward(cache: Cache, enc, grad_rgb, want_grad_enc: bool = True, scratch=None, stream=None):

@@ -85,3 +85,26 @@ def test_entry_points_reject_null_cache(N):
     assert N.lib.nrc_backward(None, P(4096), P(4096), 10, P(4096), 1 << 30, P(4096), None, None) == N.NRC_EINVAL
     assert N.lib.nrc_cache_destroy(None) == N.NRC_EINVAL
     assert N.lib.nrc_config_default(None) == N.NRC_EINVAL
+
+
+def test_record_pipeline_rejects_bad_arguments_before_device_calls(N):
+    P = ctypes.c_void_p
+    assert N.lib.nrc_shuffle_scratch_bytes(65536) == 4096
+    assert N.lib.nrc_shuffle(-1, 0, P(4096), P(4096), 4096, None) == N.NRC_EINVAL
+    assert N.lib.nrc_shuffle(1 << 31, 0, P(4096), P(4096), 4096, None) == N.NRC_EINVAL
+    assert N.lib.nrc_shuffle(0, 0, None, None, 0, None) == N.NRC_OK           # empty: nothing to do
+    assert N.lib.nrc_shuffle(10, 0, None, P(4096), 4096, None) == N.NRC_EINVAL
+    assert N.lib.nrc_shuffle(10, 0, P(4096), P(4096), 16, None) == N.NRC_ENOMEM
+    assert N.lib.nrc_train_step_indexed(None, P(4096), P(4096), P(4096), 10, P(4096), 1 << 30, None, None,
+                                        None) == N.NRC_EINVAL
+    cfg = N.make_config()
+    sb = N.nrc_frame_scratch_bytes(cfg, 65536, 4, 16384)
+    assert sb >= 65536 * 4 + N.nrc_train_scratch_bytes(cfg, 16384)
+    assert N.nrc_frame_scratch_bytes(cfg, 70000, 4, 16384) > sb                  # the permutation grows
+    for args in [(65536, 0, 16384), (65536, 65, 16384), (3, 4, 16384), (65536, 4, 0), (1 << 31, 4, 16384)]:
+        assert N.lib.nrc_frame_scratch_bytes(ctypes.byref(cfg), *args) == 0
+    assert N.lib.nrc_train_frame(None, P(4096), P(4096), 65536, 4, 16384, 0, P(4096), 1 << 30, P(4096),
+                                 P(4096), None) == N.NRC_EINVAL
+    assert N.lib.nrc_self_training_targets(P(4096), P(4096), P(4096), P(4096), 10, 0, P(4096), None) == N.NRC_EINVAL
+    assert N.lib.nrc_self_training_targets(None, P(4096), P(4096), P(4096), 10, 5, P(4096), None) == N.NRC_EINVAL
+    assert N.lib.nrc_self_training_targets(None, None, None, None, 0, 0, None, None) == N.NRC_OK

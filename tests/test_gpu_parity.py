@@ -213,7 +213,7 @@ def test_forward_empty(N):
 
 
 # ---------------------------------------------------------------------------
-# Training (Eq. 5, Sec. 5 optimizer, Sec. 3.4-3.5 schedule)
+# Training (Eq. 5, Sec. 5 optimizer, Sec. 3.3 and 3.5 schedule)
 # ---------------------------------------------------------------------------
 def _train_parity(N, prec, n, steps, seed, out_tol, loss_tol, width=64, preset=0, factorize=False):
     """Train on the GPU, in the oracle and in the rounding model; compare held-out outputs."""

@@ -1,0 +1,138 @@
+"""Training-record pipeline of one frame (Sec. 3.3 footnote, Sec. 3.5, Sec. 3.2)
+through the C ABI: the LCG shuffle (integer work: bit-exact against the
+oracle), training on gathered batches, the whole frame update, and the
+self-training targets.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import synthdata as sd
+from oracle import nrc_oracle as O
+from tests.test_gpu_parity import dev, l2_err, make_cache, rounded_input, state_of
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def N():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2106_12372_amd.nrc as nrc
+    return nrc
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 17, 1000, 16384, 65536, 65537, 100003, (1 << 20) + 5])
+@pytest.mark.parametrize("seed", [0, 1, (1 << 40) + 7])
+def test_shuffle_matches_oracle_bitwise(N, n, seed):
+    got = N.nrc_shuffle(n, seed).cpu().numpy()
+    assert np.array_equal(got, O.lcg_permutation(n, seed))
+
+
+def test_shuffle_empty(N):
+    assert N.nrc_shuffle(0, 3).numel() == 0
+
+
+def test_shuffle_large_is_a_permutation_with_the_oracle_ends(N):
+    # m = 2^26: 256 rounds per workgroup.  The whole orbit is too long for the
+    # oracle's loop, so check that the result is a permutation and that its
+    # first and last entries follow the orbit forwards from x_0 and backwards
+    # from x_0 (the inverse map x -> a^-1 (x - c) mod m).
+    n, seed = (1 << 25) + 3, 12345
+    perm = N.nrc_shuffle(n, seed)
+    srt, _ = torch.sort(perm)
+    assert torch.equal(srt, torch.arange(n, device="cuda", dtype=torch.int32))
+    m = O.lcg_modulus(n)
+    x, head = seed % m, []
+    while len(head) < 1000:
+        if x < n:
+            head.append(x)
+        x = (O.LCG_A * x + O.LCG_C) % m
+    inv = pow(O.LCG_A, -1, m)
+    x, tail = seed % m, []
+    while len(tail) < 1000:
+        x = (inv * (x - O.LCG_C)) % m
+        if x < n:
+            tail.append(x)
+    p = perm.cpu().numpy()
+    assert p[:1000].tolist() == head
+    assert p[-1000:].tolist() == tail[::-1]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16", "bf16"])
+def test_indexed_step_equals_step_on_gathered_batch(N, prec):
+    raw = sd.raw_records(5000, 81)
+    y = dev(sd.targets(raw))
+    idx = N.nrc_shuffle(5000, 4)[:1234].contiguous()
+    a, _ = make_cache(N, prec, factorize=True)
+    b, _ = make_cache(N, prec, factorize=True)
+    enc = N.nrc_encode(a, dev(raw), 0)
+    la, sa = N.nrc_train_step_indexed(a, enc, y, idx)
+    il = idx.long()
+    lb, sb = N.nrc_train_step(b, enc[il].contiguous(), y[il].contiguous())
+    assert torch.equal(la, lb) and int(sa.item()) == int(sb.item()) == 0
+    assert np.array_equal(a.get_weights(), b.get_weights())
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16", "bf16"])
+@pytest.mark.parametrize("n_records", [65536, 50001, 70000])
+def test_train_frame_matches_oracle(N, prec, n_records):
+    c, w = make_cache(N, prec)
+    raw = sd.raw_records(n_records, 82)
+    enc = N.nrc_encode(c, dev(raw), 0)
+    e64 = enc.float().cpu().numpy().astype(np.float64)
+    y = sd.targets(raw)
+    losses, skipped = N.nrc_train_frame(c, enc, dev(y), steps=4, batch=16384, seed=77)
+    st = state_of(w)
+    q, q64 = rounded_input(O.encode(sd.raw_records(4096, sd.SEED_HELDOUT)), prec)
+    _, ref_losses, ref_skips = O.frame_shuffled(st, q64, e64, y.astype(np.float64), 4, 16384, 77)
+    assert skipped.cpu().tolist() == [0, 0, 0, 0] and not any(ref_skips)
+    tol = 1e-5 if prec == "fp32" else 1e-2
+    got_l = losses.cpu().numpy()
+    assert np.all(np.abs(got_l - ref_losses) <= tol * np.abs(ref_losses)), (got_l, ref_losses)
+    got = N.nrc_forward(c, q).cpu().numpy()
+    assert np.all(l2_err(got, O.predict(st, q64)) <= tol)
+
+
+def test_train_frame_equals_shuffle_then_indexed_steps(N):
+    raw = sd.raw_records(70000, 83)
+    y = dev(sd.targets(raw))
+    a, _ = make_cache(N, "fp16")
+    b, _ = make_cache(N, "fp16")
+    enc = N.nrc_encode(a, dev(raw), 0)
+    la, _ = N.nrc_train_frame(a, enc, y, steps=4, batch=16384, seed=5)
+    perm = N.nrc_shuffle(70000, 5)
+    lb = []
+    for k in range(4):
+        l, _ = N.nrc_train_step_indexed(b, enc, y, perm[k * 16384:(k + 1) * 16384].contiguous())
+        lb.append(l.item())
+    assert la.cpu().tolist() == lb
+    assert np.array_equal(a.get_weights(), b.get_weights())
+
+
+def test_self_training_targets(N):
+    rng = np.random.Generator(np.random.PCG64(84))
+    n, nt = 10000, 777
+    L = rng.random((n, 3)).astype(np.float32)
+    T = rng.random((n, 3)).astype(np.float32)
+    tail = rng.random((nt, 3)).astype(np.float32)
+    k = rng.integers(0, nt, n).astype(np.int32)
+    got = N.nrc_self_training_targets(dev(L), dev(T), dev(tail), dev(k, torch.int32)).cpu().numpy()
+    ref = O.self_training_targets(L, T, tail, k)
+    # one fused multiply-add in FP32: within one rounding of the exact value
+    assert np.all(np.abs(got - ref) <= 2.0 ** -24 * np.abs(ref) * 1.0001)
+
+
+def test_self_training_bad_tail_index_makes_the_step_skip(N):
+    n = 256
+    L = dev(np.ones((n, 3), np.float32))
+    tail = dev(np.ones((4, 3), np.float32))
+    k = np.zeros(n, np.int32)
+    k[9] = 4                                               # out of range
+    tgt = N.nrc_self_training_targets(L, L, tail, dev(k, torch.int32))
+    assert torch.isnan(tgt[9]).all() and not torch.isnan(tgt[:9]).any() and not torch.isnan(tgt[10:]).any()
+    c, w = make_cache(N, "fp16")
+    enc = N.nrc_encode(c, dev(sd.raw_records(n, 85)), 0)
+    _, skipped = N.nrc_train_step(c, enc, tgt)
+    assert int(skipped.item()) == 1 and np.array_equal(c.get_weights(), w)

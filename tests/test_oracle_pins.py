@@ -628,7 +628,7 @@ def test_factorised_train_gradient_central_differences():
 
 
 # ----------------------------------------------------------------------------
-# Training-record shuffle (Sec. 3.5) and self-training targets (Sec. 3.3)
+# Training-record shuffle (Sec. 3.5) and self-training targets (Sec. 3.2)
 # ----------------------------------------------------------------------------
 def _golden_lcg():
     rows = {}
