@@ -88,21 +88,22 @@ __device__ inline float wave_sum(float v) {
 // ---------------------------------------------------------------------------
 // Inference
 // ---------------------------------------------------------------------------
-// Copy n_frags operand fragments (1 KB each) from global memory to LDS; every
-// thread issues up to 12 loads before its first store.
-template <typename V>
+// Copy n_frags operand fragments (1 KB each) from global memory to LDS with
+// the NT threads of the workgroup; every thread issues up to 12 loads before
+// its first store.
+template <int NT = 256, typename V>
 __device__ inline void stage_frags(V* dst, const V* src, int n_frags) {
     const int total = n_frags * 64;
-    for (int base = 0; base < total; base += 12 * 256) {
+    for (int base = 0; base < total; base += 12 * NT) {
         V tmp[12];
         #pragma unroll
         for (int u = 0; u < 12; ++u) {
-            const int i = base + u * 256 + (int)threadIdx.x;
+            const int i = base + u * NT + (int)threadIdx.x;
             if (i < total) tmp[u] = src[i];
         }
         #pragma unroll
         for (int u = 0; u < 12; ++u) {
-            const int i = base + u * 256 + (int)threadIdx.x;
+            const int i = base + u * NT + (int)threadIdx.x;
             if (i < total) dst[i] = tmp[u];
         }
     }
@@ -112,14 +113,16 @@ __device__ inline void stage_frags(V* dst, const V* src, int n_frags) {
 // encoded features, natural order); returns the output accumulators (lanes
 // 0..15 hold rows 0..3, i.e. the RGB values and a zero row).  Each layer's
 // first K chunk starts from a zero accumulator (an inline constant operand)
-// and ReLU is applied to the packed 16-bit result.
-template <typename T, int W, int COLS>
+// and ReLU is applied to the packed 16-bit result.  NH > 0 fixes the number
+// of hidden layers at compile time (the loop unrolls); NH = 0 reads n_hidden.
+template <typename T, int W, int COLS, int NH = 0>
 __device__ inline void mlp_tile(const typename Vec8<T>::type* sfr, typename Vec8<T>::type (&b)[COLS][W / 32],
                                 int n_hidden, int lane, f32x4 (&o)[COLS]) {
     using V = typename Vec8<T>::type;
     constexpr int MB = W / 16, KC = W / 32;
+    if (NH > 0) n_hidden = NH;
     const Geo geo(W, n_hidden);
-    for (int l = 0; l < n_hidden; ++l) {
+    auto layer = [&](int l) {
         const int kc = l == 0 ? 2 : KC;    // the input layer has K = 64
         const V* fl = sfr + geo.fwd_base(l) * 64 + lane;
         f32x4 acc[COLS][MB];
@@ -144,6 +147,12 @@ __device__ inline void mlp_tile(const typename Vec8<T>::type* sfr, typename Vec8
             #pragma unroll
             for (int c = 0; c < KC; ++c)
                 b[col][c] = relu_packed(pack8<T, V>(acc[col][2 * c], acc[col][2 * c + 1]));
+    };
+    if constexpr (NH > 0) {
+        #pragma unroll
+        for (int l = 0; l < NH; ++l) layer(l);
+    } else {
+        for (int l = 0; l < n_hidden; ++l) layer(l);
     }
     const V* fo = sfr + geo.fwd_base(n_hidden) * 64 + lane;
     #pragma unroll
@@ -245,8 +254,9 @@ __global__ __launch_bounds__(256, 2) void k_fwd_mfma(const T* __restrict__ ffr, 
 // (the next tile's raw floats are loaded while the current tile computes),
 // writes its 64 features to the wave's own LDS rows, and the wave reads them
 // back as B operands.  HBM traffic per query: the raw record in, RGB out.
-template <typename T, int W, int PRESET, int LAYOUT>
-__global__ __launch_bounds__(256, 2) void k_fwd_raw_mfma(const T* __restrict__ ffr, int n_frags,
+// NW waves per workgroup share one copy of the weights in LDS.
+template <typename T, int W, int PRESET, int LAYOUT, int NW>
+__global__ __launch_bounds__(64 * NW) void k_fwd_raw_mfma(const T* __restrict__ ffr, int n_frags,
                                                          const float* __restrict__ raw, int64_t n,
                                                          float* __restrict__ rgb, int n_hidden, int fcol) {
     using V = typename Vec8<T>::type;
@@ -258,11 +268,11 @@ __global__ __launch_bounds__(256, 2) void k_fwd_raw_mfma(const T* __restrict__ f
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int g = lane >> 4, ln = lane & 15;
     T* senc = reinterpret_cast<T*>(smem_raw + n_frags * 1024) + wave * 64 * ROW;
-    stage_frags(sfr, reinterpret_cast<const V*>(ffr), n_frags);
+    stage_frags<64 * NW>(sfr, reinterpret_cast<const V*>(ffr), n_frags);
     __syncthreads();
 
     const int64_t n_tiles = (n + 63) / 64;
-    const int64_t tstride = (int64_t)gridDim.x * 4;
+    const int64_t tstride = (int64_t)gridDim.x * NW;
     float x[RW];
     auto load_raw = [&](int64_t t) {
         int64_t row = t * 64 + lane;
@@ -282,7 +292,7 @@ __global__ __launch_bounds__(256, 2) void k_fwd_raw_mfma(const T* __restrict__ f
             }
         }
     };
-    int64_t tile = (int64_t)blockIdx.x * 4 + wave;
+    int64_t tile = (int64_t)blockIdx.x * NW + wave;
     if (tile < n_tiles) load_raw(tile);
     for (; tile < n_tiles; tile += tstride) {
         {
@@ -315,6 +325,102 @@ __global__ __launch_bounds__(256, 2) void k_fwd_raw_mfma(const T* __restrict__ f
         for (int col = 0; col < COLS; ++col) reflectance_operand(b[col][1], fcol, ln, r[col]);
         f32x4 o[COLS];
         mlp_tile<T, W, COLS>(sfr, b, n_hidden, lane, o);
+        store_rgb<COLS>(o, r, tile * 64, n, g, ln, rgb);
+    }
+}
+
+// Encodes the lane's record x and stores its 64 features, rounded to T, at
+// dst (a 16-byte aligned LDS row).
+template <typename T, int PRESET, int LAYOUT>
+__device__ inline void encode_to_lds(const float* x, T* dst) {
+    using V = typename Vec8<T>::type;
+    float f[64];
+    encode_record<PRESET, LAYOUT>(x, f);
+    #pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const f32x4 lo = f32x4{f[8 * q], f[8 * q + 1], f[8 * q + 2], f[8 * q + 3]};
+        const f32x4 hi = f32x4{f[8 * q + 4], f[8 * q + 5], f[8 * q + 6], f[8 * q + 7]};
+        *reinterpret_cast<V*>(dst + 8 * q) = pack8<T, V>(lo, hi);
+    }
+}
+
+// Orders a wave's LDS accesses: those before complete before those after,
+// across the wave's lanes.
+__device__ inline void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Fused raw -> encode -> network inference for a depth fixed at compile time
+// (NH hidden layers of width 64), software-pipelined: while a wave's matrix
+// cores run tile t, its vector ALUs encode tile t + stride into the wave's LDS
+// rows.  The whole tile is one basic block (layers unrolled, loads clamped
+// instead of branched), and the weights and encode rows are distinct
+// __shared__ arrays, so the compiler may interleave the two instruction
+// streams.  Results equal k_fwd_raw_mfma's bit for bit: every record goes
+// through the same arithmetic.  (Measured: matrix and vector work of one wave
+// overlap only partly on gfx950, about half of the MFMA time.)
+template <typename T, int PRESET, int LAYOUT, int NH, int NW>
+__global__ __launch_bounds__(64 * NW) void k_fwd_raw_mfma_fixed(const T* __restrict__ ffr,
+                                                               const float* __restrict__ raw, int64_t n,
+                                                               float* __restrict__ rgb, int fcol) {
+    using V = typename Vec8<T>::type;
+    constexpr int W = 64, COLS = 4, KC = 2;
+    constexpr int RW = LAYOUT == NRC_RAW14 ? 14 : 16;
+    constexpr int ROW = 72;                                // LDS row stride of an encoded record
+    constexpr int NF = 2 * (W / 16) + (NH - 1) * (W / 16) * KC + KC;   // forward fragments
+    __shared__ V sfr[NF * 64];
+    __shared__ __attribute__((aligned(16))) T senc_all[NW * 64 * ROW];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane >> 4, ln = lane & 15;
+    T* senc = senc_all + wave * 64 * ROW;
+    stage_frags<64 * NW>(sfr, reinterpret_cast<const V*>(ffr), NF);
+    __syncthreads();
+
+    const int64_t n_tiles = (n + 63) / 64;
+    const int64_t tstride = (int64_t)gridDim.x * NW;
+    float x[RW];
+    auto load_raw = [&](int64_t t) {      // rows past the end read the last row
+        int64_t row = t * 64 + lane;
+        row = row < n ? row : n - 1;
+        const float* src = raw + row * RW;
+        if (RW == 16) {
+            #pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const float4 v = reinterpret_cast<const float4*>(src)[q];
+                x[4 * q] = v.x; x[4 * q + 1] = v.y; x[4 * q + 2] = v.z; x[4 * q + 3] = v.w;
+            }
+        } else {
+            #pragma unroll
+            for (int q = 0; q < RW / 2; ++q) {
+                const float2 v = reinterpret_cast<const float2*>(src)[q];
+                x[2 * q] = v.x; x[2 * q + 1] = v.y;
+            }
+        }
+    };
+    int64_t tile = (int64_t)blockIdx.x * NW + wave;
+    if (tile >= n_tiles) return;
+    load_raw(tile);
+    encode_to_lds<T, PRESET, LAYOUT>(x, senc + lane * ROW);
+    load_raw(tile + tstride);
+    for (; tile < n_tiles; tile += tstride) {
+        wave_lds_sync();                   // this tile's rows are written
+        V b[COLS][KC];
+        #pragma unroll
+        for (int col = 0; col < COLS; ++col)
+            #pragma unroll
+            for (int c = 0; c < 2; ++c)
+                b[col][c] = *reinterpret_cast<const V*>(senc + (16 * col + ln) * ROW + 32 * c + 8 * g);
+        wave_lds_sync();                   // and read by every lane before they are rewritten
+        float r[COLS][3];
+        #pragma unroll
+        for (int col = 0; col < COLS; ++col) reflectance_operand(b[col][1], fcol, ln, r[col]);
+        // the next tile's encoding (vector ALUs) beside this tile's network (matrix cores)
+        encode_to_lds<T, PRESET, LAYOUT>(x, senc + lane * ROW);
+        load_raw(tile + 2 * tstride);
+        f32x4 o[COLS];
+        mlp_tile<T, W, COLS, NH>(sfr, b, NH, lane, o);
         store_rgb<COLS>(o, r, tile * 64, n, g, ln, rgb);
     }
 }
@@ -588,24 +694,54 @@ hipError_t fwd_dispatch(const Geo& d, const void* ffr, const void* enc, int64_t 
     return hipGetLastError();
 }
 
-template <typename T, int W, int PRESET, int LAYOUT>
+// Waves per workgroup of the fused kernel and the persistent grid's size:
+// 12 waves share one LDS copy of the weights (42 KB) beside their 12 encode
+// buffers (110 KB), one workgroup per CU, three waves per SIMD.
+constexpr int kRawWaves = 12;
+constexpr int kRawMaxBlocks = 512;
+
+template <typename T, int W, int PRESET, int LAYOUT, int NW = kRawWaves>
 hipError_t fwd_raw_launch(const Geo& d, const void* ffr, const float* raw, int64_t n, float* rgb,
-                          hipStream_t s) {
+                          hipStream_t s, int max_blocks = kRawMaxBlocks) {
     const int64_t tiles = (n + 63) / 64;
     if (tiles == 0) return hipSuccess;
-    const size_t lds = (size_t)d.n_fwd_frags() * 1024 + 4 * 64 * 72 * sizeof(T);
-    int64_t blocks = (tiles + 3) / 4;
-    if (blocks > 2048) blocks = 2048;
-    auto k = k_fwd_raw_mfma<T, W, PRESET, LAYOUT>;
+    const size_t lds = (size_t)d.n_fwd_frags() * 1024 + (size_t)NW * 64 * 72 * sizeof(T);
+    int64_t blocks = (tiles + NW - 1) / NW;
+    if (blocks > max_blocks) blocks = max_blocks;
+    auto k = k_fwd_raw_mfma<T, W, PRESET, LAYOUT, NW>;
     (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(256), lds, s, (const T*)ffr, d.n_fwd_frags(), raw,
+    hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(64 * NW), lds, s, (const T*)ffr, d.n_fwd_frags(), raw,
                        n, rgb, d.H, d.F);
+    return hipGetLastError();
+}
+
+// The fixed-depth, software-pipelined kernel for the paper's 5 hidden layers.
+template <typename T, int PRESET, int LAYOUT>
+hipError_t fwd_raw_fixed_launch(const Geo& d, const void* ffr, const float* raw, int64_t n, float* rgb,
+                                hipStream_t s, int max_blocks = kRawMaxBlocks) {
+    constexpr int NW = kRawWaves;
+    const int64_t tiles = (n + 63) / 64;
+    if (tiles == 0) return hipSuccess;
+    int64_t blocks = (tiles + NW - 1) / NW;
+    if (blocks > max_blocks) blocks = max_blocks;
+    hipLaunchKernelGGL((k_fwd_raw_mfma_fixed<T, PRESET, LAYOUT, 5, NW>), dim3((unsigned)blocks),
+                       dim3(64 * NW), 0, s, (const T*)ffr, raw, n, rgb, d.F);
     return hipGetLastError();
 }
 
 template <typename T, int W>
 hipError_t fwd_raw_dispatch(const Geo& d, int preset, int layout, const void* ffr, const float* raw,
                             int64_t n, float* rgb, hipStream_t s) {
+    if (W == 64 && d.H == 5) {
+        if (preset == NRC_PRESET_PAPER_TRI)
+            return layout == NRC_RAW14 ? fwd_raw_fixed_launch<T, NRC_PRESET_PAPER_TRI, NRC_RAW14>(d, ffr, raw, n, rgb, s)
+                                       : fwd_raw_fixed_launch<T, NRC_PRESET_PAPER_TRI, NRC_RAW16>(d, ffr, raw, n, rgb, s);
+        if (preset == NRC_PRESET_PAPER)
+            return layout == NRC_RAW14 ? fwd_raw_fixed_launch<T, NRC_PRESET_PAPER, NRC_RAW14>(d, ffr, raw, n, rgb, s)
+                                       : fwd_raw_fixed_launch<T, NRC_PRESET_PAPER, NRC_RAW16>(d, ffr, raw, n, rgb, s);
+        return layout == NRC_RAW14 ? fwd_raw_fixed_launch<T, NRC_PRESET_CONFIG, NRC_RAW14>(d, ffr, raw, n, rgb, s)
+                                   : fwd_raw_fixed_launch<T, NRC_PRESET_CONFIG, NRC_RAW16>(d, ffr, raw, n, rgb, s);
+    }
     if (preset == NRC_PRESET_PAPER_TRI)
         return layout == NRC_RAW14 ? fwd_raw_launch<T, W, NRC_PRESET_PAPER_TRI, NRC_RAW14>(d, ffr, raw, n, rgb, s)
                                    : fwd_raw_launch<T, W, NRC_PRESET_PAPER_TRI, NRC_RAW16>(d, ffr, raw, n, rgb, s);

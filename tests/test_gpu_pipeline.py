@@ -75,11 +75,60 @@ def test_indexed_step_equals_step_on_gathered_batch(N, prec):
     assert np.array_equal(a.get_weights(), b.get_weights())
 
 
+def check_fp32_adam_step(w_gpu, st_before, w_ref, x, y):
+    """FP32 weights after one Adam step against the oracle's step from the same
+    state.  Adam moves a weight by about lr * sign(g) when its moments are young,
+    so a gradient component within FP32 rounding of zero (the GPU sums 16,384
+    products per component in FP32 tiles of 64: relative error of order 1e-6
+    of the sum of magnitudes) can take the other sign and move by 2 lr.  Such
+    flips are allowed only where the FP64 gradient is below 1e-6 of its norm,
+    and at most a handful; every other weight must match to 1e-5 normwise."""
+    _, g = O.gradient(st_before, x, y)
+    d = np.asarray(w_gpu, np.float64) - w_ref
+    flipped = np.abs(d) > 1e-3                       # a flip moves by 2 lr = 0.02
+    assert flipped.sum() <= 8, int(flipped.sum())
+    assert np.all(np.abs(g[flipped]) <= 1e-6 * np.linalg.norm(g)), (np.abs(g[flipped]), np.linalg.norm(g))
+    rest = np.where(flipped, 0.0, d)
+    assert np.linalg.norm(rest) / np.linalg.norm(w_ref) <= 1e-5
+
+
 @pytest.mark.parametrize("prec", ["fp32", "fp16", "bf16"])
 @pytest.mark.parametrize("n_records", [65536, 50001, 70000])
-def test_train_frame_matches_oracle(N, prec, n_records):
+def test_frame_steps_match_oracle_from_the_same_state(N, prec, n_records):
+    # Each of the frame's steps against the oracle's step from the GPU's own
+    # state before it (weights, Adam moments, t), on the oracle's shuffled
+    # batch: the arithmetic of every step is checked without the rounding
+    # differences of earlier steps compounding through Adam's sign-like
+    # first update.
     c, w = make_cache(N, prec)
     raw = sd.raw_records(n_records, 82)
+    enc = N.nrc_encode(c, dev(raw), 0)
+    e64 = enc.float().cpu().numpy().astype(np.float64)
+    y = sd.targets(raw)
+    yd = dev(y)
+    perm = N.nrc_shuffle(n_records, 77)
+    batches = O.frame_batches(n_records, 4, 16384, 77)
+    assert np.array_equal(perm.cpu().numpy()[:sum(b.size for b in batches)], np.concatenate(batches))
+    tol = 1e-5 if prec == "fp32" else 1e-2
+    lo = 0
+    for k, idx in enumerate(batches):
+        wt, m, v, t = c.get_state()
+        st = O.CacheState(wt.astype(np.float64), m=m.astype(np.float64), v=v.astype(np.float64), t=t)
+        st_before = O.CacheState(st.w.copy(), m=st.m.copy(), v=st.v.copy(), t=t)
+        ref_loss, ref_skip = O.train_step(st, e64[idx], y[idx].astype(np.float64))
+        loss, skipped = N.nrc_train_step_indexed(c, enc, yd, perm[lo:lo + idx.size].contiguous())
+        lo += idx.size
+        assert int(skipped.item()) == 0 and not ref_skip
+        assert abs(loss.item() - ref_loss) <= tol * abs(ref_loss), (k, loss.item(), ref_loss)
+        if prec == "fp32":
+            check_fp32_adam_step(c.get_weights(), st_before, st.w, e64[idx], y[idx].astype(np.float64))
+
+
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+def test_train_frame_matches_oracle_frame(N, prec):
+    # The whole reduced-precision frame against the oracle's frame (4 x 16,384).
+    c, w = make_cache(N, prec)
+    raw = sd.raw_records(65536, 82)
     enc = N.nrc_encode(c, dev(raw), 0)
     e64 = enc.float().cpu().numpy().astype(np.float64)
     y = sd.targets(raw)
@@ -88,18 +137,18 @@ def test_train_frame_matches_oracle(N, prec, n_records):
     q, q64 = rounded_input(O.encode(sd.raw_records(4096, sd.SEED_HELDOUT)), prec)
     _, ref_losses, ref_skips = O.frame_shuffled(st, q64, e64, y.astype(np.float64), 4, 16384, 77)
     assert skipped.cpu().tolist() == [0, 0, 0, 0] and not any(ref_skips)
-    tol = 1e-5 if prec == "fp32" else 1e-2
     got_l = losses.cpu().numpy()
-    assert np.all(np.abs(got_l - ref_losses) <= tol * np.abs(ref_losses)), (got_l, ref_losses)
+    assert np.all(np.abs(got_l - ref_losses) <= 1e-2 * np.abs(ref_losses)), (got_l, ref_losses)
     got = N.nrc_forward(c, q).cpu().numpy()
-    assert np.all(l2_err(got, O.predict(st, q64)) <= tol)
+    assert np.all(l2_err(got, O.predict(st, q64)) <= 1e-2)
 
 
-def test_train_frame_equals_shuffle_then_indexed_steps(N):
+@pytest.mark.parametrize("prec", ["fp32", "fp16", "bf16"])
+def test_train_frame_equals_shuffle_then_indexed_steps(N, prec):
     raw = sd.raw_records(70000, 83)
     y = dev(sd.targets(raw))
-    a, _ = make_cache(N, "fp16")
-    b, _ = make_cache(N, "fp16")
+    a, _ = make_cache(N, prec)
+    b, _ = make_cache(N, prec)
     enc = N.nrc_encode(a, dev(raw), 0)
     la, _ = N.nrc_train_frame(a, enc, y, steps=4, batch=16384, seed=5)
     perm = N.nrc_shuffle(70000, 5)
