@@ -113,16 +113,22 @@ __device__ inline float wave_sum(float v) {
 // With the reflectance factorisation (fcol != 0) y is the network output times
 // R = alpha + beta; the network's output gradient is dL/dy * R, and dL/denc
 // also takes dL/dy_c * f_c on both albedo columns of channel c.
-template <bool UPSTREAM, bool GENC>
-__global__ __launch_bounds__(256) void k_train_fp32(const float* __restrict__ w,
-                                                    const float* __restrict__ enc,
-                                                    const float* __restrict__ tgt,
-                                                    const int32_t* __restrict__ idx, int64_t n,
-                                                    int n_hidden, int n_params, float loss_eps,
-                                                    float grad_scale, float* __restrict__ partials,
-                                                    float* __restrict__ loss_part,
-                                                    int32_t* __restrict__ tile_bad,
-                                                    float* __restrict__ genc, int fcol) {
+// NWV waves share a tile of 64 records; wave w owns FPW = 64 / NWV features
+// (forward and data backward, lane = record) and FPW rows of each dW_l (lane =
+// input feature).  More waves per tile give each SIMD more waves to hide the
+// latency of LDS and scalar weight loads.
+template <bool UPSTREAM, bool GENC, int NWV>
+__global__ __launch_bounds__(64 * NWV) void k_train_fp32(const float* __restrict__ w,
+                                                         const float* __restrict__ enc,
+                                                         const float* __restrict__ tgt,
+                                                         const int32_t* __restrict__ idx, int64_t n,
+                                                         int n_hidden, int n_params, float loss_eps,
+                                                         float grad_scale, float* __restrict__ partials,
+                                                         float* __restrict__ loss_part,
+                                                         int32_t* __restrict__ tile_bad,
+                                                         float* __restrict__ genc, int fcol) {
+    constexpr int FPW = kW / NWV;                          // features (or dW rows) per wave
+    constexpr int NT = 64 * NWV;
     extern __shared__ __attribute__((aligned(16))) float smem[];
     float* hs = smem;                                     // (n_hidden+1) x [64][kLd]
     float* dbuf0 = hs + (n_hidden + 1) * kTile * kLd;     // 2 x [64][kLd]
@@ -139,9 +145,10 @@ __global__ __launch_bounds__(256) void k_train_fp32(const float* __restrict__ w,
     // record read for this slot: idx[row] for a gathered batch, else row
     const int64_t src = !valid ? 0 : idx ? (int64_t)idx[row] : row;
     float* part = partials + tile * (int64_t)n_params;
+    const int f0 = FPW * wave;                            // this wave's first feature / dW row
 
     // Stage the tile's inputs as h_0 (zeros past the end of the batch).
-    for (int i = tid; i < kTile * 16; i += 256) {
+    for (int i = tid; i < kTile * 16; i += NT) {
         const int s = i >> 4, q = i & 15;
         const int64_t r = tile * kTile + s;
         float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -150,7 +157,7 @@ __global__ __launch_bounds__(256) void k_train_fp32(const float* __restrict__ w,
     }
     __syncthreads();
 
-    // Forward: wave w writes features 16w..16w+15 of every sample (lane = sample).
+    // Forward: wave w writes features f0..f0+FPW-1 of every sample (lane = sample).
     // Layer l's weights start at w + l * 64 * 64 (the input layer is 64 x 64
     // too); addressing them from the base pointer, not a running one, keeps the
     // scalar register file from spilling.
@@ -158,15 +165,15 @@ __global__ __launch_bounds__(256) void k_train_fp32(const float* __restrict__ w,
         const float* wl = w + l * kW * kW;
         const float* hin = hs + l * kTile * kLd + lane * kLd;
         float* hout = hs + (l + 1) * kTile * kLd + lane * kLd;
-        float acc[16];
+        float acc[FPW];
         #pragma unroll
-        for (int j = 0; j < 16; ++j) acc[j] = 0.0f;
+        for (int j = 0; j < FPW; ++j) acc[j] = 0.0f;
         #pragma unroll
         for (int k4 = 0; k4 < 16; ++k4) {
             const float4 hv = *reinterpret_cast<const float4*>(hin + 4 * k4);
             #pragma unroll
-            for (int j = 0; j < 16; ++j) {
-                const float* wr = wl + (16 * wave + j) * kW + 4 * k4;
+            for (int j = 0; j < FPW; ++j) {
+                const float* wr = wl + (f0 + j) * kW + 4 * k4;
                 acc[j] = fmaf(wr[0], hv.x, acc[j]);
                 acc[j] = fmaf(wr[1], hv.y, acc[j]);
                 acc[j] = fmaf(wr[2], hv.z, acc[j]);
@@ -174,8 +181,8 @@ __global__ __launch_bounds__(256) void k_train_fp32(const float* __restrict__ w,
             }
         }
         #pragma unroll
-        for (int j4 = 0; j4 < 4; ++j4)
-            *reinterpret_cast<float4*>(hout + 16 * wave + 4 * j4) =
+        for (int j4 = 0; j4 < FPW / 4; ++j4)
+            *reinterpret_cast<float4*>(hout + f0 + 4 * j4) =
                 make_float4(fmaxf(acc[4 * j4], 0.f), fmaxf(acc[4 * j4 + 1], 0.f),
                             fmaxf(acc[4 * j4 + 2], 0.f), fmaxf(acc[4 * j4 + 3], 0.f));
         __syncthreads();
@@ -226,14 +233,14 @@ __global__ __launch_bounds__(256) void k_train_fp32(const float* __restrict__ w,
     }
     __syncthreads();
 
-    // delta_H = W_H^T dL/dy, masked by ReLU'(z_H); wave w: features 16w..16w+15.
+    // delta_H = W_H^T dL/dy, masked by ReLU'(z_H); wave w: features f0..f0+FPW-1.
     {
         const float4 dv = *reinterpret_cast<const float4*>(dout + lane * 4);
-        const float* hr = hlast + lane * kLd + 16 * wave;
-        float* dst = dbuf0 + lane * kLd + 16 * wave;
+        const float* hr = hlast + lane * kLd + f0;
+        float* dst = dbuf0 + lane * kLd + f0;
         #pragma unroll
-        for (int j = 0; j < 16; ++j) {
-            const int i = 16 * wave + j;
+        for (int j = 0; j < FPW; ++j) {
+            const int i = f0 + j;
             float g = wout[i] * dv.x;
             g = fmaf(wout[kW + i], dv.y, g);
             g = fmaf(wout[2 * kW + i], dv.z, g);
@@ -258,16 +265,16 @@ __global__ __launch_bounds__(256) void k_train_fp32(const float* __restrict__ w,
         off -= kW * cols;
         const float* wlay = w + off;
         const float* hl = hs + l * kTile * kLd;
-        // dW_l rows 16w..16w+15, lane = input feature i.
+        // dW_l rows f0..f0+FPW-1, lane = input feature i.
         {
-            float acc[16];
+            float acc[FPW];
             #pragma unroll
-            for (int j = 0; j < 16; ++j) acc[j] = 0.0f;
+            for (int j = 0; j < FPW; ++j) acc[j] = 0.0f;
             for (int s = 0; s < kTile; ++s) {
                 const float hv = hl[s * kLd + lane];
-                const float* dr = dcur + s * kLd + 16 * wave;
+                const float* dr = dcur + s * kLd + f0;
                 #pragma unroll
-                for (int j4 = 0; j4 < 4; ++j4) {
+                for (int j4 = 0; j4 < FPW / 4; ++j4) {
                     const float4 dv = *reinterpret_cast<const float4*>(dr + 4 * j4);
                     acc[4 * j4] = fmaf(dv.x, hv, acc[4 * j4]);
                     acc[4 * j4 + 1] = fmaf(dv.y, hv, acc[4 * j4 + 1]);
@@ -276,23 +283,23 @@ __global__ __launch_bounds__(256) void k_train_fp32(const float* __restrict__ w,
                 }
             }
             #pragma unroll
-            for (int j = 0; j < 16; ++j) {
-                part[off + (16 * wave + j) * cols + lane] = acc[j];
+            for (int j = 0; j < FPW; ++j) {
+                part[off + (f0 + j) * cols + lane] = acc[j];
                 bad |= !isfinite(acc[j]);
             }
         }
         // delta_l = W_l^T delta_{l+1}, masked (l >= 1); or dL/dh_0 (l == 0).
         if (l >= 1 || GENC) {
-            float acc[16];
+            float acc[FPW];
             #pragma unroll
-            for (int j = 0; j < 16; ++j) acc[j] = 0.0f;
+            for (int j = 0; j < FPW; ++j) acc[j] = 0.0f;
             const float* dr = dcur + lane * kLd;
             #pragma unroll
             for (int o4 = 0; o4 < 16; ++o4) {
                 const float4 dv = *reinterpret_cast<const float4*>(dr + 4 * o4);
                 #pragma unroll
-                for (int j = 0; j < 16; ++j) {
-                    const float* wc = wlay + (4 * o4) * cols + 16 * wave + j;
+                for (int j = 0; j < FPW; ++j) {
+                    const float* wc = wlay + (4 * o4) * cols + f0 + j;
                     acc[j] = fmaf(wc[0], dv.x, acc[j]);
                     acc[j] = fmaf(wc[cols], dv.y, acc[j]);
                     acc[j] = fmaf(wc[2 * cols], dv.z, acc[j]);
@@ -300,16 +307,16 @@ __global__ __launch_bounds__(256) void k_train_fp32(const float* __restrict__ w,
                 }
             }
             if (l >= 1) {
-                const float* hr = hl + lane * kLd + 16 * wave;
-                float* dst = dnxt + lane * kLd + 16 * wave;
+                const float* hr = hl + lane * kLd + f0;
+                float* dst = dnxt + lane * kLd + f0;
                 #pragma unroll
-                for (int j = 0; j < 16; ++j) dst[j] = hr[j] > 0.0f ? acc[j] : 0.0f;
+                for (int j = 0; j < FPW; ++j) dst[j] = hr[j] > 0.0f ? acc[j] : 0.0f;
             } else if (valid) {
                 if (fcol) {
                     // d(f_c R_c)/d(albedo column) = f_c on the diffuse and specular column.
                     #pragma unroll
-                    for (int j = 0; j < 16; ++j) {
-                        int c = 16 * wave + j - fcol;
+                    for (int j = 0; j < FPW; ++j) {
+                        int c = f0 + j - fcol;
                         if (c >= 0 && c < 6) {
                             c = c >= 3 ? c - 3 : c;
                             acc[j] = fmaf(tgt[src * 3 + c], fout[lane * 4 + c], acc[j]);
@@ -317,8 +324,8 @@ __global__ __launch_bounds__(256) void k_train_fp32(const float* __restrict__ w,
                     }
                 }
                 #pragma unroll
-                for (int j4 = 0; j4 < 4; ++j4)
-                    *reinterpret_cast<float4*>(genc + row * kEncWidth + 16 * wave + 4 * j4) =
+                for (int j4 = 0; j4 < FPW / 4; ++j4)
+                    *reinterpret_cast<float4*>(genc + row * kEncWidth + f0 + 4 * j4) =
                         make_float4(acc[4 * j4], acc[4 * j4 + 1], acc[4 * j4 + 2], acc[4 * j4 + 3]);
             }
         }
@@ -368,31 +375,36 @@ size_t fp32_train_lds_bytes(int n_hidden) {
     return ((size_t)(n_hidden + 1) * kTile * kLd + 2 * kTile * kLd + 2 * kTile * 4) * sizeof(float);
 }
 
-hipError_t launch_train_fp32(const Geo& d, const float* w, const float* enc, const float* tgt,
-                             const int32_t* idx, int64_t n, bool upstream, float loss_eps, float grad_scale,
+// Waves per 64-record training tile of the FP32 form.
+constexpr int kTrainWaves = 16;
+
+template <bool UP, bool GE, int NWV>
+hipError_t train_fp32_launch(const Geo& d, const float* w, const float* enc, const float* tgt,
+                             const int32_t* idx, int64_t n, float loss_eps, float grad_scale,
                              float* partials, float* loss_part, int32_t* tile_bad, float* genc,
                              hipStream_t s) {
     const int64_t tiles = (n + kTile - 1) / kTile;
     if (tiles == 0) return hipSuccess;
     const size_t lds = fp32_train_lds_bytes(d.H);
-    const dim3 grid((unsigned)tiles), block(256);
-    if (!upstream) {
-        auto k = k_train_fp32<false, false>;
-        (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        hipLaunchKernelGGL(k, grid, block, lds, s, w, enc, tgt, idx, n, d.H, d.n_params(),
-                           loss_eps, grad_scale, partials, loss_part, tile_bad, genc, d.F);
-    } else if (genc) {
-        auto k = k_train_fp32<true, true>;
-        (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        hipLaunchKernelGGL(k, grid, block, lds, s, w, enc, tgt, idx, n, d.H, d.n_params(),
-                           loss_eps, grad_scale, partials, loss_part, tile_bad, genc, d.F);
-    } else {
-        auto k = k_train_fp32<true, false>;
-        (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        hipLaunchKernelGGL(k, grid, block, lds, s, w, enc, tgt, idx, n, d.H, d.n_params(),
-                           loss_eps, grad_scale, partials, loss_part, tile_bad, genc, d.F);
-    }
+    auto k = k_train_fp32<UP, GE, NWV>;
+    (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k, dim3((unsigned)tiles), dim3(64 * NWV), lds, s, w, enc, tgt, idx, n, d.H,
+                       d.n_params(), loss_eps, grad_scale, partials, loss_part, tile_bad, genc, d.F);
     return hipGetLastError();
+}
+
+hipError_t launch_train_fp32(const Geo& d, const float* w, const float* enc, const float* tgt,
+                             const int32_t* idx, int64_t n, bool upstream, float loss_eps, float grad_scale,
+                             float* partials, float* loss_part, int32_t* tile_bad, float* genc,
+                             hipStream_t s) {
+    if (!upstream)
+        return train_fp32_launch<false, false, kTrainWaves>(d, w, enc, tgt, idx, n, loss_eps, grad_scale,
+                                                            partials, loss_part, tile_bad, genc, s);
+    if (genc)
+        return train_fp32_launch<true, true, kTrainWaves>(d, w, enc, tgt, idx, n, loss_eps, grad_scale,
+                                                          partials, loss_part, tile_bad, genc, s);
+    return train_fp32_launch<true, false, kTrainWaves>(d, w, enc, tgt, idx, n, loss_eps, grad_scale,
+                                                       partials, loss_part, tile_bad, genc, s);
 }
 
 }  // namespace nrc
