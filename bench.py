@@ -42,7 +42,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-KERNEL_SOURCES = {"k_fwd_raw_mfma": ["mlp_mfma.hip", "encode_impl.h", "nrc_internal.h"],
+KERNEL_SOURCES = {"k_fwd_raw_mfma_fixed": ["mlp_mfma.hip", "encode_impl.h", "nrc_internal.h"],
                   "k_fwd_raw_fp32": ["mlp_fp32.hip", "encode_impl.h", "nrc_internal.h"]}
 
 
@@ -150,13 +150,13 @@ def frame_bench(form: str, steps: int, warmup: int):
         "mlp_only_queries_per_s": N_QUERIES / t_fwd,
         "train_only_samples_per_s": N_TRAIN_BATCHES * TRAIN_BATCH / (comp[2] * 1e-3),
         "roofline": {
-            "kernel": "k_fwd_raw_mfma" if form != "fp32" else "k_fwd_raw_fp32",
+            "kernel": "k_fwd_raw_mfma_fixed" if form != "fp32" else "k_fwd_raw_fp32",
             "bound": BOUND[form],
             "achieved": achieved,
             "peak": PEAK_TFLOPS[form],
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_TFLOPS[form],
-            "traffic": measured_traffic("k_fwd_raw_mfma" if form != "fp32" else "k_fwd_raw_fp32", form),
+            "traffic": measured_traffic("k_fwd_raw_mfma_fixed" if form != "fp32" else "k_fwd_raw_fp32", form),
             "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "flop_per_query": FLOP_PER_QUERY,
             "queries_per_launch": N_QUERIES,
