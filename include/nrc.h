@@ -113,7 +113,8 @@ int64_t nrc_param_count(const nrc_config* cfg);
 size_t nrc_cache_bytes(const nrc_config* cfg);
 
 /* Bytes of device scratch one nrc_train_step / nrc_backward over n records
- * needs (per-tile weight-gradient partials and loss partials). */
+ * needs: two regions of per-tile weight-gradient partials (consecutive steps
+ * of a cache alternate between them), loss partials and flags. */
 size_t nrc_train_scratch_bytes(const nrc_config* cfg, int64_t n);
 
 /* Bytes per element of the encoded input at the cache precision (4 or 2). */

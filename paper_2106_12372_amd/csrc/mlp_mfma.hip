@@ -666,8 +666,8 @@ __global__ __launch_bounds__(256) void k_train_mfma(const T* __restrict__ ffr,
                     for (int kc = 1; kc < TK; ++kc)
                         acc = mfma(*reinterpret_cast<const V*>(dl + (16 * mb + ln) * LDT + 32 * kc + 8 * g),
                                    bb[kc], acc);
-                    *reinterpret_cast<float4*>(part + woff + ((mb * NB + nb) * 64 + lane) * 4) =
-                        make_float4(acc[0], acc[1], acc[2], acc[3]);
+                    // streamed past the caches: read once, by the reduction
+                    __builtin_nontemporal_store(acc, reinterpret_cast<f32x4*>(part + woff + ((mb * NB + nb) * 64 + lane) * 4));
                     #pragma unroll
                     for (int j = 0; j < 4; ++j) bad |= !isfinite(acc[j]);
                 }

@@ -107,6 +107,7 @@ ScratchLayout scratch_layout(const nrc_config& c, int64_t n) {
     auto take = [&](size_t bytes) { const size_t o = off; off = align256(off + bytes); return o; };
     L.tiles = (int64_t)tiles;
     L.partials = take(tiles * P * 4);
+    L.partials2 = take(tiles * P * 4);
     L.loss_part = take(tiles * 4);
     L.grad = take(P * 4);
     L.flags = take(tiles * 4);
@@ -129,7 +130,7 @@ int enqueue_train_step(nrc_cache* c, const void* enc, const float* target, const
     const nrc_config& cfg = c->cfg;
     const Geo d = kernel_geo(cfg);
     const ScratchLayout sl = scratch_layout(cfg, n);
-    float* partials = (float*)(scratch + sl.partials);
+    float* partials = (float*)(scratch + (c->parity ? sl.partials2 : sl.partials));
     float* loss_part = (float*)(scratch + sl.loss_part);
     int32_t* tile_bad = (int32_t*)(scratch + sl.flags);
     const float scale = cfg.loss_scale;

@@ -97,15 +97,18 @@ __global__ __launch_bounds__(256) void k_reduce(const float* __restrict__ partia
     }
     float s = 0.0f, c = 0.0f;
     if (sidx < P) {
+        // 16 loads in flight per thread before the (order-preserving) sums
         int t = grp;
-        for (; t + 3 * kRedGroups < n_tiles; t += 4 * kRedGroups) {
-            float x[4];
+        for (; t + 15 * kRedGroups < n_tiles; t += 16 * kRedGroups) {
+            float x[16];
             #pragma unroll
-            for (int u = 0; u < 4; ++u) x[u] = partials[(int64_t)(t + u * kRedGroups) * P + sidx];
+            for (int u = 0; u < 16; ++u)
+                x[u] = __builtin_nontemporal_load(&partials[(int64_t)(t + u * kRedGroups) * P + sidx]);
             #pragma unroll
-            for (int u = 0; u < 4; ++u) neumaier_add(s, c, x[u]);
+            for (int u = 0; u < 16; ++u) neumaier_add(s, c, x[u]);
         }
-        for (; t < n_tiles; t += kRedGroups) neumaier_add(s, c, partials[(int64_t)t * P + sidx]);
+        for (; t < n_tiles; t += kRedGroups)
+            neumaier_add(s, c, __builtin_nontemporal_load(&partials[(int64_t)t * P + sidx]));
     }
     s_sum[grp][pl] = s;
     s_cmp[grp][pl] = c;
