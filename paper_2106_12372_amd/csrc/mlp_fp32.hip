@@ -252,7 +252,7 @@ __global__ __launch_bounds__(64 * NWV) void k_train_fp32(const float* __restrict
     if (wave < kNOut) {
         float acc = 0.0f;
         for (int s = 0; s < kTile; ++s) acc = fmaf(dout[s * 4 + wave], hlast[s * kLd + lane], acc);
-        part[(n_params - kNOut * kW) + wave * kW + lane] = acc;
+        __builtin_nontemporal_store(acc, &part[(n_params - kNOut * kW) + wave * kW + lane]);
         bad |= !isfinite(acc);
     }
     __syncthreads();
@@ -284,7 +284,8 @@ __global__ __launch_bounds__(64 * NWV) void k_train_fp32(const float* __restrict
             }
             #pragma unroll
             for (int j = 0; j < FPW; ++j) {
-                part[off + (f0 + j) * cols + lane] = acc[j];
+                // streamed past the caches: read once, by the reduction
+                __builtin_nontemporal_store(acc[j], &part[off + (f0 + j) * cols + lane]);
                 bad |= !isfinite(acc[j]);
             }
         }

@@ -729,6 +729,16 @@ hipError_t fwd_raw_fixed_launch(const Geo& d, const void* ffr, const float* raw,
     return hipGetLastError();
 }
 
+// Runtime-depth fused kernel: 12 waves per workgroup when the weights and 12
+// encode buffers fit in the 160 KB of LDS, else 8 (deeper networks).
+template <typename T, int W, int PRESET, int LAYOUT>
+hipError_t fwd_raw_generic(const Geo& d, const void* ffr, const float* raw, int64_t n, float* rgb,
+                           hipStream_t s) {
+    const size_t lds12 = (size_t)d.n_fwd_frags() * 1024 + (size_t)12 * 64 * 72 * sizeof(T);
+    if (lds12 <= 160 * 1024) return fwd_raw_launch<T, W, PRESET, LAYOUT, 12>(d, ffr, raw, n, rgb, s);
+    return fwd_raw_launch<T, W, PRESET, LAYOUT, 8>(d, ffr, raw, n, rgb, s, 2 * kRawMaxBlocks);
+}
+
 template <typename T, int W>
 hipError_t fwd_raw_dispatch(const Geo& d, int preset, int layout, const void* ffr, const float* raw,
                             int64_t n, float* rgb, hipStream_t s) {
@@ -743,13 +753,13 @@ hipError_t fwd_raw_dispatch(const Geo& d, int preset, int layout, const void* ff
                                    : fwd_raw_fixed_launch<T, NRC_PRESET_CONFIG, NRC_RAW16>(d, ffr, raw, n, rgb, s);
     }
     if (preset == NRC_PRESET_PAPER_TRI)
-        return layout == NRC_RAW14 ? fwd_raw_launch<T, W, NRC_PRESET_PAPER_TRI, NRC_RAW14>(d, ffr, raw, n, rgb, s)
-                                   : fwd_raw_launch<T, W, NRC_PRESET_PAPER_TRI, NRC_RAW16>(d, ffr, raw, n, rgb, s);
+        return layout == NRC_RAW14 ? fwd_raw_generic<T, W, NRC_PRESET_PAPER_TRI, NRC_RAW14>(d, ffr, raw, n, rgb, s)
+                                   : fwd_raw_generic<T, W, NRC_PRESET_PAPER_TRI, NRC_RAW16>(d, ffr, raw, n, rgb, s);
     if (preset == NRC_PRESET_PAPER)
-        return layout == NRC_RAW14 ? fwd_raw_launch<T, W, NRC_PRESET_PAPER, NRC_RAW14>(d, ffr, raw, n, rgb, s)
-                                   : fwd_raw_launch<T, W, NRC_PRESET_PAPER, NRC_RAW16>(d, ffr, raw, n, rgb, s);
-    return layout == NRC_RAW14 ? fwd_raw_launch<T, W, NRC_PRESET_CONFIG, NRC_RAW14>(d, ffr, raw, n, rgb, s)
-                               : fwd_raw_launch<T, W, NRC_PRESET_CONFIG, NRC_RAW16>(d, ffr, raw, n, rgb, s);
+        return layout == NRC_RAW14 ? fwd_raw_generic<T, W, NRC_PRESET_PAPER, NRC_RAW14>(d, ffr, raw, n, rgb, s)
+                                   : fwd_raw_generic<T, W, NRC_PRESET_PAPER, NRC_RAW16>(d, ffr, raw, n, rgb, s);
+    return layout == NRC_RAW14 ? fwd_raw_generic<T, W, NRC_PRESET_CONFIG, NRC_RAW14>(d, ffr, raw, n, rgb, s)
+                               : fwd_raw_generic<T, W, NRC_PRESET_CONFIG, NRC_RAW16>(d, ffr, raw, n, rgb, s);
 }
 
 template <typename T, int W, bool UP, bool GE>

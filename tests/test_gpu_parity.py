@@ -145,8 +145,10 @@ def test_forward_width128(N, prec):
 
 
 @pytest.mark.parametrize("prec", PRECS)
-@pytest.mark.parametrize("n_hidden", [1, 2, 3])
+@pytest.mark.parametrize("n_hidden", [1, 2, 3, 6, 8])
 def test_forward_other_depths(N, prec, n_hidden):
+    if prec == "fp32" and n_hidden > 6:
+        pytest.skip("the FP32 form supports up to 6 hidden layers")
     c, w = make_cache(N, prec, n_hidden=n_hidden)
     x, x64 = rounded_input(sd.uniform_features(777, 64, 9), prec)
     rgb = N.nrc_forward(c, x).cpu().numpy()
@@ -177,6 +179,22 @@ def test_forward_raw_equals_encode_then_forward(N, prec, preset, layout, n):
     if n >= 64:   # a normwise error over a handful of near-zero outputs says little
         ref = O.predict(state_of(w), O.encode(raw.cpu().numpy(), layout, preset))
         check_outputs(fused.cpu().numpy(), ref, FWD_TOL[prec], FWD_TOL_MAX[prec])
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("n_hidden", [1, 3, 6, 8])
+@pytest.mark.parametrize("factorize", [False, True])
+def test_forward_raw_other_depths(N, prec, n_hidden, factorize):
+    # Depths other than 5 run the runtime-depth fused kernel; it must still
+    # equal encode -> forward bit for bit and follow the oracle.
+    if prec == "fp32" and n_hidden > 6:
+        pytest.skip("the FP32 form supports up to 6 hidden layers")
+    c, w = make_cache(N, prec, n_hidden=n_hidden, factorize=factorize)
+    raw = dev(sd.raw_records(3001, 250 + n_hidden))
+    fused = N.nrc_forward_raw(c, raw)
+    assert torch.equal(fused, N.nrc_forward(c, N.nrc_encode(c, raw)))
+    st = O.CacheState(w.astype(np.float64), n_hidden=n_hidden, factorize=factorize)
+    check_outputs(fused.cpu().numpy(), O.predict(st, O.encode(raw.cpu().numpy())), FWD_TOL[prec], FWD_TOL_MAX[prec])
 
 
 def test_forward_raw_rejects_width128(N):
@@ -274,6 +292,24 @@ def test_train_mfma_four_steps_frame_schedule(N, prec):
 @pytest.mark.parametrize("prec", ["fp16", "bf16"])
 def test_train_width128_one_step(N, prec):
     _train_parity(N, prec, 2048, 1, 21, SINGLE_STEP_TOL[prec], 1e-2, width=128)
+
+
+@pytest.mark.parametrize("prec,width,n_hidden", [("fp32", 64, 1), ("fp32", 64, 6), ("fp16", 64, 1),
+                                                  ("fp16", 64, 8), ("bf16", 64, 3), ("fp16", 128, 2)])
+def test_train_other_depths(N, prec, width, n_hidden):
+    c, w = make_cache(N, prec, width=width, n_hidden=n_hidden)
+    raw = sd.raw_records(2048, 300 + n_hidden)
+    enc = N.nrc_encode(c, dev(raw), 0)
+    e64 = enc.float().cpu().numpy().astype(np.float64)
+    y = sd.targets(raw)
+    loss, skipped = N.nrc_train_step(c, enc, dev(y))
+    st = state_of(w, width, n_hidden)
+    ref_loss, _ = O.train_step(st, e64, y.astype(np.float64))
+    assert int(skipped.item()) == 0
+    assert abs(loss.item() - ref_loss) <= (1e-5 if prec == "fp32" else 1e-2) * abs(ref_loss)
+    q, q64 = rounded_input(O.encode(sd.raw_records(4096, sd.SEED_HELDOUT)), prec)
+    err = l2_err(N.nrc_forward(c, q).cpu().numpy(), O.predict(st, q64))
+    assert np.all(err <= SINGLE_STEP_TOL[prec]), err
 
 
 @pytest.mark.parametrize("prec", PRECS)
