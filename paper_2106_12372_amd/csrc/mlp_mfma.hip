@@ -55,9 +55,23 @@ template <typename V> __device__ inline V zero8() {
 // Two accumulator blocks (features 4g..4g+3 and 16+4g..16+4g+3 of a chunk)
 // -> one B operand in chained order.
 typedef float f32x8 __attribute__((ext_vector_type(8)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 template <typename T, typename V> __device__ inline V pack8(f32x4 lo, f32x4 hi) {
-    const f32x8 f = __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
-    return __builtin_convertvector(f, V);
+    if constexpr (sizeof(T) == 2 && !__is_same(T, _Float16)) {
+        // BF16: one v_cvt_pk_bf16_f32 per pair (the generic vector conversion
+        // is split into single conversions and byte permutes)
+        u32x4 r;
+        r[0] = __builtin_bit_cast(unsigned int, __builtin_convertvector(f32x2{lo[0], lo[1]}, bf16x2));
+        r[1] = __builtin_bit_cast(unsigned int, __builtin_convertvector(f32x2{lo[2], lo[3]}, bf16x2));
+        r[2] = __builtin_bit_cast(unsigned int, __builtin_convertvector(f32x2{hi[0], hi[1]}, bf16x2));
+        r[3] = __builtin_bit_cast(unsigned int, __builtin_convertvector(f32x2{hi[2], hi[3]}, bf16x2));
+        return __builtin_bit_cast(V, r);
+    } else {
+        const f32x8 f = __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
+        return __builtin_convertvector(f, V);
+    }
 }
 
 typedef short s16x8 __attribute__((ext_vector_type(8)));
