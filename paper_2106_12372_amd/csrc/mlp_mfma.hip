@@ -509,6 +509,12 @@ __global__ __launch_bounds__(256) void k_train_mfma(const T* __restrict__ ffr,
     }
     float r[3];                      // reflectance factor of record sl (lanes 0..15)
     reflectance_operand(b[1], fcol, ln, r);
+    // this record's targets (or upstream gradient), loaded now and used after the forward pass
+    float tg[3] = {0.f, 0.f, 0.f};
+    if (g == 0 && valid) {
+        #pragma unroll
+        for (int c = 0; c < 3; ++c) tg[c] = tgt[src * 3 + c];
+    }
     for (int l = 0; l < n_hidden; ++l) {
         const int kc = l == 0 ? 2 : KC;
         const V* fl = gf + geo.fwd_base(l) * 64;
@@ -542,16 +548,16 @@ __global__ __launch_bounds__(256) void k_train_mfma(const T* __restrict__ ffr,
     float d0 = 0.f, d1 = 0.f, d2 = 0.f, lterm = 0.f;
     if (g == 0 && valid) {
         if (UPSTREAM) {
-            d0 = tgt[src * 3 + 0] * grad_scale * r[0];
-            d1 = tgt[src * 3 + 1] * grad_scale * r[1];
-            d2 = tgt[src * 3 + 2] * grad_scale * r[2];
+            d0 = tg[0] * grad_scale * r[0];
+            d1 = tg[1] * grad_scale * r[1];
+            d2 = tg[2] * grad_scale * r[2];
         } else {
             const float p0 = y[0] * r[0], p1 = y[1] * r[1], p2 = y[2] * r[2];
             const float lum = (p0 + p1 + p2) * (1.0f / 3.0f);
             const float inv_den = 1.0f / (lum * lum + loss_eps);
-            const float e0 = p0 - tgt[src * 3 + 0];
-            const float e1 = p1 - tgt[src * 3 + 1];
-            const float e2 = p2 - tgt[src * 3 + 2];
+            const float e0 = p0 - tg[0];
+            const float e1 = p1 - tg[1];
+            const float e2 = p2 - tg[2];
             lterm = (e0 * e0 + e1 * e1 + e2 * e2) * inv_den;
             d0 = 2.0f * e0 * inv_den * grad_scale * r[0];
             d1 = 2.0f * e1 * inv_den * grad_scale * r[1];
