@@ -162,15 +162,20 @@ bool nrc_server::try_launch(Request& r, std::unique_lock<std::mutex>&) {
                 hipMemcpyAsync(&host_out[slot].skipped, sc + sl.skipped, 4, hipMemcpyDeviceToHost, s) != hipSuccess)
                 rc = NRC_EDEVICE;
         }
-        dp.last_train = r.ticket;
-        dp.reads.clear();
     } else {
         rc = enqueue_forward(c, r.req.enc, r.req.n, r.req.rgb, s);
         host_out[slot].loss = 0.0f;
         host_out[slot].skipped = 0;
-        dp.reads.push_back(r.ticket);
     }
     if (rc == NRC_OK && hipEventRecord(slot_event[slot], s) != hipSuccess) rc = NRC_EDEVICE;
+    if (rc == NRC_OK) {                   // later requests of this cache order after this one
+        if (r.req.kind == NRC_REQ_TRAIN) {
+            dp.last_train = r.ticket;
+            dp.reads.clear();
+        } else {
+            dp.reads.push_back(r.ticket);
+        }
+    }
     Inflight f{r, slot, st, off, now_s()};
     if (rc != NRC_OK) {
         arena.release(off, r.scratch_bytes);
