@@ -217,7 +217,7 @@ __global__ __launch_bounds__(64 * NWV) void k_train_fp32(const float* __restrict
                 #pragma unroll
                 for (int o = 0; o < kNOut; ++o) y[o] = f[o] * r[o];
                 const float lum = (y[0] + y[1] + y[2]) * (1.0f / 3.0f);
-                const float inv_den = 1.0f / (lum * lum + loss_eps);
+                const float inv_den = 1.0f / fmaf(lum, lum, loss_eps);
                 #pragma unroll
                 for (int o = 0; o < kNOut; ++o) {
                     const float diff = y[o] - tgt[src * 3 + o];

@@ -177,6 +177,44 @@ __device__ inline void mlp_tile(const typename Vec8<T>::type* sfr, typename Vec8
         for (int col = 0; col < COLS; ++col) o[col] = mfma(fo[c * 64], b[col][c], o[col]);
 }
 
+// The same network for width 64 and a depth fixed at compile time, with the
+// products ordered column block by column block: a layer's eight weight
+// fragments are read once into registers, then each column block runs its
+// eight products and its epilogue before the next block starts, so the
+// epilogue of one block can issue beside the matrix instructions of the next.
+// Every accumulator sees the same products in the same order as mlp_tile, so
+// the outputs are equal bit for bit.
+template <typename T, int COLS, int NH>
+__device__ inline void mlp_tile_colwise(const typename Vec8<T>::type* sfr, typename Vec8<T>::type (&b)[COLS][2],
+                                        int lane, f32x4 (&o)[COLS]) {
+    using V = typename Vec8<T>::type;
+    constexpr int MB = 4;
+    const Geo geo(64, NH);
+    #pragma unroll
+    for (int l = 0; l < NH; ++l) {
+        const V* fl = sfr + geo.fwd_base(l) * 64 + lane;
+        V a[MB][2];
+        #pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+            #pragma unroll
+            for (int c = 0; c < 2; ++c) a[mb][c] = fl[(mb * 2 + c) * 64];
+        #pragma unroll
+        for (int col = 0; col < COLS; ++col) {
+            f32x4 acc[MB];
+            #pragma unroll
+            for (int mb = 0; mb < MB; ++mb) acc[mb] = mfma(a[mb][0], b[col][0], f32x4{0.f, 0.f, 0.f, 0.f});
+            #pragma unroll
+            for (int mb = 0; mb < MB; ++mb) acc[mb] = mfma(a[mb][1], b[col][1], acc[mb]);
+            #pragma unroll
+            for (int c = 0; c < 2; ++c) b[col][c] = relu_packed(pack8<T, V>(acc[2 * c], acc[2 * c + 1]));
+        }
+    }
+    const V* fo = sfr + geo.fwd_base(NH) * 64 + lane;
+    const V a0 = fo[0], a1 = fo[64];
+    #pragma unroll
+    for (int col = 0; col < COLS; ++col) o[col] = mfma(a1, b[col][1], mfma(a0, b[col][0], f32x4{0.f, 0.f, 0.f, 0.f}));
+}
+
 // Reflectance factor alpha + beta (Sec. 5) of record ln from the B operand
 // holding input features 32..63 in natural order (lane 16g + ln: features
 // 32 + 8g .. 32 + 8g + 7); valid in lanes 0..15, 1 when fcol == 0.  Config
@@ -434,7 +472,7 @@ __global__ __launch_bounds__(64 * NW) void k_fwd_raw_mfma_fixed(const T* __restr
         encode_to_lds<T, PRESET, LAYOUT>(x, senc + lane * ROW);
         load_raw(tile + 2 * tstride);
         f32x4 o[COLS];
-        mlp_tile<T, W, COLS, NH>(sfr, b, NH, lane, o);
+        mlp_tile_colwise<T, COLS, NH>(sfr, b, lane, o);
         store_rgb<COLS>(o, r, tile * 64, n, g, ln, rgb);
     }
 }
@@ -554,11 +592,11 @@ __global__ __launch_bounds__(256) void k_train_mfma(const T* __restrict__ ffr,
         } else {
             const float p0 = y[0] * r[0], p1 = y[1] * r[1], p2 = y[2] * r[2];
             const float lum = (p0 + p1 + p2) * (1.0f / 3.0f);
-            const float inv_den = 1.0f / (lum * lum + loss_eps);
+            const float inv_den = 1.0f / fmaf(lum, lum, loss_eps);
             const float e0 = p0 - tg[0];
             const float e1 = p1 - tg[1];
             const float e2 = p2 - tg[2];
-            lterm = (e0 * e0 + e1 * e1 + e2 * e2) * inv_den;
+            lterm = fmaf(e2, e2, fmaf(e1, e1, e0 * e0)) * inv_den;
             d0 = 2.0f * e0 * inv_den * grad_scale * r[0];
             d1 = 2.0f * e1 * inv_den * grad_scale * r[1];
             d2 = 2.0f * e2 * inv_den * grad_scale * r[2];

@@ -88,12 +88,26 @@ __global__ __launch_bounds__(256) void k_reduce(const float* __restrict__ partia
     const int pl = tid % kRedParams, grp = tid / kRedParams;
     const int sidx = blockIdx.x * kRedParams + pl;          // partial slot (coalesced across lanes)
 
+    // Wave 0 ORs the per-tile non-finite flags; the first 256 are loaded now
+    // and combined after the sums, so no load waits on another.
+    int bad4[4] = {0, 0, 0, 0};
     if (ADAM && tid < 64) {
-        int any = 0;
-        for (int t = tid; t < n_tiles; t += 64) any |= tile_bad[t];
         #pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) any |= __shfl_xor(any, off, 64);
-        if (tid == 0) s_skip = any;
+        for (int u = 0; u < 4; ++u)
+            if (tid + 64 * u < n_tiles) bad4[u] = tile_bad[tid + 64 * u];
+    }
+    // The update's operands for this thread's weight are loaded before the
+    // partials, so their latency overlaps the sums.
+    const bool owner = grp == 0 && sidx < P;
+    const int p = NATIVE ? param_of_slot(d, owner ? sidx : 0) : sidx;
+    float w0 = 0.0f, m0 = 0.0f, v0 = 0.0f, e0 = 0.0f;
+    int t_old = 0;
+    if (ADAM && owner) {
+        w0 = w[p];
+        m0 = m[p];
+        v0 = v[p];
+        if (ema.alpha > 0.0f) e0 = ema.e[p];
+        t_old = tslots[parity];
     }
     float s = 0.0f, c = 0.0f;
     if (sidx < P) {
@@ -110,6 +124,13 @@ __global__ __launch_bounds__(256) void k_reduce(const float* __restrict__ partia
         for (; t < n_tiles; t += kRedGroups)
             neumaier_add(s, c, __builtin_nontemporal_load(&partials[(int64_t)t * P + sidx]));
     }
+    if (ADAM && tid < 64) {
+        int any = bad4[0] | bad4[1] | bad4[2] | bad4[3];
+        for (int t = tid + 256; t < n_tiles; t += 64) any |= tile_bad[t];
+        #pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) any |= __shfl_xor(any, off, 64);
+        if (tid == 0) s_skip = any;
+    }
     s_sum[grp][pl] = s;
     s_cmp[grp][pl] = c;
     __syncthreads();
@@ -122,8 +143,7 @@ __global__ __launch_bounds__(256) void k_reduce(const float* __restrict__ partia
         for (int off = 32; off >= 1; off >>= 1) lv += __shfl_xor(lv, off, 64);
         if (lane == 0) *loss_out = lv * inv_count;
     }
-    if (grp != 0 || sidx >= P) return;   // workgroup 0's thread 0 has slot 0 and stays
-    const int p = NATIVE ? param_of_slot(d, sidx) : sidx;
+    if (!owner) return;   // workgroup 0's thread 0 has slot 0 and stays
     float gv = 0.0f;
     {
         float S = 0.0f, C = 0.0f;
@@ -139,25 +159,26 @@ __global__ __launch_bounds__(256) void k_reduce(const float* __restrict__ partia
         return;
     }
     const int skip = s_skip;
-    const int t_old = tslots[parity];
     const int t_new = skip ? t_old : t_old + 1;
     if (blockIdx.x == 0 && tid == 0) {
         tslots[parity ^ 1] = t_new;
         if (skipped_out) *skipped_out = skip;
     }
     if (skip) return;
-    const float m1 = hp.beta1 * m[p] + (1.0f - hp.beta1) * gv;
-    const float v1 = hp.beta2 * v[p] + (1.0f - hp.beta2) * gv * gv;
+    // explicit fused multiply-adds: the rounding does not depend on which
+    // product the compiler would contract
+    const float m1 = fmaf(hp.beta1, m0, (1.0f - hp.beta1) * gv);
+    const float v1 = fmaf(hp.beta2, v0, ((1.0f - hp.beta2) * gv) * gv);
     const float bc1 = 1.0f - powf(hp.beta1, (float)t_new);
     const float bc2 = 1.0f - powf(hp.beta2, (float)t_new);
-    const float w1 = w[p] - hp.lr * (m1 / bc1) / (sqrtf(v1 / bc2) + hp.eps);
+    const float w1 = w0 - hp.lr * (m1 / bc1) / (sqrtf(v1 / bc2) + hp.eps);
     w[p] = w1;
     m[p] = m1;
     v[p] = v1;
     if (ffr != nullptr) write_frags<T>(d, p, w1, ffr, bfr);
     if (ema.alpha > 0.0f) {
         // Eq. 2, bias-corrected: E_t = a E_{t-1} + (1 - a) W_t, W_bar_t = E_t / (1 - a^t).
-        const float e1 = ema.alpha * ema.e[p] + (1.0f - ema.alpha) * w1;
+        const float e1 = fmaf(ema.alpha, e0, (1.0f - ema.alpha) * w1);
         const float wb = e1 / (1.0f - powf(ema.alpha, (float)t_new));
         ema.e[p] = e1;
         ema.wbar[p] = wb;

@@ -10,6 +10,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import sys
 from ctypes import POINTER, c_double, c_float, c_int, c_int32, c_int64, c_size_t, c_uint64, c_void_p
 from typing import Optional
 
@@ -218,6 +219,10 @@ class Cache:
         self._scratch = None
 
     def __del__(self):
+        # at interpreter exit the module's globals may already be gone; the
+        # process ends and the driver reclaims the device memory
+        if sys.is_finalizing() or lib is None:
+            return
         h = getattr(self, "handle", None)
         if h is not None and h.value:
             lib.nrc_cache_destroy(h)
@@ -503,6 +508,8 @@ class Server:
             self.handle = None
 
     def __del__(self):
+        if sys.is_finalizing() or lib is None:
+            return
         try:
             self.close()
         except Exception:
