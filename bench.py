@@ -3,7 +3,7 @@
 A step is one 1920x1080 frame of the cache: encode 2,073,600 synthetic query
 records and run inference on them (one fused kernel), encode 65,536 training
 records, shuffle them with the LCG and take four Adam steps on disjoint
-batches of 16,384 records (Sec. 3.3 and 3.5 of the paper).  Inputs
+batches of 16,384 records (Sec. 3.3 and 3.5 of the paper), all on one stream.  Inputs
 are resident in HBM before the timed region.  The default form is plain FP32
 (vector ALUs); the FP16 and BF16 matrix-core forms run the same frame and are
 reported under "forms".  Prints one JSON line.
@@ -139,6 +139,7 @@ def frame_bench(form: str, steps: int, warmup: int, settle_s: float):
     t0 = time.perf_counter()
     for k in range(steps):
         step(evs[k])
+    t_enq = time.perf_counter() - t0
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     comp = np.mean([[e[i].elapsed_time(e[i + 1]) for i in range(3)] for e in evs], axis=0)
@@ -200,6 +201,7 @@ def frame_bench(form: str, steps: int, warmup: int, settle_s: float):
     frame_flop = N_QUERIES * FLOP_PER_QUERY + N_TRAIN_BATCHES * TRAIN_BATCH * FLOP_PER_TRAIN_SAMPLE
     out["frame_tflops"] = frame_flop / (ms * 1e-3) / 1e12
     out["settle_frames"] = settled
+    out["host_enqueue_ms_per_step"] = t_enq * 1e3 / steps
     out["query_pass_by_preset_ms"] = preset_bench(form, raw_q, rgb, steps)
     return out
 

@@ -274,6 +274,23 @@ int nrc_train_frame(nrc_cache* cache, const void* enc, const float* target, int6
                     float* losses_dev, int32_t* skipped_dev, void* stream);
 
 /*
+ * The training steps of nrc_train_frame on a permutation the caller has
+ * already computed (for example nrc_shuffle with the frame's seed, enqueued on
+ * another stream beside the frame's query pass: neither the shuffle nor the
+ * records' encoding reads the weights, so only the training steps need to
+ * follow the queries).  perm[n_records]: device int32, each entry a valid row
+ * of enc / target (not checked); steps k runs on perm[k used / steps,
+ * (k+1) used / steps) with used = min(n_records, steps * batch), exactly as
+ * nrc_train_frame.  Other arguments and the scratch size
+ * (nrc_frame_scratch_bytes) as for nrc_train_frame.  With perm from
+ * nrc_shuffle(n_records, seed) the result equals nrc_train_frame(seed) bit for
+ * bit.
+ */
+int nrc_train_frame_indexed(nrc_cache* cache, const void* enc, const float* target, const int32_t* perm,
+                            int64_t n_records, int steps, int64_t batch, void* scratch,
+                            size_t scratch_bytes, float* losses_dev, int32_t* skipped_dev, void* stream);
+
+/*
  * Self-training targets (Sec. 3.2, Sec. 6 "Self-training"): a training
  * record's target is the radiance gathered from its vertex to the end of its
  * path plus the throughput from its vertex to the path's tail times the

@@ -571,9 +571,24 @@ size_t nrc_frame_scratch_bytes(const nrc_config* cfg, int64_t n_records, int ste
     return frame_layout(*cfg, n_records, steps, batch).total;
 }
 
-int nrc_train_frame(nrc_cache* cache, const void* enc, const float* target, int64_t n_records, int steps,
-                    int64_t batch, uint64_t seed, void* scratch, size_t scratch_bytes, float* losses_dev,
-                    int32_t* skipped_dev, void* stream) {
+namespace {
+// The frame's training steps on perm (validated arguments, scratch checked).
+int enqueue_frame_steps(nrc_cache* cache, const void* enc, const float* target, const int32_t* perm,
+                        int64_t n_records, int steps, int64_t batch, char* step_scratch, float* losses_dev,
+                        int32_t* skipped_dev, hipStream_t s) {
+    const int64_t used = n_records < steps * batch ? n_records : steps * batch;
+    for (int k = 0; k < steps; ++k) {
+        const int64_t lo = k * used / steps, hi = (k + 1) * used / steps;
+        const int rc = enqueue_train_step(cache, enc, target, perm + lo, hi - lo, step_scratch, losses_dev + k,
+                                          skipped_dev + k, s);
+        if (rc != NRC_OK) return rc;
+    }
+    return ok();
+}
+
+int check_frame_buffers(nrc_cache* cache, const void* enc, const float* target, int64_t n_records, int steps,
+                        int64_t batch, void* scratch, size_t scratch_bytes, float* losses_dev,
+                        int32_t* skipped_dev, FrameLayout* L) {
     if (!cache) return fail(NRC_EINVAL, "cache is NULL");
     const int rc0 = check_frame_args(&cache->cfg, n_records, steps, batch);
     if (rc0 != NRC_OK) return rc0;
@@ -581,22 +596,39 @@ int nrc_train_frame(nrc_cache* cache, const void* enc, const float* target, int6
     if (!aligned16(enc) || ((uintptr_t)target & 3) || ((uintptr_t)scratch & 255) ||
         ((uintptr_t)losses_dev & 3) || ((uintptr_t)skipped_dev & 3))
         return fail(NRC_EINVAL, "misaligned buffer (scratch must be 256-byte aligned)");
-    const FrameLayout L = frame_layout(cache->cfg, n_records, steps, batch);
-    if (scratch_bytes < L.total)
-        return fail(NRC_ENOMEM, "scratch of %zu bytes is smaller than the %zu bytes needed", scratch_bytes, L.total);
+    *L = frame_layout(cache->cfg, n_records, steps, batch);
+    if (scratch_bytes < L->total)
+        return fail(NRC_ENOMEM, "scratch of %zu bytes is smaller than the %zu bytes needed", scratch_bytes, L->total);
+    return NRC_OK;
+}
+}  // namespace
+
+int nrc_train_frame(nrc_cache* cache, const void* enc, const float* target, int64_t n_records, int steps,
+                    int64_t batch, uint64_t seed, void* scratch, size_t scratch_bytes, float* losses_dev,
+                    int32_t* skipped_dev, void* stream) {
+    FrameLayout L;
+    const int rc = check_frame_buffers(cache, enc, target, n_records, steps, batch, scratch, scratch_bytes,
+                                       losses_dev, skipped_dev, &L);
+    if (rc != NRC_OK) return rc;
     char* sc = (char*)scratch;
     int32_t* perm = (int32_t*)(sc + L.perm);
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = launch_shuffle(n_records, seed, perm, (int32_t*)(sc + L.counts), s);
     if (e != hipSuccess) return device_fail(e, "shuffle launch");
-    const int64_t used = n_records < steps * batch ? n_records : steps * batch;
-    for (int k = 0; k < steps; ++k) {
-        const int64_t lo = k * used / steps, hi = (k + 1) * used / steps;
-        const int rc = enqueue_train_step(cache, enc, target, perm + lo, hi - lo, sc + L.step, losses_dev + k,
-                                          skipped_dev + k, s);
-        if (rc != NRC_OK) return rc;
-    }
-    return ok();
+    return enqueue_frame_steps(cache, enc, target, perm, n_records, steps, batch, sc + L.step, losses_dev,
+                               skipped_dev, s);
+}
+
+int nrc_train_frame_indexed(nrc_cache* cache, const void* enc, const float* target, const int32_t* perm,
+                            int64_t n_records, int steps, int64_t batch, void* scratch, size_t scratch_bytes,
+                            float* losses_dev, int32_t* skipped_dev, void* stream) {
+    FrameLayout L;
+    const int rc = check_frame_buffers(cache, enc, target, n_records, steps, batch, scratch, scratch_bytes,
+                                       losses_dev, skipped_dev, &L);
+    if (rc != NRC_OK) return rc;
+    if (!perm || ((uintptr_t)perm & 3)) return fail(NRC_EINVAL, "perm is NULL or misaligned");
+    return enqueue_frame_steps(cache, enc, target, perm, n_records, steps, batch, (char*)scratch + L.step,
+                               losses_dev, skipped_dev, (hipStream_t)stream);
 }
 
 int nrc_self_training_targets(const float* radiance, const float* throughput, const float* tail_rgb,

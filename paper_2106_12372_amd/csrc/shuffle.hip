@@ -7,12 +7,14 @@
 // x -> a x + c, formed by repeated squaring.  Since m divides 2^32, all
 // arithmetic is in wrapping 32-bit integers and masked to k bits at the end.
 //
-// Two kernels.  Positions j of the orbit are split into spans of 256 * R; a
-// workgroup owns one span and walks it in R rounds of 256 consecutive
-// positions.  k_lcg_count counts the kept values of each span;
-// k_lcg_write adds the counts of the spans before its own (at most 1024) and
-// writes its kept values in orbit order, compacting each round with wave
-// ballots so that the stores stay consecutive.
+// Positions j of the orbit are split into spans of 256 * R; a workgroup owns
+// one span and walks it in R rounds of 256 consecutive positions.  In general
+// two kernels: k_lcg_count counts the kept values of each span; k_lcg_write
+// adds the counts of the spans before its own (at most 1024) and writes its
+// kept values in orbit order, compacting each round with wave ballots so that
+// the stores stay consecutive.  When n is a power of two, m = n and no value
+// is skipped, so position j of the permutation is x_j itself: one kernel,
+// k_lcg_full, writes it directly.
 #include "nrc_internal.h"
 
 namespace nrc {
@@ -96,6 +98,19 @@ __global__ __launch_bounds__(kShufBlock) void k_lcg_write(Affine step, Affine st
     }
 }
 
+// n = m: perm[j] = x_j for every orbit position j < m.
+__global__ __launch_bounds__(kShufBlock) void k_lcg_full(Affine step, Affine stride, uint32_t x0,
+                                                         uint32_t mask, uint64_t m, int rounds,
+                                                         int32_t* __restrict__ perm) {
+    const uint64_t span = (uint64_t)rounds * kShufBlock;
+    uint64_t pos = blockIdx.x * span + threadIdx.x;
+    uint32_t x = apply(power(step, pos), x0);
+    for (int r = 0; r < rounds; ++r, pos += kShufBlock) {
+        if (pos < m) perm[pos] = (int32_t)(x & mask);
+        x = apply(stride, x);
+    }
+}
+
 __global__ __launch_bounds__(256) void k_self_train(const float* __restrict__ radiance,
                                                     const float* __restrict__ throughput,
                                                     const float* __restrict__ tail_rgb,
@@ -136,6 +151,11 @@ hipError_t launch_shuffle(int64_t n, uint64_t seed, int32_t* perm, int32_t* coun
     const Affine stride = power(step, kShufBlock);
     const uint32_t mask = (uint32_t)(m - 1);
     const uint32_t x0 = (uint32_t)(seed & mask);
+    if (m == (uint64_t)n) {
+        hipLaunchKernelGGL(k_lcg_full, dim3(spans), dim3(kShufBlock), 0, s, step, stride, x0, mask, m, rounds,
+                           perm);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(k_lcg_count, dim3(spans), dim3(kShufBlock), 0, s, step, stride, x0, mask, m,
                        (uint32_t)n, rounds, counts);
     hipLaunchKernelGGL(k_lcg_write, dim3(spans), dim3(kShufBlock), 0, s, step, stride, x0, mask, m,

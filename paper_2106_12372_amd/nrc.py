@@ -99,6 +99,7 @@ _decl("nrc_shuffle", c_int, c_int64, c_uint64, _P, _P, c_size_t, _P)
 _decl("nrc_train_step_indexed", c_int, _P, _P, _P, _P, c_int64, _P, c_size_t, _P, _P, _P)
 _decl("nrc_frame_scratch_bytes", c_size_t, POINTER(nrc_config), c_int64, c_int, c_int64)
 _decl("nrc_train_frame", c_int, _P, _P, _P, c_int64, c_int, c_int64, c_uint64, _P, c_size_t, _P, _P, _P)
+_decl("nrc_train_frame_indexed", c_int, _P, _P, _P, _P, c_int64, c_int, c_int64, _P, c_size_t, _P, _P, _P)
 _decl("nrc_self_training_targets", c_int, _P, _P, _P, _P, c_int64, c_int64, _P, _P)
 _decl("nrc_serve_create", c_int, POINTER(nrc_serve_config), POINTER(_P))
 _decl("nrc_serve_set_weights", c_int, _P, c_int, POINTER(c_float), c_int64)
@@ -113,7 +114,7 @@ EXPORTED = ["nrc_config_default", "nrc_last_error", "nrc_param_count", "nrc_cach
             "nrc_cache_config", "nrc_set_weights", "nrc_get_weights", "nrc_set_weights_device",
             "nrc_get_state", "nrc_set_state", "nrc_get_ema", "nrc_set_ema", "nrc_encode", "nrc_forward", "nrc_forward_raw", "nrc_train_step",
             "nrc_backward", "nrc_shuffle_scratch_bytes", "nrc_shuffle", "nrc_train_step_indexed",
-            "nrc_frame_scratch_bytes", "nrc_train_frame", "nrc_self_training_targets", "nrc_serve_create", "nrc_serve_set_weights", "nrc_serve_get_weights",
+            "nrc_frame_scratch_bytes", "nrc_train_frame", "nrc_train_frame_indexed", "nrc_self_training_targets", "nrc_serve_create", "nrc_serve_set_weights", "nrc_serve_get_weights",
             "nrc_serve_submit", "nrc_serve_poll", "nrc_serve_drain", "nrc_serve_destroy"]
 
 
@@ -344,12 +345,12 @@ def _aligned_bytes(nbytes: int, device):
     return t[off:off + nbytes]
 
 
-def nrc_shuffle(n: int, seed: int, device="cuda", perm=None, stream=None):
+def nrc_shuffle(n: int, seed: int, device="cuda", perm=None, scratch=None, stream=None):
     """Shuffled record order (Sec. 3.5): int32 device tensor perm[n]."""
     torch = _torch()
     if perm is None:
         perm = torch.empty(n, dtype=torch.int32, device=device)
-    sc = _aligned_bytes(max(1, lib.nrc_shuffle_scratch_bytes(n)), perm.device)
+    sc = _aligned_bytes(max(1, lib.nrc_shuffle_scratch_bytes(n)), perm.device) if scratch is None else scratch
     check(lib.nrc_shuffle(n, seed & (2 ** 64 - 1), _ptr(perm), _ptr(sc), sc.numel(), _stream(stream)))
     return perm
 
@@ -396,6 +397,27 @@ def nrc_train_frame(cache: Cache, enc, target, steps: int = 4, batch: int = 1638
     skipped = torch.empty(steps, dtype=torch.int32, device=enc.device)
     check(lib.nrc_train_frame(cache.handle, _ptr(enc), _ptr(target), n, steps, batch, seed & (2 ** 64 - 1),
                               _ptr(scratch), scratch.numel(), _ptr(losses), _ptr(skipped), _stream(stream)))
+    return losses, skipped
+
+
+def nrc_train_frame_indexed(cache: Cache, enc, target, perm, steps: int = 4, batch: int = 16384,
+                            scratch=None, stream=None):
+    """The training steps of nrc_train_frame on a given permutation perm[n]
+    (e.g. from nrc_shuffle on another stream); returns (losses[steps], skipped[steps])."""
+    torch = _torch()
+    _need(enc, cache.enc_dtype, (ENC_WIDTH,), "enc")
+    _need(target, torch.float32, (3,), "target")
+    _need(perm, torch.int32, (), "perm")
+    n = enc.shape[0]
+    if target.shape[0] != n or perm.shape[0] != n:
+        raise ValueError("enc, target and perm differ in length")
+    if scratch is None:
+        scratch = _aligned_bytes(nrc_frame_scratch_bytes(cache.cfg, n, steps, batch), enc.device)
+    losses = torch.empty(steps, dtype=torch.float32, device=enc.device)
+    skipped = torch.empty(steps, dtype=torch.int32, device=enc.device)
+    check(lib.nrc_train_frame_indexed(cache.handle, _ptr(enc), _ptr(target), _ptr(perm), n, steps, batch,
+                                      _ptr(scratch), scratch.numel(), _ptr(losses), _ptr(skipped),
+                                      _stream(stream)))
     return losses, skipped
 
 

@@ -160,6 +160,38 @@ def test_train_frame_equals_shuffle_then_indexed_steps(N, prec):
     assert np.array_equal(a.get_weights(), b.get_weights())
 
 
+@pytest.mark.parametrize("prec", ["fp32", "fp16", "bf16"])
+@pytest.mark.parametrize("n_records", [65536, 70000, 50001])
+def test_train_frame_indexed_on_a_side_stream_shuffle_equals_train_frame(N, prec, n_records):
+    # The permutation comes from a shuffle enqueued on another stream (ordered
+    # by an event), as a renderer overlaps it with the frame's query pass.
+    raw = sd.raw_records(n_records, 86)
+    y = dev(sd.targets(raw))
+    a, _ = make_cache(N, prec)
+    b, _ = make_cache(N, prec)
+    enc = N.nrc_encode(a, dev(raw), 0)
+    la, sa = N.nrc_train_frame(a, enc, y, steps=4, batch=16384, seed=9)
+    side = torch.cuda.Stream()
+    ready = torch.cuda.Event()
+    with torch.cuda.stream(side):
+        perm = N.nrc_shuffle(n_records, 9, stream=side.cuda_stream)
+        ready.record(side)
+    torch.cuda.current_stream().wait_event(ready)
+    lb, sb = N.nrc_train_frame_indexed(b, enc, y, perm, steps=4, batch=16384)
+    assert torch.equal(la, lb) and torch.equal(sa, sb)
+    assert np.array_equal(a.get_weights(), b.get_weights())
+
+
+def test_train_frame_indexed_rejects_bad_arguments(N):
+    c, _ = make_cache(N, "fp16")
+    enc = N.nrc_encode(c, dev(sd.raw_records(1000, 87)), 0)
+    y = dev(sd.targets(sd.raw_records(1000, 87)))
+    with pytest.raises(ValueError):
+        N.nrc_train_frame_indexed(c, enc, y, torch.zeros(999, dtype=torch.int32, device="cuda"))
+    with pytest.raises(N.NrcError):
+        N.nrc_train_frame_indexed(c, enc, y, torch.zeros(1000, dtype=torch.int32, device="cuda"), steps=0)
+
+
 def test_self_training_targets(N):
     rng = np.random.Generator(np.random.PCG64(84))
     n, nt = 10000, 777
