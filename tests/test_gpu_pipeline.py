@@ -34,12 +34,14 @@ def test_shuffle_empty(N):
     assert N.nrc_shuffle(0, 3).numel() == 0
 
 
-def test_shuffle_large_is_a_permutation_with_the_oracle_ends(N):
-    # m = 2^26: 256 rounds per workgroup.  The whole orbit is too long for the
-    # oracle's loop, so check that the result is a permutation and that its
-    # first and last entries follow the orbit forwards from x_0 and backwards
-    # from x_0 (the inverse map x -> a^-1 (x - c) mod m).
-    n, seed = (1 << 25) + 3, 12345
+@pytest.mark.parametrize("n", [(1 << 25) + 3, 1 << 24])
+def test_shuffle_large_is_a_permutation_with_the_oracle_ends(N, n):
+    # 2^25 + 3 (m = 2^26, the counting kernels, 256 rounds per workgroup) and
+    # 2^24 (m = n, the single kernel, 64 rounds).  The whole orbit is too long
+    # for the oracle's loop, so check that the result is a permutation and that
+    # its first and last entries follow the orbit forwards from x_0 and
+    # backwards from x_0 (the inverse map x -> a^-1 (x - c) mod m).
+    seed = 12345
     perm = N.nrc_shuffle(n, seed)
     srt, _ = torch.sort(perm)
     assert torch.equal(srt, torch.arange(n, device="cuda", dtype=torch.int32))
