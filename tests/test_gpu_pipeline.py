@@ -10,7 +10,8 @@ torch = pytest.importorskip("torch")
 
 import synthdata as sd
 from oracle import nrc_oracle as O
-from tests.test_gpu_parity import dev, l2_err, make_cache, rounded_input, state_of
+from tests import rounding_model as RM
+from tests.test_gpu_parity import MODEL_TOL, dev, l2_err, make_cache, rounded_input, state_of
 
 pytestmark = pytest.mark.gpu
 
@@ -126,9 +127,14 @@ def test_frame_steps_match_oracle_from_the_same_state(N, prec, n_records):
             check_fp32_adam_step(c.get_weights(), st_before, st.w, e64[idx], y[idx].astype(np.float64))
 
 
+FRAME_MAX_TOL = {"fp16": 1e-2, "bf16": 1.5e-2}
+
+
 @pytest.mark.parametrize("prec", ["fp16", "bf16"])
 def test_train_frame_matches_oracle_frame(N, prec):
-    # The whole reduced-precision frame against the oracle's frame (4 x 16,384).
+    # The whole reduced-precision frame against the oracle's frame (4 x 16,384),
+    # then per-channel error on 65,536 held-out queries through the trained
+    # weights: normwise L2 and normwise max (max_i |got - ref| / max_i |ref|).
     c, w = make_cache(N, prec)
     raw = sd.raw_records(65536, 82)
     enc = N.nrc_encode(c, dev(raw), 0)
@@ -136,13 +142,25 @@ def test_train_frame_matches_oracle_frame(N, prec):
     y = sd.targets(raw)
     losses, skipped = N.nrc_train_frame(c, enc, dev(y), steps=4, batch=16384, seed=77)
     st = state_of(w)
-    q, q64 = rounded_input(O.encode(sd.raw_records(4096, sd.SEED_HELDOUT)), prec)
+    q, q64 = rounded_input(O.encode(sd.raw_records(65536, sd.SEED_HELDOUT)), prec)
     _, ref_losses, ref_skips = O.frame_shuffled(st, q64, e64, y.astype(np.float64), 4, 16384, 77)
     assert skipped.cpu().tolist() == [0, 0, 0, 0] and not any(ref_skips)
     got_l = losses.cpu().numpy()
     assert np.all(np.abs(got_l - ref_losses) <= 1e-2 * np.abs(ref_losses)), (got_l, ref_losses)
     got = N.nrc_forward(c, q).cpu().numpy()
-    assert np.all(l2_err(got, O.predict(st, q64)) <= 1e-2)
+    ref = O.predict(st, q64)
+    e2, em = l2_err(got, ref), O.channel_rel_error(got, ref)
+    print(f"{prec} frame, 65,536 held-out queries: per-channel L2 {e2}, max {em}")
+    # L2 within 1e-2 in both formats.  The max-normwise error of BF16 (unit
+    # roundoff 2^-8) reaches 1.14e-2 in the rounding model, which carries out
+    # this frame with exactly the kernels' roundings: that is the format's own
+    # loss, so its bound is 1.5e-2 (FP16: model 2.3e-3, bound 1e-2).
+    assert np.all(e2 <= 1e-2) and np.all(em <= FRAME_MAX_TOL[prec]), (e2, em)
+    # the kernels against the rounding model of the same frame
+    model = RM.TrainModel(w, prec, loss_scale=c.cfg.loss_scale)
+    for idx in O.frame_batches(65536, 4, 16384, 77):
+        model.step(e64[idx], y[idx].astype(np.float64))
+    assert np.all(l2_err(got, model.predict(q64)) <= MODEL_TOL[prec])
 
 
 @pytest.mark.parametrize("prec", ["fp32", "fp16", "bf16"])
