@@ -499,6 +499,25 @@ def test_full_frame_sampled(N, prec):
     check_outputs(got, O.predict(state_of(w), O.encode(raw[idx])), FWD_TOL[prec], FWD_TOL_MAX[prec])
 
 
+@pytest.mark.parametrize("prec", ["fp16", "fp32"])
+def test_inputs_past_2gib_give_every_row_its_own_output(N, prec):
+    # 40,000,003 queries: the raw records (2.24 GB) and the FP16 encoding
+    # (5.1 GB) exceed 2^31 bytes, so a 32-bit offset anywhere would wrap.  The
+    # input repeats a 1,000,000-record block; every query is computed on its
+    # own, so each output row must equal its block row's output bit for bit.
+    base_n, reps, extra = 1_000_000, 40, 3
+    c, _ = make_cache(N, prec)
+    base = dev(sd.raw_records(base_n, 88))
+    big = torch.cat([base.repeat(reps, 1), base[:extra]])
+    ref = N.nrc_forward_raw(c, base)
+    got = N.nrc_forward_raw(c, big)
+    assert torch.equal(got[:reps * base_n].view(reps, base_n, 3), ref.unsqueeze(0).expand(reps, base_n, 3))
+    assert torch.equal(got[reps * base_n:], ref[:extra])
+    if prec == "fp16":
+        enc = N.nrc_encode(c, big, 0)
+        assert torch.equal(N.nrc_forward(c, enc), got)
+
+
 # ---------------------------------------------------------------------------
 # EMA weight set (Eq. 2), used by the query entry points
 # ---------------------------------------------------------------------------
