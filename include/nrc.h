@@ -348,7 +348,10 @@ int nrc_serve_get_weights(nrc_server* srv, int cache_id, float* host_w, int64_t 
 /* Queues a request and returns a ticket without blocking.  NRC_ENOMEM if the
  * request could never fit the arena.  Request buffers must stay valid until
  * nrc_serve_poll returns NRC_OK for the ticket.  Requests on one cache run in
- * submission order. */
+ * submission order.  The server launches on its own non-blocking streams and
+ * does not wait for device work the caller enqueued elsewhere: the request's
+ * inputs must be complete, and nothing else may write its buffers, from the
+ * call on (synchronise the producing stream first). */
 int nrc_serve_submit(nrc_server* srv, int cache_id, const nrc_request* req, uint64_t* ticket);
 /* NRC_PENDING until the request has finished, then NRC_OK and *res filled
  * (once; a finished ticket is then forgotten: NRC_ENOTFOUND afterwards). */

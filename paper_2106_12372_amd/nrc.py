@@ -459,7 +459,9 @@ class Server:
 
     The arena (caches + per-request scratch) is one device tensor of
     `arena_bytes`.  Request tensors are kept alive here until their ticket has
-    been collected by poll().
+    been collected by poll().  The server runs requests on its own streams and
+    does not wait for work queued on others: a request's tensors must be
+    complete (e.g. after torch.cuda.synchronize()) when it is submitted.
     """
 
     def __init__(self, n_caches: int, cfg: nrc_config, arena_bytes: int, n_streams: int = 4,

@@ -55,14 +55,16 @@ def test_mix_equals_solo_replay(N, prec):
     srv = N.Server(n_caches, cfg, arena_bytes=1 << 30, n_streams=4, max_inflight=16)
     for i, w in enumerate(weights):
         srv.set_weights(i, w)
-    outs, tickets = [], []
-    for (kind, cache, n), (enc, tgt) in zip(reqs, data):
+    # outputs pre-filled with NaN, complete before any submission (the server's
+    # streams do not wait for work on this one)
+    outs = [torch.full((n, 3), float("nan"), device="cuda") if kind == "infer" else None
+            for kind, cache, n in reqs]
+    torch.cuda.synchronize()
+    tickets = []
+    for (kind, cache, n), (enc, tgt), rgb in zip(reqs, data, outs):
         if kind == "infer":
-            rgb = torch.full((n, 3), float("nan"), device="cuda")
-            outs.append(rgb)
             tickets.append(srv.submit_infer(cache, enc, rgb))
         else:
-            outs.append(None)
             tickets.append(srv.submit_train(cache, enc, tgt))
     results = []
     for t in tickets:
@@ -108,6 +110,7 @@ def test_admission_by_memory_never_drops(N):
     c0 = N.Cache(cfg)
     enc = N.nrc_encode(c0, torch.from_numpy(raw).to("cuda"))
     tgt = torch.from_numpy(sd.targets(raw)).to("cuda")
+    torch.cuda.synchronize()              # inputs complete before the server reads them
     tickets = [srv.submit_train(k % 2, enc, tgt) for k in range(12)]
     rgb = torch.empty((4096, 3), device="cuda")
     tickets.append(srv.submit_infer(0, enc, rgb))
