@@ -97,6 +97,63 @@ def test_mix_equals_solo_replay(N, prec):
         assert np.array_equal(c.get_weights(), final_w[i])
 
 
+def test_concurrent_submitters_match_solo_replay(N):
+    # The serving entry points are thread-safe: four threads submit and poll
+    # at once (ctypes drops the GIL inside the calls), thread i on cache i, so
+    # each cache's requests keep their thread's order; every result must equal
+    # the solo replay bit for bit.
+    import threading
+    cfg = N.make_config(precision="fp16")
+    n_caches, per_thread = 4, 12
+    reqs = [[(kind, i, n) for kind, _, n in _requests(1, per_thread, 90 + i)] for i in range(n_caches)]
+    data = [_inputs(N, cfg, reqs[i], 900 + 100 * i) for i in range(n_caches)]
+    outs = [[torch.full((n, 3), float("nan"), device="cuda") if kind == "infer" else None
+             for kind, _, n in reqs[i]] for i in range(n_caches)]
+    weights = [sd.glorot_weights(seed=95 + i) for i in range(n_caches)]
+    srv = N.Server(n_caches, cfg, arena_bytes=1 << 30, n_streams=4, max_inflight=16)
+    for i, w in enumerate(weights):
+        srv.set_weights(i, w)
+    torch.cuda.synchronize()
+    results = [None] * n_caches
+    errors = []
+
+    def worker(i):
+        try:
+            tickets = []
+            for (kind, _, n), (enc, tgt), rgb in zip(reqs[i], data[i], outs[i]):
+                tickets.append(srv.submit_infer(i, enc, rgb) if kind == "infer" else srv.submit_train(i, enc, tgt))
+            res = []
+            for t in tickets:
+                r = srv.poll(t)
+                while r is None:
+                    r = srv.poll(t)
+                res.append(r)
+            results[i] = res
+        except Exception as e:  # reported after the join
+            errors.append(e)
+
+    threads = [threading.Thread(target=worker, args=(i,)) for i in range(n_caches)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    assert not errors, errors
+    srv.drain()
+    final_w = [srv.get_weights(i) for i in range(n_caches)]
+    srv.close()
+    for i in range(n_caches):
+        c = N.Cache(cfg)
+        c.set_weights(weights[i])
+        for (kind, _, n), (enc, tgt), out, res in zip(reqs[i], data[i], outs[i], results[i]):
+            assert res["status"] == 0
+            if kind == "infer":
+                assert torch.equal(N.nrc_forward(c, enc), out)
+            else:
+                loss, skipped = N.nrc_train_step(c, enc, tgt)
+                assert loss.item() == res["loss"] and int(skipped.item()) == res["skipped"] == 0
+        assert np.array_equal(c.get_weights(), final_w[i])
+
+
 def test_admission_by_memory_never_drops(N):
     cfg = N.make_config(precision="fp16")
     cache_bytes = N.nrc_cache_bytes(cfg)
