@@ -114,7 +114,8 @@ size_t nrc_cache_bytes(const nrc_config* cfg);
 
 /* Bytes of device scratch one nrc_train_step / nrc_backward over n records
  * needs: two regions of per-tile weight-gradient partials (consecutive steps
- * of a cache alternate between them), loss partials and flags. */
+ * of a cache alternate between them), loss partials and flags.  0 (with
+ * NRC_EINVAL as the last error) on an invalid config or n outside [0, 2^31]. */
 size_t nrc_train_scratch_bytes(const nrc_config* cfg, int64_t n);
 
 /* Bytes per element of the encoded input at the cache precision (4 or 2). */

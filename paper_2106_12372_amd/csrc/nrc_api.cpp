@@ -209,7 +209,7 @@ size_t nrc_cache_bytes(const nrc_config* cfg) {
 
 size_t nrc_train_scratch_bytes(const nrc_config* cfg, int64_t n) {
     if (validate_config(cfg) != NRC_OK) return 0;
-    if (n < 0) { fail(NRC_EINVAL, "n must be >= 0"); return 0; }
+    if (n < 0 || n > ((int64_t)1 << 31)) { fail(NRC_EINVAL, "n must be in [0, 2^31]"); return 0; }
     ok();
     return scratch_layout(*cfg, n).total;
 }

@@ -62,6 +62,9 @@ def test_workspace_and_scratch_sizes(N):
     assert s1 >= 256 * P * 4                      # one weight-gradient partial per 64-record tile
     assert N.nrc_train_scratch_bytes(cfg, 16385) > s1
     assert N.nrc_train_scratch_bytes(N.make_config(precision="fp32"), 1) > 0
+    # beyond the largest training batch the size is refused, never wrapped
+    assert N.lib.nrc_train_scratch_bytes(ctypes.byref(cfg), (1 << 31) + 1) == 0
+    assert N.lib.nrc_train_scratch_bytes(ctypes.byref(cfg), 1 << 62) == 0
 
 
 def test_create_rejects_bad_workspace_before_device_calls(N):
