@@ -113,6 +113,64 @@ def _targets_wrong_tail(radiance, throughput, tail_rgb, tail_index):
         (np.asarray(tail_index) + 1) % len(tail_rgb)]
 
 
+def _sph_angles_swapped(v):
+    return O.__dict__["_orig_sph"](v)[:, ::-1]
+
+
+def _sph_azimuth_unshifted(v):
+    v = np.asarray(v, dtype=np.float64)
+    theta = np.arccos(np.clip(v[:, 2], -1.0, 1.0))
+    return np.stack([theta / np.pi, np.arctan2(v[:, 1], v[:, 0]) / (2.0 * np.pi)], axis=1)
+
+
+def _tri_cosine_phase(x):
+    return 2.0 * np.abs(np.mod(x, 2.0) - 1.0) - 1.0
+
+
+def _loss_sum_luminance(y_hat, y, eps=O.LOSS_EPS):
+    y_hat = np.asarray(y_hat, float)
+    n = y_hat.shape[0]
+    lum = y_hat.sum(axis=1, keepdims=True)
+    den = lum * lum + eps
+    diff = y_hat - np.asarray(y, float)
+    return float((diff * diff / den).sum() / (3 * n)), 2 * diff / den / (3 * n)
+
+
+def _loss_eps_squared(y_hat, y, eps=O.LOSS_EPS):
+    y_hat = np.asarray(y_hat, float)
+    n = y_hat.shape[0]
+    lum = y_hat.mean(axis=1, keepdims=True)
+    den = (lum + eps) ** 2
+    diff = y_hat - np.asarray(y, float)
+    return float((diff * diff / den).sum() / (3 * n)), 2 * diff / den / (3 * n)
+
+
+def _adam_eps_inside_sqrt(w, m, v, t, g, cfg):
+    t = t + 1
+    m = cfg.beta1 * m + (1 - cfg.beta1) * g
+    v = cfg.beta2 * v + (1 - cfg.beta2) * g * g
+    m_hat, v_hat = m / (1 - cfg.beta1 ** t), v / (1 - cfg.beta2 ** t)
+    return w - cfg.lr * m_hat / np.sqrt(v_hat + cfg.eps), m, v, t
+
+
+def _ema_no_bias_correction(w_bar_prev, w, t, alpha):
+    return (1.0 - alpha) * w + alpha * w_bar_prev
+
+
+def _frame_batches_unshuffled(n, steps, batch, seed):
+    used = min(n, steps * batch)
+    return [np.arange(s * used // steps, (s + 1) * used // steps) for s in range(steps)]
+
+
+def _frame_batches_fixed_size(n, steps, batch, seed):
+    perm = O.lcg_permutation(n, seed)
+    return [perm[s * batch:(s + 1) * batch] for s in range(steps)]
+
+
+def _one_blob_bins_reversed(s, k=O.N_BLOBS):
+    return O.__dict__["_orig_one_blob"](s, k)[..., ::-1]
+
+
 MUTANTS = [
     ("freq", _freq_no_pi, [P.test_freq_matches_libm_closed_form, P.test_freq_dyadic_points_exact]),
     ("one_blob", _one_blob_no_tails, [P.test_one_blob_exact_dyadic_fixture, P.test_one_blob_invariants]),
@@ -129,6 +187,17 @@ MUTANTS = [
     ("lcg_permutation", _lcg_even_increment, [P.test_lcg_full_period_and_permutation]),
     ("lcg_permutation", _lcg_keeps_n, [P.test_lcg_orbit_matches_hand_derived_fixture]),
     ("self_training_targets", _targets_wrong_tail, [P.test_self_training_targets]),
+    ("sph", _sph_angles_swapped, [P.test_sph_axes, P.test_sph_inverts_spherical_parametrisation]),
+    ("sph", _sph_azimuth_unshifted, [P.test_sph_axes, P.test_sph_inverts_spherical_parametrisation]),
+    ("tri", _tri_cosine_phase, [P.test_triangle_wave_closed_form]),
+    ("relative_l2", _loss_sum_luminance, [P.test_loss_single_sample_by_hand]),
+    ("relative_l2", _loss_eps_squared, [P.test_loss_single_sample_by_hand]),
+    ("adam", _adam_eps_inside_sqrt, [P.test_adam_constant_gradient_closed_form]),
+    ("ema_step", _ema_no_bias_correction, [P.test_ema_matches_explicit_weighted_average,
+                                           P.test_ema_first_step_and_constant_weights]),
+    ("frame_batches", _frame_batches_unshuffled, [P.test_frame_batches_are_disjoint_and_spread_over_the_records]),
+    ("frame_batches", _frame_batches_fixed_size, [P.test_frame_batches_are_disjoint_and_spread_over_the_records]),
+    ("one_blob", _one_blob_bins_reversed, [P.test_one_blob_exact_dyadic_fixture]),
 ]
 
 
