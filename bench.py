@@ -444,6 +444,14 @@ def main():
         "cpu_baseline": cpu,
         "forms": forms,
         "serve": serve,
+        # the paper's own timings on its GPU (half precision), context only: not this
+        # metric's baseline, hence vs_baseline stays null
+        "paper_context": {
+            "gpu": "RTX 3090", "precision": "fp16", "query_pass_ms": 1.59, "train_4_steps_ms": 1.11,
+            "frame_ms": 2.70,
+            "frame_time_ratio_fp16": (2.70 / forms["fp16"]["ms_per_step"]) if "fp16" in forms else None,
+            "frame_time_ratio_bf16": (2.70 / forms["bf16"]["ms_per_step"]) if "bf16" in forms else None,
+        },
     }
     print(json.dumps(res), flush=True)
 
