@@ -72,3 +72,28 @@ def test_triangle_wave_encoding_fits_as_well_as_sines(N):
         pred = N.nrc_forward_raw(c, dev(held)).cpu().numpy().astype(np.float64)
         losses[preset], _ = O.relative_l2(pred, sd.targets(held).astype(np.float64))
     assert losses[O.PRESET_PAPER_TRI] < 1.5 * losses[O.PRESET_PAPER] + 1e-3, losses
+
+
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+def test_long_online_training_stays_finite_and_keeps_improving(N, prec):
+    # 200 frames of online training (new records each frame, 4 x 16,384 shuffled
+    # steps) with the static loss scale of 128: no step is skipped, the outputs
+    # stay finite, and the held-out relative L2 after 200 frames is below 2% of
+    # that after 10 (measured: 0.113 -> 0.00045 in both formats).
+    c, _ = make_cache(N, prec)
+    held = sd.raw_records(16384, sd.SEED_HELDOUT)
+    held_d, held_y = dev(held), sd.targets(held).astype(np.float64)
+    errs = {}
+    skipped = 0
+    for f in range(200):
+        raw = sd.raw_records(65536, 5000 + f)
+        enc = N.nrc_encode(c, dev(raw))
+        _, sk = N.nrc_train_frame(c, enc, dev(sd.targets(raw)), steps=4, batch=16384, seed=f)
+        skipped += int(sk.sum().item())
+        if f + 1 in (10, 200):
+            pred = N.nrc_forward_raw(c, held_d).cpu().numpy().astype(np.float64)
+            assert np.all(np.isfinite(pred))
+            errs[f + 1], _ = O.relative_l2(pred, held_y)
+    print(f"{prec}: held-out relative L2 after 10 frames {errs[10]:.5f}, after 200 {errs[200]:.5f}")
+    assert skipped == 0
+    assert errs[200] <= 0.02 * errs[10], errs
