@@ -30,7 +30,11 @@ notes):
 * Cheap primitives (Sec. 5): the one-blob kernel is the quartic throughout;
   the "paper-tri" preset also replaces each sine sin(2^d pi p) by the triangle
   wave of the same period and phase, tri(x) = 2|(x - 1/2) mod 2 - 1| - 1, which
-  meets sin(pi x) at every multiple of 1/2.
+  meets sin(pi x) at every multiple of 1/2.  The "paper-gauss" preset keeps
+  the sines and uses the kernel the quartic replaced, a Gaussian: the paper
+  gives no width (it defers the one-blob encoding to its earlier work), read
+  as a standard deviation of one bin, with the bin masses from the normal CDF
+  Phi(u) = (1 + erf(u / sqrt 2)) / 2 and the edge bins again taking the tails.
 * Architecture (Sec. 5 Architecture): 6 weight matrices, no biases, ReLU after
   each hidden layer, linear output.  ReLU'(0) = 0.
 * Loss (Eq. 5, Sec. 5 Relative loss): per channel (y_hat - y)^2 / (lum^2 + eps)
@@ -84,13 +88,15 @@ RAW16 = 1
 PRESET_CONFIG = 0
 PRESET_PAPER = 1
 PRESET_PAPER_TRI = 2   # paper preset with the triangle wave in place of sin (Sec. 5)
+PRESET_PAPER_GAUSS = 3  # paper preset with a Gaussian one-blob kernel in place of the quartic (Sec. 5)
+PAPER_PRESETS = (PRESET_PAPER, PRESET_PAPER_TRI, PRESET_PAPER_GAUSS)
 
 
 def albedo_columns(preset: int):
     """Columns of the diffuse and specular albedo in the encoded row (Sec. 3.6
     concatenation order): after roughness at 52 (config), after the roughness
     one-blob at 52..55 (paper)."""
-    return (56, 59) if preset in (PRESET_PAPER, PRESET_PAPER_TRI) else (53, 56)
+    return (56, 59) if preset in PAPER_PRESETS else (53, 56)
 
 
 # ---------------------------------------------------------------------------
@@ -120,7 +126,7 @@ def freq(p: np.ndarray, preset: int = PRESET_CONFIG) -> np.ndarray:
             # the sine of frequency 2^d replaced by the triangle wave of the same period
             for d in range(PAPER_OCTAVES):
                 cols.append(tri(p[:, c] * 2.0 ** d))
-        elif preset == PRESET_PAPER:
+        elif preset in (PRESET_PAPER, PRESET_PAPER_GAUSS):
             for d in range(PAPER_OCTAVES):
                 r = np.mod(p[:, c] * 2.0 ** d, 2.0)
                 cols.append(np.sin(np.pi * r))
@@ -140,14 +146,21 @@ def quartic_cdf(u: np.ndarray) -> np.ndarray:
     return np.where(u <= -1.0, 0.0, np.where(u >= 1.0, 1.0, inner))
 
 
-def one_blob(s: np.ndarray, k: int = N_BLOBS) -> np.ndarray:
-    """One-blob encoding of scalars in [0,1] into k bins (Sec. 3.6): kernel mass per bin."""
+def gauss_cdf(u: np.ndarray) -> np.ndarray:
+    """CDF of the standard normal kernel, (1 + erf(u / sqrt 2)) / 2."""
+    u = np.asarray(u, dtype=np.float64)
+    return 0.5 * (1.0 + np.vectorize(math.erf)(u / math.sqrt(2.0)))
+
+
+def one_blob(s: np.ndarray, k: int = N_BLOBS, cdf=quartic_cdf) -> np.ndarray:
+    """One-blob encoding of scalars in [0,1] into k bins (Sec. 3.6): kernel mass
+    per bin, the kernel centred at k s in bin units, the edge bins taking the tails."""
     s = np.asarray(s, dtype=np.float64)
     c = k * s
     out = np.empty(s.shape + (k,), dtype=np.float64)
     for j in range(k):
-        hi = np.ones_like(c) if j == k - 1 else quartic_cdf(j + 1 - c)
-        lo = np.zeros_like(c) if j == 0 else quartic_cdf(j - c)
+        hi = np.ones_like(c) if j == k - 1 else cdf(j + 1 - c)
+        lo = np.zeros_like(c) if j == 0 else cdf(j - c)
         out[..., j] = hi - lo
     return out
 
@@ -164,12 +177,13 @@ def encode(raw: np.ndarray, layout: int = RAW14, preset: int = PRESET_CONFIG) ->
     else:
         raise ValueError(f"unknown layout {layout}")
     rough, diffuse, specular = rest[:, 0:1], rest[:, 1:4], rest[:, 4:7]
+    cdf = gauss_cdf if preset == PRESET_PAPER_GAUSS else quartic_cdf
     parts = [freq(pos, preset),
-             one_blob(d_sph).reshape(n, 8),
-             one_blob(n_sph).reshape(n, 8)]
-    paper = preset in (PRESET_PAPER, PRESET_PAPER_TRI)
+             one_blob(d_sph, cdf=cdf).reshape(n, 8),
+             one_blob(n_sph, cdf=cdf).reshape(n, 8)]
+    paper = preset in PAPER_PRESETS
     if paper:
-        parts.append(one_blob(1.0 - np.exp(-rough[:, 0])).reshape(n, 4))
+        parts.append(one_blob(1.0 - np.exp(-rough[:, 0]), cdf=cdf).reshape(n, 4))
     else:
         parts.append(rough)
     parts += [diffuse, specular]

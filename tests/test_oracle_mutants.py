@@ -171,6 +171,10 @@ def _one_blob_bins_reversed(s, k=O.N_BLOBS):
     return O.__dict__["_orig_one_blob"](s, k)[..., ::-1]
 
 
+def _gauss_twice_as_wide(u):
+    return O.__dict__["_orig_gauss_cdf"](np.asarray(u, dtype=np.float64) / 2.0)
+
+
 MUTANTS = [
     ("freq", _freq_no_pi, [P.test_freq_matches_libm_closed_form, P.test_freq_dyadic_points_exact]),
     ("one_blob", _one_blob_no_tails, [P.test_one_blob_exact_dyadic_fixture, P.test_one_blob_invariants]),
@@ -198,6 +202,8 @@ MUTANTS = [
     ("frame_batches", _frame_batches_unshuffled, [P.test_frame_batches_are_disjoint_and_spread_over_the_records]),
     ("frame_batches", _frame_batches_fixed_size, [P.test_frame_batches_are_disjoint_and_spread_over_the_records]),
     ("one_blob", _one_blob_bins_reversed, [P.test_one_blob_exact_dyadic_fixture]),
+    ("gauss_cdf", _gauss_twice_as_wide, [P.test_gauss_one_blob_matches_numerical_bin_integrals,
+                                         P.test_gauss_one_blob_invariants]),
 ]
 
 

@@ -119,6 +119,45 @@ def test_one_blob_matches_numerical_bin_integrals():
         assert np.allclose(O.one_blob(np.array([s]))[0], want, atol=1e-12)
 
 
+def test_gauss_one_blob_matches_numerical_bin_integrals():
+    # Brute force: integrate the standard normal density (one bin per unit of
+    # standard deviation) over each bin; the edge bins take the tails.
+    pdf = lambda x: math.exp(-0.5 * x * x) / math.sqrt(2.0 * math.pi)
+    for s in [0.0, 0.03, 0.2, 0.41, 0.5, 0.77, 0.96, 1.0]:
+        c = 4 * s
+        want = []
+        for j in range(4):
+            lo = -np.inf if j == 0 else j - c
+            hi = np.inf if j == 3 else j + 1 - c
+            want.append(integrate.quad(pdf, lo, hi, epsabs=1e-14, epsrel=1e-13)[0])
+        got = O.one_blob(np.array([s]), cdf=O.gauss_cdf)[0]
+        assert np.allclose(got, want, atol=1e-12), (s, got, want)
+
+
+def test_gauss_one_blob_invariants():
+    s = np.concatenate([np.linspace(0.0, 1.0, 401), sd.uniform_features(200, 1, 13)[:, 0]])
+    e = O.one_blob(s, cdf=O.gauss_cdf)
+    assert np.allclose(e.sum(axis=1), 1.0, atol=1e-14)           # telescoping partition of unity
+    assert np.all(e > 0.0)                                        # a Gaussian reaches every bin
+    assert np.allclose(e, O.one_blob(1.0 - s, cdf=O.gauss_cdf)[:, ::-1], atol=1e-14)   # mirror symmetry
+    # the centre bin's mass: at s = 1/8 (centre of bin 0, half a bin from its
+    # inner edge) it is Phi(1/2) of the whole tail-absorbing edge bin
+    assert np.isclose(O.one_blob(np.array([0.125]), cdf=O.gauss_cdf)[0, 0], O.gauss_cdf(np.array(0.5)), atol=1e-15)
+
+
+def test_encode_paper_gauss_preset_layout():
+    raw = sd.raw_records(64, 91)
+    a = O.encode(raw, preset=O.PRESET_PAPER)
+    b = O.encode(raw, preset=O.PRESET_PAPER_GAUSS)
+    r = raw.astype(np.float64)
+    assert np.array_equal(a[:, :36], b[:, :36])                   # the same 12 sines per coordinate
+    assert np.array_equal(a[:, 56:], b[:, 56:])                   # albedos and the padding of ones
+    # dir (2 x 4 bins), normal (2 x 4), 1 - exp(-roughness) (4): Gaussian blobs
+    for k, v in enumerate([r[:, 3], r[:, 4], r[:, 5], r[:, 6], 1.0 - np.exp(-r[:, 7])]):
+        assert np.allclose(b[:, 36 + 4 * k:40 + 4 * k], O.one_blob(v, cdf=O.gauss_cdf), atol=1e-15)
+    assert not np.allclose(a[:, 36:56], b[:, 36:56])
+
+
 def test_sph_axes():
     v = np.array([[0, 0, 1], [0, 0, -1], [1, 0, 0], [0, 1, 0], [0, -1, 0], [-1, 0, 1e-300]], dtype=np.float64)
     v[5] /= np.linalg.norm(v[5])
