@@ -208,8 +208,9 @@ def frame_bench(form: str, steps: int, warmup: int, settle_s: float):
 
 def preset_bench(form: str, raw_q, rgb, steps: int):
     """The fused query pass under each encoding preset: config (sin and cos of 6
-    octaves), paper (12 sines) and paper-tri (12 triangle waves, the cheap
-    primitive of Sec. 5); average kernel time in ms."""
+    octaves), paper (12 sines, quartic one-blobs), paper-tri (12 triangle waves,
+    the cheap primitive of Sec. 5) and paper-gauss (Gaussian one-blobs, the
+    kernel the quartic replaces); average kernel time in ms."""
     import torch
     from paper_2106_12372_amd import nrc as N
 
@@ -217,7 +218,7 @@ def preset_bench(form: str, raw_q, rgb, steps: int):
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
     out = {}
     for name, preset in (("config", N.NRC_PRESET_CONFIG), ("paper", N.NRC_PRESET_PAPER),
-                         ("paper_tri", N.NRC_PRESET_PAPER_TRI)):
+                         ("paper_tri", N.NRC_PRESET_PAPER_TRI), ("paper_gauss", N.NRC_PRESET_PAPER_GAUSS)):
         cache = N.Cache(N.make_config(width=WIDTH, n_hidden=N_HIDDEN, precision=form, enc_preset=preset),
                         device=raw_q.device)
         cache.set_weights(sd.glorot_weights(WIDTH, N_HIDDEN))

@@ -52,6 +52,8 @@ extern "C" {
 #define NRC_PRESET_CONFIG 0 /* 6 octaves sin+cos, roughness as is, zero pad */
 #define NRC_PRESET_PAPER 1  /* 12 sines, one-blob of 1-exp(-r), pad with one */
 #define NRC_PRESET_PAPER_TRI 2 /* as PAPER with the triangle wave of Sec. 5 in place of sin */
+#define NRC_PRESET_PAPER_GAUSS 3 /* as PAPER with a Gaussian one-blob kernel (one bin wide), the
+                                    kernel the quartic of Sec. 5 replaces */
 
 /* Raw path-vertex record layouts (FP32, row-major). */
 #define NRC_RAW14 0 /* pos 3 | dir (u,w) 2 | normal (u,w) 2 | roughness | diffuse 3 | specular 3 */

@@ -65,7 +65,9 @@ hipError_t dispatch_encode(int preset, int layout, const float* raw, int64_t n, 
 #define NRC_ENC_LAUNCH(PR, LA) \
     hipLaunchKernelGGL((k_encode<T, PR, LA>), grid, block, 0, s, raw, n, enc)
     const bool r14 = layout == NRC_RAW14;
-    if (preset == NRC_PRESET_PAPER_TRI) {
+    if (preset == NRC_PRESET_PAPER_GAUSS) {
+        if (r14) NRC_ENC_LAUNCH(NRC_PRESET_PAPER_GAUSS, NRC_RAW14); else NRC_ENC_LAUNCH(NRC_PRESET_PAPER_GAUSS, NRC_RAW16);
+    } else if (preset == NRC_PRESET_PAPER_TRI) {
         if (r14) NRC_ENC_LAUNCH(NRC_PRESET_PAPER_TRI, NRC_RAW14); else NRC_ENC_LAUNCH(NRC_PRESET_PAPER_TRI, NRC_RAW16);
     } else if (preset == NRC_PRESET_PAPER) {
         if (r14) NRC_ENC_LAUNCH(NRC_PRESET_PAPER, NRC_RAW14); else NRC_ENC_LAUNCH(NRC_PRESET_PAPER, NRC_RAW16);

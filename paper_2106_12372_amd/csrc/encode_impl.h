@@ -47,6 +47,22 @@ __device__ inline void one_blob4(float s, float* e) {
     e[3] = 1.0f - f3;
 }
 
+// The Gaussian one-blob the quartic kernel replaces (Sec. 5 "cheap
+// primitives"), one bin per standard deviation: bin masses from the normal
+// CDF (1 + erf(u / sqrt 2)) / 2; the edge bins also take the tails.
+__device__ inline float gauss_cdf(float u) { return 0.5f + 0.5f * erff(u * 0.707106781186547524f); }
+
+__device__ inline void one_blob4_gauss(float s, float* e) {
+    const float c = 4.0f * s;
+    const float f1 = gauss_cdf(1.0f - c);
+    const float f2 = gauss_cdf(2.0f - c);
+    const float f3 = gauss_cdf(3.0f - c);
+    e[0] = f1;
+    e[1] = f2 - f1;
+    e[2] = f3 - f2;
+    e[3] = 1.0f - f3;
+}
+
 // Unit vector -> spherical coordinates normalised to [0,1]^2.
 __device__ inline void sph(float x, float y, float z, float& u, float& w) {
     u = acosf(fminf(fmaxf(z, -1.0f), 1.0f)) * kInvPi;
@@ -84,15 +100,17 @@ __device__ inline void octaves(float p, float* sn, float* cs) {
 //   paper preset: 12 sines per coordinate (36), one-blob of the angles (16),
 //   one-blob of 1 - exp(-roughness) (4), albedos (6), two ones.
 //   paper-tri preset: as paper with tri(2^d p) in place of sin(2^d pi p).
+//   paper-gauss preset: as paper with Gaussian one-blobs.
 template <int PRESET, int LAYOUT>
 __device__ inline void encode_record(const float* x, float* o) {
-    constexpr bool paper = PRESET == NRC_PRESET_PAPER || PRESET == NRC_PRESET_PAPER_TRI;
+    constexpr bool paper = PRESET != NRC_PRESET_CONFIG;
+    constexpr bool gauss = PRESET == NRC_PRESET_PAPER_GAUSS;
     #pragma unroll
     for (int c = 0; c < 3; ++c) {
         if (PRESET == NRC_PRESET_PAPER_TRI) {
             #pragma unroll
             for (int d = 0; d < 12; ++d) o[12 * c + d] = tri(x[c] * (float)(1 << d));
-        } else if (PRESET == NRC_PRESET_PAPER) {
+        } else if (PRESET == NRC_PRESET_PAPER || PRESET == NRC_PRESET_PAPER_GAUSS) {
             float sn[12], cs[12];
             octaves<12>(x[c], sn, cs);
             #pragma unroll
@@ -118,9 +136,11 @@ __device__ inline void encode_record(const float* x, float* o) {
         rest = x + 9;
     }
     #pragma unroll
-    for (int a = 0; a < 4; ++a) one_blob4(ang[a], o + 36 + 4 * a);
+    for (int a = 0; a < 4; ++a) {
+        if (gauss) one_blob4_gauss(ang[a], o + 36 + 4 * a); else one_blob4(ang[a], o + 36 + 4 * a);
+    }
     if (paper) {
-        one_blob4(1.0f - expf(-rest[0]), o + 52);
+        if (gauss) one_blob4_gauss(1.0f - expf(-rest[0]), o + 52); else one_blob4(1.0f - expf(-rest[0]), o + 52);
         #pragma unroll
         for (int j = 0; j < 6; ++j) o[56 + j] = rest[1 + j];
         o[62] = 1.0f;

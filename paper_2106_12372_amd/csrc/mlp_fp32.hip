@@ -353,7 +353,12 @@ hipError_t launch_fwd_raw_fp32(const Geo& d, int preset, int layout, const float
     const int64_t blocks = (n + 255) / 256;
     if (blocks == 0) return hipSuccess;
     const dim3 grid((unsigned)blocks), block(256);
-    if (preset == NRC_PRESET_PAPER_TRI) {
+    if (preset == NRC_PRESET_PAPER_GAUSS) {
+        if (layout == NRC_RAW14)
+            hipLaunchKernelGGL((k_fwd_raw_fp32<NRC_PRESET_PAPER_GAUSS, NRC_RAW14>), grid, block, 0, s, w, raw, n, rgb, d.H, d.F);
+        else
+            hipLaunchKernelGGL((k_fwd_raw_fp32<NRC_PRESET_PAPER_GAUSS, NRC_RAW16>), grid, block, 0, s, w, raw, n, rgb, d.H, d.F);
+    } else if (preset == NRC_PRESET_PAPER_TRI) {
         if (layout == NRC_RAW14)
             hipLaunchKernelGGL((k_fwd_raw_fp32<NRC_PRESET_PAPER_TRI, NRC_RAW14>), grid, block, 0, s, w, raw, n, rgb, d.H, d.F);
         else

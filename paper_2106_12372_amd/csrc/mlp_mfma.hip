@@ -801,6 +801,9 @@ template <typename T, int W>
 hipError_t fwd_raw_dispatch(const Geo& d, int preset, int layout, const void* ffr, const float* raw,
                             int64_t n, float* rgb, hipStream_t s) {
     if (W == 64 && d.H == 5) {
+        if (preset == NRC_PRESET_PAPER_GAUSS)
+            return layout == NRC_RAW14 ? fwd_raw_fixed_launch<T, NRC_PRESET_PAPER_GAUSS, NRC_RAW14>(d, ffr, raw, n, rgb, s)
+                                       : fwd_raw_fixed_launch<T, NRC_PRESET_PAPER_GAUSS, NRC_RAW16>(d, ffr, raw, n, rgb, s);
         if (preset == NRC_PRESET_PAPER_TRI)
             return layout == NRC_RAW14 ? fwd_raw_fixed_launch<T, NRC_PRESET_PAPER_TRI, NRC_RAW14>(d, ffr, raw, n, rgb, s)
                                        : fwd_raw_fixed_launch<T, NRC_PRESET_PAPER_TRI, NRC_RAW16>(d, ffr, raw, n, rgb, s);
@@ -810,6 +813,9 @@ hipError_t fwd_raw_dispatch(const Geo& d, int preset, int layout, const void* ff
         return layout == NRC_RAW14 ? fwd_raw_fixed_launch<T, NRC_PRESET_CONFIG, NRC_RAW14>(d, ffr, raw, n, rgb, s)
                                    : fwd_raw_fixed_launch<T, NRC_PRESET_CONFIG, NRC_RAW16>(d, ffr, raw, n, rgb, s);
     }
+    if (preset == NRC_PRESET_PAPER_GAUSS)
+        return layout == NRC_RAW14 ? fwd_raw_generic<T, W, NRC_PRESET_PAPER_GAUSS, NRC_RAW14>(d, ffr, raw, n, rgb, s)
+                                   : fwd_raw_generic<T, W, NRC_PRESET_PAPER_GAUSS, NRC_RAW16>(d, ffr, raw, n, rgb, s);
     if (preset == NRC_PRESET_PAPER_TRI)
         return layout == NRC_RAW14 ? fwd_raw_generic<T, W, NRC_PRESET_PAPER_TRI, NRC_RAW14>(d, ffr, raw, n, rgb, s)
                                    : fwd_raw_generic<T, W, NRC_PRESET_PAPER_TRI, NRC_RAW16>(d, ffr, raw, n, rgb, s);

@@ -54,7 +54,7 @@ int validate_config(const nrc_config* c) {
     if (c->precision != NRC_FP32 && c->precision != NRC_FP16 && c->precision != NRC_BF16)
         return fail(NRC_EINVAL, "unknown precision %d", c->precision);
     if (c->enc_preset != NRC_PRESET_CONFIG && c->enc_preset != NRC_PRESET_PAPER &&
-        c->enc_preset != NRC_PRESET_PAPER_TRI)
+        c->enc_preset != NRC_PRESET_PAPER_TRI && c->enc_preset != NRC_PRESET_PAPER_GAUSS)
         return fail(NRC_EINVAL, "unknown encoding preset %d", c->enc_preset);
     if (c->precision == NRC_FP32 && (c->width != 64 || c->n_hidden > 6))
         return fail(NRC_EINVAL, "the FP32 form supports width 64 and n_hidden <= 6");

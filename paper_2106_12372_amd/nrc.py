@@ -24,7 +24,7 @@ lib = ctypes.CDLL(_LIB_PATH)
 # Status codes, precisions, presets and layouts (same values as nrc.h).
 NRC_OK, NRC_PENDING, NRC_EINVAL, NRC_ENOMEM, NRC_EDEVICE, NRC_EBUSY, NRC_ENOTFOUND = 0, 1, -1, -2, -3, -4, -5
 NRC_FP32, NRC_FP16, NRC_BF16 = 0, 1, 2
-NRC_PRESET_CONFIG, NRC_PRESET_PAPER, NRC_PRESET_PAPER_TRI = 0, 1, 2
+NRC_PRESET_CONFIG, NRC_PRESET_PAPER, NRC_PRESET_PAPER_TRI, NRC_PRESET_PAPER_GAUSS = 0, 1, 2, 3
 NRC_RAW14, NRC_RAW16 = 0, 1
 NRC_REQ_INFER, NRC_REQ_TRAIN = 0, 1
 ENC_WIDTH = 64

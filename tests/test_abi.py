@@ -41,7 +41,7 @@ def test_param_count_matches_architecture(N):
 
 def test_config_validation(N):
     bad = [dict(width=96), dict(n_hidden=0), dict(n_hidden=9), dict(precision=7),
-           dict(enc_preset=3), dict(lr=-1.0), dict(beta1=1.0), dict(loss_eps=0.0),
+           dict(enc_preset=4), dict(lr=-1.0), dict(beta1=1.0), dict(loss_eps=0.0),
            dict(loss_scale=0.0), dict(precision="fp32", width=128), dict(width=128, n_hidden=6)]
     raw_bad = N.make_config()
     raw_bad.factorize = 2                         # only 0 and 1 are defined

@@ -87,7 +87,7 @@ def state_of(w, width=64, n_hidden=5):
 # Encoding (Sec. 3.6)
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("prec", PRECS)
-@pytest.mark.parametrize("preset", [0, 1, 2])
+@pytest.mark.parametrize("preset", [0, 1, 2, 3])
 @pytest.mark.parametrize("layout", [0, 1])
 @pytest.mark.parametrize("n", [4096, 1000, 129, 1])
 def test_encode_matches_oracle(N, prec, preset, layout, n):
@@ -164,7 +164,7 @@ def test_forward_encoded_records_end_to_end(N, prec):
 
 
 @pytest.mark.parametrize("prec", PRECS)
-@pytest.mark.parametrize("preset", [0, 1, 2])
+@pytest.mark.parametrize("preset", [0, 1, 2, 3])
 @pytest.mark.parametrize("layout", [0, 1])
 @pytest.mark.parametrize("n", [5000, 4097, 64, 63, 1])
 def test_forward_raw_equals_encode_then_forward(N, prec, preset, layout, n):
@@ -426,7 +426,7 @@ def _torch_factor(enc, preset):
 
 
 @pytest.mark.parametrize("prec", PRECS)
-@pytest.mark.parametrize("preset", [0, 1, 2])
+@pytest.mark.parametrize("preset", [0, 1, 2, 3])
 @pytest.mark.parametrize("layout", [0, 1])
 @pytest.mark.parametrize("n", [4097, 1000, 63])
 def test_forward_factorised(N, prec, preset, layout, n):
