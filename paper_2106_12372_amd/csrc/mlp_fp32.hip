@@ -1,9 +1,16 @@
-// Plain FP32 form of the network (Sec. 4 and Sec. 5 "Architecture"), on the
-// vector ALUs only: the precision baseline for the matrix-core forms.
+// Plain FP32 form of the network (Sec. 4 and Sec. 5 "Architecture"): every
+// product and sum in single precision, the precision baseline for the 16-bit
+// matrix-core forms.
 //
-// Inference: one lane per query; the query's 64 activations live in VGPRs and
-// every weight is a wave-uniform operand fetched with scalar loads, so a layer
-// is 4096 FMAs per lane with no LDS or cross-lane traffic.
+// Inference runs on the FP32 matrix cores (v_mfma_f32_16x16x4_f32), whose dense
+// rate equals the packed-FP32 vector rate, twice what unpacked vector FMAs
+// reach.  A wave takes 64 queries, one per lane: each lane loads (or encodes)
+// its query's 64 features, then a 4 x 4 transpose across the four 16-lane
+// groups (v_permlane32_swap, v_permlane16_swap) turns them into the B operands
+// of four 16-query columns with no LDS round trip.  A layer's accumulators are
+// the next layer's B operands as they stand (the weight's K index follows the
+// accumulator layout), so activations never leave VGPRs.  The weights of all
+// layers sit in LDS as per-lane float4 A fragments, one workgroup per CU.
 //
 // Training: a workgroup of 4 waves owns a tile of 64 records.  Activations of
 // every layer stay in LDS ([sample][feature], padded rows).  In the forward and
@@ -21,35 +28,10 @@ namespace {
 constexpr int kW = 64;      // the FP32 form supports width 64
 constexpr int kLd = 68;     // padded LDS row stride (floats)
 constexpr int kTile = 64;       // training records per workgroup
+constexpr int kQWaves = 8;      // waves per query workgroup (two per SIMD)
+constexpr int kQMaxBlocks = 256;    // query workgroups: one per CU (LDS-bound)
 
-// One 64 -> 64 ReLU layer on the activations in h (VGPRs); every weight is a
-// wave-uniform operand fetched with scalar loads.
-__device__ inline void layer_fp32(float (&h)[kW], const float* __restrict__ wl) {
-    float z[kW];
-    #pragma unroll
-    for (int o = 0; o < kW; ++o) {
-        float acc = 0.0f;
-        #pragma unroll
-        for (int k = 0; k < kW; ++k) acc = fmaf(wl[o * kW + k], h[k], acc);
-        z[o] = acc;
-    }
-    #pragma unroll
-    for (int o = 0; o < kW; ++o) h[o] = fmaxf(z[o], 0.0f);
-}
-
-// The network on one record whose 64 input features are in h.
-__device__ inline void mlp_fp32(float (&h)[kW], const float* __restrict__ w, int n_hidden,
-                                float (&y)[kNOut]) {
-    for (int l = 0; l < n_hidden; ++l) layer_fp32(h, w + l * kW * kW);
-    const float* wo = w + n_hidden * kW * kW;
-    #pragma unroll
-    for (int o = 0; o < kNOut; ++o) {
-        float acc = 0.0f;
-        #pragma unroll
-        for (int k = 0; k < kW; ++k) acc = fmaf(wo[o * kW + k], h[k], acc);
-        y[o] = acc;
-    }
-}
+typedef float f4 __attribute__((ext_vector_type(4)));
 
 // Output of one query: the network output times the reflectance factor.
 __device__ inline void store_query(float* __restrict__ rgb, int64_t s, const float (&y)[kNOut],
@@ -59,46 +41,168 @@ __device__ inline void store_query(float* __restrict__ rgb, int64_t s, const flo
     rgb[s * 3 + 2] = y[2] * r[2];
 }
 
-__global__ __launch_bounds__(256) void k_fwd_fp32(const float* __restrict__ w,
-                                                  const float* __restrict__ enc, int64_t n,
-                                                  float* __restrict__ rgb, int n_hidden, int fcol) {
-    const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (s >= n) return;
-    float h[kW];
-    const float4* row = reinterpret_cast<const float4*>(enc + s * kEncWidth);
-    #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-        const float4 v = row[q];
-        h[4 * q] = v.x; h[4 * q + 1] = v.y; h[4 * q + 2] = v.z; h[4 * q + 3] = v.w;
-    }
-    float r[kNOut], y[kNOut];
-    reflectance_row(h, fcol, r);
-    mlp_fp32(h, w, n_hidden, y);
-    store_query(rgb, s, y, r);
+// Transposes a 4 x 4 block of (16-lane group, register): afterwards register
+// c of group g holds what register g of group c held.  permlane32_swap trades
+// groups {2,3} of its first operand for groups {0,1} of its second;
+// permlane16_swap trades groups {1,3} of its first for groups {0,2} of its
+// second.
+__device__ inline void xpose4(float& r0, float& r1, float& r2, float& r3) {
+    const auto s02 = __builtin_amdgcn_permlane32_swap(__float_as_uint(r0), __float_as_uint(r2), false, false);
+    const auto s13 = __builtin_amdgcn_permlane32_swap(__float_as_uint(r1), __float_as_uint(r3), false, false);
+    const auto s01 = __builtin_amdgcn_permlane16_swap(s02[0], s13[0], false, false);
+    const auto s23 = __builtin_amdgcn_permlane16_swap(s02[1], s13[1], false, false);
+    r0 = __uint_as_float(s01[0]);
+    r1 = __uint_as_float(s01[1]);
+    r2 = __uint_as_float(s23[0]);
+    r3 = __uint_as_float(s23[1]);
 }
 
-// Inference from raw records with the encoding fused in: each lane encodes its
-// record straight into the VGPRs of the first layer's input.
-template <int PRESET, int LAYOUT>
-__global__ __launch_bounds__(256) void k_fwd_raw_fp32(const float* __restrict__ w,
-                                                      const float* __restrict__ raw, int64_t n,
-                                                      float* __restrict__ rgb, int n_hidden, int fcol) {
-    constexpr int RW = LAYOUT == NRC_RAW14 ? 14 : 16;
-    const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (s >= n) return;
-    float x[RW];
-    const float2* src = reinterpret_cast<const float2*>(raw + s * RW);
-    #pragma unroll
-    for (int q = 0; q < RW / 2; ++q) {
-        const float2 v = src[q];
-        x[2 * q] = v.x; x[2 * q + 1] = v.y;
+// Operand layout of v_mfma_f32_16x16x4_f32 (D = A B + C, 16 x 4 by 4 x 16):
+// lane 16k + i supplies A[i][k], lane 16k + j supplies B[k][j], and lane
+// 16g + j holds D[4g + r][j] in register r.  With j a query and i an output
+// neuron of block ob, lane (g, j) ends a layer holding neurons 16 ob + 4g + r.
+// The K step s = 4 ob' + r of the next layer therefore takes neuron
+// 16 ob' + 4g + r from lane group g, and the A fragment of (ob, ob') gives lane
+// (g, i) the float4 W[16 ob + i][16 ob' + 4g .. 16 ob' + 4g + 3], one element
+// per r.  Fragments of layer l occupy [16 l, 16 l + 16) (index 4 ob + ob'), the
+// output layer's four follow (rows 3..15 zero).
+__device__ inline void stage_query_frags(f4* sw, const float* __restrict__ w, int H) {
+    const int nfr = 16 * H + 4;
+    for (int idx = threadIdx.x; idx < nfr * 64; idx += blockDim.x) {
+        const int f = idx >> 6, lane = idx & 63, g = lane >> 4, i = lane & 15;
+        f4 v = {0.0f, 0.0f, 0.0f, 0.0f};
+        const float* src = nullptr;
+        if (f < 16 * H) {
+            const int l = f >> 4, ob = (f >> 2) & 3, obp = f & 3;
+            src = w + l * kW * kW + (16 * ob + i) * kW + 16 * obp + 4 * g;
+        } else if (i < kNOut) {
+            src = w + H * kW * kW + i * kW + 16 * (f - 16 * H) + 4 * g;
+        }
+        if (src) v = f4{src[0], src[1], src[2], src[3]};
+        sw[idx] = v;
     }
-    float h[kW];
-    encode_record<PRESET, LAYOUT>(x, h);
-    float r[kNOut], y[kNOut];
-    reflectance_row(h, fcol, r);
-    mlp_fp32(h, w, n_hidden, y);
-    store_query(rgb, s, y, r);
+}
+
+// The network on the wave's 64 queries.  h: this lane's 64 input features; y:
+// this lane's 3 outputs.
+__device__ inline void mlp_query_mfma(const f4* __restrict__ sw, int H, int lane, const float (&h)[kW],
+                                      float (&y)[kNOut]) {
+    float act[4][16];   // [column][K step]: lane group g, step 4b + r = neuron 16b + 4g + r
+    #pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        #pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            float q0 = h[16 * b + r], q1 = h[16 * b + 4 + r], q2 = h[16 * b + 8 + r], q3 = h[16 * b + 12 + r];
+            xpose4(q0, q1, q2, q3);
+            act[0][4 * b + r] = q0;
+            act[1][4 * b + r] = q1;
+            act[2][4 * b + r] = q2;
+            act[3][4 * b + r] = q3;
+        }
+    }
+    for (int l = 0; l < H; ++l) {
+        const f4* fl = sw + l * 16 * 64 + lane;
+        f4 acc[4][4];   // [column][ob]
+        #pragma unroll
+        for (int c = 0; c < 4; ++c)
+            #pragma unroll
+            for (int ob = 0; ob < 4; ++ob) acc[c][ob] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+        #pragma unroll
+        for (int obp = 0; obp < 4; ++obp) {
+            #pragma unroll
+            for (int ob = 0; ob < 4; ++ob) {
+                const f4 a = fl[(4 * ob + obp) * 64];
+                #pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    #pragma unroll
+                    for (int c = 0; c < 4; ++c)
+                        acc[c][ob] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r], act[c][4 * obp + r], acc[c][ob], 0, 0, 0);
+            }
+        }
+        #pragma unroll
+        for (int c = 0; c < 4; ++c)
+            #pragma unroll
+            for (int ob = 0; ob < 4; ++ob)
+                #pragma unroll
+                for (int r = 0; r < 4; ++r) act[c][4 * ob + r] = fmaxf(acc[c][ob][r], 0.0f);
+    }
+    const f4* fo = sw + H * 16 * 64 + lane;
+    f4 o[4];
+    #pragma unroll
+    for (int c = 0; c < 4; ++c) o[c] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+    #pragma unroll
+    for (int obp = 0; obp < 4; ++obp) {
+        const f4 a = fo[obp * 64];
+        #pragma unroll
+        for (int r = 0; r < 4; ++r)
+            #pragma unroll
+            for (int c = 0; c < 4; ++c) o[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r], act[c][4 * obp + r], o[c], 0, 0, 0);
+    }
+    // lane group 0 holds output channel ch of column c's queries in o[c][ch];
+    // the transpose hands it to group c, the lanes that loaded those queries
+    #pragma unroll
+    for (int ch = 0; ch < kNOut; ++ch) {
+        float t0 = o[0][ch], t1 = o[1][ch], t2 = o[2][ch], t3 = o[3][ch];
+        xpose4(t0, t1, t2, t3);
+        y[ch] = t0;
+    }
+}
+
+// Inference: RAW = false reads 64 encoded features per query; RAW = true reads
+// raw records and encodes them in the lane (Sec. 3.6).  A wave takes 64
+// consecutive queries per tile; lanes past the end compute on the last query
+// and store nothing, so every lane joins every matrix instruction.
+template <bool RAW, int PRESET, int LAYOUT>
+__device__ inline void query_fp32(const float* __restrict__ w, const float* __restrict__ in, int64_t n,
+                                  float* __restrict__ rgb, int H, int fcol) {
+    extern __shared__ f4 sw[];
+    constexpr int RW = LAYOUT == NRC_RAW14 ? 14 : 16;
+    stage_query_frags(sw, w, H);
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t n_tiles = (n + 63) / 64;
+    const int64_t stride = (int64_t)gridDim.x * kQWaves;
+    for (int64_t t = (int64_t)blockIdx.x * kQWaves + wave; t < n_tiles; t += stride) {
+        int64_t s = t * 64 + lane;
+        const bool valid = s < n;
+        if (!valid) s = n - 1;
+        float h[kW];
+        if (RAW) {
+            float x[RW];
+            const float2* src = reinterpret_cast<const float2*>(in + s * RW);
+            #pragma unroll
+            for (int q = 0; q < RW / 2; ++q) {
+                const float2 v = src[q];
+                x[2 * q] = v.x; x[2 * q + 1] = v.y;
+            }
+            encode_record<PRESET, LAYOUT>(x, h);
+        } else {
+            const float4* row = reinterpret_cast<const float4*>(in + s * kEncWidth);
+            #pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const float4 v = row[q];
+                h[4 * q] = v.x; h[4 * q + 1] = v.y; h[4 * q + 2] = v.z; h[4 * q + 3] = v.w;
+            }
+        }
+        float r[kNOut], y[kNOut];
+        reflectance_row(h, fcol, r);
+        mlp_query_mfma(sw, H, lane, h, y);
+        if (valid) store_query(rgb, s, y, r);
+    }
+}
+
+__global__ __launch_bounds__(64 * kQWaves) void k_fwd_fp32(const float* __restrict__ w,
+                                                          const float* __restrict__ enc, int64_t n,
+                                                          float* __restrict__ rgb, int n_hidden, int fcol) {
+    query_fp32<false, NRC_PRESET_CONFIG, NRC_RAW14>(w, enc, n, rgb, n_hidden, fcol);
+}
+
+// Inference from raw records with the encoding fused in.
+template <int PRESET, int LAYOUT>
+__global__ __launch_bounds__(64 * kQWaves) void k_fwd_raw_fp32(const float* __restrict__ w,
+                                                              const float* __restrict__ raw, int64_t n,
+                                                              float* __restrict__ rgb, int n_hidden, int fcol) {
+    query_fp32<true, PRESET, LAYOUT>(w, raw, n, rgb, n_hidden, fcol);
 }
 
 // Fixed-order sum over the 64 lanes of a wave (same tree on every call).
@@ -337,44 +441,52 @@ __global__ __launch_bounds__(64 * NWV) void k_train_fp32(const float* __restrict
     if (tid == 0) tile_bad[tile] = any_bad ? 1 : 0;
 }
 
+// Query grid: one workgroup of kQWaves waves per CU (the fragments of every
+// layer, (16 H + 4) KB, fill most of the CU's LDS), each wave striding over
+// 64-query tiles.
+inline size_t query_lds_bytes(const Geo& d) { return (size_t)(16 * d.H + 4) * 64 * sizeof(f4); }
+inline int64_t query_blocks(int64_t n) {
+    const int64_t tiles = (n + 63) / 64;
+    const int64_t b = (tiles + kQWaves - 1) / kQWaves;
+    return b < kQMaxBlocks ? b : kQMaxBlocks;
+}
+
+template <typename K>
+hipError_t launch_query(K kernel, const Geo& d, const float* w, const float* in, int64_t n, float* rgb,
+                        hipStream_t s) {
+    const int64_t blocks = query_blocks(n);
+    if (blocks == 0) return hipSuccess;
+    const size_t lds = query_lds_bytes(d);
+    hipError_t e = hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kernel, dim3((unsigned)blocks), dim3(64 * kQWaves), lds, s, w, in, n, rgb, d.H, d.F);
+    return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t launch_fwd_fp32(const Geo& d, const float* w, const float* enc, int64_t n, float* rgb,
                            hipStream_t s) {
-    const int64_t blocks = (n + 255) / 256;
-    if (blocks == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_fwd_fp32, dim3((unsigned)blocks), dim3(256), 0, s, w, enc, n, rgb,
-                       d.H, d.F);
-    return hipGetLastError();
+    return launch_query(k_fwd_fp32, d, w, enc, n, rgb, s);
 }
 
 hipError_t launch_fwd_raw_fp32(const Geo& d, int preset, int layout, const float* w, const float* raw,
                                int64_t n, float* rgb, hipStream_t s) {
-    const int64_t blocks = (n + 255) / 256;
-    if (blocks == 0) return hipSuccess;
-    const dim3 grid((unsigned)blocks), block(256);
-    if (preset == NRC_PRESET_PAPER_GAUSS) {
-        if (layout == NRC_RAW14)
-            hipLaunchKernelGGL((k_fwd_raw_fp32<NRC_PRESET_PAPER_GAUSS, NRC_RAW14>), grid, block, 0, s, w, raw, n, rgb, d.H, d.F);
-        else
-            hipLaunchKernelGGL((k_fwd_raw_fp32<NRC_PRESET_PAPER_GAUSS, NRC_RAW16>), grid, block, 0, s, w, raw, n, rgb, d.H, d.F);
-    } else if (preset == NRC_PRESET_PAPER_TRI) {
-        if (layout == NRC_RAW14)
-            hipLaunchKernelGGL((k_fwd_raw_fp32<NRC_PRESET_PAPER_TRI, NRC_RAW14>), grid, block, 0, s, w, raw, n, rgb, d.H, d.F);
-        else
-            hipLaunchKernelGGL((k_fwd_raw_fp32<NRC_PRESET_PAPER_TRI, NRC_RAW16>), grid, block, 0, s, w, raw, n, rgb, d.H, d.F);
-    } else if (preset == NRC_PRESET_PAPER) {
-        if (layout == NRC_RAW14)
-            hipLaunchKernelGGL((k_fwd_raw_fp32<NRC_PRESET_PAPER, NRC_RAW14>), grid, block, 0, s, w, raw, n, rgb, d.H, d.F);
-        else
-            hipLaunchKernelGGL((k_fwd_raw_fp32<NRC_PRESET_PAPER, NRC_RAW16>), grid, block, 0, s, w, raw, n, rgb, d.H, d.F);
-    } else {
-        if (layout == NRC_RAW14)
-            hipLaunchKernelGGL((k_fwd_raw_fp32<NRC_PRESET_CONFIG, NRC_RAW14>), grid, block, 0, s, w, raw, n, rgb, d.H, d.F);
-        else
-            hipLaunchKernelGGL((k_fwd_raw_fp32<NRC_PRESET_CONFIG, NRC_RAW16>), grid, block, 0, s, w, raw, n, rgb, d.H, d.F);
+    const bool r14 = layout == NRC_RAW14;
+    switch (preset) {
+    case NRC_PRESET_PAPER_GAUSS:
+        return r14 ? launch_query(k_fwd_raw_fp32<NRC_PRESET_PAPER_GAUSS, NRC_RAW14>, d, w, raw, n, rgb, s)
+                   : launch_query(k_fwd_raw_fp32<NRC_PRESET_PAPER_GAUSS, NRC_RAW16>, d, w, raw, n, rgb, s);
+    case NRC_PRESET_PAPER_TRI:
+        return r14 ? launch_query(k_fwd_raw_fp32<NRC_PRESET_PAPER_TRI, NRC_RAW14>, d, w, raw, n, rgb, s)
+                   : launch_query(k_fwd_raw_fp32<NRC_PRESET_PAPER_TRI, NRC_RAW16>, d, w, raw, n, rgb, s);
+    case NRC_PRESET_PAPER:
+        return r14 ? launch_query(k_fwd_raw_fp32<NRC_PRESET_PAPER, NRC_RAW14>, d, w, raw, n, rgb, s)
+                   : launch_query(k_fwd_raw_fp32<NRC_PRESET_PAPER, NRC_RAW16>, d, w, raw, n, rgb, s);
+    default:
+        return r14 ? launch_query(k_fwd_raw_fp32<NRC_PRESET_CONFIG, NRC_RAW14>, d, w, raw, n, rgb, s)
+                   : launch_query(k_fwd_raw_fp32<NRC_PRESET_CONFIG, NRC_RAW16>, d, w, raw, n, rgb, s);
     }
-    return hipGetLastError();
 }
 
 size_t fp32_train_lds_bytes(int n_hidden) {
