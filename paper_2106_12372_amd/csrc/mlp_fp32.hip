@@ -12,13 +12,14 @@
 // accumulator layout), so activations never leave VGPRs.  The weights of all
 // layers sit in LDS as per-lane float4 A fragments, one workgroup per CU.
 //
-// Training: a workgroup of 4 waves owns a tile of 64 records.  Activations of
-// every layer stay in LDS ([sample][feature], padded rows).  In the forward and
-// data-backward passes wave w produces features 16w..16w+15 of all 64 samples
-// (lane = sample); for the weight gradient it produces rows 16w..16w+15 of
-// dW_l for all 64 input features (lane = input feature), summing over the
-// tile's samples.  Each tile writes its dW partial; a separate fixed-order
-// reduction sums the partials (no atomics, so results are reproducible).
+// Training: a workgroup of 16 waves owns a tile of 64 records.  Activations
+// of every layer stay in LDS ([sample][feature], padded rows).  Each of the
+// tile's three 64 x 64 products per layer (forward, data backward, weight
+// gradient) is 16 blocks of 16 x 16, one per wave, each block 16 FP32 matrix
+// instructions over a K of 64; operands come from LDS and, for weights, from
+// the L2-resident master copy.  Each tile writes its dW partial; a separate
+// fixed-order reduction sums the partials (no atomics, so results are
+// reproducible).
 #include "encode_impl.h"
 #include "nrc_internal.h"
 
@@ -217,10 +218,13 @@ __device__ inline float wave_sum(float v) {
 // With the reflectance factorisation (fcol != 0) y is the network output times
 // R = alpha + beta; the network's output gradient is dL/dy * R, and dL/denc
 // also takes dL/dy_c * f_c on both albedo columns of channel c.
-// NWV waves share a tile of 64 records; wave w owns FPW = 64 / NWV features
-// (forward and data backward, lane = record) and FPW rows of each dW_l (lane =
-// input feature).  More waves per tile give each SIMD more waves to hide the
-// latency of LDS and scalar weight loads.
+// NWV = 16 waves share a tile of 64 records.  In the three products of a
+// layer wave w owns one 16 x 16 block (block row w / 4, block column w % 4);
+// with the MFMA layout above, lane (g, j) supplies K index 16g + t in step t,
+// so each lane's operand run over the 16 steps is contiguous in the row-major
+// weights or in an LDS row, or strided by a row.  The output layer (3 rows)
+// and the loss stay on the vector ALUs (lane = record, FPW = 4 features per
+// wave where a pass is split by feature).
 template <bool UPSTREAM, bool GENC, int NWV>
 __global__ __launch_bounds__(64 * NWV) void k_train_fp32(const float* __restrict__ w,
                                                          const float* __restrict__ enc,
@@ -231,7 +235,8 @@ __global__ __launch_bounds__(64 * NWV) void k_train_fp32(const float* __restrict
                                                          float* __restrict__ loss_part,
                                                          int32_t* __restrict__ tile_bad,
                                                          float* __restrict__ genc, int fcol) {
-    constexpr int FPW = kW / NWV;                          // features (or dW rows) per wave
+    static_assert(NWV == 16, "one 16 x 16 block of each 64 x 64 product per wave");
+    constexpr int FPW = kW / NWV;                          // features per wave (output layer)
     constexpr int NT = 64 * NWV;
     extern __shared__ __attribute__((aligned(16))) float smem[];
     float* hs = smem;                                     // (n_hidden+1) x [64][kLd]
@@ -249,7 +254,9 @@ __global__ __launch_bounds__(64 * NWV) void k_train_fp32(const float* __restrict
     // record read for this slot: idx[row] for a gathered batch, else row
     const int64_t src = !valid ? 0 : idx ? (int64_t)idx[row] : row;
     float* part = partials + tile * (int64_t)n_params;
-    const int f0 = FPW * wave;                            // this wave's first feature / dW row
+    const int f0 = FPW * wave;                            // this wave's first feature (output layer)
+    const int g = lane >> 4, j = lane & 15;               // MFMA lane group and column
+    const int bro = wave >> 2, bco = wave & 3;            // this wave's block row and column
 
     // Stage the tile's inputs as h_0 (zeros past the end of the batch).
     for (int i = tid; i < kTile * 16; i += NT) {
@@ -261,34 +268,27 @@ __global__ __launch_bounds__(64 * NWV) void k_train_fp32(const float* __restrict
     }
     __syncthreads();
 
-    // Forward: wave w writes features f0..f0+FPW-1 of every sample (lane = sample).
-    // Layer l's weights start at w + l * 64 * 64 (the input layer is 64 x 64
-    // too); addressing them from the base pointer, not a running one, keeps the
-    // scalar register file from spilling.
+    // Forward: z = W_l h, wave w the block (out features 16 bro.., samples
+    // 16 bco..).  A: lane (g, i) takes W_l[16 bro + i][16g + t]; B: lane (g, j)
+    // takes h[16 bco + j][16g + t]; D: lane (g, j) ends with out features
+    // 16 bro + 4g .. +3 of sample 16 bco + j.  Layer l's weights start at
+    // w + l * 64 * 64 (the input layer is 64 x 64 too).
     for (int l = 0; l < n_hidden; ++l) {
-        const float* wl = w + l * kW * kW;
-        const float* hin = hs + l * kTile * kLd + lane * kLd;
-        float* hout = hs + (l + 1) * kTile * kLd + lane * kLd;
-        float acc[FPW];
+        const float* arow = w + l * kW * kW + (16 * bro + j) * kW + 16 * g;
+        const float* brow = hs + l * kTile * kLd + (16 * bco + j) * kLd + 16 * g;
+        f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
         #pragma unroll
-        for (int j = 0; j < FPW; ++j) acc[j] = 0.0f;
-        #pragma unroll
-        for (int k4 = 0; k4 < 16; ++k4) {
-            const float4 hv = *reinterpret_cast<const float4*>(hin + 4 * k4);
-            #pragma unroll
-            for (int j = 0; j < FPW; ++j) {
-                const float* wr = wl + (f0 + j) * kW + 4 * k4;
-                acc[j] = fmaf(wr[0], hv.x, acc[j]);
-                acc[j] = fmaf(wr[1], hv.y, acc[j]);
-                acc[j] = fmaf(wr[2], hv.z, acc[j]);
-                acc[j] = fmaf(wr[3], hv.w, acc[j]);
-            }
+        for (int t4 = 0; t4 < 4; ++t4) {
+            const float4 a = *reinterpret_cast<const float4*>(arow + 4 * t4);
+            const float4 b = *reinterpret_cast<const float4*>(brow + 4 * t4);
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.y, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, b.z, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, b.w, acc, 0, 0, 0);
         }
-        #pragma unroll
-        for (int j4 = 0; j4 < FPW / 4; ++j4)
-            *reinterpret_cast<float4*>(hout + f0 + 4 * j4) =
-                make_float4(fmaxf(acc[4 * j4], 0.f), fmaxf(acc[4 * j4 + 1], 0.f),
-                            fmaxf(acc[4 * j4 + 2], 0.f), fmaxf(acc[4 * j4 + 3], 0.f));
+        float* hout = hs + (l + 1) * kTile * kLd + (16 * bco + j) * kLd + 16 * bro + 4 * g;
+        *reinterpret_cast<float4*>(hout) = make_float4(fmaxf(acc[0], 0.f), fmaxf(acc[1], 0.f),
+                                                       fmaxf(acc[2], 0.f), fmaxf(acc[3], 0.f));
         __syncthreads();
     }
     const float* wout = w + n_hidden * kW * kW;           // [3][64]
@@ -369,69 +369,67 @@ __global__ __launch_bounds__(64 * NWV) void k_train_fp32(const float* __restrict
         off -= kW * cols;
         const float* wlay = w + off;
         const float* hl = hs + l * kTile * kLd;
-        // dW_l rows f0..f0+FPW-1, lane = input feature i.
+        // dW_l[o][i] = sum_s delta[s][o] h_l[s][i], wave w the block (rows
+        // 16 bro.., columns 16 bco..).  A: lane (g, i) takes delta[16g + t][16 bro + i];
+        // B: lane (g, j) takes h_l[16g + t][16 bco + j]; D: lane (g, j) ends with
+        // rows 16 bro + 4g .. +3 of column 16 bco + j.
         {
-            float acc[FPW];
+            const float* da = dcur + 16 * g * kLd + 16 * bro + j;
+            const float* hb = hl + 16 * g * kLd + 16 * bco + j;
+            f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
             #pragma unroll
-            for (int j = 0; j < FPW; ++j) acc[j] = 0.0f;
-            for (int s = 0; s < kTile; ++s) {
-                const float hv = hl[s * kLd + lane];
-                const float* dr = dcur + s * kLd + f0;
-                #pragma unroll
-                for (int j4 = 0; j4 < FPW / 4; ++j4) {
-                    const float4 dv = *reinterpret_cast<const float4*>(dr + 4 * j4);
-                    acc[4 * j4] = fmaf(dv.x, hv, acc[4 * j4]);
-                    acc[4 * j4 + 1] = fmaf(dv.y, hv, acc[4 * j4 + 1]);
-                    acc[4 * j4 + 2] = fmaf(dv.z, hv, acc[4 * j4 + 2]);
-                    acc[4 * j4 + 3] = fmaf(dv.w, hv, acc[4 * j4 + 3]);
-                }
-            }
+            for (int t = 0; t < 16; ++t)
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(da[t * kLd], hb[t * kLd], acc, 0, 0, 0);
+            float* dst = part + off + (16 * bro + 4 * g) * cols + 16 * bco + j;
             #pragma unroll
-            for (int j = 0; j < FPW; ++j) {
+            for (int r = 0; r < 4; ++r) {
                 // streamed past the caches: read once, by the reduction
-                __builtin_nontemporal_store(acc[j], &part[off + (f0 + j) * cols + lane]);
-                bad |= !isfinite(acc[j]);
+                __builtin_nontemporal_store(acc[r], dst + r * cols);
+                bad |= !isfinite(acc[r]);
             }
         }
         // delta_l = W_l^T delta_{l+1}, masked (l >= 1); or dL/dh_0 (l == 0).
+        // Wave w the block (features 16 bro.., samples 16 bco..).  A: lane (g, i)
+        // takes W_l[16g + t][16 bro + i]; B: lane (g, j) takes
+        // delta[16 bco + j][16g + t]; D: lane (g, j) ends with features
+        // 16 bro + 4g .. +3 of sample 16 bco + j.
         if (l >= 1 || GENC) {
-            float acc[FPW];
+            const float* wa = wlay + 16 * g * cols + 16 * bro + j;
+            const float* db = dcur + (16 * bco + j) * kLd + 16 * g;
+            f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
             #pragma unroll
-            for (int j = 0; j < FPW; ++j) acc[j] = 0.0f;
-            const float* dr = dcur + lane * kLd;
-            #pragma unroll
-            for (int o4 = 0; o4 < 16; ++o4) {
-                const float4 dv = *reinterpret_cast<const float4*>(dr + 4 * o4);
-                #pragma unroll
-                for (int j = 0; j < FPW; ++j) {
-                    const float* wc = wlay + (4 * o4) * cols + f0 + j;
-                    acc[j] = fmaf(wc[0], dv.x, acc[j]);
-                    acc[j] = fmaf(wc[cols], dv.y, acc[j]);
-                    acc[j] = fmaf(wc[2 * cols], dv.z, acc[j]);
-                    acc[j] = fmaf(wc[3 * cols], dv.w, acc[j]);
-                }
+            for (int t4 = 0; t4 < 4; ++t4) {
+                const float4 b = *reinterpret_cast<const float4*>(db + 4 * t4);
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(wa[(4 * t4) * cols], b.x, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(wa[(4 * t4 + 1) * cols], b.y, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(wa[(4 * t4 + 2) * cols], b.z, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(wa[(4 * t4 + 3) * cols], b.w, acc, 0, 0, 0);
             }
+            const int sm = 16 * bco + j;                  // this lane's sample in the tile
+            const int fb = 16 * bro + 4 * g;              // its first feature
             if (l >= 1) {
-                const float* hr = hl + lane * kLd + f0;
-                float* dst = dnxt + lane * kLd + f0;
-                #pragma unroll
-                for (int j = 0; j < FPW; ++j) dst[j] = hr[j] > 0.0f ? acc[j] : 0.0f;
-            } else if (valid) {
-                if (fcol) {
-                    // d(f_c R_c)/d(albedo column) = f_c on the diffuse and specular column.
-                    #pragma unroll
-                    for (int j = 0; j < FPW; ++j) {
-                        int c = f0 + j - fcol;
-                        if (c >= 0 && c < 6) {
-                            c = c >= 3 ? c - 3 : c;
-                            acc[j] = fmaf(tgt[src * 3 + c], fout[lane * 4 + c], acc[j]);
+                const float4 hv = *reinterpret_cast<const float4*>(hl + sm * kLd + fb);
+                *reinterpret_cast<float4*>(dnxt + sm * kLd + fb) =
+                    make_float4(hv.x > 0.0f ? acc[0] : 0.0f, hv.y > 0.0f ? acc[1] : 0.0f,
+                                hv.z > 0.0f ? acc[2] : 0.0f, hv.w > 0.0f ? acc[3] : 0.0f);
+            } else {
+                const int64_t srow = tile * kTile + sm;
+                if (srow < n) {
+                    if (fcol) {
+                        // d(f_c R_c)/d(albedo column) = f_c on the diffuse and specular column.
+                        const int64_t ssrc = idx ? (int64_t)idx[srow] : srow;
+                        #pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            int c = fb + r - fcol;
+                            if (c >= 0 && c < 6) {
+                                c = c >= 3 ? c - 3 : c;
+                                acc[r] = fmaf(tgt[ssrc * 3 + c], fout[sm * 4 + c], acc[r]);
+                            }
                         }
                     }
+                    *reinterpret_cast<float4*>(genc + srow * kEncWidth + fb) =
+                        make_float4(acc[0], acc[1], acc[2], acc[3]);
                 }
-                #pragma unroll
-                for (int j4 = 0; j4 < FPW / 4; ++j4)
-                    *reinterpret_cast<float4*>(genc + row * kEncWidth + f0 + 4 * j4) =
-                        make_float4(acc[4 * j4], acc[4 * j4 + 1], acc[4 * j4 + 2], acc[4 * j4 + 3]);
             }
         }
         __syncthreads();

@@ -219,10 +219,11 @@ class Cache:
         self.n_params = nrc_param_count(cfg)
         self._scratch = None
 
-    def __del__(self):
-        # at interpreter exit the module's globals may already be gone; the
-        # process ends and the driver reclaims the device memory
-        if sys.is_finalizing() or lib is None:
+    def __del__(self, _finalizing=sys.is_finalizing):
+        # at interpreter exit the module's globals may already be gone (the
+        # default argument keeps the check itself alive); the process ends and
+        # the driver reclaims the device memory
+        if _finalizing() or lib is None:
             return
         h = getattr(self, "handle", None)
         if h is not None and h.value:
@@ -531,8 +532,8 @@ class Server:
             check(lib.nrc_serve_destroy(self.handle))
             self.handle = None
 
-    def __del__(self):
-        if sys.is_finalizing() or lib is None:
+    def __del__(self, _finalizing=sys.is_finalizing):
+        if _finalizing() or lib is None:
             return
         try:
             self.close()

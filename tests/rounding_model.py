@@ -96,3 +96,20 @@ class TrainModel:
         vh = self.v / f(1 - self.b2 ** self.t)
         self.w = (self.w - f(self.lr) * mh / (np.sqrt(vh) + f(self.eps))).astype(np.float32)
         return loss
+
+
+def relu_undecided_rows(mats, x, rel=1e-5):
+    """Records whose ReLU masks FP32 arithmetic does not decide: some hidden
+    pre-activation z lies within rel * sum |w h| of zero, well inside the FP32
+    error bound of a 64-term dot product over inputs that carry their own
+    rounding.  ReLU' is a step at zero, so for such a unit the sign, and with
+    it the whole backward contribution through it, depends on summation order;
+    the FP64 oracle's choice is no more right than the kernel's.  Returns a
+    boolean mask over the records."""
+    h = np.asarray(x, np.float64)
+    undecided = np.zeros(h.shape[0], bool)
+    for w in mats[:-1]:
+        z = h @ w.T
+        undecided |= np.any(np.abs(z) <= rel * (np.abs(h) @ np.abs(w).T), axis=1)
+        h = np.maximum(z, 0.0)
+    return undecided

@@ -34,6 +34,13 @@ def test_autograd_gradients(AG, prec, width, n):
     dt = mod.cache.enc_dtype
     x = torch.from_numpy(sd.uniform_features(n, 64, 51)).to("cuda").to(dt).requires_grad_(True)
     r = sd.gaussian((n, 3), sd.SEED_FD)
+    if prec == "fp32":
+        # records whose ReLU masks rounding decides take no upstream gradient,
+        # so the strict FP32 bound compares only what the arithmetic fixes
+        # (with this seed, one unit of 4096 records sits 1.4e-8 from zero)
+        st0 = O.CacheState(mod.weights.detach().cpu().numpy(), width=width)
+        x0 = x.detach().float().cpu().numpy().astype(np.float64)
+        r[RM.relu_undecided_rows(st0.mats(), x0)] = 0.0
     y = mod(x)
     (y * torch.from_numpy(r).to("cuda")).sum().backward()
     gw = mod.weights.grad.cpu().numpy().astype(np.float64)
