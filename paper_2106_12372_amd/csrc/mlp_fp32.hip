@@ -220,9 +220,11 @@ __device__ inline float wave_sum(float v) {
 // also takes dL/dy_c * f_c on both albedo columns of channel c.
 // NWV = 16 waves share a tile of 64 records.  In the three products of a
 // layer wave w owns one 16 x 16 block (block row w / 4, block column w % 4);
-// with the MFMA layout above, lane (g, j) supplies K index 16g + t in step t,
-// so each lane's operand run over the 16 steps is contiguous in the row-major
-// weights or in an LDS row, or strided by a row.  The output layer (3 rows)
+// with the MFMA layout above, lane (g, j) supplies K index 16g + t in step t
+// of the forward and data-backward products, so each lane's operand run over
+// the 16 steps is contiguous in the row-major weights or in an LDS row, or
+// strided by a row (the weight gradient orders its K, the samples, for
+// conflict-free LDS banks instead).  The output layer (3 rows)
 // and the loss stay on the vector ALUs (lane = record, FPW = 4 features per
 // wave where a pass is split by feature).
 template <bool UPSTREAM, bool GENC, int NWV>
@@ -370,16 +372,21 @@ __global__ __launch_bounds__(64 * NWV) void k_train_fp32(const float* __restrict
         const float* wlay = w + off;
         const float* hl = hs + l * kTile * kLd;
         // dW_l[o][i] = sum_s delta[s][o] h_l[s][i], wave w the block (rows
-        // 16 bro.., columns 16 bco..).  A: lane (g, i) takes delta[16g + t][16 bro + i];
-        // B: lane (g, j) takes h_l[16g + t][16 bco + j]; D: lane (g, j) ends with
-        // rows 16 bro + 4g .. +3 of column 16 bco + j.
+        // 16 bro.., columns 16 bco..).  In step t lane group g takes sample
+        // s = 16 (t / 4) + 4g + t % 4, so the four groups read rows 4 apart
+        // (16 banks apart at the 68-float stride; rows 16 apart would share
+        // banks).  A: lane (g, i) takes delta[s][16 bro + i]; B: lane (g, j)
+        // takes h_l[s][16 bco + j]; D: lane (g, j) ends with rows
+        // 16 bro + 4g .. +3 of column 16 bco + j.
         {
-            const float* da = dcur + 16 * g * kLd + 16 * bro + j;
-            const float* hb = hl + 16 * g * kLd + 16 * bco + j;
+            const float* da = dcur + 4 * g * kLd + 16 * bro + j;
+            const float* hb = hl + 4 * g * kLd + 16 * bco + j;
             f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
             #pragma unroll
-            for (int t = 0; t < 16; ++t)
-                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(da[t * kLd], hb[t * kLd], acc, 0, 0, 0);
+            for (int t = 0; t < 16; ++t) {
+                const int so = (16 * (t >> 2) + (t & 3)) * kLd;
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(da[so], hb[so], acc, 0, 0, 0);
+            }
             float* dst = part + off + (16 * bro + 4 * g) * cols + 16 * bco + j;
             #pragma unroll
             for (int r = 0; r < 4; ++r) {
