@@ -44,7 +44,7 @@ extern "C" {
 #define NRC_ENOTFOUND (-5)
 
 /* Arithmetic of the layer products. */
-#define NRC_FP32 0 /* plain FP32 vector arithmetic, FP32 encoded input */
+#define NRC_FP32 0 /* FP32 products and sums (FP32 matrix cores), FP32 encoded input */
 #define NRC_FP16 1 /* FP16 matrix-core products, FP32 accumulation and master weights */
 #define NRC_BF16 2 /* BF16 matrix-core products, FP32 accumulation and master weights */
 
