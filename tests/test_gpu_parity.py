@@ -182,6 +182,21 @@ def test_forward_raw_equals_encode_then_forward(N, prec, preset, layout, n):
 
 
 @pytest.mark.parametrize("prec", PRECS)
+def test_forward_past_one_round_of_resident_waves(N, prec):
+    # The query kernels keep a fixed grid resident and stride each wave over
+    # 64-query tiles: 256 workgroups of 8 waves in FP32, 512 of 12 in FP16 and
+    # BF16.  65 queries past one full round give every wave a second tile and
+    # end on a ragged one; every row is checked against the oracle.
+    waves = 256 * 8 if prec == "fp32" else 512 * 12
+    n = waves * 64 + 65
+    c, w = make_cache(N, prec)
+    raw = sd.raw_records(n, 301)
+    fused = N.nrc_forward_raw(c, dev(raw))
+    assert torch.equal(fused, N.nrc_forward(c, N.nrc_encode(c, dev(raw))))
+    check_outputs(fused.cpu().numpy(), O.predict(state_of(w), O.encode(raw)), FWD_TOL[prec], FWD_TOL_MAX[prec])
+
+
+@pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("n_hidden", [1, 3, 6, 8])
 @pytest.mark.parametrize("factorize", [False, True])
 def test_forward_raw_other_depths(N, prec, n_hidden, factorize):
