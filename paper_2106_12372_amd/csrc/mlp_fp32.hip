@@ -65,28 +65,35 @@ __device__ inline void xpose4(float& r0, float& r1, float& r2, float& r3) {
 // The K step s = 4 ob' + r of the next layer therefore takes neuron
 // 16 ob' + 4g + r from lane group g, and the A fragment of (ob, ob') gives lane
 // (g, i) the float4 W[16 ob + i][16 ob' + 4g .. 16 ob' + 4g + 3], one element
-// per r.  Fragments of layer l occupy [16 l, 16 l + 16) (index 4 ob + ob'), the
-// output layer's four follow (rows 3..15 zero).
+// per r.  Fragments of layer l occupy [16 l, 16 l + 16) (index 4 ob + ob').
 __device__ inline void stage_query_frags(f4* sw, const float* __restrict__ w, int H) {
-    const int nfr = 16 * H + 4;
+    const int nfr = 16 * H;
     for (int idx = threadIdx.x; idx < nfr * 64; idx += blockDim.x) {
         const int f = idx >> 6, lane = idx & 63, g = lane >> 4, i = lane & 15;
-        f4 v = {0.0f, 0.0f, 0.0f, 0.0f};
-        const float* src = nullptr;
-        if (f < 16 * H) {
-            const int l = f >> 4, ob = (f >> 2) & 3, obp = f & 3;
-            src = w + l * kW * kW + (16 * ob + i) * kW + 16 * obp + 4 * g;
-        } else if (i < kNOut) {
-            src = w + H * kW * kW + i * kW + 16 * (f - 16 * H) + 4 * g;
-        }
-        if (src) v = f4{src[0], src[1], src[2], src[3]};
-        sw[idx] = v;
+        const int l = f >> 4, ob = (f >> 2) & 3, obp = f & 3;
+        const float* src = w + l * kW * kW + (16 * ob + i) * kW + 16 * obp + 4 * g;
+        sw[idx] = f4{src[0], src[1], src[2], src[3]};
     }
 }
 
+// The output layer's weights a lane needs: wo[o][b] = W_out[o][16b + 4g .. +3],
+// the neurons lane group g holds.
+__device__ inline void load_out_weights(const float* __restrict__ w, int H, int g, float4 (&wo)[kNOut][4]) {
+    const float* base = w + H * kW * kW + 4 * g;
+    #pragma unroll
+    for (int o = 0; o < kNOut; ++o)
+        #pragma unroll
+        for (int b = 0; b < 4; ++b) wo[o][b] = *reinterpret_cast<const float4*>(base + o * kW + 16 * b);
+}
+
 // The network on the wave's 64 queries.  h: this lane's 64 input features; y:
-// this lane's 3 outputs.
-__device__ inline void mlp_query_mfma(const f4* __restrict__ sw, int H, int lane, const float (&h)[kW],
+// this lane's 3 outputs.  The hidden layers run on the matrix cores; the
+// 3-row output layer, which would use 3 of an MFMA block's 16 rows, runs on
+// the vector ALUs: each lane forms the partial dots over the 16 neurons it
+// holds for its four columns' queries, and one transpose per channel gathers
+// the four lane groups' partials onto the lane that loaded the query.
+__device__ inline void mlp_query_mfma(const f4* __restrict__ sw, int H, int lane,
+                                      const float4 (&wo)[kNOut][4], const float (&h)[kW],
                                       float (&y)[kNOut]) {
     float act[4][16];   // [column][K step]: lane group g, step 4b + r = neuron 16b + 4g + r
     #pragma unroll
@@ -127,25 +134,25 @@ __device__ inline void mlp_query_mfma(const f4* __restrict__ sw, int H, int lane
                 #pragma unroll
                 for (int r = 0; r < 4; ++r) act[c][4 * ob + r] = fmaxf(acc[c][ob][r], 0.0f);
     }
-    const f4* fo = sw + H * 16 * 64 + lane;
-    f4 o[4];
     #pragma unroll
-    for (int c = 0; c < 4; ++c) o[c] = f4{0.0f, 0.0f, 0.0f, 0.0f};
-    #pragma unroll
-    for (int obp = 0; obp < 4; ++obp) {
-        const f4 a = fo[obp * 64];
+    for (int o = 0; o < kNOut; ++o) {
+        float p[4];   // p[c]: this lane group's share of channel o for column c's query
         #pragma unroll
-        for (int r = 0; r < 4; ++r)
+        for (int c = 0; c < 4; ++c) {
+            float acc = 0.0f;
             #pragma unroll
-            for (int c = 0; c < 4; ++c) o[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r], act[c][4 * obp + r], o[c], 0, 0, 0);
-    }
-    // lane group 0 holds output channel ch of column c's queries in o[c][ch];
-    // the transpose hands it to group c, the lanes that loaded those queries
-    #pragma unroll
-    for (int ch = 0; ch < kNOut; ++ch) {
-        float t0 = o[0][ch], t1 = o[1][ch], t2 = o[2][ch], t3 = o[3][ch];
-        xpose4(t0, t1, t2, t3);
-        y[ch] = t0;
+            for (int b = 0; b < 4; ++b) {
+                acc = fmaf(wo[o][b].x, act[c][4 * b], acc);
+                acc = fmaf(wo[o][b].y, act[c][4 * b + 1], acc);
+                acc = fmaf(wo[o][b].z, act[c][4 * b + 2], acc);
+                acc = fmaf(wo[o][b].w, act[c][4 * b + 3], acc);
+            }
+            p[c] = acc;
+        }
+        // afterwards register c of group g holds group c's share for column
+        // g's query: the four registers of a lane add up to its own query
+        xpose4(p[0], p[1], p[2], p[3]);
+        y[o] = (p[0] + p[1]) + (p[2] + p[3]);
     }
 }
 
@@ -159,8 +166,10 @@ __device__ inline void query_fp32(const float* __restrict__ w, const float* __re
     extern __shared__ f4 sw[];
     constexpr int RW = LAYOUT == NRC_RAW14 ? 14 : 16;
     stage_query_frags(sw, w, H);
-    __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    float4 wo[kNOut][4];
+    load_out_weights(w, H, lane >> 4, wo);
+    __syncthreads();
     const int64_t n_tiles = (n + 63) / 64;
     const int64_t stride = (int64_t)gridDim.x * kQWaves;
     for (int64_t t = (int64_t)blockIdx.x * kQWaves + wave; t < n_tiles; t += stride) {
@@ -187,7 +196,7 @@ __device__ inline void query_fp32(const float* __restrict__ w, const float* __re
         }
         float r[kNOut], y[kNOut];
         reflectance_row(h, fcol, r);
-        mlp_query_mfma(sw, H, lane, h, y);
+        mlp_query_mfma(sw, H, lane, wo, h, y);
         if (valid) store_query(rgb, s, y, r);
     }
 }
@@ -447,9 +456,9 @@ __global__ __launch_bounds__(64 * NWV) void k_train_fp32(const float* __restrict
 }
 
 // Query grid: one workgroup of kQWaves waves per CU (the fragments of every
-// layer, (16 H + 4) KB, fill most of the CU's LDS), each wave striding over
+// hidden layer, 16 H KB, fill most of the CU's LDS), each wave striding over
 // 64-query tiles.
-inline size_t query_lds_bytes(const Geo& d) { return (size_t)(16 * d.H + 4) * 64 * sizeof(f4); }
+inline size_t query_lds_bytes(const Geo& d) { return (size_t)(16 * d.H) * 64 * sizeof(f4); }
 inline int64_t query_blocks(int64_t n) {
     const int64_t tiles = (n + 63) / 64;
     const int64_t b = (tiles + kQWaves - 1) / kQWaves;
