@@ -29,8 +29,11 @@ notes):
   the paper preset encodes 1 - exp(-r) with one-blob and pads with 1.
 * Cheap primitives (Sec. 5): the one-blob kernel is the quartic throughout;
   the "paper-tri" preset also replaces each sine sin(2^d pi p) by the triangle
-  wave of the same period and phase, tri(x) = 2|(x - 1/2) mod 2 - 1| - 1, which
-  meets sin(pi x) at every multiple of 1/2.  The "paper-gauss" preset keeps
+  wave the paper defines in its figure "cheap_primitives",
+  tri(x) = 2|x mod 2 - 1| - 1, evaluated at x = 2^d p.  Its period is 2, that
+  of sin(pi x); its phase is the printed one (tri(0) = 1, tri(1) = -1, the
+  phase of cos(pi x)), which the paper gives and the oracle keeps.  The
+  "paper-gauss" preset keeps
   the sines and uses the kernel the quartic replaced, a Gaussian: the paper
   gives no width (it defers the one-blob encoding to its earlier work), read
   as a standard deviation of one bin, with the bin masses from the normal CDF
@@ -111,9 +114,9 @@ def sph(v: np.ndarray) -> np.ndarray:
 
 
 def tri(x: np.ndarray) -> np.ndarray:
-    """Triangle wave of Sec. 5 (figure "cheap_primitives") standing in for sin(pi x):
-    period 2, in phase with the sine, 2 |(x - 1/2) mod 2 - 1| - 1."""
-    return 2.0 * np.abs(np.mod(x - 0.5, 2.0) - 1.0) - 1.0
+    """Triangle wave of Sec. 5 (figure "cheap_primitives"), the stand-in for the
+    sine of the frequency encoding: 2 |x mod 2 - 1| - 1, period 2."""
+    return 2.0 * np.abs(np.mod(x, 2.0) - 1.0) - 1.0
 
 
 def freq(p: np.ndarray, preset: int = PRESET_CONFIG) -> np.ndarray:

@@ -123,8 +123,14 @@ def _sph_azimuth_unshifted(v):
     return np.stack([theta / np.pi, np.arctan2(v[:, 1], v[:, 0]) / (2.0 * np.pi)], axis=1)
 
 
-def _tri_cosine_phase(x):
-    return 2.0 * np.abs(np.mod(x, 2.0) - 1.0) - 1.0
+def _tri_sine_phase(x):
+    # the printed wave shifted by a quarter period (in phase with sin(pi x))
+    return 2.0 * np.abs(np.mod(x - 0.5, 2.0) - 1.0) - 1.0
+
+
+def _tri_unit_period(x):
+    # the reduction taken mod 1 instead of mod 2
+    return 2.0 * np.abs(np.mod(x, 1.0) - 1.0) - 1.0
 
 
 def _loss_sum_luminance(y_hat, y, eps=O.LOSS_EPS):
@@ -193,7 +199,8 @@ MUTANTS = [
     ("self_training_targets", _targets_wrong_tail, [P.test_self_training_targets]),
     ("sph", _sph_angles_swapped, [P.test_sph_axes, P.test_sph_inverts_spherical_parametrisation]),
     ("sph", _sph_azimuth_unshifted, [P.test_sph_axes, P.test_sph_inverts_spherical_parametrisation]),
-    ("tri", _tri_cosine_phase, [P.test_triangle_wave_closed_form]),
+    ("tri", _tri_sine_phase, [P.test_triangle_wave_closed_form, P.test_encode_paper_tri_preset_layout]),
+    ("tri", _tri_unit_period, [P.test_triangle_wave_closed_form, P.test_encode_paper_tri_preset_layout]),
     ("relative_l2", _loss_sum_luminance, [P.test_loss_single_sample_by_hand]),
     ("relative_l2", _loss_eps_squared, [P.test_loss_single_sample_by_hand]),
     ("adam", _adam_eps_inside_sqrt, [P.test_adam_constant_gradient_closed_form]),

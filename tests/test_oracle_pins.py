@@ -522,22 +522,30 @@ def test_ema_does_not_feed_back_into_training():
 # Triangle wave (Sec. 5, cheap primitives)
 # ----------------------------------------------------------------------------
 def test_triangle_wave_closed_form():
-    # The triangle wave through the extrema and zeros of sin(pi x): period 2,
-    # tri(0) = 0, tri(1/2) = 1, tri(1) = 0, tri(3/2) = -1, linear in between
-    # (slope +2 on [-1/2, 1/2], -2 on [1/2, 3/2]).
-    x = np.array([0.0, 0.25, 0.5, 0.75, 1.0, 1.5, 2.0, 2.25, -0.5, 7.0, 7.5])
-    want = np.array([0.0, 0.5, 1.0, 0.5, 0.0, -1.0, 0.0, 0.5, -1.0, 0.0, -1.0])
-    assert np.allclose(O.tri(x), want, atol=1e-15)
-    t = np.linspace(-0.5, 0.5, 101)
-    assert np.allclose(O.tri(t), 2.0 * t, atol=1e-14)
-    assert np.allclose(O.tri(t + 1.0), -2.0 * t, atol=1e-14)
-    # agrees with sin(pi x) at every multiple of 1/2 and has its sign everywhere
+    # The triangle wave printed in Sec. 5 (figure "cheap_primitives"),
+    # tri(x) = 2|x mod 2 - 1| - 1: period 2, tri(0) = 1, tri(1/2) = 0,
+    # tri(1) = -1, tri(3/2) = 0, slope -2 on [0, 1] and +2 on [1, 2].
+    x = np.array([0.0, 0.25, 0.5, 0.75, 1.0, 1.25, 1.5, 1.75, 2.0, 2.5, -0.5, -1.0, 7.0, 7.5, 8.0])
+    want = np.array([1.0, 0.5, 0.0, -0.5, -1.0, -0.5, 0.0, 0.5, 1.0, 0.0, 0.0, -1.0, -1.0, 0.0, 1.0])
+    assert np.array_equal(O.tri(x), want)
+    t = np.linspace(0.0, 1.0, 101)
+    assert np.allclose(O.tri(t), 1.0 - 2.0 * t, atol=1e-14)          # falling edge
+    assert np.allclose(O.tri(t + 1.0), -1.0 + 2.0 * t, atol=1e-14)    # rising edge
+    # period 2 and even symmetry, at points where both sides are exact
+    y = np.arange(-4096, 4096) / 256.0
+    assert np.array_equal(O.tri(y + 2.0), O.tri(y))
+    assert np.array_equal(O.tri(-y), O.tri(y))
+    # range [-1, 1], zero mean over a period
+    assert O.tri(y).min() == -1.0 and O.tri(y).max() == 1.0
+    assert abs(np.mean(O.tri(np.arange(512) / 256.0))) < 1e-15
+    # it meets cos(pi x) at every multiple of 1/2 and has its sign everywhere,
+    # lying inside it in magnitude (a cosine half-wave lies above its chords)
     h = np.arange(-8, 9) * 0.5
-    assert np.allclose(O.tri(h), np.round(np.sin(np.pi * h), 12), atol=1e-15)
-    y = np.linspace(-3.0, 3.0, 6001)
-    s = np.round(np.sin(np.pi * y), 12)
-    assert np.array_equal(np.sign(np.round(O.tri(y), 12)), np.sign(s))
-    assert np.all(np.abs(O.tri(y)) <= np.abs(s) + 1e-12)   # sin lies above its chords (concave)
+    assert np.allclose(O.tri(h), np.round(np.cos(np.pi * h), 12), atol=1e-15)
+    z = np.linspace(-3.0, 3.0, 6001)
+    c = np.round(np.cos(np.pi * z), 12)
+    assert np.array_equal(np.sign(np.round(O.tri(z), 12)), np.sign(c))
+    assert np.all(np.abs(O.tri(z)) <= np.abs(c) + 1e-12)
 
 
 def test_encode_paper_tri_preset_layout():
@@ -548,11 +556,11 @@ def test_encode_paper_tri_preset_layout():
     for c in range(3):
         for d in range(12):
             x = 2 ** d * r[:, c]
-            # with k the nearest integer to x: rising edge 2 (x - k) for even k,
-            # falling edge -2 (x - k) for odd k
-            k = np.floor(x + 0.5)                      # nearest integer
-            frac = x - k                               # in [-1/2, 1/2)
-            want = np.where(np.mod(k, 2) == 0, 2 * frac, -2 * frac)
+            # with k = floor(x): falling edge 1 - 2 (x - k) for even k, rising
+            # edge -1 + 2 (x - k) for odd k
+            k = np.floor(x)
+            frac = x - k                               # in [0, 1)
+            want = np.where(np.mod(k, 2) == 0, 1.0 - 2.0 * frac, -1.0 + 2.0 * frac)
             assert np.allclose(b[:, 12 * c + d], want, atol=1e-12)
     assert np.array_equal(a[:, 36:], b[:, 36:])          # everything after the position is shared
 
