@@ -69,10 +69,11 @@ __device__ inline void sph(float x, float y, float z, float& u, float& w) {
     w = (atan2f(y, x) + kPi) * (0.5f * kInvPi);
 }
 
-// Triangle wave of Sec. 5 ("cheap primitives") in place of sin(pi x): period 2,
-// in phase with the sine, 2 |(x - 1/2) mod 2 - 1| - 1.  For the positions used
-// here x - 1/2 is exact unless |x| < 1/4, where its rounding is below 2^-26.
-__device__ inline float tri(float x) { return 2.0f * fabsf(mod2(x - 0.5f) - 1.0f) - 1.0f; }
+// Triangle wave of Sec. 5 (figure "cheap primitives"), the stand-in for the
+// frequency encoding's sine: tri(x) = 2 |x mod 2 - 1| - 1, period 2, tri(0) = 1.
+// The reduction is exact; r - 1 is exact for r >= 1/2 and rounds by at most
+// 2^-25 below it, and 2|.| - 1 is exact (Sterbenz), so |error| <= 2^-24.
+__device__ inline float tri(float x) { return 2.0f * fabsf(mod2(x) - 1.0f) - 1.0f; }
 
 // sin and cos of pi * 2^d * p for d = 0 .. NOCT-1.  Octaves 0, 3, 6, 9 are
 // evaluated directly (sincospi_r of the exactly reduced phase); the two octaves

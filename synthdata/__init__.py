@@ -147,3 +147,58 @@ def serve_trace(n_requests: int, n_caches: int = 8, p_infer: float = 0.6,
         else:
             out.append(dict(t_arrive=float(t[k]), kind="train", cache=int(caches[k]), n=n_train))
     return out
+
+
+# Special values of the edge-case records: exact integers and halves, the
+# ends of the unit interval, large magnitudes and values just inside them.
+EDGE_POSITIONS = (0.0, 1.0, -1.0, 0.5, -0.5, 0.25, 2.0, -2.0, 3.0, -4.0, 4.0 - 2.0 ** -20,
+                  1.0 - 2.0 ** -24, 2.0 ** -30, -(2.0 ** -30), 1000.0, -1000.0, 1000.375, -999.625)
+EDGE_ANGLES = (0.0, 0.125, 0.25, 0.375, 0.5, 0.625, 0.75, 0.875, 1.0, 2.0 ** -24, 1.0 - 2.0 ** -24)
+EDGE_ROUGHNESS = (0.0, 1e-7, 0.5, 1.0, 20.0, 1000.0)
+EDGE_ALBEDO = (0.0, 0.5, 1.0)
+# Unit vectors on the axes, with the signed zeros that pick atan2's branch at
+# the poles and on the negative x axis.
+EDGE_VECTORS = ((0.0, 0.0, 1.0), (0.0, 0.0, -1.0), (-0.0, 0.0, 1.0), (-0.0, -0.0, 1.0),
+                (0.0, -0.0, -1.0), (1.0, 0.0, 0.0), (-1.0, 0.0, 0.0), (-1.0, -0.0, 0.0),
+                (0.0, 1.0, 0.0), (0.0, -1.0, 0.0), (1.0, -0.0, 0.0))
+
+
+def edge_records(n_random: int, seed: int, layout: int = RAW14) -> np.ndarray:
+    """Records at the edges of each field's range, then `n_random` records with
+    positions U[-4, 4) (a third of them U[-1000, 1000)), roughness U[0, 20) and
+    the other fields as in `raw_records`.
+
+    The special part cycles every field through its special values (positions,
+    spherical angles or axis unit vectors, roughness, albedos) with different
+    strides, so each value meets many values of the other fields.  Signed
+    zeros of the unit vectors survive the cast to float32.
+    """
+    w = RAW_WIDTH[layout]
+    n_special = 3 * len(EDGE_POSITIONS) * len(EDGE_ANGLES)
+    sp = np.zeros((n_special, w), dtype=np.float64)
+    i = np.arange(n_special)
+    P, A, V = len(EDGE_POSITIONS), len(EDGE_ANGLES), len(EDGE_VECTORS)
+    pos = np.asarray(EDGE_POSITIONS)
+    for c in range(3):
+        sp[:, c] = pos[(i + 5 * c) % P]
+    if layout == RAW14:
+        ang = np.asarray(EDGE_ANGLES)
+        for a in range(4):
+            sp[:, 3 + a] = ang[(i * (a + 1) + 3 * a) % A]
+        rest = 7
+    else:
+        vec = np.asarray(EDGE_VECTORS)
+        sp[:, 3:6] = vec[i % V]
+        sp[:, 6:9] = vec[(3 * i + 4) % V]
+        rest = 9
+    sp[:, rest] = np.asarray(EDGE_ROUGHNESS)[i % len(EDGE_ROUGHNESS)]
+    alb = np.asarray(EDGE_ALBEDO)
+    for j in range(6):
+        sp[:, rest + 1 + j] = alb[(i + j) % len(alb)]
+    rnd = raw_records(n_random, seed, layout).astype(np.float64)
+    rng = _rng(seed + 1)
+    rnd[:, 0:3] = rng.uniform(-4.0, 4.0, size=(n_random, 3))
+    big = rng.random(n_random) < 1.0 / 3.0
+    rnd[big, 0:3] = rng.uniform(-1000.0, 1000.0, size=(int(big.sum()), 3))
+    rnd[:, rest] = rng.uniform(0.0, 20.0, size=n_random)
+    return np.ascontiguousarray(np.concatenate([sp, rnd], axis=0).astype(np.float32))

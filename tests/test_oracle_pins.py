@@ -755,3 +755,60 @@ def test_self_training_targets():
     for i in range(50):                                                           # record by record
         for c in range(3):
             assert got[i, c] == L[i, c] + T[i, c] * tail[k[i], c]
+
+
+# ----------------------------------------------------------------------------
+# Positions anywhere in R^3 (Table "parameters": the position is a point of the
+# scene, not a unit-cube coordinate)
+# ----------------------------------------------------------------------------
+def test_freq_far_from_the_unit_cube():
+    # Beyond [0,1) the exact mod-2 reduction must still give sin/cos(2^d pi p):
+    # checked against libm on the unreduced FP64 argument, whose rounding at
+    # |2^d pi p| < 2^24 is below 1e-8.
+    raw = sd.edge_records(2000, 31)
+    p = raw[:, 0:3].astype(np.float64)
+    f = O.freq(p, O.PRESET_CONFIG).reshape(-1, 3, 6, 2)
+    for d in range(6):
+        a = np.pi * 2.0 ** d * p
+        assert np.max(np.abs(f[:, :, d, 0] - np.sin(a))) < 1e-8
+        assert np.max(np.abs(f[:, :, d, 1] - np.cos(a))) < 1e-8
+    g = O.freq(p, O.PRESET_PAPER).reshape(-1, 3, 12)
+    for d in range(12):
+        assert np.max(np.abs(g[:, :, d] - np.sin(np.pi * 2.0 ** d * p))) < 1e-8
+    # the triangle wave is even and 2-periodic, so -p and p + 2 give the same
+    # features as p, exactly
+    t = O.freq(p, O.PRESET_PAPER_TRI)
+    assert np.array_equal(O.freq(-p, O.PRESET_PAPER_TRI), t)
+    assert np.array_equal(O.freq(p + 2.0, O.PRESET_PAPER_TRI), t)
+    assert np.all(np.abs(t) <= 1.0)
+
+
+def test_encode_edge_records_invariants():
+    # Poles, signed zeros, bin edges, roughness 0 and 20: every one-blob group
+    # sums to one, every value is in range, nothing is non-finite, and the
+    # roughness one-blob takes its end values.
+    for layout in (O.RAW14, O.RAW16):
+        raw = sd.edge_records(500, 32, layout)
+        for preset in (O.PRESET_CONFIG, O.PRESET_PAPER, O.PRESET_PAPER_TRI, O.PRESET_PAPER_GAUSS):
+            e = O.encode(raw, layout, preset)
+            assert np.all(np.isfinite(e))
+            ob = e[:, 36:56 if preset != O.PRESET_CONFIG else 52].reshape(len(e), -1, 4)
+            assert np.allclose(ob.sum(axis=2), 1.0, atol=1e-14)
+            assert np.all(ob >= -1e-15) and np.all(ob <= 1.0 + 1e-15)
+            assert np.all(np.abs(e[:, :36]) <= 1.0 + 1e-15)
+        if layout == O.RAW16:
+            # at the poles the polar angle is 0 or 1 exactly, so one-blob gives a unit vector
+            s = O.sph(raw[:, 3:6])
+            pole = raw[:, 5] == 1.0
+            assert np.all(s[pole, 0] == 0.0)
+            assert np.array_equal(O.one_blob(s[pole, 0]), np.tile([1.0, 0, 0, 0], (int(pole.sum()), 1)))
+            # atan2's signed-zero branches (IEEE 754 / C99): the azimuth of
+            # (-1, +0, 0) is 1, of (-1, -0, 0) is 0, of (+0, +0, 1) is 1/2 and of
+            # (-0, -0, 1) is 0
+            v = np.array([[-1.0, 0.0, 0.0], [-1.0, -0.0, 0.0], [0.0, 0.0, 1.0], [-0.0, -0.0, 1.0]])
+            assert np.array_equal(O.sph(v)[:, 1], [1.0, 0.0, 0.5, 0.0])
+    raw = sd.edge_records(0, 33, O.RAW14)
+    e = O.encode(raw, O.RAW14, O.PRESET_PAPER)
+    r = raw[:, 7]
+    assert np.array_equal(e[r == 0.0, 52:56], np.tile([1.0, 0, 0, 0], (int((r == 0.0).sum()), 1)))
+    assert np.allclose(e[r >= 20.0, 52:56], [0.0, 0.0, 0.0, 1.0], atol=1e-15)
