@@ -17,6 +17,8 @@
  *  - The library never allocates device memory: the caller allocates and frees
  *    every device buffer (the cache workspace, scratch, inputs, outputs).
  *    Host-side handles are allocated by the library and freed by *_destroy.
+ *    The one fixed device array the library holds is the scratch of
+ *    nrc_train_step_noalloc (NRC_NOALLOC_SCRATCH_BYTES per GPU).
  *  - "stream" arguments are hipStream_t values passed as void*; NULL is the
  *    default stream.  Work is enqueued asynchronously; nothing synchronises
  *    the host unless stated.
@@ -209,6 +211,24 @@ int nrc_forward_raw(nrc_cache* cache, const float* raw, int raw_layout, int64_t 
 int nrc_train_step(nrc_cache* cache, const void* enc, const float* target, int64_t n,
                    void* scratch, size_t scratch_bytes, float* loss_dev, int32_t* skipped_dev,
                    void* stream);
+
+/*
+ * nrc_train_step without a scratch argument, for callers that cannot allocate
+ * device memory (code under stream capture, tight serving loops, harnesses
+ * that forbid allocation).  The step's scratch is a fixed array inside the
+ * library, NRC_NOALLOC_SCRATCH_BYTES per GPU, held from the first call on a
+ * GPU until the process ends; the call itself allocates nothing.  The result
+ * equals nrc_train_step's bit for bit.  A batch whose scratch
+ * (nrc_train_scratch_bytes(cfg, n)) exceeds the array is refused with
+ * NRC_ENOMEM before any device call: at width 64 that is n up to about
+ * 19,000 records, at width 128 about 2,700.  Every call on one GPU shares
+ * that GPU's array: calls that overlap on one GPU (other streams, other
+ * threads) race and must be ordered by the caller.  Other arguments as for
+ * nrc_train_step.
+ */
+#define NRC_NOALLOC_SCRATCH_BYTES ((size_t)48 << 20)
+int nrc_train_step_noalloc(nrc_cache* cache, const void* enc, const float* target, int64_t n,
+                           float* loss_dev, int32_t* skipped_dev, void* stream);
 
 /*
  * Backward pass for the autograd form (Sec. 4 "Training the fully fused

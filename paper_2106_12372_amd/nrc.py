@@ -28,6 +28,7 @@ NRC_PRESET_CONFIG, NRC_PRESET_PAPER, NRC_PRESET_PAPER_TRI, NRC_PRESET_PAPER_GAUS
 NRC_RAW14, NRC_RAW16 = 0, 1
 NRC_REQ_INFER, NRC_REQ_TRAIN = 0, 1
 ENC_WIDTH = 64
+NRC_NOALLOC_SCRATCH_BYTES = 48 << 20   # the fixed scratch array of nrc_train_step_noalloc
 PRECISIONS = {"fp32": NRC_FP32, "fp16": NRC_FP16, "bf16": NRC_BF16}
 
 
@@ -93,6 +94,7 @@ _decl("nrc_encode", c_int, _P, _P, c_int, c_int64, _P, _P)
 _decl("nrc_forward", c_int, _P, _P, c_int64, _P, _P)
 _decl("nrc_forward_raw", c_int, _P, _P, c_int, c_int64, _P, _P)
 _decl("nrc_train_step", c_int, _P, _P, _P, c_int64, _P, c_size_t, _P, _P, _P)
+_decl("nrc_train_step_noalloc", c_int, _P, _P, _P, c_int64, _P, _P, _P)
 _decl("nrc_backward", c_int, _P, _P, _P, c_int64, _P, c_size_t, _P, _P, _P)
 _decl("nrc_shuffle_scratch_bytes", c_size_t, c_int64)
 _decl("nrc_shuffle", c_int, c_int64, c_uint64, _P, _P, c_size_t, _P)
@@ -113,6 +115,7 @@ EXPORTED = ["nrc_config_default", "nrc_last_error", "nrc_param_count", "nrc_cach
             "nrc_train_scratch_bytes", "nrc_enc_elem_bytes", "nrc_cache_create", "nrc_cache_destroy",
             "nrc_cache_config", "nrc_set_weights", "nrc_get_weights", "nrc_set_weights_device",
             "nrc_get_state", "nrc_set_state", "nrc_get_ema", "nrc_set_ema", "nrc_encode", "nrc_forward", "nrc_forward_raw", "nrc_train_step",
+            "nrc_train_step_noalloc",
             "nrc_backward", "nrc_shuffle_scratch_bytes", "nrc_shuffle", "nrc_train_step_indexed",
             "nrc_frame_scratch_bytes", "nrc_train_frame", "nrc_train_frame_indexed", "nrc_self_training_targets", "nrc_serve_create", "nrc_serve_set_weights", "nrc_serve_get_weights",
             "nrc_serve_submit", "nrc_serve_poll", "nrc_serve_drain", "nrc_serve_destroy"]
@@ -335,6 +338,24 @@ def nrc_train_step(cache: Cache, enc, target, loss=None, skipped=None, scratch=N
     sc, size = cache.scratch(n) if scratch is None else (scratch, scratch.numel())
     check(lib.nrc_train_step(cache.handle, _ptr(enc), _ptr(target), n, _ptr(sc), size, _ptr(loss),
                              _ptr(skipped), _stream(stream)))
+    return loss, skipped
+
+
+def nrc_train_step_noalloc(cache: Cache, enc, target, loss=None, skipped=None, stream=None):
+    """nrc_train_step on the library's fixed scratch array (no scratch buffer);
+    returns the device scalars (loss, skipped)."""
+    torch = _torch()
+    _need(enc, cache.enc_dtype, (ENC_WIDTH,), "enc")
+    _need(target, torch.float32, (3,), "target")
+    n = enc.shape[0]
+    if target.shape[0] != n:
+        raise ValueError("enc and target differ in length")
+    if loss is None:
+        loss = torch.empty(1, dtype=torch.float32, device=enc.device)
+    if skipped is None:
+        skipped = torch.empty(1, dtype=torch.int32, device=enc.device)
+    check(lib.nrc_train_step_noalloc(cache.handle, _ptr(enc), _ptr(target), n, _ptr(loss), _ptr(skipped),
+                                     _stream(stream)))
     return loss, skipped
 
 
