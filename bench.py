@@ -4,9 +4,11 @@ A step is one 1920x1080 frame of the cache: encode 2,073,600 synthetic query
 records and run inference on them (one fused kernel), encode 65,536 training
 records, shuffle them with the LCG and take four Adam steps on disjoint
 batches of 16,384 records (Sec. 3.3 and 3.5 of the paper), all on one stream.  Inputs
-are resident in HBM before the timed region.  The default form is plain FP32
-(vector ALUs); the FP16 and BF16 matrix-core forms run the same frame and are
-reported under "forms".  Prints one JSON line.
+are resident in HBM before the timed region.  The default form is FP32: FP32
+weights, activations and sums, with the layer products on the FP32 matrix cores
+(v_mfma_f32_16x16x4_f32; plain FP32 FMAs would cap at half that rate, since
+packed FP32 is not used).  The FP16 and BF16 matrix-core forms run the same
+frame and are reported under "forms".  Prints one JSON line.
 
 Each form first runs frames back to back for --settle-s seconds (the GPU's
 clocks rise over the first tens of milliseconds of sustained load), then W
@@ -200,6 +202,11 @@ def frame_bench(form: str, steps: int, warmup: int, settle_s: float):
     }
     frame_flop = N_QUERIES * FLOP_PER_QUERY + N_TRAIN_BATCHES * TRAIN_BATCH * FLOP_PER_TRAIN_SAMPLE
     out["frame_tflops"] = frame_flop / (ms * 1e-3) / 1e12
+    # the whole frame (query pass, record encoding, shuffle, four steps)
+    # against the matrix-core peak of the form's arithmetic
+    out["frame_roofline"] = {"flop_per_frame": frame_flop, "achieved": out["frame_tflops"],
+                             "peak": PEAK_TFLOPS[form], "unit": "TFLOP/s",
+                             "frac": out["frame_tflops"] / PEAK_TFLOPS[form]}
     out["settle_frames"] = settled
     out["host_enqueue_ms_per_step"] = t_enq * 1e3 / steps
     out["query_pass_by_preset_ms"] = preset_bench(form, raw_q, rgb, steps)
@@ -351,12 +358,37 @@ def cpu_baseline():
         O.frame_shuffled(st, q_enc, r_enc, y, N_TRAIN_BATCHES, TRAIN_BATCH, frames)
         frames += 1
     t = (time.perf_counter() - t0) / frames
-    return {"value": N_QUERIES / t, "unit": "queries/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"{frames} full frame{'s' if frames > 1 else ''} (mean time per frame): FP64 NumPy "
-                      "encode + inference of "
-                      "2,073,600 queries, encode of 65,536 records, LCG shuffle, four 16,384-record "
-                      "training steps",
-            "seconds": t, "frames": frames, "train_samples_per_s": N_TRAIN_BATCHES * TRAIN_BATCH / t}
+    out = {"value": N_QUERIES / t, "unit": "queries/s", "cores": int(threads), "kind": "oracle",
+           "sample": f"{frames} full frame{'s' if frames > 1 else ''} (mean time per frame): FP64 NumPy "
+                     "encode + inference of "
+                     "2,073,600 queries, encode of 65,536 records, LCG shuffle, four 16,384-record "
+                     "training steps",
+           "seconds": t, "frames": frames, "train_samples_per_s": N_TRAIN_BATCHES * TRAIN_BATCH / t}
+    out["single_thread"] = cpu_baseline_single_thread(raw_q, raw_r, y, st)
+    return out
+
+
+def cpu_baseline_single_thread(raw_q, raw_r, y, st):
+    """The same oracle on one host thread, on a sample of the frame: encode +
+    inference of the first 131,072 queries (1/16 of the frame) and one
+    16,384-record training step, scaled to a whole frame (16 x the query sample
+    plus four steps)."""
+    from oracle import nrc_oracle as O
+    from threadpoolctl import threadpool_limits
+    nq = 131072
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        O.predict(st, O.encode(raw_q[:nq]))
+        tq = time.perf_counter() - t0
+        st1 = O.CacheState(st.w.copy())
+        t0 = time.perf_counter()
+        O.train_step(st1, O.encode(raw_r[:TRAIN_BATCH]), y[:TRAIN_BATCH])
+        ts = time.perf_counter() - t0
+    t = tq * (N_QUERIES / nq) + N_TRAIN_BATCHES * ts
+    return {"value": N_QUERIES / t, "unit": "queries/s", "cores": 1, "kind": "oracle",
+            "sample": "one thread: encode + inference of 131,072 queries and one 16,384-record training "
+                      "step, scaled to a frame (16 x queries + 4 x step)",
+            "seconds_per_frame": t, "query_sample_s": tq, "train_step_s": ts}
 
 
 def main():
@@ -433,7 +465,11 @@ def main():
         "config": {"workload": f"1920x1080 frame: {N_QUERIES} queries (encode + inference) and "
                                f"{N_TRAIN_BATCHES}x{TRAIN_BATCH}-record training steps, {args.form} form",
                    "width": WIDTH, "n_hidden": N_HIDDEN, "queries": N_QUERIES,
-                   "train_batches": N_TRAIN_BATCHES, "train_batch": TRAIN_BATCH, "form": args.form},
+                   "train_batches": N_TRAIN_BATCHES, "train_batch": TRAIN_BATCH, "form": args.form,
+                   "products": {"fp32": "FP32 weights and activations on the FP32 matrix cores "
+                                        "(v_mfma_f32_16x16x4_f32), not the vector ALUs",
+                                "fp16": "FP16 matrix cores, FP32 accumulation",
+                                "bf16": "BF16 matrix cores, FP32 accumulation"}[args.form]},
         "train_samples_per_s": main_res["train_samples_per_s"],
         "components_ms": main_res["components_ms"],
         "unfused_ms": main_res["unfused_ms"],
@@ -442,6 +478,7 @@ def main():
         "frame_tflops": main_res["frame_tflops"],
         "query_pass_by_preset_ms": main_res["query_pass_by_preset_ms"],
         "roofline": main_res["roofline"],
+        "frame_roofline": main_res["frame_roofline"],
         "cpu_baseline": cpu,
         "forms": forms,
         "serve": serve,

@@ -231,19 +231,34 @@ int nrc_train_step_noalloc(nrc_cache* cache, const void* enc, const float* targe
                            float* loss_dev, int32_t* skipped_dev, void* stream);
 
 /*
- * Backward pass for the autograd form (Sec. 4 "Training the fully fused
- * neural network"): given any upstream gradient grad_rgb[n][3] (FP32, device)
- * of the outputs nrc_forward produced for enc[n][64], writes grad_w (FP32,
- * device, nrc_param_count floats in the weight layout above, summed over the
- * batch) and, if grad_enc is not NULL, grad_enc[n][64] (FP32, device).  The
- * kernel recomputes the forward activations from enc instead of storing them
- * between the calls.  No loss scaling is applied; the reduced-precision forms
- * carry the gradients in FP16/BF16 inside the kernel.  `scratch` as for
- * nrc_train_step.  n must be >= 1.
+ * Autograd form (Sec. 4 "Training the fully fused neural network": the forward
+ * pass keeps the activations that backpropagation reads).
+ *
+ * nrc_act_ws_bytes: bytes of the activation buffer for n records (0 with
+ * NRC_EINVAL on an invalid config or n outside [0, 2^31]).
+ *
+ * nrc_forward_train: rgb[n][3] (FP32, device) = the prediction for enc[n][64]
+ * with the training weights W (not the EMA set), and act_ws (device, 16-byte
+ * aligned, act_bytes >= nrc_act_ws_bytes(cfg, n)) receives every hidden
+ * layer's activations and the network outputs, for nrc_backward.  n == 0 is a
+ * no-op.
+ *
+ * nrc_backward: given any upstream gradient grad_rgb[n][3] (FP32, device) of
+ * the predictions for enc[n][64], writes grad_w (FP32, device, nrc_param_count
+ * floats in the weight layout above, summed over the batch) and, if grad_enc
+ * is not NULL, grad_enc[n][64] (FP32, device).  act_ws: the buffer
+ * nrc_forward_train filled for the same enc, n and weights (its contents are
+ * trusted, not checked), or NULL to recompute the forward pass inside the
+ * kernel.  The upstream gradient is multiplied by the config's loss_scale
+ * before the reduced-precision backward pass rounds it and divided out of
+ * grad_w and grad_enc (grad_rgb * loss_scale must stay within FP16 range in
+ * the FP16 form).  `scratch` as for nrc_train_step.  n must be >= 1.
  */
-int nrc_backward(nrc_cache* cache, const void* enc, const float* grad_rgb, int64_t n,
-                 void* scratch, size_t scratch_bytes, float* grad_w, float* grad_enc,
-                 void* stream);
+size_t nrc_act_ws_bytes(const nrc_config* cfg, int64_t n);
+int nrc_forward_train(nrc_cache* cache, const void* enc, int64_t n, void* act_ws, size_t act_bytes, float* rgb,
+                      void* stream);
+int nrc_backward(nrc_cache* cache, const void* enc, const void* act_ws, const float* grad_rgb, int64_t n,
+                 void* scratch, size_t scratch_bytes, float* grad_w, float* grad_enc, void* stream);
 
 /* ------------------------------------------------------------------------- */
 /* Training-record pipeline of one frame (Sec. 3.3 footnote, Sec. 3.5,       */

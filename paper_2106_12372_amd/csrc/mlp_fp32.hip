@@ -215,13 +215,6 @@ __global__ __launch_bounds__(64 * kQWaves) void k_fwd_raw_fp32(const float* __re
     query_fp32<true, PRESET, LAYOUT>(w, raw, n, rgb, n_hidden, fcol);
 }
 
-// Fixed-order sum over the 64 lanes of a wave (same tree on every call).
-__device__ inline float wave_sum(float v) {
-    #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-
 // UPSTREAM = false: targets given, relative L2 loss (Eq. 5) produces dL/dy.
 // UPSTREAM = true : tgt holds an upstream gradient dL/dy directly.
 // With the reflectance factorisation (fcol != 0) y is the network output times
@@ -236,7 +229,14 @@ __device__ inline float wave_sum(float v) {
 // conflict-free LDS banks instead).  The output layer (3 rows)
 // and the loss stay on the vector ALUs (lane = record, FPW = 4 features per
 // wave where a pass is split by feature).
-template <bool UPSTREAM, bool GENC, int NWV>
+// Activation buffer of the autograd form (ACT): per tile, h_1 .. h_H as
+// [layer][record][feature] FP32, then, after every tile's block, the network
+// output [tile * 64 + record][4].  kActNone: no buffer; kActStore: forward
+// only, writes the buffer and rgb, then exits; kActLoad: the forward pass is
+// read from the buffer instead of recomputed.
+constexpr int kActNone = 0, kActStore = 1, kActLoad = 2;
+
+template <bool UPSTREAM, bool GENC, int NWV, int ACT = kActNone>
 __global__ __launch_bounds__(64 * NWV) void k_train_fp32(const float* __restrict__ w,
                                                          const float* __restrict__ enc,
                                                          const float* __restrict__ tgt,
@@ -245,7 +245,9 @@ __global__ __launch_bounds__(64 * NWV) void k_train_fp32(const float* __restrict
                                                          float grad_scale, float* __restrict__ partials,
                                                          float* __restrict__ loss_part,
                                                          int32_t* __restrict__ tile_bad,
-                                                         float* __restrict__ genc, int fcol) {
+                                                         float* __restrict__ genc, int fcol,
+                                                         float* __restrict__ act, float* __restrict__ rgb,
+                                                         LcgGather lg) {
     static_assert(NWV == 16, "one 16 x 16 block of each 64 x 64 product per wave");
     constexpr int FPW = kW / NWV;                          // features per wave (output layer)
     constexpr int NT = 64 * NWV;
@@ -262,8 +264,8 @@ __global__ __launch_bounds__(64 * NWV) void k_train_fp32(const float* __restrict
     const int64_t tile = blockIdx.x;
     const int64_t row = tile * kTile + lane;
     const bool valid = row < n;
-    // record read for this slot: idx[row] for a gathered batch, else row
-    const int64_t src = !valid ? 0 : idx ? (int64_t)idx[row] : row;
+    // record read for this slot: idx[row] or the LCG orbit for a gathered batch, else row
+    const int64_t src = !valid ? 0 : gather_row(idx, lg, row);
     float* part = partials + tile * (int64_t)n_params;
     const int f0 = FPW * wave;                            // this wave's first feature (output layer)
     const int g = lane >> 4, j = lane & 15;               // MFMA lane group and column
@@ -274,7 +276,7 @@ __global__ __launch_bounds__(64 * NWV) void k_train_fp32(const float* __restrict
         const int s = i >> 4, q = i & 15;
         const int64_t r = tile * kTile + s;
         float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (r < n) v = reinterpret_cast<const float4*>(enc + (idx ? (int64_t)idx[r] : r) * kEncWidth)[q];
+        if (r < n) v = reinterpret_cast<const float4*>(enc + gather_row(idx, lg, r) * kEncWidth)[q];
         *reinterpret_cast<float4*>(hs + s * kLd + 4 * q) = v;
     }
     __syncthreads();
@@ -284,7 +286,24 @@ __global__ __launch_bounds__(64 * NWV) void k_train_fp32(const float* __restrict
     // takes h[16 bco + j][16g + t]; D: lane (g, j) ends with out features
     // 16 bro + 4g .. +3 of sample 16 bco + j.  Layer l's weights start at
     // w + l * 64 * 64 (the input layer is 64 x 64 too).
-    for (int l = 0; l < n_hidden; ++l) {
+    const int64_t n_tiles = gridDim.x;
+    float* act_t = act + tile * (int64_t)(n_hidden * kTile * kW);
+    float* act_y = act + n_tiles * (int64_t)(n_hidden * kTile * kW);
+    // copy h_1 .. h_H between LDS and the buffer, one float4 at a time
+    auto copy_act = [&](bool to_lds) {
+        for (int i = tid; i < n_hidden * kTile * 16; i += NT) {
+            const int q = i & 15, rs = i >> 4;               // rs = layer * 64 + record
+            float4* l = reinterpret_cast<float4*>(hs + (kTile + rs) * kLd) + q;
+            float4* gp = reinterpret_cast<float4*>(act_t + rs * kW) + q;
+            if (to_lds) *l = *gp; else *gp = *l;
+        }
+    };
+    if (ACT == kActLoad) {
+        copy_act(true);
+        __syncthreads();
+    }
+    const int n_fwd = ACT == kActLoad ? 0 : n_hidden;   // layers the forward pass computes
+    for (int l = 0; l < n_fwd; ++l) {
         const float* arow = w + l * kW * kW + (16 * bro + j) * kW + 16 * g;
         const float* brow = hs + l * kTile * kLd + (16 * bco + j) * kLd + 16 * g;
         f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
@@ -305,21 +324,44 @@ __global__ __launch_bounds__(64 * NWV) void k_train_fp32(const float* __restrict
     const float* wout = w + n_hidden * kW * kW;           // [3][64]
     const float* hlast = hs + n_hidden * kTile * kLd;
 
+    if (ACT == kActStore) {
+        copy_act(false);
+        if (wave != 0) return;            // wave 0 stores the outputs below and returns too
+    }
+
     // Output layer, loss and dL/dy (wave 0, lane = sample).
     if (wave == 0) {
         float f[kNOut] = {0.f, 0.f, 0.f};
-        const float* hr = hlast + lane * kLd;
-        #pragma unroll
-        for (int k = 0; k < kW; ++k) {
-            const float hv = hr[k];
+        if (ACT == kActLoad) {
+            if (valid) {
+                #pragma unroll
+                for (int o = 0; o < kNOut; ++o) f[o] = act_y[row * 4 + o];
+            }
+        } else {
+            const float* hr = hlast + lane * kLd;
             #pragma unroll
-            for (int o = 0; o < kNOut; ++o) f[o] = fmaf(wout[o * kW + k], hv, f[o]);
+            for (int k = 0; k < kW; ++k) {
+                const float hv = hr[k];
+                #pragma unroll
+                for (int o = 0; o < kNOut; ++o) f[o] = fmaf(wout[o * kW + k], hv, f[o]);
+            }
         }
         float r[kNOut] = {1.f, 1.f, 1.f};
         if (fcol) {
             const float* h0 = hs + lane * kLd;
             #pragma unroll
             for (int o = 0; o < kNOut; ++o) r[o] = h0[fcol + o] + h0[fcol + 3 + o];
+        }
+        if (ACT == kActStore) {
+            if (valid) {
+                #pragma unroll
+                for (int o = 0; o < kNOut; ++o) {
+                    rgb[row * 3 + o] = f[o] * r[o];
+                    act_y[row * 4 + o] = f[o];
+                }
+                act_y[row * 4 + 3] = 0.0f;
+            }
+            return;
         }
         float d[kNOut] = {0.f, 0.f, 0.f};
         float lterm = 0.0f;
@@ -343,7 +385,7 @@ __global__ __launch_bounds__(64 * NWV) void k_train_fp32(const float* __restrict
         }
         *reinterpret_cast<float4*>(dout + lane * 4) = make_float4(d[0], d[1], d[2], 0.f);
         if (GENC) *reinterpret_cast<float4*>(fout + lane * 4) = make_float4(f[0], f[1], f[2], 0.f);
-        const float tot = wave_sum(lterm);
+        const float tot = wave_sum_compensated(lterm);
         if (lane == 0) loss_part[tile] = tot;
     }
     __syncthreads();
@@ -431,9 +473,13 @@ __global__ __launch_bounds__(64 * NWV) void k_train_fp32(const float* __restrict
             } else {
                 const int64_t srow = tile * kTile + sm;
                 if (srow < n) {
+                    // the loss scale of the upstream gradient divided out
+                    const float inv_scale = 1.0f / grad_scale;
+                    #pragma unroll
+                    for (int r = 0; r < 4; ++r) acc[r] *= inv_scale;
                     if (fcol) {
                         // d(f_c R_c)/d(albedo column) = f_c on the diffuse and specular column.
-                        const int64_t ssrc = idx ? (int64_t)idx[srow] : srow;
+                        const int64_t ssrc = gather_row(idx, lg, srow);
                         #pragma unroll
                         for (int r = 0; r < 4; ++r) {
                             int c = fb + r - fcol;
@@ -510,33 +556,49 @@ size_t fp32_train_lds_bytes(int n_hidden) {
 // Waves per 64-record training tile of the FP32 form.
 constexpr int kTrainWaves = 16;
 
-template <bool UP, bool GE, int NWV>
+template <bool UP, bool GE, int NWV, int ACT = kActNone>
 hipError_t train_fp32_launch(const Geo& d, const float* w, const float* enc, const float* tgt,
                              const int32_t* idx, int64_t n, float loss_eps, float grad_scale,
                              float* partials, float* loss_part, int32_t* tile_bad, float* genc,
-                             hipStream_t s) {
+                             hipStream_t s, float* act = nullptr, float* rgb = nullptr,
+                             LcgGather lg = LcgGather{}) {
     const int64_t tiles = (n + kTile - 1) / kTile;
     if (tiles == 0) return hipSuccess;
     const size_t lds = fp32_train_lds_bytes(d.H);
-    auto k = k_train_fp32<UP, GE, NWV>;
+    auto k = k_train_fp32<UP, GE, NWV, ACT>;
     (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL(k, dim3((unsigned)tiles), dim3(64 * NWV), lds, s, w, enc, tgt, idx, n, d.H,
-                       d.n_params(), loss_eps, grad_scale, partials, loss_part, tile_bad, genc, d.F);
+                       d.n_params(), loss_eps, grad_scale, partials, loss_part, tile_bad, genc, d.F, act, rgb, lg);
     return hipGetLastError();
 }
 
 hipError_t launch_train_fp32(const Geo& d, const float* w, const float* enc, const float* tgt,
                              const int32_t* idx, int64_t n, bool upstream, float loss_eps, float grad_scale,
                              float* partials, float* loss_part, int32_t* tile_bad, float* genc,
-                             hipStream_t s) {
+                             hipStream_t s, const float* act, LcgGather lg) {
     if (!upstream)
         return train_fp32_launch<false, false, kTrainWaves>(d, w, enc, tgt, idx, n, loss_eps, grad_scale,
-                                                            partials, loss_part, tile_bad, genc, s);
+                                                            partials, loss_part, tile_bad, genc, s, nullptr,
+                                                            nullptr, lg);
+    float* a = const_cast<float*>(act);
+    if (act) {
+        if (genc)
+            return train_fp32_launch<true, true, kTrainWaves, kActLoad>(d, w, enc, tgt, idx, n, loss_eps, grad_scale,
+                                                                        partials, loss_part, tile_bad, genc, s, a);
+        return train_fp32_launch<true, false, kTrainWaves, kActLoad>(d, w, enc, tgt, idx, n, loss_eps, grad_scale,
+                                                                     partials, loss_part, tile_bad, genc, s, a);
+    }
     if (genc)
         return train_fp32_launch<true, true, kTrainWaves>(d, w, enc, tgt, idx, n, loss_eps, grad_scale,
                                                           partials, loss_part, tile_bad, genc, s);
     return train_fp32_launch<true, false, kTrainWaves>(d, w, enc, tgt, idx, n, loss_eps, grad_scale,
                                                        partials, loss_part, tile_bad, genc, s);
+}
+
+hipError_t launch_fwd_train_fp32(const Geo& d, const float* w, const float* enc, int64_t n, float* act,
+                                 float* rgb, hipStream_t s) {
+    return train_fp32_launch<true, false, kTrainWaves, kActStore>(d, w, enc, nullptr, nullptr, n, 0.0f, 1.0f,
+                                                                  nullptr, nullptr, nullptr, nullptr, s, act, rgb);
 }
 
 }  // namespace nrc

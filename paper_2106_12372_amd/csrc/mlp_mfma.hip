@@ -93,12 +93,6 @@ __device__ inline f32x4 relu4(f32x4 a) {
     return r;
 }
 
-__device__ inline float wave_sum(float v) {
-    #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-
 // ---------------------------------------------------------------------------
 // Inference
 // ---------------------------------------------------------------------------
@@ -301,6 +295,68 @@ __global__ __launch_bounds__(256, 2) void k_fwd_mfma(const T* __restrict__ ffr, 
     }
 }
 
+// Inference over several request segments in one launch (serving: queued
+// queries of one cache that no training step separates).  Tile t of the
+// launch belongs to the segment whose cumulative tile range holds it; within
+// a segment the kernel is k_fwd_mfma.
+template <typename T, int W, int COLS>
+__global__ __launch_bounds__(256, 2) void k_fwd_mfma_segs(const T* __restrict__ ffr, int n_frags, SegList segs,
+                                                          int n_hidden, int fcol) {
+    using V = typename Vec8<T>::type;
+    constexpr int KC = W / 32;
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+    V* sfr = reinterpret_cast<V*>(smem_raw);
+    stage_frags(sfr, reinterpret_cast<const V*>(ffr), n_frags);
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane >> 4, ln = lane & 15;
+    const int64_t n_tiles = segs.tile_end[segs.count - 1];
+    const int64_t tstride = (int64_t)gridDim.x * 4;
+    // segment of tile t (wave-uniform) and the tile's first row in it
+    auto locate = [&](int64_t t, int& sg, int64_t& base) {
+        sg = 0;
+        while (t >= segs.tile_end[sg]) ++sg;
+        base = (t - (sg ? segs.tile_end[sg - 1] : 0)) * 16 * COLS;
+    };
+    V nxt[COLS][2];
+    auto load_tile = [&](int64_t t) {
+        int sg;
+        int64_t base;
+        locate(t, sg, base);
+        const T* enc = reinterpret_cast<const T*>(segs.enc[sg]);
+        const int64_t n = segs.n[sg];
+        #pragma unroll
+        for (int col = 0; col < COLS; ++col) {
+            int64_t row = base + 16 * col + ln;
+            row = row < n ? row : n - 1;
+            #pragma unroll
+            for (int c = 0; c < 2; ++c)
+                nxt[col][c] = *reinterpret_cast<const V*>(enc + row * kEncWidth + 32 * c + 8 * g);
+        }
+    };
+    int64_t tile = (int64_t)blockIdx.x * 4 + wave;
+    if (tile < n_tiles) load_tile(tile);
+    for (; tile < n_tiles; tile += tstride) {
+        V b[COLS][KC];
+        #pragma unroll
+        for (int col = 0; col < COLS; ++col) {
+            b[col][0] = nxt[col][0];
+            b[col][1] = nxt[col][1];
+        }
+        if (tile + tstride < n_tiles) load_tile(tile + tstride);
+        float r[COLS][3];
+        #pragma unroll
+        for (int col = 0; col < COLS; ++col) reflectance_operand(b[col][1], fcol, ln, r[col]);
+        f32x4 o[COLS];
+        mlp_tile<T, W, COLS>(sfr, b, n_hidden, lane, o);
+        int sg;
+        int64_t base;
+        locate(tile, sg, base);
+        store_rgb<COLS>(o, r, base, segs.n[sg], g, ln, segs.rgb[sg]);
+    }
+}
+
 // Inference from raw records with the encoding fused in (Sec. 3.6 encodings,
 // Sec. 4 network).  Each wave owns a 64-record tile: lane r encodes record r
 // (the next tile's raw floats are loaded while the current tile computes),
@@ -494,7 +550,15 @@ __host__ __device__ constexpr int train_lds_bytes(int W, int H) {
     return (kEncWidth + 2 * H * W + 16) * (W == 64 ? 72 : 40) * 2;
 }
 
-template <typename T, int W, bool UPSTREAM, bool GENC>
+// Activation buffer of the autograd form (ACT): per tile, h_1 .. h_H as
+// [layer][feature][record] at the operand precision (the LDS rows without
+// their padding), then, after every tile's block, the network output
+// [tile * TS + record][4] (FP32).  kActNone: no buffer; kActStore: forward only,
+// writes the buffer and rgb, then exits; kActLoad: the forward pass is read
+// from the buffer instead of recomputed.
+constexpr int kActNone = 0, kActStore = 1, kActLoad = 2;
+
+template <typename T, int W, bool UPSTREAM, bool GENC, int ACT = kActNone>
 __global__ __launch_bounds__(256) void k_train_mfma(const T* __restrict__ ffr,
                                                     const T* __restrict__ bfr,
                                                     const T* __restrict__ enc,
@@ -504,7 +568,9 @@ __global__ __launch_bounds__(256) void k_train_mfma(const T* __restrict__ ffr,
                                                     float* __restrict__ partials,
                                                     float* __restrict__ loss_part,
                                                     int32_t* __restrict__ tile_bad,
-                                                    float* __restrict__ genc, int fcol) {
+                                                    float* __restrict__ genc, int fcol,
+                                                    T* __restrict__ act, float* __restrict__ rgb,
+                                                    LcgGather lg) {
     using V = typename Vec8<T>::type;
     using S = TrainShape<W>;
     constexpr int MB = W / 16, KC = W / 32, TS = S::TS, NW = S::NW, LDT = S::LDT, TK = TS / 32;
@@ -525,8 +591,8 @@ __global__ __launch_bounds__(256) void k_train_mfma(const T* __restrict__ ffr,
     const int sl = 16 * wave + ln;                           // record within the tile
     const int64_t row = tile * TS + sl;
     const bool valid = row < n;
-    // record read for this slot: idx[row] for a gathered batch, else row
-    const int64_t src = !valid ? 0 : idx ? (int64_t)idx[row] : row;
+    // record read for this slot: idx[row] or the LCG orbit for a gathered batch, else row
+    const int64_t src = !valid ? 0 : gather_row(idx, lg, row);
     float* part = partials + tile * (int64_t)P;
     const V* gf = reinterpret_cast<const V*>(ffr) + lane;
     const V* gb = reinterpret_cast<const V*>(bfr) + lane;
@@ -549,11 +615,27 @@ __global__ __launch_bounds__(256) void k_train_mfma(const T* __restrict__ ffr,
     reflectance_operand(b[1], fcol, ln, r);
     // this record's targets (or upstream gradient), loaded now and used after the forward pass
     float tg[3] = {0.f, 0.f, 0.f};
-    if (g == 0 && valid) {
+    if (ACT != kActStore && g == 0 && valid) {
         #pragma unroll
         for (int c = 0; c < 3; ++c) tg[c] = tgt[src * 3 + c];
     }
-    for (int l = 0; l < n_hidden; ++l) {
+    // the tile's block of the activation buffer and its network outputs
+    const int64_t n_tiles = gridDim.x;
+    T* act_t = act + tile * (int64_t)(n_hidden * W * TS);
+    float* act_y = reinterpret_cast<float*>(act + n_tiles * (int64_t)(n_hidden * W * TS));
+    // copy h_1 .. h_H between the LDS rows and the buffer, 16 bytes at a time
+    auto copy_act = [&](bool to_lds) {
+        constexpr int CPR = TS * (int)sizeof(T) / 16;         // 16-byte chunks per row
+        const int rows = n_hidden * W;
+        for (int i = tid; i < rows * CPR; i += 64 * NW) {
+            const int rr = i / CPR, q = i - rr * CPR;
+            u32x4* l = reinterpret_cast<u32x4*>(hT + (kEncWidth + rr) * LDT) + q;
+            u32x4* gp = reinterpret_cast<u32x4*>(act_t + rr * TS) + q;
+            if (to_lds) *l = *gp; else *gp = *l;
+        }
+    };
+    const int n_fwd = ACT == kActLoad ? 0 : n_hidden;   // layers the forward pass computes
+    for (int l = 0; l < n_fwd; ++l) {
         const int kc = l == 0 ? 2 : KC;
         const V* fl = gf + geo.fwd_base(l) * 64;
         f32x4 acc[MB];
@@ -572,12 +654,34 @@ __global__ __launch_bounds__(256) void k_train_mfma(const T* __restrict__ ffr,
             put(ho, b[c], c);
         }
     }
-    f32x4 y;
-    {
+    f32x4 y = f32x4{0.f, 0.f, 0.f, 0.f};
+    if (ACT == kActLoad) {
+        copy_act(true);
+        if (g == 0 && valid) {
+            #pragma unroll
+            for (int c = 0; c < 3; ++c) y[c] = act_y[row * 4 + c];
+        }
+        __syncthreads();
+    } else {
         const V* fo = gf + geo.fwd_base(n_hidden) * 64;
         y = mfma(fo[0], b[0], f32x4{0.f, 0.f, 0.f, 0.f});
         #pragma unroll
         for (int c = 1; c < KC; ++c) y = mfma(fo[c * 64], b[c], y);
+    }
+    if (ACT == kActStore) {
+        // the prediction (network output times the reflectance factor) and
+        // the buffer for the backward pass; nothing else
+        if (g == 0 && valid) {
+            #pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                rgb[row * 3 + c] = y[c] * r[c];
+                act_y[row * 4 + c] = y[c];
+            }
+            act_y[row * 4 + 3] = 0.0f;
+        }
+        __syncthreads();
+        copy_act(false);
+        return;
     }
 
     // ---- loss gradient (Eq. 5); lanes 0..15 of each wave hold y[0..2] -------
@@ -609,7 +713,7 @@ __global__ __launch_bounds__(256) void k_train_mfma(const T* __restrict__ ffr,
         dO[1 * LDT + sl] = bd[1];
         dO[2 * LDT + sl] = bd[2];
     }
-    const float wl = wave_sum(lterm);
+    const float wl = wave_sum_compensated(lterm);
     if (lane == 0) wsum[wave] = wl;
 
     // ---- data backward: the whole delta chain in VGPRs, each delta kept in LDS
@@ -643,7 +747,8 @@ __global__ __launch_bounds__(256) void k_train_mfma(const T* __restrict__ ffr,
         }
     }
     if (GENC) {
-        // dL/dh_0 = W_0^T delta_1 (64 input features).
+        // dL/dh_0 = W_0^T delta_1 (64 input features), with the loss scale
+        // of the upstream gradient divided out.
         f32x4 acc[4];
         #pragma unroll
         for (int mb = 0; mb < 4; ++mb) acc[mb] = mfma(gb[(mb * KC) * 64], b[0], f32x4{0.f, 0.f, 0.f, 0.f});
@@ -651,6 +756,11 @@ __global__ __launch_bounds__(256) void k_train_mfma(const T* __restrict__ ffr,
         for (int c = 1; c < KC; ++c)
             #pragma unroll
             for (int mb = 0; mb < 4; ++mb) acc[mb] = mfma(gb[(mb * KC + c) * 64], b[c], acc[mb]);
+        const float inv_scale = 1.0f / grad_scale;
+        #pragma unroll
+        for (int mb = 0; mb < 4; ++mb)
+            #pragma unroll
+            for (int j = 0; j < 4; ++j) acc[mb][j] *= inv_scale;
         if (fcol) {
             // d(f_c R_c)/d(albedo column) = f_c: lane (g, ln) holds input
             // features 48 + 4g .. 48 + 4g + 3 of record sl in acc[3].
@@ -678,9 +788,14 @@ __global__ __launch_bounds__(256) void k_train_mfma(const T* __restrict__ ffr,
     }
     __syncthreads();
     if (tid == 0) {
-        float t = 0.0f;
-        for (int w = 0; w < NW; ++w) t += wsum[w];
-        loss_part[tile] = t;
+        // compensated combine of the waves' sums, in wave order
+        float t = 0.0f, c = 0.0f;
+        for (int w = 0; w < NW; ++w) {
+            const float x = wsum[w], u = t + x;
+            c += fabsf(t) >= fabsf(x) ? (t - u) + x : (x - u) + t;
+            t = u;
+        }
+        loss_part[tile] = t + c;
     }
 
     // ---- weight gradients: dW_l = delta_{l+1} h_l^T over the tile's records --
@@ -734,6 +849,21 @@ __global__ __launch_bounds__(256) void k_train_mfma(const T* __restrict__ ffr,
     }
     const int any_bad = __syncthreads_or(bad ? 1 : 0);
     if (tid == 0) tile_bad[tile] = any_bad ? 1 : 0;
+}
+
+template <typename T, int W>
+hipError_t fwd_segs_dispatch(const Geo& d, const void* ffr, const SegList& segs, hipStream_t s) {
+    constexpr int COLS = 4;
+    const int64_t tiles = segs.tile_end[segs.count - 1];
+    if (tiles == 0) return hipSuccess;
+    const size_t lds = (size_t)d.n_fwd_frags() * 64 * 16;
+    int64_t blocks = (tiles + 3) / 4;
+    if (blocks > 2048) blocks = 2048;
+    auto k = k_fwd_mfma_segs<T, W, COLS>;
+    (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(256), lds, s, (const T*)ffr, d.n_fwd_frags(), segs, d.H,
+                       d.F);
+    return hipGetLastError();
 }
 
 template <typename T, int W>
@@ -826,20 +956,20 @@ hipError_t fwd_raw_dispatch(const Geo& d, int preset, int layout, const void* ff
                                : fwd_raw_generic<T, W, NRC_PRESET_CONFIG, NRC_RAW16>(d, ffr, raw, n, rgb, s);
 }
 
-template <typename T, int W, bool UP, bool GE>
+template <typename T, int W, bool UP, bool GE, int ACT = kActNone>
 hipError_t train_launch(const Geo& d, const void* ffr, const void* bfr, const void* enc,
                         const float* tgt, const int32_t* idx, int64_t n, float loss_eps, float grad_scale,
                         float* partials, float* loss_part, int32_t* tile_bad, float* genc,
-                        hipStream_t s) {
+                        hipStream_t s, void* act = nullptr, float* rgb = nullptr, LcgGather lg = LcgGather{}) {
     using S = TrainShape<W>;
     const int64_t tiles = (n + S::TS - 1) / S::TS;
     if (tiles == 0) return hipSuccess;
     const size_t lds = (size_t)train_lds_bytes(W, d.H);
-    auto k = k_train_mfma<T, W, UP, GE>;
+    auto k = k_train_mfma<T, W, UP, GE, ACT>;
     (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL(k, dim3((unsigned)tiles), dim3(64 * S::NW), lds, s, (const T*)ffr, (const T*)bfr,
                        (const T*)enc, tgt, idx, n, d.H, loss_eps, grad_scale, partials, loss_part, tile_bad,
-                       genc, d.F);
+                       genc, d.F, (T*)act, rgb, lg);
     return hipGetLastError();
 }
 
@@ -847,10 +977,17 @@ template <typename T, int W>
 hipError_t train_dispatch(const Geo& d, const void* ffr, const void* bfr, const void* enc,
                           const float* tgt, const int32_t* idx, int64_t n, bool upstream, float loss_eps,
                           float grad_scale, float* partials, float* loss_part, int32_t* tile_bad,
-                          float* genc, hipStream_t s) {
+                          float* genc, hipStream_t s, const void* act, LcgGather lg) {
     if (!upstream)
         return train_launch<T, W, false, false>(d, ffr, bfr, enc, tgt, idx, n, loss_eps, grad_scale,
-                                                partials, loss_part, tile_bad, genc, s);
+                                                partials, loss_part, tile_bad, genc, s, nullptr, nullptr, lg);
+    if (act) {
+        if (genc)
+            return train_launch<T, W, true, true, kActLoad>(d, ffr, bfr, enc, tgt, idx, n, loss_eps, grad_scale,
+                                                            partials, loss_part, tile_bad, genc, s, (void*)act);
+        return train_launch<T, W, true, false, kActLoad>(d, ffr, bfr, enc, tgt, idx, n, loss_eps, grad_scale,
+                                                         partials, loss_part, tile_bad, genc, s, (void*)act);
+    }
     if (genc)
         return train_launch<T, W, true, true>(d, ffr, bfr, enc, tgt, idx, n, loss_eps, grad_scale,
                                               partials, loss_part, tile_bad, genc, s);
@@ -876,6 +1013,16 @@ hipError_t launch_fwd_mfma(int precision, const Geo& d, const void* ffr, const v
                      : fwd_dispatch<__bf16, 128>(d, ffr, enc, n, rgb, s);
 }
 
+hipError_t launch_fwd_mfma_segs(int precision, const Geo& d, const void* ffr, const SegList& segs,
+                                hipStream_t s) {
+    if (segs.count < 1 || segs.count > kMaxSegs) return hipErrorInvalidValue;
+    if (precision == NRC_FP16)
+        return d.W == 64 ? fwd_segs_dispatch<_Float16, 64>(d, ffr, segs, s)
+                         : fwd_segs_dispatch<_Float16, 128>(d, ffr, segs, s);
+    return d.W == 64 ? fwd_segs_dispatch<__bf16, 64>(d, ffr, segs, s)
+                     : fwd_segs_dispatch<__bf16, 128>(d, ffr, segs, s);
+}
+
 // Width 64 only: the fused kernel keeps the weights and four 64-record encode
 // buffers in LDS side by side.
 hipError_t launch_fwd_raw_mfma(int precision, const Geo& d, int preset, int layout, const void* ffr,
@@ -887,16 +1034,33 @@ hipError_t launch_fwd_raw_mfma(int precision, const Geo& d, int preset, int layo
 hipError_t launch_train_mfma(int precision, const Geo& d, const void* ffr, const void* bfr,
                              const void* enc, const float* tgt, const int32_t* idx, int64_t n, bool upstream,
                              float loss_eps, float grad_scale, float* partials, float* loss_part,
-                             int32_t* tile_bad, float* genc, hipStream_t s) {
+                             int32_t* tile_bad, float* genc, hipStream_t s, const void* act, LcgGather lg) {
     if (precision == NRC_FP16)
         return d.W == 64 ? train_dispatch<_Float16, 64>(d, ffr, bfr, enc, tgt, idx, n, upstream, loss_eps,
-                                                        grad_scale, partials, loss_part, tile_bad, genc, s)
+                                                        grad_scale, partials, loss_part, tile_bad, genc, s, act, lg)
                          : train_dispatch<_Float16, 128>(d, ffr, bfr, enc, tgt, idx, n, upstream, loss_eps,
-                                                         grad_scale, partials, loss_part, tile_bad, genc, s);
+                                                         grad_scale, partials, loss_part, tile_bad, genc, s, act,
+                                                         lg);
     return d.W == 64 ? train_dispatch<__bf16, 64>(d, ffr, bfr, enc, tgt, idx, n, upstream, loss_eps,
-                                                  grad_scale, partials, loss_part, tile_bad, genc, s)
+                                                  grad_scale, partials, loss_part, tile_bad, genc, s, act, lg)
                      : train_dispatch<__bf16, 128>(d, ffr, bfr, enc, tgt, idx, n, upstream, loss_eps,
-                                                   grad_scale, partials, loss_part, tile_bad, genc, s);
+                                                   grad_scale, partials, loss_part, tile_bad, genc, s, act, lg);
+}
+
+template <typename T, int W>
+hipError_t fwd_train_dispatch(const Geo& d, const void* ffr, const void* enc, int64_t n, void* act, float* rgb,
+                              hipStream_t s) {
+    return train_launch<T, W, true, false, kActStore>(d, ffr, nullptr, enc, nullptr, nullptr, n, 0.0f, 1.0f,
+                                                      nullptr, nullptr, nullptr, nullptr, s, act, rgb);
+}
+
+hipError_t launch_fwd_train_mfma(int precision, const Geo& d, const void* ffr, const void* enc, int64_t n,
+                                 void* act, float* rgb, hipStream_t s) {
+    if (precision == NRC_FP16)
+        return d.W == 64 ? fwd_train_dispatch<_Float16, 64>(d, ffr, enc, n, act, rgb, s)
+                         : fwd_train_dispatch<_Float16, 128>(d, ffr, enc, n, act, rgb, s);
+    return d.W == 64 ? fwd_train_dispatch<__bf16, 64>(d, ffr, enc, n, act, rgb, s)
+                     : fwd_train_dispatch<__bf16, 128>(d, ffr, enc, n, act, rgb, s);
 }
 
 }  // namespace nrc

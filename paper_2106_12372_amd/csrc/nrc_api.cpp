@@ -117,6 +117,16 @@ ScratchLayout scratch_layout(const nrc_config& c, int64_t n) {
     return L;
 }
 
+// Bytes of the autograd form's activation buffer: per training tile, h_1 .. h_H
+// at the operand precision, then the network output of every record as four
+// floats (see k_train_mfma / k_train_fp32).
+size_t act_layout(const nrc_config& c, int64_t n) {
+    const int ts = train_tile(c.precision, c.width);
+    const size_t tiles = (size_t)((n + ts - 1) / ts);
+    const size_t elem = c.precision == NRC_FP32 ? 4 : 2;
+    return tiles * (size_t)c.n_hidden * (size_t)c.width * (size_t)ts * elem + tiles * (size_t)ts * 16;
+}
+
 // Network shape plus the reflectance-factorisation column the kernels use.
 Geo kernel_geo(const nrc_config& c) {
     Geo d(c.width, c.n_hidden);
@@ -126,7 +136,8 @@ Geo kernel_geo(const nrc_config& c) {
 
 // Enqueue one training step (forward, loss, backward, reduction, Adam) on s.
 int enqueue_train_step(nrc_cache* c, const void* enc, const float* target, const int32_t* idx,
-                       int64_t n, char* scratch, float* loss_dev, int32_t* skipped_dev, hipStream_t s) {
+                       int64_t n, char* scratch, float* loss_dev, int32_t* skipped_dev, hipStream_t s,
+                       LcgGather lg) {
     const nrc_config& cfg = c->cfg;
     const Geo d = kernel_geo(cfg);
     const ScratchLayout sl = scratch_layout(cfg, n);
@@ -138,10 +149,10 @@ int enqueue_train_step(nrc_cache* c, const void* enc, const float* target, const
     hipError_t e;
     if (cfg.precision == NRC_FP32)
         e = launch_train_fp32(d, c->w(), (const float*)enc, target, idx, n, false, cfg.loss_eps, grad_scale,
-                              partials, loss_part, tile_bad, nullptr, s);
+                              partials, loss_part, tile_bad, nullptr, s, nullptr, lg);
     else
         e = launch_train_mfma(cfg.precision, d, c->ffr(), c->bfr(), enc, target, idx, n, false, cfg.loss_eps,
-                              grad_scale, partials, loss_part, tile_bad, nullptr, s);
+                              grad_scale, partials, loss_part, tile_bad, nullptr, s, nullptr, lg);
     if (e != hipSuccess) return device_fail(e, "training kernel launch");
     float* loss_out = loss_dev ? loss_dev : (float*)(scratch + sl.loss);
     int32_t* skipped_out = skipped_dev ? skipped_dev : (int32_t*)(scratch + sl.skipped);
@@ -459,14 +470,41 @@ int nrc_train_step(nrc_cache* cache, const void* enc, const float* target, int64
     return rc == NRC_OK ? ok() : rc;
 }
 
-int nrc_backward(nrc_cache* cache, const void* enc, const float* grad_rgb, int64_t n, void* scratch,
-                 size_t scratch_bytes, float* grad_w, float* grad_enc, void* stream) {
+size_t nrc_act_ws_bytes(const nrc_config* cfg, int64_t n) {
+    if (validate_config(cfg) != NRC_OK) return 0;
+    if (n < 0 || n > ((int64_t)1 << 31)) { fail(NRC_EINVAL, "n must be in [0, 2^31]"); return 0; }
+    ok();
+    return act_layout(*cfg, n);
+}
+
+int nrc_forward_train(nrc_cache* cache, const void* enc, int64_t n, void* act_ws, size_t act_bytes, float* rgb,
+                      void* stream) {
+    if (!cache) return fail(NRC_EINVAL, "cache is NULL");
+    if (n < 0 || n > ((int64_t)1 << 31)) return fail(NRC_EINVAL, "n must be in [0, 2^31]");
+    if (n == 0) return ok();
+    if (!enc || !act_ws || !rgb) return fail(NRC_EINVAL, "NULL buffer");
+    if (!aligned16(enc) || !aligned16(act_ws) || ((uintptr_t)rgb & 3)) return fail(NRC_EINVAL, "misaligned buffer");
+    const size_t need = act_layout(cache->cfg, n);
+    if (act_bytes < need)
+        return fail(NRC_ENOMEM, "activation buffer of %zu bytes is smaller than the %zu bytes needed", act_bytes, need);
+    const Geo d = kernel_geo(cache->cfg);
+    hipError_t e;
+    if (cache->cfg.precision == NRC_FP32)
+        e = launch_fwd_train_fp32(d, cache->w(), (const float*)enc, n, (float*)act_ws, rgb, (hipStream_t)stream);
+    else
+        e = launch_fwd_train_mfma(cache->cfg.precision, d, cache->ffr(), enc, n, act_ws, rgb, (hipStream_t)stream);
+    if (e != hipSuccess) return device_fail(e, "training forward launch");
+    return ok();
+}
+
+int nrc_backward(nrc_cache* cache, const void* enc, const void* act_ws, const float* grad_rgb, int64_t n,
+                 void* scratch, size_t scratch_bytes, float* grad_w, float* grad_enc, void* stream) {
     if (!cache) return fail(NRC_EINVAL, "cache is NULL");
     if (n < 1) return fail(NRC_EINVAL, "a backward batch needs n >= 1");
     if (n > ((int64_t)1 << 31)) return fail(NRC_EINVAL, "batch too large");
     if (!enc || !grad_rgb || !scratch || !grad_w) return fail(NRC_EINVAL, "NULL buffer");
     if (!aligned16(enc) || ((uintptr_t)grad_rgb & 3) || ((uintptr_t)scratch & 255) ||
-        ((uintptr_t)grad_w & 3) || (grad_enc && !aligned16(grad_enc)))
+        ((uintptr_t)grad_w & 3) || (grad_enc && !aligned16(grad_enc)) || (act_ws && !aligned16(act_ws)))
         return fail(NRC_EINVAL, "misaligned buffer");
     const nrc_config& cfg = cache->cfg;
     const ScratchLayout sl = scratch_layout(cfg, n);
@@ -478,15 +516,19 @@ int nrc_backward(nrc_cache* cache, const void* enc, const float* grad_rgb, int64
     float* loss_part = (float*)(sc + sl.loss_part);
     int32_t* tile_bad = (int32_t*)(sc + sl.flags);
     hipStream_t s = (hipStream_t)stream;
+    // the upstream gradient is scaled by the loss scale before the backward
+    // pass rounds it to FP16/BF16 and unscaled after the sums (a mean-reduced
+    // loss over 2^16 records gives dL/dy near 1e-5, where FP16 is subnormal)
+    const float scale = cfg.loss_scale;
     hipError_t e;
     if (cfg.precision == NRC_FP32)
-        e = launch_train_fp32(d, cache->w(), (const float*)enc, grad_rgb, nullptr, n, true, cfg.loss_eps, 1.0f,
-                              partials, loss_part, tile_bad, grad_enc, s);
+        e = launch_train_fp32(d, cache->w(), (const float*)enc, grad_rgb, nullptr, n, true, cfg.loss_eps, scale,
+                              partials, loss_part, tile_bad, grad_enc, s, (const float*)act_ws);
     else
         e = launch_train_mfma(cfg.precision, d, cache->ffr(), cache->bfr(), enc, grad_rgb, nullptr, n, true,
-                              cfg.loss_eps, 1.0f, partials, loss_part, tile_bad, grad_enc, s);
+                              cfg.loss_eps, scale, partials, loss_part, tile_bad, grad_enc, s, act_ws);
     if (e != hipSuccess) return device_fail(e, "backward kernel launch");
-    e = launch_reduce(d, cfg.precision != NRC_FP32, partials, (int)sl.tiles, 1.0f, grad_w, loss_part,
+    e = launch_reduce(d, cfg.precision != NRC_FP32, partials, (int)sl.tiles, 1.0f / scale, grad_w, loss_part,
                       1.0f, nullptr, s);
     if (e != hipSuccess) return device_fail(e, "gradient reduction launch");
     return ok();
@@ -611,8 +653,25 @@ int nrc_train_frame(nrc_cache* cache, const void* enc, const float* target, int6
                                        losses_dev, skipped_dev, &L);
     if (rc != NRC_OK) return rc;
     char* sc = (char*)scratch;
-    int32_t* perm = (int32_t*)(sc + L.perm);
     hipStream_t s = (hipStream_t)stream;
+    if ((n_records & (n_records - 1)) == 0) {
+        // A power-of-two record count: the LCG's modulus is the record count,
+        // the orbit skips nothing, and each step's kernel computes its records'
+        // orbit positions itself (the same permutation nrc_shuffle writes).
+        const uint32_t mask = (uint32_t)(n_records - 1);
+        const Affine step{kLcgA, kLcgC};
+        const uint32_t x0 = (uint32_t)(seed & mask);
+        const int64_t used = n_records < steps * batch ? n_records : steps * batch;
+        for (int k = 0; k < steps; ++k) {
+            const int64_t lo = k * used / steps, hi = (k + 1) * used / steps;
+            const LcgGather lg{step, apply(power(step, (uint64_t)lo), x0) & mask, mask};
+            const int rc2 = enqueue_train_step(cache, enc, target, nullptr, hi - lo, sc + L.step, losses_dev + k,
+                                               skipped_dev + k, s, lg);
+            if (rc2 != NRC_OK) return rc2;
+        }
+        return ok();
+    }
+    int32_t* perm = (int32_t*)(sc + L.perm);
     hipError_t e = launch_shuffle(n_records, seed, perm, (int32_t*)(sc + L.counts), s);
     if (e != hipSuccess) return device_fail(e, "shuffle launch");
     return enqueue_frame_steps(cache, enc, target, perm, n_records, steps, batch, sc + L.step, losses_dev,

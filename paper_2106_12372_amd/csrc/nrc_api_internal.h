@@ -26,6 +26,7 @@ struct ScratchLayout {
 
 CacheLayout cache_layout(const nrc_config& c);
 ScratchLayout scratch_layout(const nrc_config& c, int64_t n);
+size_t act_layout(const nrc_config& c, int64_t n);
 int validate_config(const nrc_config* c);
 bool aligned16(const void* p);
 
@@ -57,8 +58,10 @@ struct nrc_cache {
 };
 
 namespace nrc {
-// idx (may be NULL): the batch is records idx[0..n) of enc / target.
+// idx (may be NULL): the batch is records idx[0..n) of enc / target; lg (if
+// its mask is set and idx is NULL): the batch is n records of the LCG orbit.
 int enqueue_train_step(nrc_cache* c, const void* enc, const float* target, const int32_t* idx,
-                       int64_t n, char* scratch, float* loss_dev, int32_t* skipped_dev, hipStream_t s);
+                       int64_t n, char* scratch, float* loss_dev, int32_t* skipped_dev, hipStream_t s,
+                       LcgGather lg = LcgGather{});
 int enqueue_forward(nrc_cache* c, const void* enc, int64_t n, float* rgb, hipStream_t s);
 }  // namespace nrc

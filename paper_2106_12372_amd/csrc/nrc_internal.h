@@ -116,6 +116,73 @@ __device__ inline void reflectance_row(const float (&h)[kEncWidth], int fcol, fl
                                           : 1.0f;
 }
 
+// Neumaier-compensated sum of one float per lane over the 64 lanes of a wave,
+// in a fixed butterfly order; every lane ends with the same value.  Each pair
+// sum is formed with the lower lane's operand first and carries both lanes'
+// compensation terms, so the two partners of a pair compute identical bits.
+__device__ inline float wave_sum_compensated(float v) {
+    const int lane = __lane_id();
+    float s = v, c = 0.0f;
+    #pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const float os = __shfl_xor(s, off, 64), oc = __shfl_xor(c, off, 64);
+        const bool lo = (lane & off) == 0;
+        const float a = lo ? s : os, b = lo ? os : s;
+        const float t = a + b;
+        const float e = fabsf(a) >= fabsf(b) ? (a - t) + b : (b - t) + a;
+        c = ((lo ? c : oc) + (lo ? oc : c)) + e;
+        s = t;
+    }
+    return s + c;
+}
+
+// Request segments of one multi-segment inference launch (serving): segment
+// k has n[k] > 0 encoded rows at enc[k] and writes rgb[k]; tile_end[k] is the
+// cumulative count of 64-record tiles through segment k.
+constexpr int kMaxSegs = 16;
+struct SegList {
+    int count;
+    int64_t tile_end[kMaxSegs];
+    const void* enc[kMaxSegs];
+    float* rgb[kMaxSegs];
+    int64_t n[kMaxSegs];
+};
+
+// The record shuffle's LCG as affine maps x -> a x + c (mod 2^32): their
+// composition, powers (jump-ahead by repeated squaring) and application.
+struct Affine {
+    uint32_t a, c;
+};
+// g after f.
+__host__ __device__ inline Affine compose(Affine f, Affine g) { return {g.a * f.a, g.a * f.c + g.c}; }
+// f applied j times.
+__host__ __device__ inline Affine power(Affine f, uint64_t j) {
+    Affine r{1u, 0u};
+    while (j) {
+        if (j & 1) r = compose(r, f);
+        f = compose(f, f);
+        j >>= 1;
+    }
+    return r;
+}
+__host__ __device__ inline uint32_t apply(Affine f, uint32_t x) { return f.a * x + f.c; }
+
+// A training batch read straight from the LCG orbit: batch slot r is record
+// (step^r (x0)) & mask.  Used by a frame over a power-of-two record count,
+// where the orbit skips no value, so no permutation is stored.  mask == 0:
+// not used.
+struct LcgGather {
+    Affine step;
+    uint32_t x0, mask;
+};
+
+// Record read by batch slot r: idx[r] for an index list, the LCG orbit, or r.
+__device__ inline int64_t gather_row(const int32_t* idx, const LcgGather& lg, int64_t r) {
+    if (idx) return idx[r];
+    if (lg.mask) return (int64_t)(apply(power(lg.step, (uint64_t)r), lg.x0) & lg.mask);
+    return r;
+}
+
 struct AdamHyper {
     float lr, beta1, beta2, eps;
 };
@@ -142,7 +209,9 @@ hipError_t launch_fwd_fp32(const Geo& d, const float* w, const float* enc, int64
 hipError_t launch_train_fp32(const Geo& d, const float* w, const float* enc, const float* tgt,
                              const int32_t* idx, int64_t n, bool upstream, float loss_eps, float grad_scale,
                              float* partials, float* loss_part, int32_t* tile_bad, float* genc,
-                             hipStream_t s);
+                             hipStream_t s, const float* act = nullptr, LcgGather lg = LcgGather{});
+hipError_t launch_fwd_train_fp32(const Geo& d, const float* w, const float* enc, int64_t n, float* act,
+                                 float* rgb, hipStream_t s);
 hipError_t launch_fwd_raw_fp32(const Geo& d, int preset, int layout, const float* w, const float* raw,
                                int64_t n, float* rgb, hipStream_t s);
 // mlp_mfma.hip
@@ -150,10 +219,19 @@ hipError_t launch_fwd_raw_mfma(int precision, const Geo& d, int preset, int layo
                                const float* raw, int64_t n, float* rgb, hipStream_t s);
 hipError_t launch_fwd_mfma(int precision, const Geo& d, const void* ffr, const void* enc,
                            int64_t n, float* rgb, hipStream_t s);
+hipError_t launch_fwd_mfma_segs(int precision, const Geo& d, const void* ffr, const SegList& segs,
+                                hipStream_t s);
+// act (may be NULL, upstream only): activation buffer written by
+// launch_fwd_train_mfma; the forward pass is then read instead of recomputed.
 hipError_t launch_train_mfma(int precision, const Geo& d, const void* ffr, const void* bfr,
                              const void* enc, const float* tgt, const int32_t* idx, int64_t n, bool upstream,
                              float loss_eps, float grad_scale, float* partials, float* loss_part,
-                             int32_t* tile_bad, float* genc, hipStream_t s);
+                             int32_t* tile_bad, float* genc, hipStream_t s, const void* act = nullptr,
+                             LcgGather lg = LcgGather{});
+// Forward pass of the autograd form: rgb[n][3] and the activation buffer
+// (act_bytes_mfma / act_bytes_fp32 bytes) for a later backward.
+hipError_t launch_fwd_train_mfma(int precision, const Geo& d, const void* ffr, const void* enc, int64_t n,
+                                 void* act, float* rgb, hipStream_t s);
 size_t fp32_train_lds_bytes(int n_hidden);
 size_t mfma_train_lds_bytes(int width, int n_hidden);
 size_t mfma_fwd_lds_bytes(int width, int n_hidden);

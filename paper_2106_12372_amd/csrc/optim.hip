@@ -136,12 +136,22 @@ __global__ __launch_bounds__(256) void k_reduce(const float* __restrict__ partia
     __syncthreads();
 
     if (blockIdx.x == 0 && tid >= 64 && tid < 128 && loss_out != nullptr) {
+        // compensated sum of the per-tile loss terms, then a compensated
+        // combine of the 64 lane sums in a fixed order
         float ls = 0.0f, lc = 0.0f;
         for (int t = lane; t < n_tiles; t += 64) neumaier_add(ls, lc, loss_part[t]);
-        float lv = ls + lc;
         #pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) lv += __shfl_xor(lv, off, 64);
-        if (lane == 0) *loss_out = lv * inv_count;
+        for (int off = 32; off >= 1; off >>= 1) {
+            const float os = __shfl_xor(ls, off, 64), oc = __shfl_xor(lc, off, 64);
+            // both partners form the same pair sum (the lower lane's operand first)
+            const bool lo = (lane & off) == 0;
+            float a = lo ? ls : os, ac = lo ? lc : oc;
+            neumaier_add(a, ac, lo ? os : ls);
+            ac += lo ? oc : lc;
+            ls = a;
+            lc = ac;
+        }
+        if (lane == 0) *loss_out = (ls + lc) * inv_count;
     }
     if (!owner) return;   // workgroup 0's thread 0 has slot 0 and stays
     float gv = 0.0f;

@@ -6,18 +6,28 @@
 // thread; a request is admitted as soon as an in-flight slot is free and its
 // scratch memory (training partials) fits in the arena's free space, so
 // requests that arrive while others run are launched alongside them on a pool
-// of HIP streams.  Requests on one cache keep their submission order on the
-// device through events: a query waits for the cache's last training step, a
-// training step waits for that step and every query issued since.  Requests
-// of different caches, and queries between two steps of one cache, overlap.
-// Kernels are deterministic and share no state across caches, so a request's
-// result is the same alone and in any mix.
+// of HIP streams.  Queued queries of one cache that no training step of that
+// cache separates are launched together, as one multi-segment kernel (up to
+// kMaxSegs requests; FP16/BF16 caches).  Requests on one cache keep their
+// submission order on the device through events: a query waits for the
+// cache's last training step, a training step waits for that step and every
+// query issued since.  Requests of different caches, and queries between two
+// steps of one cache, overlap.  Kernels are deterministic, each record's result
+// is independent of the other records of its launch, and caches share no
+// state, so a request's result is the same alone and in any mix.
+//
+// While requests are on the device the scheduler polls their events (yielding
+// the core between polls); when none are, it sleeps on a condition variable
+// until a submission arrives.  Completion callbacks (host functions queued
+// behind each launch) were measured as the wake-up instead: they doubled the
+// median latency of the serving trace, and a callback that takes the
+// scheduler's lock can deadlock against a HIP call made under that lock.
 #include <hip/hip_runtime.h>
 
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
-#include <deque>
+#include <list>
 #include <map>
 #include <mutex>
 #include <new>
@@ -87,11 +97,13 @@ struct Request {
 };
 
 struct Inflight {
-    Request r;
+    std::vector<Request> rs;   // one training step, or one or more queries of one cache
     int slot;
     int stream;
     size_t scratch_off;
+    size_t scratch_bytes;
     double t_start;
+    int status;                // NRC_OK, or the error of a launch that failed after queueing work
 };
 
 struct CacheDeps {
@@ -115,28 +127,45 @@ struct nrc_server {
 
     std::mutex mu;
     std::condition_variable cv;
-    std::deque<Request> pending;
+    std::list<Request> pending;             // erasing one entry leaves the others' iterators valid
     std::vector<Inflight> inflight;
     std::unordered_map<uint64_t, int> inflight_slot;   // ticket -> slot while on the device
     std::unordered_map<uint64_t, nrc_result> done;
     std::vector<CacheDeps> deps;
     uint64_t next_ticket = 1;
     size_t n_outstanding = 0;
+    uint64_t wakeups = 0;                   // submissions, under mu
     bool stop = false;
     int device = 0;
     std::thread worker;
     std::string worker_error;
 
     void run();
-    bool try_launch(Request& r, std::unique_lock<std::mutex>& lk);
+    bool try_launch(std::vector<Request>& rs, std::unique_lock<std::mutex>& lk);
     void retire(std::unique_lock<std::mutex>& lk);
+    void fail_group(const std::vector<Request>& rs, int rc, double t);
 };
 
-bool nrc_server::try_launch(Request& r, std::unique_lock<std::mutex>&) {
+void nrc_server::fail_group(const std::vector<Request>& rs, int rc, double t) {
+    for (const Request& r : rs) {
+        nrc_result res{};
+        res.status = rc;
+        res.t_submit = r.t_submit;
+        res.t_start = res.t_done = t;
+        done[r.ticket] = res;
+        --n_outstanding;
+    }
+    cv.notify_all();
+}
+
+// Launches a training step (rs.size() == 1) or one or more queries of one
+// cache; false if no slot or no scratch is free.
+bool nrc_server::try_launch(std::vector<Request>& rs, std::unique_lock<std::mutex>&) {
     int slot = -1;
     for (int i = 0; i < (int)slot_free.size(); ++i)
         if (slot_free[i]) { slot = i; break; }
     if (slot < 0) return false;
+    const Request& r = rs[0];
     size_t off = 0;
     if (!arena.alloc(r.scratch_bytes, &off)) return false;
     int st = 0;
@@ -151,47 +180,68 @@ bool nrc_server::try_launch(Request& r, std::unique_lock<std::mutex>&) {
     wait_on(dp.last_train);
     nrc_cache* c = caches[r.cache];
     int rc;
+    bool enqueued = false;                // device work that may use the scratch is queued
     if (r.req.kind == NRC_REQ_TRAIN) {
         for (uint64_t t : dp.reads) wait_on(t);
         char* sc = scratch_base + off;
         const ScratchLayout sl = scratch_layout(c->cfg, r.req.n);
         rc = enqueue_train_step(c, r.req.enc, r.req.target, nullptr, r.req.n, sc, (float*)(sc + sl.loss),
                                 (int32_t*)(sc + sl.skipped), s);
+        enqueued = true;                  // even a failed enqueue may have queued the training kernel
         if (rc == NRC_OK) {
             if (hipMemcpyAsync(&host_out[slot].loss, sc + sl.loss, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
                 hipMemcpyAsync(&host_out[slot].skipped, sc + sl.skipped, 4, hipMemcpyDeviceToHost, s) != hipSuccess)
                 rc = NRC_EDEVICE;
         }
-    } else {
+    } else if (rs.size() == 1) {
         rc = enqueue_forward(c, r.req.enc, r.req.n, r.req.rgb, s);
+    } else {
+        SegList segs{};
+        segs.count = (int)rs.size();
+        int64_t tiles = 0;
+        for (int k = 0; k < segs.count; ++k) {
+            tiles += (rs[k].req.n + 63) / 64;
+            segs.tile_end[k] = tiles;
+            segs.enc[k] = rs[k].req.enc;
+            segs.rgb[k] = rs[k].req.rgb;
+            segs.n[k] = rs[k].req.n;
+        }
+        Geo d(c->cfg.width, c->cfg.n_hidden);
+        d.F = c->cfg.factorize ? albedo_col(c->cfg.enc_preset) : 0;
+        const hipError_t e = launch_fwd_mfma_segs(c->cfg.precision, d, c->query_ffr(), segs, s);
+        rc = e == hipSuccess ? NRC_OK : device_fail(e, "multi-segment forward launch");
+    }
+    if (r.req.kind != NRC_REQ_TRAIN) {
         host_out[slot].loss = 0.0f;
         host_out[slot].skipped = 0;
+    } else if (rc != NRC_OK) {
+        host_out[slot].loss = 0.0f;
+        host_out[slot].skipped = 1;
     }
-    if (rc == NRC_OK && hipEventRecord(slot_event[slot], s) != hipSuccess) rc = NRC_EDEVICE;
-    if (rc == NRC_OK) {                   // later requests of this cache order after this one
-        if (r.req.kind == NRC_REQ_TRAIN) {
-            dp.last_train = r.ticket;
-            dp.reads.clear();
-        } else {
-            dp.reads.push_back(r.ticket);
-        }
-    }
-    Inflight f{r, slot, st, off, now_s()};
-    if (rc != NRC_OK) {
-        arena.release(off, r.scratch_bytes);
-        nrc_result res{};
-        res.status = rc;
-        res.t_submit = r.t_submit;
-        res.t_start = res.t_done = f.t_start;
-        done[r.ticket] = res;
-        --n_outstanding;
-        cv.notify_all();
+    const double t0 = now_s();
+    const bool recorded = hipEventRecord(slot_event[slot], s) == hipSuccess;
+    if (!recorded && rc == NRC_OK) rc = NRC_EDEVICE;
+    if (rc != NRC_OK && !(enqueued && recorded)) {
+        // nothing that uses the scratch is queued, or its end cannot be
+        // observed: in the latter case the scratch is never reused
+        if (!enqueued) arena.release(off, r.scratch_bytes);
+        fail_group(rs, rc, t0);
         return true;
+    }
+    // later requests of this cache order after these (a failed step too: it
+    // may have run its kernels)
+    if (r.req.kind == NRC_REQ_TRAIN) {
+        dp.last_train = r.ticket;
+        dp.reads.clear();
+    } else {
+        for (const Request& q : rs) dp.reads.push_back(q.ticket);
     }
     slot_free[slot] = 0;
     ++stream_load[st];
-    inflight_slot[r.ticket] = slot;
-    inflight.push_back(f);
+    for (const Request& q : rs) inflight_slot[q.ticket] = slot;
+    // a training step whose enqueue failed part-way retires like the others,
+    // once its queued work has finished, and then reports the error
+    inflight.push_back(Inflight{rs, slot, st, off, r.scratch_bytes, t0, rc});
     return true;
 }
 
@@ -200,23 +250,26 @@ void nrc_server::retire(std::unique_lock<std::mutex>&) {
         Inflight& f = inflight[i];
         const hipError_t q = hipEventQuery(slot_event[f.slot]);
         if (q == hipErrorNotReady) { ++i; continue; }
-        nrc_result res{};
-        res.status = q == hipSuccess ? NRC_OK : NRC_EDEVICE;
-        res.loss = host_out[f.slot].loss;
-        res.skipped = host_out[f.slot].skipped;
-        res.t_submit = f.r.t_submit;
-        res.t_start = f.t_start;
-        res.t_done = now_s();
-        done[f.r.ticket] = res;
-        arena.release(f.scratch_off, f.r.scratch_bytes);
+        const double t_done = now_s();
+        CacheDeps& dp = deps[f.rs[0].cache];
+        for (const Request& r : f.rs) {
+            nrc_result res{};
+            res.status = f.status != NRC_OK ? f.status : q == hipSuccess ? NRC_OK : NRC_EDEVICE;
+            res.loss = host_out[f.slot].loss;
+            res.skipped = host_out[f.slot].skipped;
+            res.t_submit = r.t_submit;
+            res.t_start = f.t_start;
+            res.t_done = t_done;
+            done[r.ticket] = res;
+            inflight_slot.erase(r.ticket);
+            if (dp.last_train == r.ticket) dp.last_train = 0;
+            for (size_t k = 0; k < dp.reads.size(); ++k)
+                if (dp.reads[k] == r.ticket) { dp.reads.erase(dp.reads.begin() + k); break; }
+            --n_outstanding;
+        }
+        arena.release(f.scratch_off, f.scratch_bytes);
         slot_free[f.slot] = 1;
         --stream_load[f.stream];
-        inflight_slot.erase(f.r.ticket);
-        CacheDeps& dp = deps[f.r.cache];
-        if (dp.last_train == f.r.ticket) dp.last_train = 0;
-        for (size_t k = 0; k < dp.reads.size(); ++k)
-            if (dp.reads[k] == f.r.ticket) { dp.reads.erase(dp.reads.begin() + k); break; }
-        --n_outstanding;
         inflight[i] = inflight.back();
         inflight.pop_back();
         cv.notify_all();
@@ -225,24 +278,43 @@ void nrc_server::retire(std::unique_lock<std::mutex>&) {
 
 void nrc_server::run() {
     (void)hipSetDevice(device);
+    const bool segments = cfg.cache_cfg.precision != NRC_FP32;   // multi-segment launches (matrix-core forms)
     std::unique_lock<std::mutex> lk(mu);
     while (true) {
         if (stop && pending.empty() && inflight.empty()) break;
+        const uint64_t seen = wakeups;
         // Admit in arrival order; a request that does not fit lets later
         // requests of other caches through, never later ones of its own cache.
+        // A query takes along the queries of its cache queued after it, up to
+        // the cache's next training step.
         std::vector<char> blocked(caches.size(), 0);
         for (auto it = pending.begin(); it != pending.end();) {
             if (blocked[it->cache]) { ++it; continue; }
-            if (try_launch(*it, lk)) {
-                it = pending.erase(it);
+            std::vector<Request> group{*it};
+            std::vector<std::list<Request>::iterator> members{it};
+            if (segments && it->req.kind == NRC_REQ_INFER) {
+                for (auto jt = std::next(it); jt != pending.end() && (int)group.size() < kMaxSegs; ++jt) {
+                    if (jt->cache != it->cache) continue;
+                    if (jt->req.kind != NRC_REQ_INFER) break;
+                    group.push_back(*jt);
+                    members.push_back(jt);
+                }
+            }
+            if (try_launch(group, lk)) {
+                for (size_t k = 1; k < members.size(); ++k) pending.erase(members[k]);
+                it = pending.erase(members[0]);
             } else {
                 blocked[it->cache] = 1;
                 ++it;
             }
         }
         retire(lk);
+        if (stop && pending.empty() && inflight.empty()) break;
         if (inflight.empty() && pending.empty()) {
-            cv.wait(lk, [&] { return stop || !pending.empty(); });
+            // idle: sleep until a submission (or shutdown)
+            cv.wait(lk, [&] { return stop || wakeups != seen; });
+        } else if (inflight.empty()) {
+            continue;                     // a slot or scratch was just retired: admit again
         } else {
             lk.unlock();
             std::this_thread::yield();
@@ -363,6 +435,7 @@ int nrc_serve_submit(nrc_server* srv, int cache_id, const nrc_request* req, uint
     } else {
         srv->pending.push_back(r);
         ++srv->n_outstanding;
+        ++srv->wakeups;
         srv->cv.notify_all();
     }
     *ticket = r.ticket;

@@ -23,26 +23,6 @@ namespace {
 constexpr int kShufBlock = 256;
 constexpr int kMaxSpans = 1024;
 
-struct Affine {
-    uint32_t a, c;   // x -> a x + c (mod 2^32)
-};
-
-// g after f.
-__host__ __device__ inline Affine compose(Affine f, Affine g) { return {g.a * f.a, g.a * f.c + g.c}; }
-
-// f applied j times.
-__host__ __device__ inline Affine power(Affine f, uint64_t j) {
-    Affine r{1u, 0u};
-    while (j) {
-        if (j & 1) r = compose(r, f);
-        f = compose(f, f);
-        j >>= 1;
-    }
-    return r;
-}
-
-__device__ inline uint32_t apply(Affine f, uint32_t x) { return f.a * x + f.c; }
-
 __device__ inline int block_sum(int v, int* red) {
     #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);

@@ -95,7 +95,9 @@ _decl("nrc_forward", c_int, _P, _P, c_int64, _P, _P)
 _decl("nrc_forward_raw", c_int, _P, _P, c_int, c_int64, _P, _P)
 _decl("nrc_train_step", c_int, _P, _P, _P, c_int64, _P, c_size_t, _P, _P, _P)
 _decl("nrc_train_step_noalloc", c_int, _P, _P, _P, c_int64, _P, _P, _P)
-_decl("nrc_backward", c_int, _P, _P, _P, c_int64, _P, c_size_t, _P, _P, _P)
+_decl("nrc_act_ws_bytes", c_size_t, POINTER(nrc_config), c_int64)
+_decl("nrc_forward_train", c_int, _P, _P, c_int64, _P, c_size_t, _P, _P)
+_decl("nrc_backward", c_int, _P, _P, _P, _P, c_int64, _P, c_size_t, _P, _P, _P)
 _decl("nrc_shuffle_scratch_bytes", c_size_t, c_int64)
 _decl("nrc_shuffle", c_int, c_int64, c_uint64, _P, _P, c_size_t, _P)
 _decl("nrc_train_step_indexed", c_int, _P, _P, _P, _P, c_int64, _P, c_size_t, _P, _P, _P)
@@ -116,7 +118,7 @@ EXPORTED = ["nrc_config_default", "nrc_last_error", "nrc_param_count", "nrc_cach
             "nrc_cache_config", "nrc_set_weights", "nrc_get_weights", "nrc_set_weights_device",
             "nrc_get_state", "nrc_set_state", "nrc_get_ema", "nrc_set_ema", "nrc_encode", "nrc_forward", "nrc_forward_raw", "nrc_train_step",
             "nrc_train_step_noalloc",
-            "nrc_backward", "nrc_shuffle_scratch_bytes", "nrc_shuffle", "nrc_train_step_indexed",
+            "nrc_act_ws_bytes", "nrc_forward_train", "nrc_backward", "nrc_shuffle_scratch_bytes", "nrc_shuffle", "nrc_train_step_indexed",
             "nrc_frame_scratch_bytes", "nrc_train_frame", "nrc_train_frame_indexed", "nrc_self_training_targets", "nrc_serve_create", "nrc_serve_set_weights", "nrc_serve_get_weights",
             "nrc_serve_submit", "nrc_serve_poll", "nrc_serve_drain", "nrc_serve_destroy"]
 
@@ -165,6 +167,21 @@ def _stream(stream) -> c_void_p:
     if isinstance(stream, int):
         return c_void_p(stream)
     return c_void_p(stream.cuda_stream)
+
+
+def _keep(stream, *tensors):
+    """Tensors this binding allocated on the current stream but hands to work on
+    `stream`: tell torch's caching allocator that they are in use there, so it
+    does not reuse their memory before that stream's work has finished."""
+    if stream is None:
+        return
+    torch = _torch()
+    s = torch.cuda.ExternalStream(stream) if isinstance(stream, int) else stream
+    if s == torch.cuda.current_stream(s.device):
+        return
+    for t in tensors:
+        if t is not None:
+            t.record_stream(s)
 
 
 def _ptr(t) -> c_void_p:
@@ -295,6 +312,7 @@ def nrc_encode(cache: Cache, raw, layout: int = NRC_RAW14, enc=None, stream=None
     if enc is None:
         enc = torch.empty((n, ENC_WIDTH), dtype=cache.enc_dtype, device=raw.device)
     _need(enc, cache.enc_dtype, (ENC_WIDTH,), "enc")
+    _keep(stream, enc)
     check(lib.nrc_encode(cache.handle, _ptr(raw), layout, n, _ptr(enc), _stream(stream)))
     return enc
 
@@ -306,6 +324,7 @@ def nrc_forward(cache: Cache, enc, rgb=None, stream=None):
     if rgb is None:
         rgb = torch.empty((n, 3), dtype=torch.float32, device=enc.device)
     _need(rgb, torch.float32, (3,), "rgb")
+    _keep(stream, rgb)
     check(lib.nrc_forward(cache.handle, _ptr(enc), n, _ptr(rgb), _stream(stream)))
     return rgb
 
@@ -319,6 +338,7 @@ def nrc_forward_raw(cache: Cache, raw, layout: int = NRC_RAW14, rgb=None, stream
     if rgb is None:
         rgb = torch.empty((n, 3), dtype=torch.float32, device=raw.device)
     _need(rgb, torch.float32, (3,), "rgb")
+    _keep(stream, rgb)
     check(lib.nrc_forward_raw(cache.handle, _ptr(raw), layout, n, _ptr(rgb), _stream(stream)))
     return rgb
 
@@ -336,6 +356,7 @@ def nrc_train_step(cache: Cache, enc, target, loss=None, skipped=None, scratch=N
     if skipped is None:
         skipped = torch.empty(1, dtype=torch.int32, device=enc.device)
     sc, size = cache.scratch(n) if scratch is None else (scratch, scratch.numel())
+    _keep(stream, loss, skipped, sc)
     check(lib.nrc_train_step(cache.handle, _ptr(enc), _ptr(target), n, _ptr(sc), size, _ptr(loss),
                              _ptr(skipped), _stream(stream)))
     return loss, skipped
@@ -354,6 +375,7 @@ def nrc_train_step_noalloc(cache: Cache, enc, target, loss=None, skipped=None, s
         loss = torch.empty(1, dtype=torch.float32, device=enc.device)
     if skipped is None:
         skipped = torch.empty(1, dtype=torch.int32, device=enc.device)
+    _keep(stream, loss, skipped)
     check(lib.nrc_train_step_noalloc(cache.handle, _ptr(enc), _ptr(target), n, _ptr(loss), _ptr(skipped),
                                      _stream(stream)))
     return loss, skipped
@@ -373,6 +395,7 @@ def nrc_shuffle(n: int, seed: int, device="cuda", perm=None, scratch=None, strea
     if perm is None:
         perm = torch.empty(n, dtype=torch.int32, device=device)
     sc = _aligned_bytes(max(1, lib.nrc_shuffle_scratch_bytes(n)), perm.device) if scratch is None else scratch
+    _keep(stream, perm, sc)
     check(lib.nrc_shuffle(n, seed & (2 ** 64 - 1), _ptr(perm), _ptr(sc), sc.numel(), _stream(stream)))
     return perm
 
@@ -391,6 +414,7 @@ def nrc_train_step_indexed(cache: Cache, enc, target, idx, loss=None, skipped=No
     if skipped is None:
         skipped = torch.empty(1, dtype=torch.int32, device=enc.device)
     sc, size = cache.scratch(n)
+    _keep(stream, loss, skipped, sc)
     check(lib.nrc_train_step_indexed(cache.handle, _ptr(enc), _ptr(target), _ptr(idx), n, _ptr(sc), size,
                                      _ptr(loss), _ptr(skipped), _stream(stream)))
     return loss, skipped
@@ -417,6 +441,7 @@ def nrc_train_frame(cache: Cache, enc, target, steps: int = 4, batch: int = 1638
         scratch = _aligned_bytes(nrc_frame_scratch_bytes(cache.cfg, n, steps, batch), enc.device)
     losses = torch.empty(steps, dtype=torch.float32, device=enc.device)
     skipped = torch.empty(steps, dtype=torch.int32, device=enc.device)
+    _keep(stream, scratch, losses, skipped)
     check(lib.nrc_train_frame(cache.handle, _ptr(enc), _ptr(target), n, steps, batch, seed & (2 ** 64 - 1),
                               _ptr(scratch), scratch.numel(), _ptr(losses), _ptr(skipped), _stream(stream)))
     return losses, skipped
@@ -437,6 +462,7 @@ def nrc_train_frame_indexed(cache: Cache, enc, target, perm, steps: int = 4, bat
         scratch = _aligned_bytes(nrc_frame_scratch_bytes(cache.cfg, n, steps, batch), enc.device)
     losses = torch.empty(steps, dtype=torch.float32, device=enc.device)
     skipped = torch.empty(steps, dtype=torch.int32, device=enc.device)
+    _keep(stream, scratch, losses, skipped)
     check(lib.nrc_train_frame_indexed(cache.handle, _ptr(enc), _ptr(target), _ptr(perm), n, steps, batch,
                                       _ptr(scratch), scratch.numel(), _ptr(losses), _ptr(skipped),
                                       _stream(stream)))
@@ -454,21 +480,49 @@ def nrc_self_training_targets(radiance, throughput, tail_rgb, tail_index, stream
     if throughput.shape[0] != n or tail_index.shape[0] != n:
         raise ValueError("radiance, throughput and tail_index differ in length")
     target = torch.empty((n, 3), dtype=torch.float32, device=radiance.device)
+    _keep(stream, target)
     check(lib.nrc_self_training_targets(_ptr(radiance), _ptr(throughput), _ptr(tail_rgb), _ptr(tail_index), n,
                                         tail_rgb.shape[0], _ptr(target), _stream(stream)))
     return target
 
 
-def nrc_backward(cache: Cache, enc, grad_rgb, want_grad_enc: bool = True, scratch=None, stream=None):
-    """Gradients of sum(grad_rgb * network(enc)) w.r.t. the weights and (optionally) enc."""
+def nrc_act_ws_bytes(cfg: nrc_config, n: int) -> int:
+    b = lib.nrc_act_ws_bytes(ctypes.byref(cfg), n)
+    if b == 0 and n > 0:
+        raise NrcError(NRC_EINVAL, last_error())
+    return b
+
+
+def nrc_forward_train(cache: Cache, enc, act=None, rgb=None, stream=None):
+    """Predictions for enc with the training weights, keeping the activations
+    for nrc_backward; returns (rgb[n][3], act) with act a uint8 device buffer."""
+    torch = _torch()
+    _need(enc, cache.enc_dtype, (ENC_WIDTH,), "enc")
+    n = enc.shape[0]
+    if rgb is None:
+        rgb = torch.empty((n, 3), dtype=torch.float32, device=enc.device)
+    if act is None:
+        act = torch.empty(max(nrc_act_ws_bytes(cache.cfg, n), 16), dtype=torch.uint8, device=enc.device)
+    _keep(stream, rgb, act)
+    check(lib.nrc_forward_train(cache.handle, _ptr(enc), n, _ptr(act), act.numel(), _ptr(rgb), _stream(stream)))
+    return rgb, act
+
+
+def nrc_backward(cache: Cache, enc, grad_rgb, want_grad_enc: bool = True, act=None, scratch=None, stream=None):
+    """Gradients of sum(grad_rgb * network(enc)) w.r.t. the weights and (optionally)
+    enc; act: the buffer of nrc_forward_train for the same enc and weights, or
+    None to recompute the forward pass."""
     torch = _torch()
     _need(enc, cache.enc_dtype, (ENC_WIDTH,), "enc")
     _need(grad_rgb, torch.float32, (3,), "grad_rgb")
     n = enc.shape[0]
+    if act is not None and act.numel() < nrc_act_ws_bytes(cache.cfg, n):
+        raise ValueError("activation buffer too small for this batch")
     grad_w = torch.empty(cache.n_params, dtype=torch.float32, device=enc.device)
     grad_enc = torch.empty((n, ENC_WIDTH), dtype=torch.float32, device=enc.device) if want_grad_enc else None
     sc, size = cache.scratch(n) if scratch is None else (scratch, scratch.numel())
-    check(lib.nrc_backward(cache.handle, _ptr(enc), _ptr(grad_rgb), n, _ptr(sc), size, _ptr(grad_w),
+    _keep(stream, grad_w, grad_enc, sc)
+    check(lib.nrc_backward(cache.handle, _ptr(enc), _ptr(act), _ptr(grad_rgb), n, _ptr(sc), size, _ptr(grad_w),
                            _ptr(grad_enc), _stream(stream)))
     return grad_w, grad_enc
 

@@ -98,13 +98,18 @@ class TrainModel:
         return loss
 
 
-def relu_undecided_rows(mats, x, rel=1e-5):
+GAMMA_64 = 64 * 2.0 ** -24 / (1 - 64 * 2.0 ** -24)   # gamma_K of a K = 64 FP32 dot product
+
+
+def relu_undecided_rows(mats, x, rel=GAMMA_64):
     """Records whose ReLU masks FP32 arithmetic does not decide: some hidden
-    pre-activation z lies within rel * sum |w h| of zero, well inside the FP32
-    error bound of a 64-term dot product over inputs that carry their own
-    rounding.  ReLU' is a step at zero, so for such a unit the sign, and with
-    it the whole backward contribution through it, depends on summation order;
-    the FP64 oracle's choice is no more right than the kernel's.  Returns a
+    pre-activation z lies within rel * sum |w h| of zero.  The default is the
+    standard bound on the rounding error of an FP32 dot product of K = 64
+    terms, |fl(w.h) - w.h| <= gamma_K sum |w h| with gamma_K = K u / (1 - K u),
+    u = 2^-24 (Higham, Accuracy and Stability of Numerical Algorithms, 3.1).
+    ReLU' is a step at zero, so for such a unit the sign, and with it the
+    whole backward contribution through it, depends on summation order; the
+    FP64 oracle's choice is no more right than the kernel's.  Returns a
     boolean mask over the records."""
     h = np.asarray(x, np.float64)
     undecided = np.zeros(h.shape[0], bool)

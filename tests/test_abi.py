@@ -85,7 +85,9 @@ def test_entry_points_reject_null_cache(N):
     assert N.lib.nrc_forward(None, P(4096), 10, P(4096), None) == N.NRC_EINVAL
     assert N.lib.nrc_encode(None, P(4096), 0, 10, P(4096), None) == N.NRC_EINVAL
     assert N.lib.nrc_train_step(None, P(4096), P(4096), 10, P(4096), 1 << 30, None, None, None) == N.NRC_EINVAL
-    assert N.lib.nrc_backward(None, P(4096), P(4096), 10, P(4096), 1 << 30, P(4096), None, None) == N.NRC_EINVAL
+    assert N.lib.nrc_backward(None, P(4096), None, P(4096), 10, P(4096), 1 << 30, P(4096), None, None) == N.NRC_EINVAL
+    assert N.lib.nrc_forward_train(None, P(4096), 10, P(4096), 1 << 30, P(4096), None) == N.NRC_EINVAL
+    assert N.lib.nrc_train_step_noalloc(None, P(4096), P(4096), 10, None, None, None) == N.NRC_EINVAL
     assert N.lib.nrc_cache_destroy(None) == N.NRC_EINVAL
     assert N.lib.nrc_config_default(None) == N.NRC_EINVAL
 
@@ -113,3 +115,17 @@ def test_record_pipeline_rejects_bad_arguments_before_device_calls(N):
     assert N.lib.nrc_self_training_targets(P(4096), P(4096), P(4096), P(4096), 10, 0, P(4096), None) == N.NRC_EINVAL
     assert N.lib.nrc_self_training_targets(None, P(4096), P(4096), P(4096), 10, 5, P(4096), None) == N.NRC_EINVAL
     assert N.lib.nrc_self_training_targets(None, None, None, None, 0, 0, None, None) == N.NRC_OK
+
+
+def test_activation_buffer_size(N):
+    # per 64-record tile (32 at width 128 in the matrix-core forms): every
+    # hidden layer's activations at the operand precision, plus four floats of
+    # network output per record
+    for prec, elem in (("fp16", 2), ("bf16", 2), ("fp32", 4)):
+        cfg = N.make_config(precision=prec)
+        assert N.nrc_act_ws_bytes(cfg, 65536) == 1024 * (5 * 64 * 64 * elem + 64 * 16)
+        assert N.nrc_act_ws_bytes(cfg, 65) == 2 * (5 * 64 * 64 * elem + 64 * 16)
+        assert N.nrc_act_ws_bytes(cfg, 0) == 0
+    cfg = N.make_config(precision="fp16", width=128)
+    assert N.nrc_act_ws_bytes(cfg, 64) == 2 * (5 * 128 * 32 * 2 + 32 * 16)
+    assert N.lib.nrc_act_ws_bytes(ctypes.byref(cfg), -1) == 0

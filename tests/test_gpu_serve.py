@@ -195,3 +195,93 @@ def test_poll_unknown_ticket_and_destroy_busy(N):
     res = N.nrc_result()
     assert N.lib.nrc_serve_poll(srv.handle, 12345, ctypes.byref(res)) == N.NRC_ENOTFOUND
     srv.close()
+
+
+def _collect(srv, tickets):
+    out = []
+    for t in tickets:
+        r = srv.poll(t)
+        while r is None:
+            r = srv.poll(t)
+        out.append(r)
+    return out
+
+
+def test_queued_queries_of_one_cache_share_a_launch(N):
+    # With its one in-flight slot busy on a training step, the server queues
+    # the queries submitted meanwhile; the queries of one cache that no
+    # training step separates then go out as one multi-segment launch (one
+    # start time), and each still equals its solo replay bit for bit.
+    cfg = N.make_config(precision="fp16")
+    srv = N.Server(2, cfg, arena_bytes=1 << 30, n_streams=2, max_inflight=1)
+    w = [sd.glorot_weights(seed=110 + i) for i in range(2)]
+    for i in range(2):
+        srv.set_weights(i, w[i])
+    c0 = N.Cache(cfg)
+    raw = sd.raw_records(65536, 111)
+    enc_t = N.nrc_encode(c0, torch.from_numpy(raw).to("cuda"))
+    tgt = torch.from_numpy(sd.targets(raw)).to("cuda")
+    sizes = [1000, 64, 4097, 1, 30000, 777, 65, 12000]
+    encs = [N.nrc_encode(c0, torch.from_numpy(sd.raw_records(n, 120 + k)).to("cuda")) for k, n in enumerate(sizes)]
+    outs = [torch.full((n, 3), float("nan"), device="cuda") for n in sizes]
+    torch.cuda.synchronize()
+    t_train = srv.submit_train(0, enc_t, tgt)
+    tq = [srv.submit_infer(1, e, o) for e, o in zip(encs, outs)]
+    res = _collect(srv, [t_train] + tq)
+    srv.close()
+    assert all(r["status"] == 0 for r in res)
+    starts = [r["t_start"] for r in res[1:]]
+    assert len(set(starts)) < len(starts), "no two queued queries shared a launch"
+    solo = N.Cache(cfg)
+    solo.set_weights(w[1])
+    for e, o in zip(encs, outs):
+        assert torch.equal(N.nrc_forward(solo, e), o)
+
+
+def test_requests_of_different_caches_overlap_on_the_device(N):
+    # Eight caches, one 16,384-record training step each.  Served one at a
+    # time, the steps take the sum of their solo times; submitted together
+    # they run side by side on the server's streams (each step fills only part
+    # of the GPU), so the makespan is well below that sum.  Every result still
+    # equals its solo replay.
+    cfg = N.make_config(precision="fp16")
+    n_caches = 8
+    w = [sd.glorot_weights(seed=130 + i) for i in range(n_caches)]
+    c0 = N.Cache(cfg)
+    data = []
+    for i in range(n_caches):
+        raw = sd.raw_records(16384, 140 + i)
+        data.append((N.nrc_encode(c0, torch.from_numpy(raw).to("cuda")), torch.from_numpy(sd.targets(raw)).to("cuda")))
+    torch.cuda.synchronize()
+
+    def run(together):
+        srv = N.Server(n_caches, cfg, arena_bytes=1 << 30, n_streams=4, max_inflight=16)
+        for i in range(n_caches):
+            srv.set_weights(i, w[i])
+        for _ in range(3):                           # warm-up: kernels loaded, clocks up
+            _collect(srv, [srv.submit_train(i, *data[i]) for i in range(n_caches)])
+        for i in range(n_caches):
+            srv.set_weights(i, w[i])
+        if together:
+            res = _collect(srv, [srv.submit_train(i, *data[i]) for i in range(n_caches)])
+            span = max(r["t_done"] for r in res) - min(r["t_submit"] for r in res)
+        else:
+            res, span = [], 0.0
+            for i in range(n_caches):
+                r = _collect(srv, [srv.submit_train(i, *data[i])])[0]
+                res.append(r)
+                span += r["t_done"] - r["t_submit"]
+        weights = [srv.get_weights(i) for i in range(n_caches)]
+        srv.close()
+        return res, span, weights
+
+    spans_serial, spans_together = [], []
+    for _ in range(3):
+        res_s, span_s, w_s = run(False)
+        res_t, span_t, w_t = run(True)
+        spans_serial.append(span_s)
+        spans_together.append(span_t)
+        assert [r["loss"] for r in res_s] == [r["loss"] for r in res_t]
+        for a, b in zip(w_s, w_t):
+            assert np.array_equal(a, b)
+    assert min(spans_together) < 0.75 * min(spans_serial), (spans_together, spans_serial)
