@@ -8,7 +8,9 @@ are resident in HBM before the timed region.  The default form is FP32: FP32
 weights, activations and sums, with the layer products on the FP32 matrix cores
 (v_mfma_f32_16x16x4_f32; plain FP32 FMAs would cap at half that rate, since
 packed FP32 is not used).  The FP16 and BF16 matrix-core forms run the same
-frame and are reported under "forms".  Prints one JSON line.
+frame and are reported under "forms", and so is the plain FP32 form with no
+matrix instructions at all (fp32_valu, vector ALUs: the baseline the
+matrix-core forms are compared with).  Prints one JSON line.
 
 Each form first runs frames back to back for --settle-s seconds (the GPU's
 clocks rise over the first tens of milliseconds of sustained load), then W
@@ -41,8 +43,12 @@ TRAIN_BATCH = 16384
 WIDTH, N_HIDDEN = 64, 5
 FLOP_PER_QUERY = 2 * sd.n_params(WIDTH, N_HIDDEN)                 # 41,344
 FLOP_PER_TRAIN_SAMPLE = 2 * (sd.n_params() + (sd.n_params() - 64 * 64) + sd.n_params())  # 115,840
-PEAK_TFLOPS = {"fp32": 157.3, "fp16": 2500.0, "bf16": 2500.0}
-BOUND = {"fp32": "mfma", "fp16": "mfma", "bf16": "mfma"}   # the query pass runs on the matrix cores in every form
+# fp32_valu: plain FP32 FMAs on the vector ALUs without packed FP32, 256 CUs x 4 SIMDs x 16 lanes x 2 FLOP x 2.4 GHz
+PEAK_TFLOPS = {"fp32": 157.3, "fp16": 2500.0, "bf16": 2500.0, "fp32_valu": 78.6}
+BOUND = {"fp32": "mfma", "fp16": "mfma", "bf16": "mfma", "fp32_valu": "alu"}
+QUERY_KERNEL = {"fp32": "k_fwd_raw_fp32", "fp16": "k_fwd_raw_mfma_fixed", "bf16": "k_fwd_raw_mfma_fixed",
+                "fp32_valu": "k_fwd_raw_fp32_valu"}
+MLP_KERNEL = {"fp32": "k_fwd_fp32", "fp16": "k_fwd_mfma", "bf16": "k_fwd_mfma", "fp32_valu": "k_fwd_fp32_valu"}
 HBM_PEAK_GBS = 8000.0
 
 
@@ -160,7 +166,7 @@ def frame_bench(form: str, steps: int, warmup: int, settle_s: float):
 
     t_q = comp[0] * 1e-3
     achieved = N_QUERIES * FLOP_PER_QUERY / t_q / 1e12
-    enc_bytes = 2 if form != "fp32" else 4
+    enc_bytes = 2 if form in ("fp16", "bf16") else 4
     t_fwd = ue[1] * 1e-3
     out = {
         "form": form,
@@ -174,13 +180,13 @@ def frame_bench(form: str, steps: int, warmup: int, settle_s: float):
         "mlp_only_queries_per_s": N_QUERIES / t_fwd,
         "train_only_samples_per_s": N_TRAIN_BATCHES * TRAIN_BATCH / (comp[2] * 1e-3),
         "roofline": {
-            "kernel": "k_fwd_raw_mfma_fixed" if form != "fp32" else "k_fwd_raw_fp32",
+            "kernel": QUERY_KERNEL[form],
             "bound": BOUND[form],
             "achieved": achieved,
             "peak": PEAK_TFLOPS[form],
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_TFLOPS[form],
-            "traffic": measured_traffic("k_fwd_raw_mfma_fixed" if form != "fp32" else "k_fwd_raw_fp32", form),
+            "traffic": measured_traffic(QUERY_KERNEL[form], form),
             "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "flop_per_query": FLOP_PER_QUERY,
             "queries_per_launch": N_QUERIES,
@@ -188,7 +194,7 @@ def frame_bench(form: str, steps: int, warmup: int, settle_s: float):
             "hbm_gbs_algorithmic": N_QUERIES * (56 + 12) / t_q / 1e9,
         },
         "mlp_only_roofline": {
-            "kernel": "k_fwd_mfma" if form != "fp32" else "k_fwd_fp32",
+            "kernel": MLP_KERNEL[form],
             "bound": BOUND[form],
             "achieved": N_QUERIES * FLOP_PER_QUERY / t_fwd / 1e12,
             "peak": PEAK_TFLOPS[form],
@@ -398,7 +404,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--settle-s", type=float, default=0.5,
                     help="seconds of back-to-back frames before the warm-up steps (clocks settle)")
-    ap.add_argument("--form", default="fp32", choices=["fp32", "fp16", "bf16"])
+    ap.add_argument("--form", default="fp32", choices=["fp32", "fp16", "bf16", "fp32_valu"])
     ap.add_argument("--no-forms", action="store_true", help="skip the other precision forms")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
@@ -428,7 +434,7 @@ def main():
     main_res = frame_bench(args.form, args.steps, args.warmup, args.settle_s)
     forms = {}
     if not args.no_forms:
-        for f in ("fp32", "fp16", "bf16"):
+        for f in ("fp32", "fp16", "bf16", "fp32_valu"):
             if f == args.form:
                 continue
             log(f"frame bench: form {f}")
@@ -439,10 +445,10 @@ def main():
         mix = serve_bench("fp16", args.serve_requests, serial=False, loads=(0.5, 0.8, 0.95))
         log("serving: 8 caches, fp16, 512 MB arena (admission by memory binds)")
         small = serve_bench("fp16", args.serve_requests, serial=False, loads=(0.8,), arena=512 << 20)
-        log("serving: serial plain fp32, same trace and offered load")
-        ser = serve_bench("fp32", args.serve_requests, serial=True, loads=(0.8,),
+        log("serving: serial plain fp32 (vector ALUs), same trace and offered load")
+        ser = serve_bench("fp32_valu", args.serve_requests, serial=True, loads=(0.8,),
                           capacity_rps=mix["capacity"]["requests_per_s"])
-        serve = {"continuous_fp16": mix, "continuous_fp16_512mb_arena": small, "serial_fp32": ser,
+        serve = {"continuous_fp16": mix, "continuous_fp16_512mb_arena": small, "serial_fp32_valu": ser,
                  "p50_ms": mix["p50_ms"], "p99_ms": mix["p99_ms"]}
     cpu = None
     if not args.no_cpu_baseline:
@@ -460,7 +466,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp32": "f32", "fp16": "f16", "bf16": "bf16"}[args.form],
+        "dtype": {"fp32": "f32", "fp16": "f16", "bf16": "bf16", "fp32_valu": "f32"}[args.form],
         "data": "synthetic",
         "config": {"workload": f"1920x1080 frame: {N_QUERIES} queries (encode + inference) and "
                                f"{N_TRAIN_BATCHES}x{TRAIN_BATCH}-record training steps, {args.form} form",
@@ -469,7 +475,8 @@ def main():
                    "products": {"fp32": "FP32 weights and activations on the FP32 matrix cores "
                                         "(v_mfma_f32_16x16x4_f32), not the vector ALUs",
                                 "fp16": "FP16 matrix cores, FP32 accumulation",
-                                "bf16": "BF16 matrix cores, FP32 accumulation"}[args.form]},
+                                "bf16": "BF16 matrix cores, FP32 accumulation",
+                                "fp32_valu": "FP32 on the vector ALUs, no matrix instructions"}[args.form]},
         "train_samples_per_s": main_res["train_samples_per_s"],
         "components_ms": main_res["components_ms"],
         "unfused_ms": main_res["unfused_ms"],

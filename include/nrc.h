@@ -49,6 +49,8 @@ extern "C" {
 #define NRC_FP32 0 /* FP32 products and sums (FP32 matrix cores), FP32 encoded input */
 #define NRC_FP16 1 /* FP16 matrix-core products, FP32 accumulation and master weights */
 #define NRC_BF16 2 /* BF16 matrix-core products, FP32 accumulation and master weights */
+#define NRC_FP32_VALU 3 /* FP32 products and sums on the vector ALUs only, no matrix instructions: the
+                           plain FP32 baseline (width 64, n_hidden <= 6; no activation buffer) */
 
 /* Input encoding presets (Sec. 3.6, Table "parameters"). */
 #define NRC_PRESET_CONFIG 0 /* 6 octaves sin+cos, roughness as is, zero pad */
@@ -67,7 +69,7 @@ extern "C" {
 /*
  * Cache configuration.  Architecture of Sec. 5: `n_hidden` hidden layers of
  * `width` ReLU neurons, no biases, a linear output of `n_out` (= 3, RGB).
- * Supported: width 64 or 128 (FP32: 64 only); n_hidden 1..8; n_out 3.
+ * Supported: width 64 or 128 (FP32 forms: 64 only); n_hidden 1..8 (FP32 forms: 1..6); n_out 3.
  * Adam (Sec. 5 Optimizer): lr, beta1, beta2, adam_eps; loss_eps is the eps of
  * Eq. 5; loss_scale multiplies the loss gradient before the reduced-precision
  * backward pass and is divided out before Adam (use 1 for FP32).
@@ -82,7 +84,7 @@ typedef struct nrc_config {
     int32_t width;
     int32_t n_hidden;
     int32_t n_out;
-    int32_t precision;  /* NRC_FP32 / NRC_FP16 / NRC_BF16 */
+    int32_t precision;  /* NRC_FP32 / NRC_FP16 / NRC_BF16 / NRC_FP32_VALU */
     int32_t enc_preset; /* NRC_PRESET_* */
     float lr;
     float beta1;
@@ -341,6 +343,22 @@ int nrc_train_frame_indexed(nrc_cache* cache, const void* enc, const float* targ
 int nrc_self_training_targets(const float* radiance, const float* throughput, const float* tail_rgb,
                               const int32_t* tail_index, int64_t n, int64_t n_tail, float* target,
                               void* stream);
+
+/*
+ * Validation: per-channel error norms of a batch of predictions against
+ * reference values, reduced in FP64 on the device (the inputs of the
+ * per-channel relative errors of the precision forms, normwise in the L2 and
+ * the max norm).  got: device FP32 [n][3]; ref: device FP64 [n][3]; out:
+ * device FP64 [3][4] with, for channel c,
+ *   out[c][0] = sum_i (got_ic - ref_ic)^2,  out[c][1] = sum_i ref_ic^2,
+ *   out[c][2] = max_i |got_ic - ref_ic|,    out[c][3] = max_i |ref_ic|.
+ * scratch: device, 8-byte aligned, nrc_error_norms_scratch_bytes(n) bytes.
+ * The summation order is fixed, so the result is bitwise reproducible.
+ * n in [1, 2^40).
+ */
+size_t nrc_error_norms_scratch_bytes(int64_t n);
+int nrc_error_norms(const float* got, const double* ref, int64_t n, void* scratch, size_t scratch_bytes,
+                    double* out, void* stream);
 
 /* ------------------------------------------------------------------------- */
 /* Serving: continuous batching of inference and training requests over     */

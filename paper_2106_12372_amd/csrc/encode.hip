@@ -83,7 +83,8 @@ hipError_t dispatch_encode(int preset, int layout, const float* raw, int64_t n, 
 hipError_t launch_encode(int precision, int preset, int layout, const float* raw, int64_t n,
                          void* enc, hipStream_t s) {
     switch (precision) {
-        case NRC_FP32: return dispatch_encode<float>(preset, layout, raw, n, (float*)enc, s);
+        case NRC_FP32:
+        case NRC_FP32_VALU: return dispatch_encode<float>(preset, layout, raw, n, (float*)enc, s);
         case NRC_FP16: return dispatch_encode<_Float16>(preset, layout, raw, n, (_Float16*)enc, s);
         default: return dispatch_encode<__bf16>(preset, layout, raw, n, (__bf16*)enc, s);
     }

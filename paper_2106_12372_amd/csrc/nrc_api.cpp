@@ -51,14 +51,15 @@ int validate_config(const nrc_config* c) {
     if (c->width != 64 && c->width != 128) return fail(NRC_EINVAL, "width must be 64 or 128 (got %d)", c->width);
     if (c->n_hidden < 1 || c->n_hidden > 8) return fail(NRC_EINVAL, "n_hidden must be in 1..8 (got %d)", c->n_hidden);
     if (c->n_out != 3) return fail(NRC_EINVAL, "n_out must be 3 (got %d)", c->n_out);
-    if (c->precision != NRC_FP32 && c->precision != NRC_FP16 && c->precision != NRC_BF16)
+    if (c->precision != NRC_FP32 && c->precision != NRC_FP16 && c->precision != NRC_BF16 &&
+        c->precision != NRC_FP32_VALU)
         return fail(NRC_EINVAL, "unknown precision %d", c->precision);
     if (c->enc_preset != NRC_PRESET_CONFIG && c->enc_preset != NRC_PRESET_PAPER &&
         c->enc_preset != NRC_PRESET_PAPER_TRI && c->enc_preset != NRC_PRESET_PAPER_GAUSS)
         return fail(NRC_EINVAL, "unknown encoding preset %d", c->enc_preset);
-    if (c->precision == NRC_FP32 && (c->width != 64 || c->n_hidden > 6))
-        return fail(NRC_EINVAL, "the FP32 form supports width 64 and n_hidden <= 6");
-    if (c->precision != NRC_FP32 && c->width == 128 && c->n_hidden > 5)
+    if (fp32_form(c->precision) && (c->width != 64 || c->n_hidden > 6))
+        return fail(NRC_EINVAL, "the FP32 forms support width 64 and n_hidden <= 6");
+    if (!fp32_form(c->precision) && c->width == 128 && c->n_hidden > 5)
         return fail(NRC_EINVAL, "width 128 supports n_hidden <= 5");
     if (!(c->lr > 0.0f) || !std::isfinite(c->lr)) return fail(NRC_EINVAL, "lr must be positive");
     if (!(c->beta1 >= 0.0f && c->beta1 < 1.0f) || !(c->beta2 >= 0.0f && c->beta2 < 1.0f))
@@ -81,7 +82,7 @@ CacheLayout cache_layout(const nrc_config& c) {
     L.m = take(P * 4);
     L.v = take(P * 4);
     L.t = take(16);
-    if (c.precision != NRC_FP32) {
+    if (!fp32_form(c.precision)) {
         L.ffr = take((size_t)d.n_fwd_frags() * kFragElems * 2);
         L.bfr = take((size_t)d.n_bwd_frags() * kFragElems * 2);
     } else {
@@ -91,7 +92,7 @@ CacheLayout cache_layout(const nrc_config& c) {
     if (c.ema_alpha > 0.0f) {
         L.e = take(P * 4);
         L.wbar = take(P * 4);
-        if (c.precision != NRC_FP32) L.effr = take((size_t)d.n_fwd_frags() * kFragElems * 2);
+        if (!fp32_form(c.precision)) L.effr = take((size_t)d.n_fwd_frags() * kFragElems * 2);
     }
     L.total = off;
     return L;
@@ -123,7 +124,7 @@ ScratchLayout scratch_layout(const nrc_config& c, int64_t n) {
 size_t act_layout(const nrc_config& c, int64_t n) {
     const int ts = train_tile(c.precision, c.width);
     const size_t tiles = (size_t)((n + ts - 1) / ts);
-    const size_t elem = c.precision == NRC_FP32 ? 4 : 2;
+    const size_t elem = fp32_form(c.precision) ? 4 : 2;
     return tiles * (size_t)c.n_hidden * (size_t)c.width * (size_t)ts * elem + tiles * (size_t)ts * 16;
 }
 
@@ -147,7 +148,10 @@ int enqueue_train_step(nrc_cache* c, const void* enc, const float* target, const
     const float scale = cfg.loss_scale;
     const float grad_scale = (float)((double)scale / (3.0 * (double)n));
     hipError_t e;
-    if (cfg.precision == NRC_FP32)
+    if (cfg.precision == NRC_FP32_VALU)
+        e = launch_train_fp32_valu(d, c->w(), (const float*)enc, target, idx, n, false, cfg.loss_eps, grad_scale,
+                                   partials, loss_part, tile_bad, nullptr, s, lg);
+    else if (cfg.precision == NRC_FP32)
         e = launch_train_fp32(d, c->w(), (const float*)enc, target, idx, n, false, cfg.loss_eps, grad_scale,
                               partials, loss_part, tile_bad, nullptr, s, nullptr, lg);
     else
@@ -158,7 +162,7 @@ int enqueue_train_step(nrc_cache* c, const void* enc, const float* target, const
     int32_t* skipped_out = skipped_dev ? skipped_dev : (int32_t*)(scratch + sl.skipped);
     const AdamHyper hp{cfg.lr, cfg.beta1, cfg.beta2, cfg.adam_eps};
     const EmaArgs ema{c->ema() ? cfg.ema_alpha : 0.0f, c->e(), c->wbar(), c->effr()};
-    e = launch_reduce_adam(cfg.precision, d, cfg.precision != NRC_FP32, partials, (int)sl.tiles,
+    e = launch_reduce_adam(cfg.precision, d, !fp32_form(cfg.precision), partials, (int)sl.tiles,
                            tile_bad, loss_part, (float)(1.0 / (3.0 * (double)n)), loss_out,
                            1.0f / scale, c->w(), c->m(), c->v(), c->tslots(), c->parity, hp, ema,
                            skipped_out, c->ffr(), c->bfr(), s);
@@ -170,7 +174,9 @@ int enqueue_train_step(nrc_cache* c, const void* enc, const float* target, const
 int enqueue_forward(nrc_cache* c, const void* enc, int64_t n, float* rgb, hipStream_t s) {
     const Geo d = kernel_geo(c->cfg);
     hipError_t e;
-    if (c->cfg.precision == NRC_FP32)
+    if (c->cfg.precision == NRC_FP32_VALU)
+        e = launch_fwd_fp32_valu(d, c->query_w(), (const float*)enc, n, rgb, s);
+    else if (c->cfg.precision == NRC_FP32)
         e = launch_fwd_fp32(d, c->query_w(), (const float*)enc, n, rgb, s);
     else
         e = launch_fwd_mfma(c->cfg.precision, d, c->query_ffr(), enc, n, rgb, s);
@@ -228,7 +234,7 @@ size_t nrc_train_scratch_bytes(const nrc_config* cfg, int64_t n) {
 int nrc_enc_elem_bytes(const nrc_config* cfg) {
     if (validate_config(cfg) != NRC_OK) return NRC_EINVAL;
     ok();
-    return cfg->precision == NRC_FP32 ? 4 : 2;
+    return fp32_form(cfg->precision) ? 4 : 2;
 }
 
 int nrc_cache_create(const nrc_config* cfg, void* dev_ws, size_t ws_bytes, void* stream,
@@ -284,7 +290,7 @@ static hipError_t reset_ema_and_frags(nrc_cache* c, hipStream_t s) {
         e = hipMemsetAsync(c->e(), 0, bytes, s);
         if (e == hipSuccess) e = hipMemcpyAsync(c->wbar(), c->w(), bytes, hipMemcpyDeviceToDevice, s);
     }
-    if (e == hipSuccess && c->cfg.precision != NRC_FP32) {
+    if (e == hipSuccess && !fp32_form(c->cfg.precision)) {
         e = hipMemsetAsync(c->ffr(), 0, (size_t)d.n_fwd_frags() * kFragElems * 2, s);
         if (e == hipSuccess) e = hipMemsetAsync(c->bfr(), 0, (size_t)d.n_bwd_frags() * kFragElems * 2, s);
         if (e == hipSuccess && c->ema())
@@ -400,7 +406,7 @@ int nrc_set_ema(nrc_cache* cache, const float* host_w_bar, const float* host_e, 
     const size_t bytes = (size_t)d.n_params() * 4;
     hipError_t e = hipMemcpyAsync(cache->wbar(), host_w_bar, bytes, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(cache->e(), host_e, bytes, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess && cache->cfg.precision != NRC_FP32)
+    if (e == hipSuccess && !fp32_form(cache->cfg.precision))
         e = launch_build_frags(cache->cfg.precision, d, cache->wbar(), cache->effr(), nullptr, nullptr, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return device_fail(e, "EMA upload");
@@ -442,7 +448,10 @@ int nrc_forward_raw(nrc_cache* cache, const float* raw, int raw_layout, int64_t 
     if (!aligned16(raw) || ((uintptr_t)rgb & 3)) return fail(NRC_EINVAL, "misaligned buffer");
     const Geo d = kernel_geo(cache->cfg);
     hipError_t e;
-    if (cache->cfg.precision == NRC_FP32)
+    if (cache->cfg.precision == NRC_FP32_VALU)
+        e = launch_fwd_raw_fp32_valu(d, cache->cfg.enc_preset, raw_layout, cache->query_w(), raw, n, rgb,
+                                     (hipStream_t)stream);
+    else if (cache->cfg.precision == NRC_FP32)
         e = launch_fwd_raw_fp32(d, cache->cfg.enc_preset, raw_layout, cache->query_w(), raw, n, rgb,
                                 (hipStream_t)stream);
     else
@@ -484,6 +493,8 @@ int nrc_forward_train(nrc_cache* cache, const void* enc, int64_t n, void* act_ws
     if (n == 0) return ok();
     if (!enc || !act_ws || !rgb) return fail(NRC_EINVAL, "NULL buffer");
     if (!aligned16(enc) || !aligned16(act_ws) || ((uintptr_t)rgb & 3)) return fail(NRC_EINVAL, "misaligned buffer");
+    if (cache->cfg.precision == NRC_FP32_VALU)
+        return fail(NRC_EINVAL, "the vector-ALU FP32 form keeps no activation buffer (use nrc_forward)");
     const size_t need = act_layout(cache->cfg, n);
     if (act_bytes < need)
         return fail(NRC_ENOMEM, "activation buffer of %zu bytes is smaller than the %zu bytes needed", act_bytes, need);
@@ -520,15 +531,20 @@ int nrc_backward(nrc_cache* cache, const void* enc, const void* act_ws, const fl
     // pass rounds it to FP16/BF16 and unscaled after the sums (a mean-reduced
     // loss over 2^16 records gives dL/dy near 1e-5, where FP16 is subnormal)
     const float scale = cfg.loss_scale;
+    if (act_ws && cfg.precision == NRC_FP32_VALU)
+        return fail(NRC_EINVAL, "the vector-ALU FP32 form keeps no activation buffer (pass NULL)");
     hipError_t e;
-    if (cfg.precision == NRC_FP32)
+    if (cfg.precision == NRC_FP32_VALU)
+        e = launch_train_fp32_valu(d, cache->w(), (const float*)enc, grad_rgb, nullptr, n, true, cfg.loss_eps,
+                                   scale, partials, loss_part, tile_bad, grad_enc, s);
+    else if (cfg.precision == NRC_FP32)
         e = launch_train_fp32(d, cache->w(), (const float*)enc, grad_rgb, nullptr, n, true, cfg.loss_eps, scale,
                               partials, loss_part, tile_bad, grad_enc, s, (const float*)act_ws);
     else
         e = launch_train_mfma(cfg.precision, d, cache->ffr(), cache->bfr(), enc, grad_rgb, nullptr, n, true,
                               cfg.loss_eps, scale, partials, loss_part, tile_bad, grad_enc, s, act_ws);
     if (e != hipSuccess) return device_fail(e, "backward kernel launch");
-    e = launch_reduce(d, cfg.precision != NRC_FP32, partials, (int)sl.tiles, 1.0f / scale, grad_w, loss_part,
+    e = launch_reduce(d, !fp32_form(cfg.precision), partials, (int)sl.tiles, 1.0f / scale, grad_w, loss_part,
                       1.0f, nullptr, s);
     if (e != hipSuccess) return device_fail(e, "gradient reduction launch");
     return ok();
@@ -703,6 +719,26 @@ int nrc_self_training_targets(const float* radiance, const float* throughput, co
     const hipError_t e = launch_self_train(radiance, throughput, tail_rgb, tail_index, n, n_tail, target,
                                            (hipStream_t)stream);
     if (e != hipSuccess) return device_fail(e, "self-training target launch");
+    return ok();
+}
+
+size_t nrc_error_norms_scratch_bytes(int64_t n) {
+    if (n < 0) { fail(NRC_EINVAL, "n must be >= 0"); return 0; }
+    ok();
+    return error_norms_scratch_bytes();
+}
+
+int nrc_error_norms(const float* got, const double* ref, int64_t n, void* scratch, size_t scratch_bytes,
+                    double* out, void* stream) {
+    if (n < 1 || n >= ((int64_t)1 << 40)) return fail(NRC_EINVAL, "n must be in [1, 2^40)");
+    if (!got || !ref || !scratch || !out) return fail(NRC_EINVAL, "NULL buffer");
+    if (((uintptr_t)got & 3) || ((uintptr_t)ref & 7) || ((uintptr_t)scratch & 7) || ((uintptr_t)out & 7))
+        return fail(NRC_EINVAL, "misaligned buffer");
+    if (scratch_bytes < error_norms_scratch_bytes())
+        return fail(NRC_ENOMEM, "scratch of %zu bytes is smaller than the %zu bytes needed", scratch_bytes,
+                    error_norms_scratch_bytes());
+    const hipError_t e = launch_error_norms(got, ref, n, (double*)scratch, out, (hipStream_t)stream);
+    if (e != hipSuccess) return device_fail(e, "error-norm launch");
     return ok();
 }
 

@@ -46,12 +46,12 @@ struct nrc_cache {
     float* m() { return (float*)(ws + lay.m); }
     float* v() { return (float*)(ws + lay.v); }
     int32_t* tslots() { return (int32_t*)(ws + lay.t); }
-    void* ffr() { return cfg.precision == NRC_FP32 ? nullptr : (void*)(ws + lay.ffr); }
-    void* bfr() { return cfg.precision == NRC_FP32 ? nullptr : (void*)(ws + lay.bfr); }
+    void* ffr() { return nrc::fp32_form(cfg.precision) ? nullptr : (void*)(ws + lay.ffr); }
+    void* bfr() { return nrc::fp32_form(cfg.precision) ? nullptr : (void*)(ws + lay.bfr); }
     bool ema() const { return cfg.ema_alpha > 0.0f; }
     float* e() { return ema() ? (float*)(ws + lay.e) : nullptr; }
     float* wbar() { return ema() ? (float*)(ws + lay.wbar) : nullptr; }
-    void* effr() { return (ema() && cfg.precision != NRC_FP32) ? (void*)(ws + lay.effr) : nullptr; }
+    void* effr() { return (ema() && !nrc::fp32_form(cfg.precision)) ? (void*)(ws + lay.effr) : nullptr; }
     // Weights the query entry points use: the EMA set when it is kept.
     const float* query_w() { return ema() ? wbar() : w(); }
     const void* query_ffr() { return ema() ? effr() : ffr(); }

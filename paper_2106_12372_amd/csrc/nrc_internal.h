@@ -22,10 +22,15 @@ constexpr int kAlbedoColPaper = 56;
 __host__ __device__ inline int albedo_col(int preset) {
     return preset == NRC_PRESET_CONFIG ? kAlbedoColConfig : kAlbedoColPaper;
 }
+// The two FP32 forms (matrix cores, vector ALUs): FP32 encoded input, no
+// reduced-precision weight copies, row-major weight-gradient partials.
+__host__ __device__ inline bool fp32_form(int precision) {
+    return precision == NRC_FP32 || precision == NRC_FP32_VALU;
+}
 // Training records per workgroup tile: 64, except 32 for the width-128
 // matrix-core form (its activations and deltas must fit in LDS).
 __host__ __device__ inline int train_tile(int precision, int width) {
-    return (precision != NRC_FP32 && width == 128) ? 32 : 64;
+    return (!fp32_form(precision) && width == 128) ? 32 : 64;
 }
 
 // One matrix-core operand fragment: 64 lanes x 8 16-bit elements.
@@ -214,6 +219,15 @@ hipError_t launch_fwd_train_fp32(const Geo& d, const float* w, const float* enc,
                                  float* rgb, hipStream_t s);
 hipError_t launch_fwd_raw_fp32(const Geo& d, int preset, int layout, const float* w, const float* raw,
                                int64_t n, float* rgb, hipStream_t s);
+// mlp_fp32_valu.hip (NRC_FP32_VALU: vector ALUs only)
+hipError_t launch_fwd_fp32_valu(const Geo& d, const float* w, const float* enc, int64_t n, float* rgb,
+                                hipStream_t s);
+hipError_t launch_fwd_raw_fp32_valu(const Geo& d, int preset, int layout, const float* w, const float* raw,
+                                    int64_t n, float* rgb, hipStream_t s);
+hipError_t launch_train_fp32_valu(const Geo& d, const float* w, const float* enc, const float* tgt,
+                                  const int32_t* idx, int64_t n, bool upstream, float loss_eps, float grad_scale,
+                                  float* partials, float* loss_part, int32_t* tile_bad, float* genc,
+                                  hipStream_t s, LcgGather lg = LcgGather{});
 // mlp_mfma.hip
 hipError_t launch_fwd_raw_mfma(int precision, const Geo& d, int preset, int layout, const void* ffr,
                                const float* raw, int64_t n, float* rgb, hipStream_t s);
@@ -260,6 +274,10 @@ hipError_t launch_shuffle(int64_t n, uint64_t seed, int32_t* perm, int32_t* coun
 hipError_t launch_self_train(const float* radiance, const float* throughput, const float* tail_rgb,
                              const int32_t* tail_index, int64_t n, int64_t n_tail, float* target,
                              hipStream_t s);
+// validate.hip: per-channel error norms in FP64 (out[3][4], see nrc.h).
+size_t error_norms_scratch_bytes();
+hipError_t launch_error_norms(const float* got, const double* ref, int64_t n, double* scratch, double* out,
+                              hipStream_t s);
 // Writes W's forward fragments to ffr and ffr2 (each may be NULL) and its
 // backward fragments to bfr (may be NULL).
 hipError_t launch_build_frags(int precision, const Geo& d, const float* w, void* ffr, void* bfr,

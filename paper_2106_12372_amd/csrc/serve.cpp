@@ -278,7 +278,7 @@ void nrc_server::retire(std::unique_lock<std::mutex>&) {
 
 void nrc_server::run() {
     (void)hipSetDevice(device);
-    const bool segments = cfg.cache_cfg.precision != NRC_FP32;   // multi-segment launches (matrix-core forms)
+    const bool segments = !fp32_form(cfg.cache_cfg.precision);   // multi-segment launches (matrix-core forms)
     std::unique_lock<std::mutex> lk(mu);
     while (true) {
         if (stop && pending.empty() && inflight.empty()) break;

@@ -23,13 +23,13 @@ lib = ctypes.CDLL(_LIB_PATH)
 
 # Status codes, precisions, presets and layouts (same values as nrc.h).
 NRC_OK, NRC_PENDING, NRC_EINVAL, NRC_ENOMEM, NRC_EDEVICE, NRC_EBUSY, NRC_ENOTFOUND = 0, 1, -1, -2, -3, -4, -5
-NRC_FP32, NRC_FP16, NRC_BF16 = 0, 1, 2
+NRC_FP32, NRC_FP16, NRC_BF16, NRC_FP32_VALU = 0, 1, 2, 3
 NRC_PRESET_CONFIG, NRC_PRESET_PAPER, NRC_PRESET_PAPER_TRI, NRC_PRESET_PAPER_GAUSS = 0, 1, 2, 3
 NRC_RAW14, NRC_RAW16 = 0, 1
 NRC_REQ_INFER, NRC_REQ_TRAIN = 0, 1
 ENC_WIDTH = 64
 NRC_NOALLOC_SCRATCH_BYTES = 48 << 20   # the fixed scratch array of nrc_train_step_noalloc
-PRECISIONS = {"fp32": NRC_FP32, "fp16": NRC_FP16, "bf16": NRC_BF16}
+PRECISIONS = {"fp32": NRC_FP32, "fp16": NRC_FP16, "bf16": NRC_BF16, "fp32_valu": NRC_FP32_VALU}
 
 
 class NrcError(RuntimeError):
@@ -105,6 +105,8 @@ _decl("nrc_frame_scratch_bytes", c_size_t, POINTER(nrc_config), c_int64, c_int, 
 _decl("nrc_train_frame", c_int, _P, _P, _P, c_int64, c_int, c_int64, c_uint64, _P, c_size_t, _P, _P, _P)
 _decl("nrc_train_frame_indexed", c_int, _P, _P, _P, _P, c_int64, c_int, c_int64, _P, c_size_t, _P, _P, _P)
 _decl("nrc_self_training_targets", c_int, _P, _P, _P, _P, c_int64, c_int64, _P, _P)
+_decl("nrc_error_norms_scratch_bytes", c_size_t, c_int64)
+_decl("nrc_error_norms", c_int, _P, _P, c_int64, _P, c_size_t, _P, _P)
 _decl("nrc_serve_create", c_int, POINTER(nrc_serve_config), POINTER(_P))
 _decl("nrc_serve_set_weights", c_int, _P, c_int, POINTER(c_float), c_int64)
 _decl("nrc_serve_get_weights", c_int, _P, c_int, POINTER(c_float), c_int64)
@@ -119,7 +121,7 @@ EXPORTED = ["nrc_config_default", "nrc_last_error", "nrc_param_count", "nrc_cach
             "nrc_get_state", "nrc_set_state", "nrc_get_ema", "nrc_set_ema", "nrc_encode", "nrc_forward", "nrc_forward_raw", "nrc_train_step",
             "nrc_train_step_noalloc",
             "nrc_act_ws_bytes", "nrc_forward_train", "nrc_backward", "nrc_shuffle_scratch_bytes", "nrc_shuffle", "nrc_train_step_indexed",
-            "nrc_frame_scratch_bytes", "nrc_train_frame", "nrc_train_frame_indexed", "nrc_self_training_targets", "nrc_serve_create", "nrc_serve_set_weights", "nrc_serve_get_weights",
+            "nrc_frame_scratch_bytes", "nrc_train_frame", "nrc_train_frame_indexed", "nrc_self_training_targets", "nrc_error_norms_scratch_bytes", "nrc_error_norms", "nrc_serve_create", "nrc_serve_set_weights", "nrc_serve_get_weights",
             "nrc_serve_submit", "nrc_serve_poll", "nrc_serve_drain", "nrc_serve_destroy"]
 
 
@@ -145,7 +147,7 @@ def make_config(width: int = 64, n_hidden: int = 5, precision="fp16", enc_preset
     prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     cfg.width, cfg.n_hidden, cfg.precision, cfg.enc_preset = width, n_hidden, prec, enc_preset
     cfg.lr, cfg.beta1, cfg.beta2, cfg.adam_eps, cfg.loss_eps = lr, beta1, beta2, adam_eps, loss_eps
-    cfg.loss_scale = (1.0 if prec == NRC_FP32 else 128.0) if loss_scale is None else loss_scale
+    cfg.loss_scale = (1.0 if prec in (NRC_FP32, NRC_FP32_VALU) else 128.0) if loss_scale is None else loss_scale
     cfg.ema_alpha = ema_alpha
     cfg.factorize = 1 if factorize else 0
     return cfg
@@ -158,7 +160,8 @@ def _torch():
 
 def enc_dtype(cfg: nrc_config):
     torch = _torch()
-    return {NRC_FP32: torch.float32, NRC_FP16: torch.float16, NRC_BF16: torch.bfloat16}[cfg.precision]
+    return {NRC_FP32: torch.float32, NRC_FP16: torch.float16, NRC_BF16: torch.bfloat16,
+            NRC_FP32_VALU: torch.float32}[cfg.precision]
 
 
 def _stream(stream) -> c_void_p:
@@ -525,6 +528,23 @@ def nrc_backward(cache: Cache, enc, grad_rgb, want_grad_enc: bool = True, act=No
     check(lib.nrc_backward(cache.handle, _ptr(enc), _ptr(act), _ptr(grad_rgb), n, _ptr(sc), size, _ptr(grad_w),
                            _ptr(grad_enc), _stream(stream)))
     return grad_w, grad_enc
+
+
+def nrc_error_norms(got, ref, stream=None):
+    """Per-channel error norms of got [n][3] (FP32) against ref [n][3] (FP64),
+    reduced in FP64 on the device: a [3][4] FP64 tensor of (sum (got-ref)^2,
+    sum ref^2, max |got-ref|, max |ref|) per channel."""
+    torch = _torch()
+    _need(got, torch.float32, (3,), "got")
+    _need(ref, torch.float64, (3,), "ref")
+    n = got.shape[0]
+    if ref.shape[0] != n:
+        raise ValueError("got and ref differ in length")
+    sc = torch.empty(lib.nrc_error_norms_scratch_bytes(n) // 8, dtype=torch.float64, device=got.device)
+    out = torch.empty((3, 4), dtype=torch.float64, device=got.device)
+    _keep(stream, sc, out)
+    check(lib.nrc_error_norms(_ptr(got), _ptr(ref), n, _ptr(sc), sc.numel() * 8, _ptr(out), _stream(stream)))
+    return out
 
 
 # ---------------------------------------------------------------------------

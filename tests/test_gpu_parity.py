@@ -701,3 +701,22 @@ def test_ema_checkpoint_resume_and_skip(N):
     run(d, [1], bad=1)
     for x, z in zip(before, d.get_ema()):
         assert np.array_equal(x, z)
+
+
+# ---------------------------------------------------------------------------
+# FP64 validation reduction on the device
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n", [1, 255, 1000, 2073601])
+def test_error_norms_match_numpy(N, n):
+    rng = np.random.Generator(np.random.PCG64(900 + n))
+    ref = rng.standard_normal((n, 3)) * np.array([1.0, 1e-3, 1e3])
+    got = (ref * (1.0 + 1e-3 * rng.standard_normal((n, 3)))).astype(np.float32)
+    out = N.nrc_error_norms(dev(got), torch.from_numpy(ref).to("cuda")).cpu().numpy()
+    d = got.astype(np.float64) - ref
+    assert np.allclose(out[:, 0], (d * d).sum(axis=0), rtol=1e-12)
+    assert np.allclose(out[:, 1], (ref * ref).sum(axis=0), rtol=1e-12)
+    assert np.array_equal(out[:, 2], np.abs(d).max(axis=0))
+    assert np.array_equal(out[:, 3], np.abs(ref).max(axis=0))
+    # fixed order: bitwise reproducible
+    again = N.nrc_error_norms(dev(got), torch.from_numpy(ref).to("cuda")).cpu().numpy()
+    assert np.array_equal(out, again)

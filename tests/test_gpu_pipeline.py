@@ -147,10 +147,15 @@ def test_train_frame_matches_oracle_frame(N, prec):
     assert skipped.cpu().tolist() == [0, 0, 0, 0] and not any(ref_skips)
     got_l = losses.cpu().numpy()
     assert np.all(np.abs(got_l - ref_losses) <= 1e-2 * np.abs(ref_losses)), (got_l, ref_losses)
-    got = N.nrc_forward(c, q).cpu().numpy()
+    got_d = N.nrc_forward(c, q)
+    got = got_d.cpu().numpy()
     ref = O.predict(st, q64)
     e2, em = l2_err(got, ref), O.channel_rel_error(got, ref)
     print(f"{prec} frame, 65,536 held-out queries: per-channel L2 {e2}, max {em}")
+    # the same errors from the device's FP64 validation reduction
+    nrm = N.nrc_error_norms(got_d, torch.from_numpy(ref).to("cuda")).cpu().numpy()
+    assert np.allclose(np.sqrt(nrm[:, 0] / nrm[:, 1]), e2, rtol=1e-12)
+    assert np.array_equal(nrm[:, 2] / nrm[:, 3], em)
     # L2 within 1e-2 in both formats.  The max-normwise error of BF16 (unit
     # roundoff 2^-8) reaches 1.14e-2 in the rounding model, which carries out
     # this frame with exactly the kernels' roundings: that is the format's own
