@@ -596,6 +596,21 @@ __global__ __launch_bounds__(256) void k_train_mfma(const T* __restrict__ ffr,
     float* part = partials + tile * (int64_t)P;
     const V* gf = reinterpret_cast<const V*>(ffr) + lane;
     const V* gb = reinterpret_cast<const V*>(bfr) + lane;
+    // A product with a weight operand: the fragment at f[i] (hi), and in the
+    // BF16 form also its lo part, one fragment set further on (the pair carries
+    // the weight to ~16 significant bits; both operands are BF16).
+    constexpr bool SPLIT = __is_same(T, __bf16);
+    const int lo_f = geo.n_fwd_frags() * 64, lo_b = geo.n_bwd_frags() * 64;
+    auto wf = [&](const V* f, int i, const V& bop, f32x4 c) {
+        c = mfma(f[i], bop, c);
+        if (SPLIT) c = mfma(f[i + lo_f], bop, c);
+        return c;
+    };
+    auto wb = [&](const V* f, int i, const V& bop, f32x4 c) {
+        c = mfma(f[i], bop, c);
+        if (SPLIT) c = mfma(f[i + lo_b], bop, c);
+        return c;
+    };
 
     // Scatter a chained-order operand (features of chunk c) into a [feature][record] store.
     auto put = [&](T* base, const V& v, int c) {
@@ -640,12 +655,12 @@ __global__ __launch_bounds__(256) void k_train_mfma(const T* __restrict__ ffr,
         const V* fl = gf + geo.fwd_base(l) * 64;
         f32x4 acc[MB];
         #pragma unroll
-        for (int mb = 0; mb < MB; ++mb) acc[mb] = mfma(fl[(mb * kc) * 64], b[0], f32x4{0.f, 0.f, 0.f, 0.f});
+        for (int mb = 0; mb < MB; ++mb) acc[mb] = wf(fl, (mb * kc) * 64, b[0], f32x4{0.f, 0.f, 0.f, 0.f});
         #pragma unroll
         for (int c = 1; c < KC; ++c) {
             if (c >= kc) break;
             #pragma unroll
-            for (int mb = 0; mb < MB; ++mb) acc[mb] = mfma(fl[(mb * kc + c) * 64], b[c], acc[mb]);
+            for (int mb = 0; mb < MB; ++mb) acc[mb] = wf(fl, (mb * kc + c) * 64, b[c], acc[mb]);
         }
         T* ho = hrow(l + 1);
         #pragma unroll
@@ -664,9 +679,9 @@ __global__ __launch_bounds__(256) void k_train_mfma(const T* __restrict__ ffr,
         __syncthreads();
     } else {
         const V* fo = gf + geo.fwd_base(n_hidden) * 64;
-        y = mfma(fo[0], b[0], f32x4{0.f, 0.f, 0.f, 0.f});
+        y = wf(fo, 0, b[0], f32x4{0.f, 0.f, 0.f, 0.f});
         #pragma unroll
-        for (int c = 1; c < KC; ++c) y = mfma(fo[c * 64], b[c], y);
+        for (int c = 1; c < KC; ++c) y = wf(fo, c * 64, b[c], y);
     }
     if (ACT == kActStore) {
         // the prediction (network output times the reflectance factor) and
@@ -724,15 +739,15 @@ __global__ __launch_bounds__(256) void k_train_mfma(const T* __restrict__ ffr,
         if (l == n_hidden) {
             const V* fb = gb + geo.bwd_base(n_hidden) * 64;
             #pragma unroll
-            for (int mb = 0; mb < MB; ++mb) acc[mb] = mfma(fb[mb * 64], bd, f32x4{0.f, 0.f, 0.f, 0.f});
+            for (int mb = 0; mb < MB; ++mb) acc[mb] = wb(fb, mb * 64, bd, f32x4{0.f, 0.f, 0.f, 0.f});
         } else {
             const V* fb = gb + geo.bwd_base(l) * 64;
             #pragma unroll
-            for (int mb = 0; mb < MB; ++mb) acc[mb] = mfma(fb[(mb * KC) * 64], b[0], f32x4{0.f, 0.f, 0.f, 0.f});
+            for (int mb = 0; mb < MB; ++mb) acc[mb] = wb(fb, (mb * KC) * 64, b[0], f32x4{0.f, 0.f, 0.f, 0.f});
             #pragma unroll
             for (int c = 1; c < KC; ++c)
                 #pragma unroll
-                for (int mb = 0; mb < MB; ++mb) acc[mb] = mfma(fb[(mb * KC + c) * 64], b[c], acc[mb]);
+                for (int mb = 0; mb < MB; ++mb) acc[mb] = wb(fb, (mb * KC + c) * 64, b[c], acc[mb]);
         }
         #pragma unroll
         for (int mb = 0; mb < MB; ++mb)
@@ -751,11 +766,11 @@ __global__ __launch_bounds__(256) void k_train_mfma(const T* __restrict__ ffr,
         // of the upstream gradient divided out.
         f32x4 acc[4];
         #pragma unroll
-        for (int mb = 0; mb < 4; ++mb) acc[mb] = mfma(gb[(mb * KC) * 64], b[0], f32x4{0.f, 0.f, 0.f, 0.f});
+        for (int mb = 0; mb < 4; ++mb) acc[mb] = wb(gb, (mb * KC) * 64, b[0], f32x4{0.f, 0.f, 0.f, 0.f});
         #pragma unroll
         for (int c = 1; c < KC; ++c)
             #pragma unroll
-            for (int mb = 0; mb < 4; ++mb) acc[mb] = mfma(gb[(mb * KC + c) * 64], b[c], acc[mb]);
+            for (int mb = 0; mb < 4; ++mb) acc[mb] = wb(gb, (mb * KC + c) * 64, b[c], acc[mb]);
         const float inv_scale = 1.0f / grad_scale;
         #pragma unroll
         for (int mb = 0; mb < 4; ++mb)

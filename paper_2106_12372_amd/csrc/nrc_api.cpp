@@ -83,8 +83,9 @@ CacheLayout cache_layout(const nrc_config& c) {
     L.v = take(P * 4);
     L.t = take(16);
     if (!fp32_form(c.precision)) {
-        L.ffr = take((size_t)d.n_fwd_frags() * kFragElems * 2);
-        L.bfr = take((size_t)d.n_bwd_frags() * kFragElems * 2);
+        const size_t copies = (size_t)train_frag_copies(c.precision);
+        L.ffr = take(copies * d.n_fwd_frags() * kFragElems * 2);
+        L.bfr = take(copies * d.n_bwd_frags() * kFragElems * 2);
     } else {
         L.ffr = L.bfr = 0;
     }
@@ -291,8 +292,9 @@ static hipError_t reset_ema_and_frags(nrc_cache* c, hipStream_t s) {
         if (e == hipSuccess) e = hipMemcpyAsync(c->wbar(), c->w(), bytes, hipMemcpyDeviceToDevice, s);
     }
     if (e == hipSuccess && !fp32_form(c->cfg.precision)) {
-        e = hipMemsetAsync(c->ffr(), 0, (size_t)d.n_fwd_frags() * kFragElems * 2, s);
-        if (e == hipSuccess) e = hipMemsetAsync(c->bfr(), 0, (size_t)d.n_bwd_frags() * kFragElems * 2, s);
+        const size_t copies = (size_t)train_frag_copies(c->cfg.precision);
+        e = hipMemsetAsync(c->ffr(), 0, copies * d.n_fwd_frags() * kFragElems * 2, s);
+        if (e == hipSuccess) e = hipMemsetAsync(c->bfr(), 0, copies * d.n_bwd_frags() * kFragElems * 2, s);
         if (e == hipSuccess && c->ema())
             e = hipMemsetAsync(c->effr(), 0, (size_t)d.n_fwd_frags() * kFragElems * 2, s);
         if (e == hipSuccess)

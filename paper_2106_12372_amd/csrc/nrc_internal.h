@@ -35,6 +35,12 @@ __host__ __device__ inline int train_tile(int precision, int width) {
 
 // One matrix-core operand fragment: 64 lanes x 8 16-bit elements.
 constexpr int kFragElems = 64 * 8;
+// Copies of the training weight fragments: the BF16 form keeps each weight as
+// a pair hi = bf16(w), lo = bf16(w - hi) (the lo set follows the hi set in the
+// same array), and its training products take both, so training sees the
+// weights to about 16 significant bits while its operands stay BF16; queries
+// use the hi set.  FP16 keeps one copy.
+__host__ __device__ inline int train_frag_copies(int precision) { return precision == NRC_BF16 ? 2 : 1; }
 
 // Shapes and offsets of the network (Sec. 5 "Architecture"), computed
 // arithmetically so that kernels never index an array by a runtime layer.

@@ -56,13 +56,22 @@ __device__ inline void locate(const Geo& d, int p, int& l, int& o, int& k) {
     k = r - o * cols;
 }
 
+// Weight p into its forward and backward fragment slots.  split: also the lo
+// part w - hi into the second copy that follows each array (the BF16 form's
+// training fragments).
 template <typename T>
-__device__ inline void write_frags(const Geo& d, int p, float w, T* ffr, T* bfr) {
+__device__ inline void write_frags(const Geo& d, int p, float w, T* ffr, T* bfr, bool split = false) {
     int l, o, k;
     locate(d, p, l, o, k);
     const T v = (T)w;
-    if (ffr) ffr[fwd_frag_index(d, l, o, k)] = v;
-    if (bfr) bfr[bwd_frag_index(d, l, o, k)] = v;
+    const int64_t fi = fwd_frag_index(d, l, o, k), bi = bwd_frag_index(d, l, o, k);
+    if (ffr) ffr[fi] = v;
+    if (bfr) bfr[bi] = v;
+    if (split) {
+        const T lo = (T)(w - (float)v);
+        if (ffr) ffr[(int64_t)d.n_fwd_frags() * kFragElems + fi] = lo;
+        if (bfr) bfr[(int64_t)d.n_bwd_frags() * kFragElems + bi] = lo;
+    }
 }
 
 constexpr int kRedParams = 32;   // weights per workgroup
@@ -185,7 +194,7 @@ __global__ __launch_bounds__(256) void k_reduce(const float* __restrict__ partia
     w[p] = w1;
     m[p] = m1;
     v[p] = v1;
-    if (ffr != nullptr) write_frags<T>(d, p, w1, ffr, bfr);
+    if (ffr != nullptr) write_frags<T>(d, p, w1, ffr, bfr, __is_same(T, __bf16));
     if (ema.alpha > 0.0f) {
         // Eq. 2, bias-corrected: E_t = a E_{t-1} + (1 - a) W_t, W_bar_t = E_t / (1 - a^t).
         const float e1 = fmaf(ema.alpha, e0, (1.0f - ema.alpha) * w1);
@@ -203,7 +212,7 @@ __global__ __launch_bounds__(256) void k_build_frags(const float* __restrict__ w
     const Geo d(width, n_hidden);
     const int p = blockIdx.x * 256 + threadIdx.x;
     if (p >= d.n_params()) return;
-    write_frags<T>(d, p, w[p], ffr, bfr);
+    write_frags<T>(d, p, w[p], ffr, bfr, __is_same(T, __bf16) && bfr != nullptr);
     if (ffr2) write_frags<T>(d, p, w[p], ffr2, (T*)nullptr);
 }
 

@@ -23,10 +23,27 @@ def quantiser(prec):
     return lambda x: np.asarray(x, np.float64)
 
 
-def forward(mats, x, q):
+def train_weight_quantiser(prec):
+    """Weights as the training kernels see them: the BF16 form takes each weight
+    as the pair hi = bf16(w), lo = bf16(w - hi) (two products per weight
+    operand), FP16 as one FP16 value."""
+    q = quantiser(prec)
+    if prec != "bf16":
+        return q
+
+    def split(m):
+        m32 = np.asarray(m, np.float32)
+        hi = q(m32)
+        lo = q((m32 - hi.astype(np.float32)).astype(np.float32))
+        return hi + lo
+    return split
+
+
+def forward(mats, x, q, qw=None):
+    """qw: how the weights are rounded (default: like the activations)."""
     h = q(x)
     hs = [h]
-    qm = [q(m) for m in mats]
+    qm = [(qw or q)(m) for m in mats]
     for l, w in enumerate(qm):
         z = h @ w.T
         if l == len(qm) - 1:
@@ -67,6 +84,7 @@ class TrainModel:
         self.v = np.zeros_like(self.w)
         self.t = 0
         self.q = quantiser(prec)
+        self.qw = train_weight_quantiser(prec)
         self.width, self.n_hidden = width, n_hidden
         self.scale, self.lr, self.b1, self.b2, self.eps, self.loss_eps = loss_scale, lr, b1, b2, eps, loss_eps
 
@@ -78,7 +96,7 @@ class TrainModel:
 
     def step(self, x, y):
         n = x.shape[0]
-        z, hs, qm = forward(self.mats(), x, self.q)
+        z, hs, qm = forward(self.mats(), x, self.q, self.qw)
         r = factor(x, self.fcol)
         z = z * r
         lum = z.mean(axis=1, keepdims=True)

@@ -392,7 +392,7 @@ def test_train_fp32_four_steps_frame_schedule(N):
     assert rel_w < 1e-5
 
 
-SINGLE_STEP_TOL = {"fp32": 1e-5, "fp16": 3e-2, "bf16": 8e-2}
+SINGLE_STEP_TOL = {"fp32": 1e-5, "fp16": 3e-2, "bf16": 3e-2}
 
 
 @pytest.mark.parametrize("prec", ["fp16", "bf16"])
@@ -500,7 +500,7 @@ def test_backward_matches_oracle(N, prec, width):
     y, hs = O.forward(st.mats(), x64)
     grads, gin = O.backward(st.mats(), hs, r.astype(np.float64))
     q = RM.quantiser(prec)
-    _, mhs, qm = RM.forward(st.mats(), x64, q)
+    _, mhs, qm = RM.forward(st.mats(), x64, q, RM.train_weight_quantiser(prec))
     mgrads, mgin = RM.backward(qm, mhs, r.astype(np.float64), q)
     off = 0
     for l, g in enumerate(grads):

@@ -127,7 +127,7 @@ def test_frame_steps_match_oracle_from_the_same_state(N, prec, n_records):
             check_fp32_adam_step(c.get_weights(), st_before, st.w, e64[idx], y[idx].astype(np.float64))
 
 
-FRAME_MAX_TOL = {"fp16": 1e-2, "bf16": 1.5e-2}
+FRAME_MAX_TOL = {"fp16": 1e-2, "bf16": 1e-2}
 
 
 @pytest.mark.parametrize("prec", ["fp16", "bf16"])
@@ -156,10 +156,11 @@ def test_train_frame_matches_oracle_frame(N, prec):
     nrm = N.nrc_error_norms(got_d, torch.from_numpy(ref).to("cuda")).cpu().numpy()
     assert np.allclose(np.sqrt(nrm[:, 0] / nrm[:, 1]), e2, rtol=1e-12)
     assert np.array_equal(nrm[:, 2] / nrm[:, 3], em)
-    # L2 within 1e-2 in both formats.  The max-normwise error of BF16 (unit
-    # roundoff 2^-8) reaches 1.14e-2 in the rounding model, which carries out
-    # this frame with exactly the kernels' roundings: that is the format's own
-    # loss, so its bound is 1.5e-2 (FP16: model 2.3e-3, bound 1e-2).
+    # L2 and max within 1e-2 in both formats.  BF16's training products take
+    # each weight as a hi + lo pair of BF16 values: with one BF16 value per
+    # weight, the rounding model of this frame reaches 1.14e-2 max-normwise,
+    # 1.0e-2 of it from the weights training learns; with the pair it gives
+    # 0.57-0.73e-2 (FP16: 2.3e-3).
     assert np.all(e2 <= 1e-2) and np.all(em <= FRAME_MAX_TOL[prec]), (e2, em)
     # the kernels against the rounding model of the same frame
     model = RM.TrainModel(w, prec, loss_scale=c.cfg.loss_scale)
