@@ -57,7 +57,8 @@ def log(*a):
 
 
 KERNEL_SOURCES = {"k_fwd_raw_mfma_fixed": ["mlp_mfma.hip", "encode_impl.h", "nrc_internal.h"],
-                  "k_fwd_raw_fp32": ["mlp_fp32.hip", "encode_impl.h", "nrc_internal.h"]}
+                  "k_fwd_raw_fp32": ["mlp_fp32.hip", "encode_impl.h", "nrc_internal.h"],
+                  "k_fwd_raw_fp32_valu": ["mlp_fp32_valu.hip", "encode_impl.h", "nrc_internal.h"]}
 
 
 def measured_traffic(kernel: str, form: str):
