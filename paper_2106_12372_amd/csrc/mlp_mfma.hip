@@ -14,14 +14,16 @@
 // loads of the encoded rows, H+1 chained layers of MFMA, and a 12-byte RGB
 // store per query.  HBM is touched only for the encoded input and the output.
 //
-// Training: a workgroup of 4 waves owns 64 records (wave w: records
-// 16w..16w+15).  The forward pass also writes every layer's activations to
-// LDS in feature-major order; the loss gradient of Eq. 5 is formed in the
-// output lanes; the data backward pass chains W_l^T products through VGPRs
-// the same way as the forward pass; and the weight gradient of each layer,
-// a contraction over the tile's 64 records, reads delta and h back from LDS
-// with the record index contiguous.  Each tile writes its weight-gradient
-// partial sums; a fixed-order reduction follows (no atomics).
+// Training: a workgroup owns 64 records; its 4 chain waves hold 16 records
+// each (wave w: records 16w..16w+15).  The forward pass also writes every
+// layer's activations to LDS, record-major; the loss gradient of Eq. 5 is
+// formed in the output lanes; the data backward pass chains W_l^T products
+// through VGPRs the same way as the forward pass, storing each delta_l.  Four
+// more waves form the weight gradients: dW_l, a contraction over the tile's
+// 64 records, as soon as delta_{l+1} is in LDS, beside the chain's next
+// layer, reading delta and h with LDS transpose loads so that the record
+// index runs along K.  Each tile writes its weight-gradient partial sums; a
+// fixed-order reduction follows (no atomics).
 #include "encode_impl.h"
 #include "nrc_internal.h"
 
@@ -536,30 +538,34 @@ __global__ __launch_bounds__(64 * NW) void k_fwd_raw_mfma_fixed(const T* __restr
 // ---------------------------------------------------------------------------
 // Training: forward + loss gradient + data backward + per-tile weight gradient
 // ---------------------------------------------------------------------------
-// Records per workgroup: 64 at width 64 (4 waves), 32 at width 128 (2 waves),
-// so that every layer's activations and deltas of the tile fit in LDS.
+// Records per workgroup: 64 at width 64 (4 chain waves), 32 at width 128 (2
+// chain waves), so that every layer's activations and deltas of the tile fit
+// in LDS; as many weight-gradient waves again.
 template <int W> struct TrainShape {
     static constexpr int TS = W == 64 ? 64 : 32;   // records per tile
-    static constexpr int NW = TS / 16;             // waves per workgroup
-    static constexpr int LDT = TS + 8;             // LDS row stride, elements
+    static constexpr int NW = TS / 16;             // chain waves per workgroup
+    static constexpr int LDT = TS + 8;             // row stride of dL/dy, elements
+    static constexpr int LDR = W == 64 ? 72 : 144; // record row stride of h_l, delta_l
 };
-
-// LDS bytes of one training workgroup: h_0 (64 rows), h_1..h_H and
-// delta_1..delta_H (W rows each), dL/dy (16 rows), all [feature][record].
+// LDS bytes of one training workgroup: h_0 [record][64 + 8], h_1..h_H and
+// delta_1..delta_H [record][LDR], then dL/dy [3 (16) rows][record].
 __host__ __device__ constexpr int train_lds_bytes(int W, int H) {
-    return (kEncWidth + 2 * H * W + 16) * (W == 64 ? 72 : 40) * 2;
+    return ((W == 64 ? 64 : 32) * (72 + 2 * H * (W == 64 ? 72 : 144)) + 16 * (W == 64 ? 72 : 40)) * 2;
 }
 
 // Activation buffer of the autograd form (ACT): per tile, h_1 .. h_H as
-// [layer][feature][record] at the operand precision (the LDS rows without
+// [layer][record][feature] at the operand precision (the LDS rows without
 // their padding), then, after every tile's block, the network output
 // [tile * TS + record][4] (FP32).  kActNone: no buffer; kActStore: forward only,
 // writes the buffer and rgb, then exits; kActLoad: the forward pass is read
 // from the buffer instead of recomputed.
 constexpr int kActNone = 0, kActStore = 1, kActLoad = 2;
 
+// Weight-gradient waves beside the chain waves (none in the forward-only form).
+template <int W, int ACT> constexpr int train_helpers() { return ACT == kActStore ? 0 : TrainShape<W>::NW; }
+
 template <typename T, int W, bool UPSTREAM, bool GENC, int ACT = kActNone>
-__global__ __launch_bounds__(256) void k_train_mfma(const T* __restrict__ ffr,
+__global__ __launch_bounds__(512) void k_train_mfma(const T* __restrict__ ffr,
                                                     const T* __restrict__ bfr,
                                                     const T* __restrict__ enc,
                                                     const float* __restrict__ tgt,
@@ -574,23 +580,30 @@ __global__ __launch_bounds__(256) void k_train_mfma(const T* __restrict__ ffr,
     using V = typename Vec8<T>::type;
     using S = TrainShape<W>;
     constexpr int MB = W / 16, KC = W / 32, TS = S::TS, NW = S::NW, LDT = S::LDT, TK = TS / 32;
+    constexpr int LDR = S::LDR, LD0 = 72;
+    constexpr int NHW = train_helpers<W, ACT>();             // weight-gradient waves
+    constexpr int NT = 64 * (NW + NHW);
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     __shared__ float wsum[4];
     const Geo geo(W, n_hidden);
-    T* hT = reinterpret_cast<T*>(smem_raw);                  // h_0 .. h_H
-    T* dT = hT + (kEncWidth + n_hidden * W) * LDT;           // delta_1 .. delta_H
-    T* dO = dT + n_hidden * W * LDT;                         // dL/dy, rows 0..2
-    auto hrow = [&](int l) { return hT + (l == 0 ? 0 : kEncWidth + (l - 1) * W) * LDT; };
-    auto drow = [&](int l) { return dT + (l - 1) * W * LDT; };
+    // h_l and delta_l record-major (a record's features contiguous, so the
+    // chain waves store and read them 8 bytes at a time); dL/dy feature-major.
+    T* hT = reinterpret_cast<T*>(smem_raw);                  // h_0 [TS][LD0], h_1 .. h_H [TS][LDR]
+    T* dT = hT + TS * LD0 + n_hidden * TS * LDR;             // delta_1 .. delta_H [TS][LDR]
+    T* dO = dT + n_hidden * TS * LDR;                        // dL/dy, rows 0..2 [3][LDT]
+    auto hrow = [&](int l) { return hT + (l == 0 ? 0 : TS * LD0 + (l - 1) * TS * LDR); };
+    auto drow = [&](int l) { return dT + (l - 1) * TS * LDR; };
+    auto ldr = [&](int l) { return l == 0 ? LD0 : LDR; };
 
     const int P = geo.n_params();
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int g = lane >> 4, ln = lane & 15;
     const int64_t tile = blockIdx.x;
-    const int sl = 16 * wave + ln;                           // record within the tile
+    const bool chain = wave < NW;                            // a chain wave owns 16 records
+    const int sl = 16 * (chain ? wave : 0) + ln;             // record within the tile
     const int64_t row = tile * TS + sl;
-    const bool valid = row < n;
+    const bool valid = chain && row < n;
     // record read for this slot: idx[row] or the LCG orbit for a gathered batch, else row
     const int64_t src = !valid ? 0 : gather_row(idx, lg, row);
     float* part = partials + tile * (int64_t)P;
@@ -612,10 +625,13 @@ __global__ __launch_bounds__(256) void k_train_mfma(const T* __restrict__ ffr,
         return c;
     };
 
-    // Scatter a chained-order operand (features of chunk c) into a [feature][record] store.
+    // A chained-order operand (features 32c + 4g .. +3 and 32c + 16 + 4g .. +3
+    // of record sl) into a record-major store: two 8-byte writes.
+    typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
     auto put = [&](T* base, const V& v, int c) {
-        #pragma unroll
-        for (int i = 0; i < 8; ++i) base[(32 * c + (i < 4 ? 4 * g + i : 12 + 4 * g + i)) * LDT + sl] = v[i];
+        const u32x4 u = __builtin_bit_cast(u32x4, v);
+        *reinterpret_cast<u32x2*>(base + sl * LDR + 32 * c + 4 * g) = u32x2{u[0], u[1]};
+        *reinterpret_cast<u32x2*>(base + sl * LDR + 32 * c + 16 + 4 * g) = u32x2{u[2], u[3]};
     };
 
     // ---- forward (each wave: its 16 records, activations in VGPRs) ----------
@@ -623,8 +639,7 @@ __global__ __launch_bounds__(256) void k_train_mfma(const T* __restrict__ ffr,
     #pragma unroll
     for (int c = 0; c < 2; ++c) {
         b[c] = valid ? *reinterpret_cast<const V*>(enc + src * kEncWidth + 32 * c + 8 * g) : zero8<V>();
-        #pragma unroll
-        for (int i = 0; i < 8; ++i) hT[(32 * c + 8 * g + i) * LDT + sl] = b[c][i];
+        if (chain) *reinterpret_cast<V*>(hT + sl * LD0 + 32 * c + 8 * g) = b[c];
     }
     float r[3];                      // reflectance factor of record sl (lanes 0..15)
     reflectance_operand(b[1], fcol, ln, r);
@@ -640,16 +655,16 @@ __global__ __launch_bounds__(256) void k_train_mfma(const T* __restrict__ ffr,
     float* act_y = reinterpret_cast<float*>(act + n_tiles * (int64_t)(n_hidden * W * TS));
     // copy h_1 .. h_H between the LDS rows and the buffer, 16 bytes at a time
     auto copy_act = [&](bool to_lds) {
-        constexpr int CPR = TS * (int)sizeof(T) / 16;         // 16-byte chunks per row
-        const int rows = n_hidden * W;
-        for (int i = tid; i < rows * CPR; i += 64 * NW) {
+        constexpr int CPR = W * (int)sizeof(T) / 16;          // 16-byte chunks per record row
+        const int rows = n_hidden * TS;
+        for (int i = tid; i < rows * CPR; i += NT) {
             const int rr = i / CPR, q = i - rr * CPR;
-            u32x4* l = reinterpret_cast<u32x4*>(hT + (kEncWidth + rr) * LDT) + q;
-            u32x4* gp = reinterpret_cast<u32x4*>(act_t + rr * TS) + q;
+            u32x4* l = reinterpret_cast<u32x4*>(hT + TS * LD0 + rr * LDR) + q;
+            u32x4* gp = reinterpret_cast<u32x4*>(act_t + rr * W) + q;
             if (to_lds) *l = *gp; else *gp = *l;
         }
     };
-    const int n_fwd = ACT == kActLoad ? 0 : n_hidden;   // layers the forward pass computes
+    const int n_fwd = (ACT == kActLoad || !chain) ? 0 : n_hidden;   // layers the forward pass computes
     for (int l = 0; l < n_fwd; ++l) {
         const int kc = l == 0 ? 2 : KC;
         const V* fl = gf + geo.fwd_base(l) * 64;
@@ -722,18 +737,84 @@ __global__ __launch_bounds__(256) void k_train_mfma(const T* __restrict__ ffr,
         }
     }
     V bd = zero8<V>();
-    if (g == 0) {
+    if (g == 0 && chain) {
         bd[0] = to_t<T>(d0); bd[1] = to_t<T>(d1); bd[2] = to_t<T>(d2);
         dO[0 * LDT + sl] = bd[0];
         dO[1 * LDT + sl] = bd[1];
         dO[2 * LDT + sl] = bd[2];
     }
     const float wl = wave_sum_compensated(lterm);
-    if (lane == 0) wsum[wave] = wl;
+    if (lane == 0 && chain) wsum[wave] = wl;
+
+    // ---- weight gradients: dW_l = delta_{l+1} h_l^T over the tile's records --
+    // Computed by the helper waves (hw = 0 .. NHW-1) while the chain waves run
+    // the data backward pass: dW_l as soon as delta_{l+1} is in LDS.  The 16x16
+    // result blocks are stored in the accumulator's own layout, one float4 per
+    // lane: slot w_off(l) + ((mb * NB + nb) * 64 + lane) * 4 + j holds
+    // dW_l[16 mb + 4 g + j][16 nb + ln].  The output layer is row-major.
+    bool bad = false;
+    auto dw_layer = [&](int l, int hw) {
+        const int ncols = l == 0 ? kEncWidth : W;
+        const int NB = ncols / 16;
+        const T* hl = hrow(l);
+        const int lh = ldr(l);
+        const T* dl = l == n_hidden ? dO : drow(l + 1);
+        const int woff = geo.w_off(l);
+        // Operand of records 32 kc + 8 g .. +7 (K slots 8 g .. 8 g + 7) for
+        // feature 16 blk + ln from a record-major store, by two LDS transpose
+        // reads: in each 16-lane group, lane i receives element i % 4 of the
+        // 8-byte segments that lanes i / 4, i / 4 + 4, i / 4 + 8, i / 4 + 12
+        // address, so lane i addresses record rec0 + i / 4, features
+        // 16 blk + 4 (i % 4) .. +3.
+        auto gather = [&](const T* base, int stride, int blk, int kc) {
+            typedef short s16x4 __attribute__((ext_vector_type(4)));
+            typedef __attribute__((address_space(3))) s16x4 lds_s16x4;
+            const T* p = base + (32 * kc + 8 * g + (ln >> 2)) * stride + 16 * blk + 4 * (ln & 3);
+            const s16x4 lo = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s16x4*)p);
+            const s16x4 hi = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s16x4*)(p + 4 * stride));
+            return __builtin_bit_cast(V, __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7));
+        };
+        for (int nb = hw; nb < NB; nb += NHW) {
+            V bb[TK];
+            #pragma unroll
+            for (int kc = 0; kc < TK; ++kc) bb[kc] = gather(hl, lh, nb, kc);
+            if (l == n_hidden) {
+                f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
+                #pragma unroll
+                for (int kc = 0; kc < TK; ++kc) {
+                    const V a = ln < kNOut ? *reinterpret_cast<const V*>(dl + ln * LDT + 32 * kc + 8 * g)
+                                           : zero8<V>();
+                    acc = mfma(a, bb[kc], acc);
+                }
+                if (g == 0) {
+                    #pragma unroll
+                    for (int j = 0; j < kNOut; ++j) {
+                        part[woff + j * W + 16 * nb + ln] = acc[j];
+                        bad |= !isfinite(acc[j]);
+                    }
+                }
+            } else {
+                #pragma unroll
+                for (int mb = 0; mb < MB; ++mb) {
+                    f32x4 acc = mfma(gather(dl, LDR, mb, 0), bb[0], f32x4{0.f, 0.f, 0.f, 0.f});
+                    #pragma unroll
+                    for (int kc = 1; kc < TK; ++kc) acc = mfma(gather(dl, LDR, mb, kc), bb[kc], acc);
+                    // streamed past the caches: read once, by the reduction
+                    __builtin_nontemporal_store(acc, reinterpret_cast<f32x4*>(part + woff + ((mb * NB + nb) * 64 + lane) * 4));
+                    #pragma unroll
+                    for (int j = 0; j < 4; ++j) bad |= !isfinite(acc[j]);
+                }
+            }
+        }
+    };
+    __syncthreads();   // dL/dy and h_0 .. h_H are in LDS
 
     // ---- data backward: the whole delta chain in VGPRs, each delta kept in LDS
     // delta_l = (W_l^T delta_{l+1}) masked by ReLU'(z_l); W_H^T acts on dL/dy.
     for (int l = n_hidden; l >= 1; --l) {
+      if (!chain) {
+        dw_layer(l, wave - NW);
+      } else {
         const T* hl = hrow(l);
         f32x4 acc[MB];
         if (l == n_hidden) {
@@ -750,18 +831,23 @@ __global__ __launch_bounds__(256) void k_train_mfma(const T* __restrict__ ffr,
                 for (int mb = 0; mb < MB; ++mb) acc[mb] = wb(fb, (mb * KC + c) * 64, b[c], acc[mb]);
         }
         #pragma unroll
-        for (int mb = 0; mb < MB; ++mb)
+        for (int mb = 0; mb < MB; ++mb) {
+            typedef T t4 __attribute__((ext_vector_type(4)));
+            const t4 hv = *reinterpret_cast<const t4*>(hl + sl * LDR + 16 * mb + 4 * g);
             #pragma unroll
-            for (int j = 0; j < 4; ++j)
-                acc[mb][j] = (float)hl[(16 * mb + 4 * g + j) * LDT + sl] > 0.0f ? acc[mb][j] : 0.0f;
+            for (int j = 0; j < 4; ++j) acc[mb][j] = (float)hv[j] > 0.0f ? acc[mb][j] : 0.0f;
+        }
         T* dl = drow(l);
         #pragma unroll
         for (int c = 0; c < KC; ++c) {
             b[c] = pack8<T, V>(acc[2 * c], acc[2 * c + 1]);
             put(dl, b[c], c);
         }
+      }
+      __syncthreads();   // delta_l is in LDS
     }
-    if (GENC) {
+    if (!chain) dw_layer(0, wave - NW);
+    if (GENC && chain) {
         // dL/dh_0 = W_0^T delta_1 (64 input features), with the loss scale
         // of the upstream gradient divided out.
         f32x4 acc[4];
@@ -801,7 +887,6 @@ __global__ __launch_bounds__(256) void k_train_mfma(const T* __restrict__ ffr,
                     make_float4(acc[mb][0], acc[mb][1], acc[mb][2], acc[mb][3]);
         }
     }
-    __syncthreads();
     if (tid == 0) {
         // compensated combine of the waves' sums, in wave order
         float t = 0.0f, c = 0.0f;
@@ -811,56 +896,6 @@ __global__ __launch_bounds__(256) void k_train_mfma(const T* __restrict__ ffr,
             t = u;
         }
         loss_part[tile] = t + c;
-    }
-
-    // ---- weight gradients: dW_l = delta_{l+1} h_l^T over the tile's records --
-    // All layers at once (no dependence between them).  The 16x16 result
-    // blocks are stored in the accumulator's own layout, one float4 per lane:
-    // slot w_off(l) + ((mb * NB + nb) * 64 + lane) * 4 + j holds
-    // dW_l[16 mb + 4 g + j][16 nb + ln].  The output layer is row-major.
-    bool bad = false;
-    for (int l = 0; l <= n_hidden; ++l) {
-        const int ncols = l == 0 ? kEncWidth : W;
-        const int NB = ncols / 16;
-        const T* hl = hrow(l);
-        const T* dl = l == n_hidden ? dO : drow(l + 1);
-        const int woff = geo.w_off(l);
-        for (int nb = wave; nb < NB; nb += NW) {
-            V bb[TK];
-            #pragma unroll
-            for (int kc = 0; kc < TK; ++kc)
-                bb[kc] = *reinterpret_cast<const V*>(hl + (16 * nb + ln) * LDT + 32 * kc + 8 * g);
-            if (l == n_hidden) {
-                f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
-                #pragma unroll
-                for (int kc = 0; kc < TK; ++kc) {
-                    const V a = ln < kNOut ? *reinterpret_cast<const V*>(dl + ln * LDT + 32 * kc + 8 * g)
-                                           : zero8<V>();
-                    acc = mfma(a, bb[kc], acc);
-                }
-                if (g == 0) {
-                    #pragma unroll
-                    for (int j = 0; j < kNOut; ++j) {
-                        part[woff + j * W + 16 * nb + ln] = acc[j];
-                        bad |= !isfinite(acc[j]);
-                    }
-                }
-            } else {
-                #pragma unroll
-                for (int mb = 0; mb < MB; ++mb) {
-                    f32x4 acc = mfma(*reinterpret_cast<const V*>(dl + (16 * mb + ln) * LDT + 8 * g), bb[0],
-                                     f32x4{0.f, 0.f, 0.f, 0.f});
-                    #pragma unroll
-                    for (int kc = 1; kc < TK; ++kc)
-                        acc = mfma(*reinterpret_cast<const V*>(dl + (16 * mb + ln) * LDT + 32 * kc + 8 * g),
-                                   bb[kc], acc);
-                    // streamed past the caches: read once, by the reduction
-                    __builtin_nontemporal_store(acc, reinterpret_cast<f32x4*>(part + woff + ((mb * NB + nb) * 64 + lane) * 4));
-                    #pragma unroll
-                    for (int j = 0; j < 4; ++j) bad |= !isfinite(acc[j]);
-                }
-            }
-        }
     }
     const int any_bad = __syncthreads_or(bad ? 1 : 0);
     if (tid == 0) tile_bad[tile] = any_bad ? 1 : 0;
@@ -982,7 +1017,7 @@ hipError_t train_launch(const Geo& d, const void* ffr, const void* bfr, const vo
     const size_t lds = (size_t)train_lds_bytes(W, d.H);
     auto k = k_train_mfma<T, W, UP, GE, ACT>;
     (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(k, dim3((unsigned)tiles), dim3(64 * S::NW), lds, s, (const T*)ffr, (const T*)bfr,
+    hipLaunchKernelGGL(k, dim3((unsigned)tiles), dim3(64 * (S::NW + train_helpers<W, ACT>())), lds, s, (const T*)ffr, (const T*)bfr,
                        (const T*)enc, tgt, idx, n, d.H, loss_eps, grad_scale, partials, loss_part, tile_bad,
                        genc, d.F, (T*)act, rgb, lg);
     return hipGetLastError();

@@ -56,15 +56,20 @@ __device__ inline void locate(const Geo& d, int p, int& l, int& o, int& k) {
     k = r - o * cols;
 }
 
-// Weight p into its forward and backward fragment slots.  split: also the lo
-// part w - hi into the second copy that follows each array (the BF16 form's
-// training fragments).
-template <typename T>
-__device__ inline void write_frags(const Geo& d, int p, float w, T* ffr, T* bfr, bool split = false) {
+// Forward and backward fragment slots of weight p.
+__device__ inline void frag_slots(const Geo& d, int p, int64_t& fi, int64_t& bi) {
     int l, o, k;
     locate(d, p, l, o, k);
+    fi = fwd_frag_index(d, l, o, k);
+    bi = bwd_frag_index(d, l, o, k);
+}
+
+// A weight into its forward and backward fragment slots fi, bi.  split: also
+// the lo part w - hi into the second copy that follows each array (the BF16
+// form's training fragments).
+template <typename T>
+__device__ inline void put_frags(const Geo& d, int64_t fi, int64_t bi, float w, T* ffr, T* bfr, bool split) {
     const T v = (T)w;
-    const int64_t fi = fwd_frag_index(d, l, o, k), bi = bwd_frag_index(d, l, o, k);
     if (ffr) ffr[fi] = v;
     if (bfr) bfr[bi] = v;
     if (split) {
@@ -72,6 +77,13 @@ __device__ inline void write_frags(const Geo& d, int p, float w, T* ffr, T* bfr,
         if (ffr) ffr[(int64_t)d.n_fwd_frags() * kFragElems + fi] = lo;
         if (bfr) bfr[(int64_t)d.n_bwd_frags() * kFragElems + bi] = lo;
     }
+}
+
+template <typename T>
+__device__ inline void write_frags(const Geo& d, int p, float w, T* ffr, T* bfr, bool split = false) {
+    int64_t fi, bi;
+    frag_slots(d, p, fi, bi);
+    put_frags<T>(d, fi, bi, w, ffr, bfr, split);
 }
 
 constexpr int kRedParams = 32;   // weights per workgroup
@@ -118,6 +130,27 @@ __global__ __launch_bounds__(256) void k_reduce(const float* __restrict__ partia
         if (ema.alpha > 0.0f) e0 = ema.e[p];
         t_old = tslots[parity];
     }
+    // Workgroup 0's second wave loads the first 256 per-tile loss terms now,
+    // for the same reason.
+    const bool loss_wave = blockIdx.x == 0 && tid >= 64 && tid < 128 && loss_out != nullptr;
+    float lv[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    if (loss_wave) {
+        #pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (lane + 64 * u < n_tiles) lv[u] = loss_part[lane + 64 * u];
+    }
+    // Bias corrections of the step this update would make (a skipped step
+    // updates nothing) and the weight's fragment slots, evaluated while the
+    // partials are in flight.
+    const float t_next = (float)(t_old + 1);
+    float bc1 = 1.0f, bc2 = 1.0f, bce = 1.0f;
+    int64_t fi = 0, bi = 0;
+    if (ADAM && owner) {
+        bc1 = 1.0f - powf(hp.beta1, t_next);
+        bc2 = 1.0f - powf(hp.beta2, t_next);
+        if (ema.alpha > 0.0f) bce = 1.0f - powf(ema.alpha, t_next);
+        if (ffr != nullptr || ema.effr != nullptr) frag_slots(d, p, fi, bi);
+    }
     float s = 0.0f, c = 0.0f;
     if (sidx < P) {
         // 16 loads in flight per thread before the (order-preserving) sums
@@ -144,11 +177,14 @@ __global__ __launch_bounds__(256) void k_reduce(const float* __restrict__ partia
     s_cmp[grp][pl] = c;
     __syncthreads();
 
-    if (blockIdx.x == 0 && tid >= 64 && tid < 128 && loss_out != nullptr) {
+    if (loss_wave) {
         // compensated sum of the per-tile loss terms, then a compensated
         // combine of the 64 lane sums in a fixed order
         float ls = 0.0f, lc = 0.0f;
-        for (int t = lane; t < n_tiles; t += 64) neumaier_add(ls, lc, loss_part[t]);
+        #pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (lane + 64 * u < n_tiles) neumaier_add(ls, lc, lv[u]);
+        for (int t = lane + 256; t < n_tiles; t += 64) neumaier_add(ls, lc, loss_part[t]);
         #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) {
             const float os = __shfl_xor(ls, off, 64), oc = __shfl_xor(lc, off, 64);
@@ -188,20 +224,18 @@ __global__ __launch_bounds__(256) void k_reduce(const float* __restrict__ partia
     // product the compiler would contract
     const float m1 = fmaf(hp.beta1, m0, (1.0f - hp.beta1) * gv);
     const float v1 = fmaf(hp.beta2, v0, ((1.0f - hp.beta2) * gv) * gv);
-    const float bc1 = 1.0f - powf(hp.beta1, (float)t_new);
-    const float bc2 = 1.0f - powf(hp.beta2, (float)t_new);
     const float w1 = w0 - hp.lr * (m1 / bc1) / (sqrtf(v1 / bc2) + hp.eps);
     w[p] = w1;
     m[p] = m1;
     v[p] = v1;
-    if (ffr != nullptr) write_frags<T>(d, p, w1, ffr, bfr, __is_same(T, __bf16));
+    if (ffr != nullptr) put_frags<T>(d, fi, bi, w1, ffr, bfr, __is_same(T, __bf16));
     if (ema.alpha > 0.0f) {
         // Eq. 2, bias-corrected: E_t = a E_{t-1} + (1 - a) W_t, W_bar_t = E_t / (1 - a^t).
         const float e1 = fmaf(ema.alpha, e0, (1.0f - ema.alpha) * w1);
-        const float wb = e1 / (1.0f - powf(ema.alpha, (float)t_new));
+        const float wb = e1 / bce;
         ema.e[p] = e1;
         ema.wbar[p] = wb;
-        if (ema.effr != nullptr) write_frags<T>(d, p, wb, (T*)ema.effr, (T*)nullptr);
+        if (ema.effr != nullptr) put_frags<T>(d, fi, bi, wb, (T*)ema.effr, (T*)nullptr, false);
     }
 }
 
