@@ -220,72 +220,63 @@ __global__ __launch_bounds__(64 * kQWaves) void k_fwd_raw_fp32(const float* __re
 // With the reflectance factorisation (fcol != 0) y is the network output times
 // R = alpha + beta; the network's output gradient is dL/dy * R, and dL/denc
 // also takes dL/dy_c * f_c on both albedo columns of channel c.
-// NWV = 16 waves share a tile of 64 records.  In the three products of a
-// layer wave w owns one 16 x 16 block (block row w / 4, block column w % 4);
-// with the MFMA layout above, lane (g, j) supplies K index 16g + t in step t
-// of the forward and data-backward products, so each lane's operand run over
-// the 16 steps is contiguous in the row-major weights or in an LDS row, or
-// strided by a row (the weight gradient orders its K, the samples, for
-// conflict-free LDS banks instead).  The output layer (3 rows)
-// and the loss stay on the vector ALUs (lane = record, FPW = 4 features per
-// wave where a pass is split by feature).
+//
+// A workgroup owns a tile of 64 records.  Its 4 chain waves hold 16 records
+// each (wave w: records 16w .. 16w+15, lane (g, j): record 16w + j) and run
+// the forward pass, the loss and the data backward pass with the activations
+// in VGPRs in the query kernel's order: a[4b + r] is neuron 16b + 4g + r,
+// which is what an accumulator block leaves in the lane and what the next
+// product's B operand needs, so a layer is 64 v_mfma_f32_16x16x4_f32 in four
+// independent chains with no data movement.  The forward arithmetic is the
+// query kernel's, product for product, so the training forward pass equals
+// inference bit for bit.  Every h_l and delta_l also goes to LDS record-major
+// ([record][feature], 68-float rows, 16-byte stores).  Its 4 weight-gradient
+// waves form dW_l = delta_{l+1} h_l^T over the tile's records as soon as
+// delta_{l+1} is in LDS, while the chain computes delta_l: one 16-column
+// block per wave, each 16 x 16 block 16 matrix instructions over a K of 64
+// records, ordered so the four lane groups read LDS rows 4 apart (16 banks
+// apart at the 68-float stride).  The output layer (3 rows), the loss and
+// dW of the output layer stay on the vector ALUs.
 // Activation buffer of the autograd form (ACT): per tile, h_1 .. h_H as
 // [layer][record][feature] FP32, then, after every tile's block, the network
 // output [tile * 64 + record][4].  kActNone: no buffer; kActStore: forward
 // only, writes the buffer and rgb, then exits; kActLoad: the forward pass is
 // read from the buffer instead of recomputed.
 constexpr int kActNone = 0, kActStore = 1, kActLoad = 2;
+constexpr int kChainWaves = 4, kGradWaves = 4;
 
-template <bool UPSTREAM, bool GENC, int NWV, int ACT = kActNone>
-__global__ __launch_bounds__(64 * NWV) void k_train_fp32(const float* __restrict__ w,
-                                                         const float* __restrict__ enc,
-                                                         const float* __restrict__ tgt,
-                                                         const int32_t* __restrict__ idx, int64_t n,
-                                                         int n_hidden, int n_params, float loss_eps,
-                                                         float grad_scale, float* __restrict__ partials,
-                                                         float* __restrict__ loss_part,
-                                                         int32_t* __restrict__ tile_bad,
-                                                         float* __restrict__ genc, int fcol,
-                                                         float* __restrict__ act, float* __restrict__ rgb,
-                                                         LcgGather lg) {
-    static_assert(NWV == 16, "one 16 x 16 block of each 64 x 64 product per wave");
-    constexpr int FPW = kW / NWV;                          // features per wave (output layer)
-    constexpr int NT = 64 * NWV;
+template <int ACT> constexpr int fp32_train_waves() { return ACT == kActStore ? kChainWaves : kChainWaves + kGradWaves; }
+
+template <bool UPSTREAM, bool GENC, int ACT = kActNone>
+__global__ __launch_bounds__(64 * (kChainWaves + kGradWaves)) void k_train_fp32(
+        const float* __restrict__ w, const float* __restrict__ enc, const float* __restrict__ tgt,
+        const int32_t* __restrict__ idx, int64_t n, int n_hidden, int n_params, float loss_eps,
+        float grad_scale, float* __restrict__ partials, float* __restrict__ loss_part,
+        int32_t* __restrict__ tile_bad, float* __restrict__ genc, int fcol, float* __restrict__ act,
+        float* __restrict__ rgb, LcgGather lg) {
+    constexpr int NT = 64 * fp32_train_waves<ACT>();
     extern __shared__ __attribute__((aligned(16))) float smem[];
-    float* hs = smem;                                     // (n_hidden+1) x [64][kLd]
-    float* dbuf0 = hs + (n_hidden + 1) * kTile * kLd;     // 2 x [64][kLd]
+    __shared__ float wsum[kChainWaves];
+    float* hs = smem;                                     // h_0 .. h_H, each [64][kLd]
+    float* dbuf0 = hs + (n_hidden + 1) * kTile * kLd;     // deltas, double-buffered [64][kLd]
     float* dbuf1 = dbuf0 + kTile * kLd;
     float* dout = dbuf1 + kTile * kLd;                    // [64][4]: dL/d(network output)
     float* fout = dout + kTile * 4;                       // [64][4]: network output
+    auto hrow = [&](int l) { return hs + l * kTile * kLd; };
 
-    // The wave index is uniform across the wave; saying so lets weight
-    // addresses that depend on it use scalar loads.
+    // The wave index is uniform across the wave; saying so lets addresses that
+    // depend on it use scalar registers.
     const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int64_t tile = blockIdx.x;
-    const int64_t row = tile * kTile + lane;
-    const bool valid = row < n;
-    // record read for this slot: idx[row] or the LCG orbit for a gathered batch, else row
-    const int64_t src = !valid ? 0 : gather_row(idx, lg, row);
-    float* part = partials + tile * (int64_t)n_params;
-    const int f0 = FPW * wave;                            // this wave's first feature (output layer)
     const int g = lane >> 4, j = lane & 15;               // MFMA lane group and column
-    const int bro = wave >> 2, bco = wave & 3;            // this wave's block row and column
-
-    // Stage the tile's inputs as h_0 (zeros past the end of the batch).
-    for (int i = tid; i < kTile * 16; i += NT) {
-        const int s = i >> 4, q = i & 15;
-        const int64_t r = tile * kTile + s;
-        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (r < n) v = reinterpret_cast<const float4*>(enc + gather_row(idx, lg, r) * kEncWidth)[q];
-        *reinterpret_cast<float4*>(hs + s * kLd + 4 * q) = v;
-    }
-    __syncthreads();
-
-    // Forward: z = W_l h, wave w the block (out features 16 bro.., samples
-    // 16 bco..).  A: lane (g, i) takes W_l[16 bro + i][16g + t]; B: lane (g, j)
-    // takes h[16 bco + j][16g + t]; D: lane (g, j) ends with out features
-    // 16 bro + 4g .. +3 of sample 16 bco + j.  Layer l's weights start at
-    // w + l * 64 * 64 (the input layer is 64 x 64 too).
+    const bool chain = wave < kChainWaves;
+    const int64_t tile = blockIdx.x;
+    const int sl = 16 * (chain ? wave : 0) + j;           // a chain lane's record in the tile
+    const int64_t row = tile * kTile + sl;
+    const bool valid = chain && row < n;
+    // record read for this slot: idx[row] or the LCG orbit for a gathered batch, else row
+    const int64_t src = valid ? gather_row(idx, lg, row) : 0;
+    const bool out_lane = chain && g == 0;                // lanes 0..15 hold a record's outputs
+    float* part = partials + tile * (int64_t)n_params;
     const int64_t n_tiles = gridDim.x;
     float* act_t = act + tile * (int64_t)(n_hidden * kTile * kW);
     float* act_y = act + n_tiles * (int64_t)(n_hidden * kTile * kW);
@@ -298,204 +289,321 @@ __global__ __launch_bounds__(64 * NWV) void k_train_fp32(const float* __restrict
             if (to_lds) *l = *gp; else *gp = *l;
         }
     };
+
+    // ---- h_0, targets and reflectance factor of the lane's record ----------
+    float a[16];   // chain: a[4b + r] = neuron 16b + 4g + r of record sl (activations, later deltas)
+    float r[kNOut] = {1.f, 1.f, 1.f}, t[kNOut] = {0.f, 0.f, 0.f};
+    if (chain) {
+        // record src (record 0 for slots past the end, whose features are then zeroed)
+        const float* er = enc + src * kEncWidth;
+        float4 v[4];
+        #pragma unroll
+        for (int b = 0; b < 4; ++b) v[b] = *reinterpret_cast<const float4*>(er + 16 * b + 4 * g);
+        #pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            if (!valid) v[b] = make_float4(0.f, 0.f, 0.f, 0.f);
+            a[4 * b] = v[b].x; a[4 * b + 1] = v[b].y; a[4 * b + 2] = v[b].z; a[4 * b + 3] = v[b].w;
+            *reinterpret_cast<float4*>(hs + sl * kLd + 16 * b + 4 * g) = v[b];
+        }
+        if (out_lane && valid) {
+            if (fcol) {
+                #pragma unroll
+                for (int o = 0; o < kNOut; ++o) r[o] = er[fcol + o] + er[fcol + 3 + o];
+            }
+            if (ACT != kActStore) {
+                #pragma unroll
+                for (int o = 0; o < kNOut; ++o) t[o] = tgt[src * 3 + o];
+            }
+        }
+    }
     if (ACT == kActLoad) {
         copy_act(true);
         __syncthreads();
     }
-    const int n_fwd = ACT == kActLoad ? 0 : n_hidden;   // layers the forward pass computes
-    for (int l = 0; l < n_fwd; ++l) {
-        const float* arow = w + l * kW * kW + (16 * bro + j) * kW + 16 * g;
-        const float* brow = hs + l * kTile * kLd + (16 * bco + j) * kLd + 16 * g;
-        f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-        #pragma unroll
-        for (int t4 = 0; t4 < 4; ++t4) {
-            const float4 a = *reinterpret_cast<const float4*>(arow + 4 * t4);
-            const float4 b = *reinterpret_cast<const float4*>(brow + 4 * t4);
-            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.y, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, b.z, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, b.w, acc, 0, 0, 0);
+
+    // ---- forward: z = W_l h_l; lane (g, i) supplies W_l[16 ob + i][16 obp + 4g + r]
+    // in K step (obp, r), the query kernel's fragment.  The delta buffers are
+    // free until the backward pass, so they double-buffer the layers' weights
+    // in LDS ([64][kLd], row-major): the weight-gradient waves (or, in the
+    // forward-only form, the chain waves) load W_{l+1} while the chain
+    // computes layer l, and a barrier per layer hands it over.
+    const int n_fwd = ACT == kActLoad ? 0 : n_hidden;
+    constexpr int NS = ACT == kActStore ? NT : 64 * kGradWaves;   // threads that stage weights
+    static_assert(kW * 16 == 4 * NS, "four float4 of a layer's weights per staging thread");
+    const bool stager = ACT == kActStore || !chain;
+    const int st = ACT == kActStore ? tid : tid - 64 * kChainWaves;
+    // staging thread st moves float4 st + u NS (u = 0..3): row (st >> 4) + 16 u, column 4 (st & 15)
+    const int srow = st >> 4, scol = 4 * (st & 15);
+    float4 s0, s1, s2, s3;
+    if (n_fwd > 0) {
+        if (stager) {
+            const float* src = w + srow * kW + scol;
+            s0 = *reinterpret_cast<const float4*>(src);
+            s1 = *reinterpret_cast<const float4*>(src + 16 * kW);
+            s2 = *reinterpret_cast<const float4*>(src + 32 * kW);
+            s3 = *reinterpret_cast<const float4*>(src + 48 * kW);
+            float* dst = dbuf0 + srow * kLd + scol;
+            *reinterpret_cast<float4*>(dst) = s0;
+            *reinterpret_cast<float4*>(dst + 16 * kLd) = s1;
+            *reinterpret_cast<float4*>(dst + 32 * kLd) = s2;
+            *reinterpret_cast<float4*>(dst + 48 * kLd) = s3;
         }
-        float* hout = hs + (l + 1) * kTile * kLd + (16 * bco + j) * kLd + 16 * bro + 4 * g;
-        *reinterpret_cast<float4*>(hout) = make_float4(fmaxf(acc[0], 0.f), fmaxf(acc[1], 0.f),
-                                                       fmaxf(acc[2], 0.f), fmaxf(acc[3], 0.f));
         __syncthreads();
     }
-    const float* wout = w + n_hidden * kW * kW;           // [3][64]
-    const float* hlast = hs + n_hidden * kTile * kLd;
-
-    if (ACT == kActStore) {
-        copy_act(false);
-        if (wave != 0) return;            // wave 0 stores the outputs below and returns too
+    for (int l = 0; l < n_fwd; ++l) {
+        const bool more = l + 1 < n_fwd;
+        if (stager && more) {
+            const float* src = w + (l + 1) * kW * kW + srow * kW + scol;
+            s0 = *reinterpret_cast<const float4*>(src);
+            s1 = *reinterpret_cast<const float4*>(src + 16 * kW);
+            s2 = *reinterpret_cast<const float4*>(src + 32 * kW);
+            s3 = *reinterpret_cast<const float4*>(src + 48 * kW);
+        }
+        if (chain) {
+            const float* wl = (l & 1 ? dbuf1 : dbuf0) + j * kLd + 4 * g;
+            f4 fr[16];
+            #pragma unroll
+            for (int k = 0; k < 16; ++k) fr[k] = *reinterpret_cast<const f4*>(wl + 16 * (k & 3) * kLd + 16 * (k >> 2));
+            f4 acc[4];
+            #pragma unroll
+            for (int ob = 0; ob < 4; ++ob) acc[ob] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+            // the four blocks' chains interleaved: consecutive matrix instructions
+            // are independent; each accumulator still takes its K steps in order
+            #pragma unroll
+            for (int obp = 0; obp < 4; ++obp)
+                #pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    #pragma unroll
+                    for (int ob = 0; ob < 4; ++ob)
+                        acc[ob] = __builtin_amdgcn_mfma_f32_16x16x4f32(fr[4 * obp + ob][q], a[4 * obp + q], acc[ob], 0, 0, 0);
+            float* ho = hrow(l + 1) + sl * kLd + 4 * g;
+            #pragma unroll
+            for (int ob = 0; ob < 4; ++ob) {
+                #pragma unroll
+                for (int q = 0; q < 4; ++q) a[4 * ob + q] = acc[ob][q] > 0.0f ? acc[ob][q] : 0.0f;
+                *reinterpret_cast<float4*>(ho + 16 * ob) = make_float4(a[4 * ob], a[4 * ob + 1], a[4 * ob + 2], a[4 * ob + 3]);
+            }
+        }
+        if (stager && more) {
+            float* dst = (l & 1 ? dbuf0 : dbuf1) + srow * kLd + scol;
+            *reinterpret_cast<float4*>(dst) = s0;
+            *reinterpret_cast<float4*>(dst + 16 * kLd) = s1;
+            *reinterpret_cast<float4*>(dst + 32 * kLd) = s2;
+            *reinterpret_cast<float4*>(dst + 48 * kLd) = s3;
+        }
+        __syncthreads();   // W_{l+1} staged; W_l's buffer free
     }
 
-    // Output layer, loss and dL/dy (wave 0, lane = sample).
-    if (wave == 0) {
-        float f[kNOut] = {0.f, 0.f, 0.f};
+    // ---- output layer on the vector ALUs: each lane's partial dot over its 16
+    // neurons, the four lane groups' partials added as (g0 + g1) + (g2 + g3)
+    const float* wout = w + n_hidden * kW * kW;           // [3][64]
+    float f[kNOut] = {0.f, 0.f, 0.f};
+    if (chain) {
         if (ACT == kActLoad) {
-            if (valid) {
+            if (out_lane && valid) {
                 #pragma unroll
                 for (int o = 0; o < kNOut; ++o) f[o] = act_y[row * 4 + o];
             }
         } else {
-            const float* hr = hlast + lane * kLd;
             #pragma unroll
-            for (int k = 0; k < kW; ++k) {
-                const float hv = hr[k];
+            for (int o = 0; o < kNOut; ++o) {
+                const float* wo = wout + o * kW + 4 * g;
+                float p = 0.0f;
                 #pragma unroll
-                for (int o = 0; o < kNOut; ++o) f[o] = fmaf(wout[o * kW + k], hv, f[o]);
+                for (int b = 0; b < 4; ++b) {
+                    const float4 v = *reinterpret_cast<const float4*>(wo + 16 * b);
+                    p = fmaf(v.x, a[4 * b], p);
+                    p = fmaf(v.y, a[4 * b + 1], p);
+                    p = fmaf(v.z, a[4 * b + 2], p);
+                    p = fmaf(v.w, a[4 * b + 3], p);
+                }
+                const float s1 = p + __shfl_xor(p, 16, 64);
+                f[o] = s1 + __shfl_xor(s1, 32, 64);
             }
         }
-        float r[kNOut] = {1.f, 1.f, 1.f};
-        if (fcol) {
-            const float* h0 = hs + lane * kLd;
+    }
+    if (ACT == kActStore) {
+        if (out_lane && valid) {
             #pragma unroll
-            for (int o = 0; o < kNOut; ++o) r[o] = h0[fcol + o] + h0[fcol + 3 + o];
-        }
-        if (ACT == kActStore) {
-            if (valid) {
-                #pragma unroll
-                for (int o = 0; o < kNOut; ++o) {
-                    rgb[row * 3 + o] = f[o] * r[o];
-                    act_y[row * 4 + o] = f[o];
-                }
-                act_y[row * 4 + 3] = 0.0f;
+            for (int o = 0; o < kNOut; ++o) {
+                rgb[row * 3 + o] = f[o] * r[o];
+                act_y[row * 4 + o] = f[o];
             }
-            return;
+            act_y[row * 4 + 3] = 0.0f;
         }
-        float d[kNOut] = {0.f, 0.f, 0.f};
-        float lterm = 0.0f;
-        if (valid) {
-            if (UPSTREAM) {
-                #pragma unroll
-                for (int o = 0; o < kNOut; ++o) d[o] = tgt[src * 3 + o] * grad_scale * r[o];
-            } else {
-                float y[kNOut];
-                #pragma unroll
-                for (int o = 0; o < kNOut; ++o) y[o] = f[o] * r[o];
-                const float lum = (y[0] + y[1] + y[2]) * (1.0f / 3.0f);
-                const float inv_den = 1.0f / fmaf(lum, lum, loss_eps);
-                #pragma unroll
-                for (int o = 0; o < kNOut; ++o) {
-                    const float diff = y[o] - tgt[src * 3 + o];
-                    lterm = fmaf(diff * diff, inv_den, lterm);
-                    d[o] = 2.0f * diff * inv_den * grad_scale * r[o];
-                }
+        __syncthreads();
+        copy_act(false);
+        return;
+    }
+
+    // ---- loss (Eq. 5) and dL/dy in the output lanes --------------------------
+    float d[kNOut] = {0.f, 0.f, 0.f};
+    float lterm = 0.0f;
+    if (out_lane && valid) {
+        if (UPSTREAM) {
+            #pragma unroll
+            for (int o = 0; o < kNOut; ++o) d[o] = t[o] * grad_scale * r[o];
+        } else {
+            float y[kNOut];
+            #pragma unroll
+            for (int o = 0; o < kNOut; ++o) y[o] = f[o] * r[o];
+            const float lum = (y[0] + y[1] + y[2]) * (1.0f / 3.0f);
+            const float inv_den = 1.0f / fmaf(lum, lum, loss_eps);
+            #pragma unroll
+            for (int o = 0; o < kNOut; ++o) {
+                const float diff = y[o] - t[o];
+                lterm = fmaf(diff * diff, inv_den, lterm);
+                d[o] = 2.0f * diff * inv_den * grad_scale * r[o];
             }
         }
-        *reinterpret_cast<float4*>(dout + lane * 4) = make_float4(d[0], d[1], d[2], 0.f);
-        if (GENC) *reinterpret_cast<float4*>(fout + lane * 4) = make_float4(f[0], f[1], f[2], 0.f);
+    }
+    if (chain) {
+        if (out_lane) {
+            *reinterpret_cast<float4*>(dout + sl * 4) = make_float4(d[0], d[1], d[2], 0.f);
+            if (GENC) *reinterpret_cast<float4*>(fout + sl * 4) = make_float4(f[0], f[1], f[2], 0.f);
+        }
         const float tot = wave_sum_compensated(lterm);
-        if (lane == 0) loss_part[tile] = tot;
+        if (lane == 0) wsum[wave] = tot;
     }
-    __syncthreads();
+    __syncthreads();   // dL/dy and h_0 .. h_H are in LDS
 
-    // delta_H = W_H^T dL/dy, masked by ReLU'(z_H); wave w: features f0..f0+FPW-1.
-    {
-        const float4 dv = *reinterpret_cast<const float4*>(dout + lane * 4);
-        const float* hr = hlast + lane * kLd + f0;
-        float* dst = dbuf0 + lane * kLd + f0;
-        #pragma unroll
-        for (int j = 0; j < FPW; ++j) {
-            const int i = f0 + j;
-            float g = wout[i] * dv.x;
-            g = fmaf(wout[kW + i], dv.y, g);
-            g = fmaf(wout[2 * kW + i], dv.z, g);
-            dst[j] = hr[j] > 0.0f ? g : 0.0f;
-        }
-    }
-    // dW_H[o][i] = sum_s dL/dy[s][o] h_H[s][i]; wave o < 3, lane = i.
     bool bad = false;   // any non-finite weight-gradient partial in this tile
-    if (wave < kNOut) {
-        float acc = 0.0f;
-        for (int s = 0; s < kTile; ++s) acc = fmaf(dout[s * 4 + wave], hlast[s * kLd + lane], acc);
-        __builtin_nontemporal_store(acc, &part[(n_params - kNOut * kW) + wave * kW + lane]);
-        bad |= !isfinite(acc);
-    }
-    __syncthreads();
-
     float* dcur = dbuf0;
     float* dnxt = dbuf1;
-    int off = n_params - kNOut * kW;
-    for (int l = n_hidden - 1; l >= 0; --l) {
-        const int cols = (l == 0) ? kEncWidth : kW;
-        off -= kW * cols;
-        const float* wlay = w + off;
-        const float* hl = hs + l * kTile * kLd;
-        // dW_l[o][i] = sum_s delta[s][o] h_l[s][i], wave w the block (rows
-        // 16 bro.., columns 16 bco..).  In step t lane group g takes sample
-        // s = 16 (t / 4) + 4g + t % 4, so the four groups read rows 4 apart
-        // (16 banks apart at the 68-float stride; rows 16 apart would share
-        // banks).  A: lane (g, i) takes delta[s][16 bro + i]; B: lane (g, j)
-        // takes h_l[s][16 bco + j]; D: lane (g, j) ends with rows
-        // 16 bro + 4g .. +3 of column 16 bco + j.
-        {
-            const float* da = dcur + 4 * g * kLd + 16 * bro + j;
-            const float* hb = hl + 4 * g * kLd + 16 * bco + j;
-            f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+    if (chain) {
+        // delta_H = W_H^T dL/dy, masked by ReLU'(z_H), for the lane's 16 neurons
+        float dv[kNOut];
+        #pragma unroll
+        for (int o = 0; o < kNOut; ++o) dv[o] = __shfl(d[o], j, 64);
+        const float* hl = hrow(n_hidden) + sl * kLd + 4 * g;
+        #pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const float4 hv = *reinterpret_cast<const float4*>(hl + 16 * b);
+            const float hq[4] = {hv.x, hv.y, hv.z, hv.w};
             #pragma unroll
-            for (int t = 0; t < 16; ++t) {
-                const int so = (16 * (t >> 2) + (t & 3)) * kLd;
-                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(da[so], hb[so], acc, 0, 0, 0);
+            for (int q = 0; q < 4; ++q) {
+                const int i = 16 * b + 4 * g + q;
+                float s = wout[i] * dv[0];
+                s = fmaf(wout[kW + i], dv[1], s);
+                s = fmaf(wout[2 * kW + i], dv[2], s);
+                a[4 * b + q] = hq[q] > 0.0f ? s : 0.0f;
             }
-            float* dst = part + off + (16 * bro + 4 * g) * cols + 16 * bco + j;
-            #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                // streamed past the caches: read once, by the reduction
-                __builtin_nontemporal_store(acc[r], dst + r * cols);
-                bad |= !isfinite(acc[r]);
-            }
+            *reinterpret_cast<float4*>(dcur + sl * kLd + 16 * b + 4 * g) =
+                make_float4(a[4 * b], a[4 * b + 1], a[4 * b + 2], a[4 * b + 3]);
         }
-        // delta_l = W_l^T delta_{l+1}, masked (l >= 1); or dL/dh_0 (l == 0).
-        // Wave w the block (features 16 bro.., samples 16 bco..).  A: lane (g, i)
-        // takes W_l[16g + t][16 bro + i]; B: lane (g, j) takes
-        // delta[16 bco + j][16g + t]; D: lane (g, j) ends with features
-        // 16 bro + 4g .. +3 of sample 16 bco + j.
-        if (l >= 1 || GENC) {
-            const float* wa = wlay + 16 * g * cols + 16 * bro + j;
-            const float* db = dcur + (16 * bco + j) * kLd + 16 * g;
-            f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+    } else {
+        // dW_H[o][i] = sum_s dL/dy[s][o] h_H[s][i]: one (o, i) per thread
+        const int tt = tid - 64 * kChainWaves;
+        if (tt < kNOut * kW) {
+            const int o = tt >> 6, i = tt & 63;
+            const float* hl = hrow(n_hidden);
+            float acc = 0.0f;
+            for (int s = 0; s < kTile; ++s) acc = fmaf(dout[s * 4 + o], hl[s * kLd + i], acc);
+            __builtin_nontemporal_store(acc, &part[(n_params - kNOut * kW) + o * kW + i]);
+            bad |= !isfinite(acc);
+        }
+    }
+    __syncthreads();   // delta_H is in LDS
+
+    for (int l = n_hidden - 1; l >= 0; --l) {
+        const float* hl = hrow(l);
+        if (!chain) {
+            // dW_l[o][i] = sum_s delta_{l+1}[s][o] h_l[s][i]; wave nb = wave - 4
+            // the column block 16 nb.., all four row blocks.  In step t lane
+            // group g takes sample s = 16 (t / 4) + 4g + t % 4.  A: lane (g, i)
+            // takes delta[s][16 mb + i]; B: lane (g, j) takes h_l[s][16 nb + j];
+            // D: lane (g, j) ends with rows 16 mb + 4g .. +3 of column 16 nb + j.
+            const int nb = wave - kChainWaves;
+            const float* da = dcur + 4 * g * kLd + j;
+            const float* hb = hl + 4 * g * kLd + 16 * nb + j;
+            f4 acc[4];
             #pragma unroll
-            for (int t4 = 0; t4 < 4; ++t4) {
-                const float4 b = *reinterpret_cast<const float4*>(db + 4 * t4);
-                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(wa[(4 * t4) * cols], b.x, acc, 0, 0, 0);
-                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(wa[(4 * t4 + 1) * cols], b.y, acc, 0, 0, 0);
-                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(wa[(4 * t4 + 2) * cols], b.z, acc, 0, 0, 0);
-                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(wa[(4 * t4 + 3) * cols], b.w, acc, 0, 0, 0);
+            for (int mb = 0; mb < 4; ++mb) acc[mb] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+            #pragma unroll
+            for (int tq = 0; tq < 16; ++tq) {
+                const int so = (16 * (tq >> 2) + (tq & 3)) * kLd;
+                const float bv = hb[so];
+                #pragma unroll
+                for (int mb = 0; mb < 4; ++mb)
+                    acc[mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(da[so + 16 * mb], bv, acc[mb], 0, 0, 0);
             }
-            const int sm = 16 * bco + j;                  // this lane's sample in the tile
-            const int fb = 16 * bro + 4 * g;              // its first feature
-            if (l >= 1) {
-                const float4 hv = *reinterpret_cast<const float4*>(hl + sm * kLd + fb);
-                *reinterpret_cast<float4*>(dnxt + sm * kLd + fb) =
-                    make_float4(hv.x > 0.0f ? acc[0] : 0.0f, hv.y > 0.0f ? acc[1] : 0.0f,
-                                hv.z > 0.0f ? acc[2] : 0.0f, hv.w > 0.0f ? acc[3] : 0.0f);
-            } else {
-                const int64_t srow = tile * kTile + sm;
-                if (srow < n) {
-                    // the loss scale of the upstream gradient divided out
-                    const float inv_scale = 1.0f / grad_scale;
+            float* dst = part + l * kW * kW + 4 * g * kW + 16 * nb + j;
+            #pragma unroll
+            for (int mb = 0; mb < 4; ++mb)
+                #pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    // streamed past the caches: read once, by the reduction
+                    __builtin_nontemporal_store(acc[mb][q], dst + (16 * mb + q) * kW);
+                    bad |= !isfinite(acc[mb][q]);
+                }
+        } else if (l >= 1 || GENC) {
+            // W_l^T delta_{l+1}: lane (g, i) supplies W_l[16 obp + 4g + r][16 ob + i]
+            // in K step (obp, r); a holds delta_{l+1} in the same order.
+            const float* wl = w + l * kW * kW + 4 * g * kW + j;
+            f4 acc[4];
+            #pragma unroll
+            for (int ob = 0; ob < 4; ++ob) acc[ob] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+            #pragma unroll
+            for (int obp = 0; obp < 4; ++obp)
+                #pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const float* wr = wl + (16 * obp + q) * kW;
                     #pragma unroll
-                    for (int r = 0; r < 4; ++r) acc[r] *= inv_scale;
+                    for (int ob = 0; ob < 4; ++ob)
+                        acc[ob] = __builtin_amdgcn_mfma_f32_16x16x4f32(wr[16 * ob], a[4 * obp + q], acc[ob], 0, 0, 0);
+                }
+
+            if (l >= 1) {
+                // delta_l = (W_l^T delta_{l+1}) masked by ReLU'(z_l)
+                const float* hr = hl + sl * kLd + 4 * g;
+                #pragma unroll
+                for (int ob = 0; ob < 4; ++ob) {
+                    const float4 hv = *reinterpret_cast<const float4*>(hr + 16 * ob);
+                    a[4 * ob] = hv.x > 0.0f ? acc[ob][0] : 0.0f;
+                    a[4 * ob + 1] = hv.y > 0.0f ? acc[ob][1] : 0.0f;
+                    a[4 * ob + 2] = hv.z > 0.0f ? acc[ob][2] : 0.0f;
+                    a[4 * ob + 3] = hv.w > 0.0f ? acc[ob][3] : 0.0f;
+                    *reinterpret_cast<float4*>(dnxt + sl * kLd + 16 * ob + 4 * g) =
+                        make_float4(a[4 * ob], a[4 * ob + 1], a[4 * ob + 2], a[4 * ob + 3]);
+                }
+            } else if (valid) {
+                // dL/dh_0 with the loss scale of the upstream gradient divided out
+                const float inv_scale = 1.0f / grad_scale;
+                #pragma unroll
+                for (int ob = 0; ob < 4; ++ob) {
+                    const int fb = 16 * ob + 4 * g;               // the lane's first feature
+                    float v[4];
+                    #pragma unroll
+                    for (int q = 0; q < 4; ++q) v[q] = acc[ob][q] * inv_scale;
                     if (fcol) {
                         // d(f_c R_c)/d(albedo column) = f_c on the diffuse and specular column.
-                        const int64_t ssrc = gather_row(idx, lg, srow);
                         #pragma unroll
-                        for (int r = 0; r < 4; ++r) {
-                            int c = fb + r - fcol;
+                        for (int q = 0; q < 4; ++q) {
+                            int c = fb + q - fcol;
                             if (c >= 0 && c < 6) {
                                 c = c >= 3 ? c - 3 : c;
-                                acc[r] = fmaf(tgt[ssrc * 3 + c], fout[sm * 4 + c], acc[r]);
+                                v[q] = fmaf(tgt[src * 3 + c], fout[sl * 4 + c], v[q]);
                             }
                         }
                     }
-                    *reinterpret_cast<float4*>(genc + srow * kEncWidth + fb) =
-                        make_float4(acc[0], acc[1], acc[2], acc[3]);
+                    *reinterpret_cast<float4*>(genc + row * kEncWidth + fb) = make_float4(v[0], v[1], v[2], v[3]);
                 }
             }
         }
-        __syncthreads();
-        float* t = dcur; dcur = dnxt; dnxt = t;
+        if (l >= 1) {
+            __syncthreads();   // delta_l is in LDS; delta_{l+1} has been read
+            float* tp = dcur; dcur = dnxt; dnxt = tp;
+        }
+    }
+    if (tid == 0) {
+        // compensated combine of the chain waves' loss sums, in wave order
+        float ts = 0.0f, tc = 0.0f;
+        for (int wv = 0; wv < kChainWaves; ++wv) {
+            const float x = wsum[wv], u = ts + x;
+            tc += fabsf(ts) >= fabsf(x) ? (ts - u) + x : (x - u) + ts;
+            ts = u;
+        }
+        loss_part[tile] = ts + tc;
     }
     const int any_bad = __syncthreads_or(bad ? 1 : 0);
     if (tid == 0) tile_bad[tile] = any_bad ? 1 : 0;
@@ -553,10 +661,7 @@ size_t fp32_train_lds_bytes(int n_hidden) {
     return ((size_t)(n_hidden + 1) * kTile * kLd + 2 * kTile * kLd + 2 * kTile * 4) * sizeof(float);
 }
 
-// Waves per 64-record training tile of the FP32 form.
-constexpr int kTrainWaves = 16;
-
-template <bool UP, bool GE, int NWV, int ACT = kActNone>
+template <bool UP, bool GE, int ACT = kActNone>
 hipError_t train_fp32_launch(const Geo& d, const float* w, const float* enc, const float* tgt,
                              const int32_t* idx, int64_t n, float loss_eps, float grad_scale,
                              float* partials, float* loss_part, int32_t* tile_bad, float* genc,
@@ -565,10 +670,11 @@ hipError_t train_fp32_launch(const Geo& d, const float* w, const float* enc, con
     const int64_t tiles = (n + kTile - 1) / kTile;
     if (tiles == 0) return hipSuccess;
     const size_t lds = fp32_train_lds_bytes(d.H);
-    auto k = k_train_fp32<UP, GE, NWV, ACT>;
+    auto k = k_train_fp32<UP, GE, ACT>;
     (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(k, dim3((unsigned)tiles), dim3(64 * NWV), lds, s, w, enc, tgt, idx, n, d.H,
-                       d.n_params(), loss_eps, grad_scale, partials, loss_part, tile_bad, genc, d.F, act, rgb, lg);
+    hipLaunchKernelGGL(k, dim3((unsigned)tiles), dim3(64 * fp32_train_waves<ACT>()), lds, s, w, enc, tgt, idx, n,
+                       d.H, d.n_params(), loss_eps, grad_scale, partials, loss_part, tile_bad, genc, d.F, act, rgb,
+                       lg);
     return hipGetLastError();
 }
 
@@ -577,28 +683,27 @@ hipError_t launch_train_fp32(const Geo& d, const float* w, const float* enc, con
                              float* partials, float* loss_part, int32_t* tile_bad, float* genc,
                              hipStream_t s, const float* act, LcgGather lg) {
     if (!upstream)
-        return train_fp32_launch<false, false, kTrainWaves>(d, w, enc, tgt, idx, n, loss_eps, grad_scale,
-                                                            partials, loss_part, tile_bad, genc, s, nullptr,
-                                                            nullptr, lg);
+        return train_fp32_launch<false, false>(d, w, enc, tgt, idx, n, loss_eps, grad_scale, partials, loss_part,
+                                               tile_bad, genc, s, nullptr, nullptr, lg);
     float* a = const_cast<float*>(act);
     if (act) {
         if (genc)
-            return train_fp32_launch<true, true, kTrainWaves, kActLoad>(d, w, enc, tgt, idx, n, loss_eps, grad_scale,
-                                                                        partials, loss_part, tile_bad, genc, s, a);
-        return train_fp32_launch<true, false, kTrainWaves, kActLoad>(d, w, enc, tgt, idx, n, loss_eps, grad_scale,
-                                                                     partials, loss_part, tile_bad, genc, s, a);
+            return train_fp32_launch<true, true, kActLoad>(d, w, enc, tgt, idx, n, loss_eps, grad_scale, partials,
+                                                           loss_part, tile_bad, genc, s, a);
+        return train_fp32_launch<true, false, kActLoad>(d, w, enc, tgt, idx, n, loss_eps, grad_scale, partials,
+                                                        loss_part, tile_bad, genc, s, a);
     }
     if (genc)
-        return train_fp32_launch<true, true, kTrainWaves>(d, w, enc, tgt, idx, n, loss_eps, grad_scale,
-                                                          partials, loss_part, tile_bad, genc, s);
-    return train_fp32_launch<true, false, kTrainWaves>(d, w, enc, tgt, idx, n, loss_eps, grad_scale,
-                                                       partials, loss_part, tile_bad, genc, s);
+        return train_fp32_launch<true, true>(d, w, enc, tgt, idx, n, loss_eps, grad_scale, partials, loss_part,
+                                             tile_bad, genc, s);
+    return train_fp32_launch<true, false>(d, w, enc, tgt, idx, n, loss_eps, grad_scale, partials, loss_part,
+                                          tile_bad, genc, s);
 }
 
 hipError_t launch_fwd_train_fp32(const Geo& d, const float* w, const float* enc, int64_t n, float* act,
                                  float* rgb, hipStream_t s) {
-    return train_fp32_launch<true, false, kTrainWaves, kActStore>(d, w, enc, nullptr, nullptr, n, 0.0f, 1.0f,
-                                                                  nullptr, nullptr, nullptr, nullptr, s, act, rgb);
+    return train_fp32_launch<true, false, kActStore>(d, w, enc, nullptr, nullptr, n, 0.0f, 1.0f, nullptr, nullptr,
+                                                     nullptr, nullptr, s, act, rgb);
 }
 
 }  // namespace nrc

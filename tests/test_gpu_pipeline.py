@@ -11,7 +11,7 @@ torch = pytest.importorskip("torch")
 import synthdata as sd
 from oracle import nrc_oracle as O
 from tests import rounding_model as RM
-from tests.test_gpu_parity import MODEL_TOL, dev, l2_err, make_cache, rounded_input, state_of
+from tests.test_gpu_parity import MODEL_TOL, check_fp32_adam_step, dev, l2_err, make_cache, rounded_input, state_of
 
 pytestmark = pytest.mark.gpu
 
@@ -76,23 +76,6 @@ def test_indexed_step_equals_step_on_gathered_batch(N, prec):
     lb, sb = N.nrc_train_step(b, enc[il].contiguous(), y[il].contiguous())
     assert torch.equal(la, lb) and int(sa.item()) == int(sb.item()) == 0
     assert np.array_equal(a.get_weights(), b.get_weights())
-
-
-def check_fp32_adam_step(w_gpu, st_before, w_ref, x, y):
-    """FP32 weights after one Adam step against the oracle's step from the same
-    state.  Adam moves a weight by about lr * sign(g) when its moments are young,
-    so a gradient component within FP32 rounding of zero (the GPU sums 16,384
-    products per component in FP32 tiles of 64: relative error of order 1e-6
-    of the sum of magnitudes) can take the other sign and move by 2 lr.  Such
-    flips are allowed only where the FP64 gradient is below 1e-6 of its norm,
-    and at most a handful; every other weight must match to 1e-5 normwise."""
-    _, g = O.gradient(st_before, x, y)
-    d = np.asarray(w_gpu, np.float64) - w_ref
-    flipped = np.abs(d) > 1e-3                       # a flip moves by 2 lr = 0.02
-    assert flipped.sum() <= 8, int(flipped.sum())
-    assert np.all(np.abs(g[flipped]) <= 1e-6 * np.linalg.norm(g)), (np.abs(g[flipped]), np.linalg.norm(g))
-    rest = np.where(flipped, 0.0, d)
-    assert np.linalg.norm(rest) / np.linalg.norm(w_ref) <= 1e-5
 
 
 @pytest.mark.parametrize("prec", ["fp32", "fp16", "bf16"])
