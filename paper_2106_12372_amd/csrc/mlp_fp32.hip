@@ -488,8 +488,8 @@ __global__ __launch_bounds__(64 * (kChainWaves + kGradWaves)) void k_train_fp32(
                 s = fmaf(wout[2 * kW + i], dv[2], s);
                 a[4 * b + q] = hq[q] > 0.0f ? s : 0.0f;
             }
-            *reinterpret_cast<float4*>(dcur + sl * kLd + 16 * b + 4 * g) =
-                make_float4(a[4 * b], a[4 * b + 1], a[4 * b + 2], a[4 * b + 3]);
+            #pragma unroll
+            for (int q = 0; q < 4; ++q) dcur[(16 * b + 4 * g + q) * kLd + sl] = a[4 * b + q];
         }
     } else {
         // dW_H[o][i] = sum_s dL/dy[s][o] h_H[s][i]: one (o, i) per thread
@@ -514,18 +514,23 @@ __global__ __launch_bounds__(64 * (kChainWaves + kGradWaves)) void k_train_fp32(
             // takes delta[s][16 mb + i]; B: lane (g, j) takes h_l[s][16 nb + j];
             // D: lane (g, j) ends with rows 16 mb + 4g .. +3 of column 16 nb + j.
             const int nb = wave - kChainWaves;
-            const float* da = dcur + 4 * g * kLd + j;
+            const float* da = dcur + j * kLd + 4 * g;                 // delta feature-major
             const float* hb = hl + 4 * g * kLd + 16 * nb + j;
             f4 acc[4];
             #pragma unroll
             for (int mb = 0; mb < 4; ++mb) acc[mb] = f4{0.0f, 0.0f, 0.0f, 0.0f};
             #pragma unroll
-            for (int tq = 0; tq < 16; ++tq) {
-                const int so = (16 * (tq >> 2) + (tq & 3)) * kLd;
-                const float bv = hb[so];
+            for (int t = 0; t < 4; ++t) {
+                f4 av[4];
                 #pragma unroll
-                for (int mb = 0; mb < 4; ++mb)
-                    acc[mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(da[so + 16 * mb], bv, acc[mb], 0, 0, 0);
+                for (int mb = 0; mb < 4; ++mb) av[mb] = *reinterpret_cast<const f4*>(da + 16 * mb * kLd + 16 * t);
+                #pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const float bv = hb[(16 * t + u) * kLd];
+                    #pragma unroll
+                    for (int mb = 0; mb < 4; ++mb)
+                        acc[mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[mb][u], bv, acc[mb], 0, 0, 0);
+                }
             }
             float* dst = part + l * kW * kW + 4 * g * kW + 16 * nb + j;
             #pragma unroll
@@ -563,8 +568,8 @@ __global__ __launch_bounds__(64 * (kChainWaves + kGradWaves)) void k_train_fp32(
                     a[4 * ob + 1] = hv.y > 0.0f ? acc[ob][1] : 0.0f;
                     a[4 * ob + 2] = hv.z > 0.0f ? acc[ob][2] : 0.0f;
                     a[4 * ob + 3] = hv.w > 0.0f ? acc[ob][3] : 0.0f;
-                    *reinterpret_cast<float4*>(dnxt + sl * kLd + 16 * ob + 4 * g) =
-                        make_float4(a[4 * ob], a[4 * ob + 1], a[4 * ob + 2], a[4 * ob + 3]);
+                    #pragma unroll
+                    for (int q = 0; q < 4; ++q) dnxt[(16 * ob + 4 * g + q) * kLd + sl] = a[4 * ob + q];
                 }
             } else if (valid) {
                 // dL/dh_0 with the loss scale of the upstream gradient divided out
