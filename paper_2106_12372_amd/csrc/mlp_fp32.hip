@@ -132,7 +132,7 @@ __device__ inline void mlp_query_mfma(const f4* __restrict__ sw, int H, int lane
             #pragma unroll
             for (int ob = 0; ob < 4; ++ob)
                 #pragma unroll
-                for (int r = 0; r < 4; ++r) act[c][4 * ob + r] = fmaxf(acc[c][ob][r], 0.0f);
+                for (int r = 0; r < 4; ++r) act[c][4 * ob + r] = relu(acc[c][ob][r]);
     }
     #pragma unroll
     for (int o = 0; o < kNOut; ++o) {
@@ -380,7 +380,7 @@ __global__ __launch_bounds__(64 * (kChainWaves + kGradWaves)) void k_train_fp32(
             #pragma unroll
             for (int ob = 0; ob < 4; ++ob) {
                 #pragma unroll
-                for (int q = 0; q < 4; ++q) a[4 * ob + q] = acc[ob][q] > 0.0f ? acc[ob][q] : 0.0f;
+                for (int q = 0; q < 4; ++q) a[4 * ob + q] = relu(acc[ob][q]);
                 *reinterpret_cast<float4*>(ho + 16 * ob) = make_float4(a[4 * ob], a[4 * ob + 1], a[4 * ob + 2], a[4 * ob + 3]);
             }
         }

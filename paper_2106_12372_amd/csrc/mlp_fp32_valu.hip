@@ -38,7 +38,7 @@ __device__ inline void layer_fp32(float (&h)[kW], const float* __restrict__ wl) 
         z[o] = acc;
     }
     #pragma unroll
-    for (int o = 0; o < kW; ++o) h[o] = fmaxf(z[o], 0.0f);
+    for (int o = 0; o < kW; ++o) h[o] = relu(z[o]);
 }
 
 // The network on one record whose 64 input features are in h.
@@ -180,8 +180,8 @@ __global__ __launch_bounds__(64 * NWV) void k_train_fp32_valu(const float* __res
         #pragma unroll
         for (int j4 = 0; j4 < FPW / 4; ++j4)
             *reinterpret_cast<float4*>(hout + f0 + 4 * j4) =
-                make_float4(fmaxf(acc[4 * j4], 0.f), fmaxf(acc[4 * j4 + 1], 0.f),
-                            fmaxf(acc[4 * j4 + 2], 0.f), fmaxf(acc[4 * j4 + 3], 0.f));
+                make_float4(relu(acc[4 * j4]), relu(acc[4 * j4 + 1]),
+                            relu(acc[4 * j4 + 2]), relu(acc[4 * j4 + 3]));
         __syncthreads();
     }
     const float* wout = w + n_hidden * kW * kW;           // [3][64]

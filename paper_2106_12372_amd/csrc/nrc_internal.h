@@ -127,6 +127,11 @@ __device__ inline void reflectance_row(const float (&h)[kEncWidth], int fcol, fl
                                           : 1.0f;
 }
 
+// ReLU as the IEEE maximum of x and +0: one v_maximum3_f32 on gfx950, where
+// fmaxf's rule for NaN operands first needs a canonicalising max.  A NaN
+// propagates instead of becoming 0; -0 becomes +0.
+__device__ inline float relu(float x) { return __builtin_elementwise_maximum(x, 0.0f); }
+
 // Neumaier-compensated sum of one float per lane over the 64 lanes of a wave,
 // in a fixed butterfly order; every lane ends with the same value.  Each pair
 // sum is formed with the lower lane's operand first and carries both lanes'
