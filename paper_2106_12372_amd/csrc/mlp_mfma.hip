@@ -440,9 +440,13 @@ __global__ __launch_bounds__(64 * NW) void k_fwd_raw_mfma(const T* __restrict__ 
 }
 
 // Encodes the lane's record x and stores its 64 features, rounded to T, at
-// dst (a 16-byte aligned LDS row).
+// dst (a 16-byte aligned LDS row), followed by the record's reflectance
+// factor alpha + beta (Sec. 5) as 3 floats in the row's 16 spare bytes: the
+// rounded diffuse plus the rounded specular albedo per channel, the same
+// arithmetic reflectance_operand does on the B operand, here in the lane that
+// holds the record instead of three shuffles per channel and column.
 template <typename T, int PRESET, int LAYOUT>
-__device__ inline void encode_to_lds(const float* x, T* dst) {
+__device__ inline void encode_to_lds(const float* x, T* dst, int fcol) {
     using V = typename Vec8<T>::type;
     float f[64];
     encode_record<PRESET, LAYOUT>(x, f);
@@ -452,6 +456,13 @@ __device__ inline void encode_to_lds(const float* x, T* dst) {
         const f32x4 hi = f32x4{f[8 * q + 4], f[8 * q + 5], f[8 * q + 6], f[8 * q + 7]};
         *reinterpret_cast<V*>(dst + 8 * q) = pack8<T, V>(lo, hi);
     }
+    f32x4 r = f32x4{1.0f, 1.0f, 1.0f, 0.0f};
+    constexpr int ac = PRESET == NRC_PRESET_CONFIG ? kAlbedoColConfig : kAlbedoColPaper;
+    if (fcol) {
+        #pragma unroll
+        for (int c = 0; c < 3; ++c) r[c] = (float)to_t<T>(f[ac + c]) + (float)to_t<T>(f[ac + 3 + c]);
+    }
+    *reinterpret_cast<f32x4*>(dst + 64) = r;
 }
 
 // Orders a wave's LDS accesses: those before complete before those after,
@@ -512,22 +523,23 @@ __global__ __launch_bounds__(64 * NW) void k_fwd_raw_mfma_fixed(const T* __restr
     int64_t tile = (int64_t)blockIdx.x * NW + wave;
     if (tile >= n_tiles) return;
     load_raw(tile);
-    encode_to_lds<T, PRESET, LAYOUT>(x, senc + lane * ROW);
+    encode_to_lds<T, PRESET, LAYOUT>(x, senc + lane * ROW, fcol);
     load_raw(tile + tstride);
     for (; tile < n_tiles; tile += tstride) {
         wave_lds_sync();                   // this tile's rows are written
         V b[COLS][KC];
+        float r[COLS][3];
         #pragma unroll
-        for (int col = 0; col < COLS; ++col)
+        for (int col = 0; col < COLS; ++col) {
             #pragma unroll
             for (int c = 0; c < 2; ++c)
                 b[col][c] = *reinterpret_cast<const V*>(senc + (16 * col + ln) * ROW + 32 * c + 8 * g);
+            const f32x4 rv = *reinterpret_cast<const f32x4*>(senc + (16 * col + ln) * ROW + 64);
+            r[col][0] = rv[0]; r[col][1] = rv[1]; r[col][2] = rv[2];
+        }
         wave_lds_sync();                   // and read by every lane before they are rewritten
-        float r[COLS][3];
-        #pragma unroll
-        for (int col = 0; col < COLS; ++col) reflectance_operand(b[col][1], fcol, ln, r[col]);
         // the next tile's encoding (vector ALUs) beside this tile's network (matrix cores)
-        encode_to_lds<T, PRESET, LAYOUT>(x, senc + lane * ROW);
+        encode_to_lds<T, PRESET, LAYOUT>(x, senc + lane * ROW, fcol);
         load_raw(tile + 2 * tstride);
         f32x4 o[COLS];
         mlp_tile_colwise<T, COLS, NH>(sfr, b, lane, o);
