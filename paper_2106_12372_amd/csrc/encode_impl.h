@@ -94,7 +94,11 @@ __device__ inline void octaves(float p, float* sn, float* cs) {
     }
 }
 
-// The 64 encoded features of one raw record (14 or 16 floats).
+// The encoded features of one raw record (14 or 16 floats) in five parts, so
+// that a caller can spread the work: part 0..2 the frequency encoding of
+// position coordinate 0..2 (features 12c .. 12c + 11), part 3 the one-blobs of
+// the first two angles (36..43), part 4 those of the last two angles and the
+// remaining features (44..63).
 //   config preset: per position coordinate sin, cos of 6 octaves (36), one-blob
 //   of the direction and normal angles (16), roughness, diffuse and specular
 //   albedo (7), five zeros.
@@ -102,12 +106,12 @@ __device__ inline void octaves(float p, float* sn, float* cs) {
 //   one-blob of 1 - exp(-roughness) (4), albedos (6), two ones.
 //   paper-tri preset: as paper with tri(2^d p) in place of sin(2^d pi p).
 //   paper-gauss preset: as paper with Gaussian one-blobs.
-template <int PRESET, int LAYOUT>
-__device__ inline void encode_record(const float* x, float* o) {
+template <int PRESET, int LAYOUT, int PART>
+__device__ inline void encode_part(const float* x, float* o) {
     constexpr bool paper = PRESET != NRC_PRESET_CONFIG;
     constexpr bool gauss = PRESET == NRC_PRESET_PAPER_GAUSS;
-    #pragma unroll
-    for (int c = 0; c < 3; ++c) {
+    if constexpr (PART <= 2) {
+        constexpr int c = PART;
         if (PRESET == NRC_PRESET_PAPER_TRI) {
             #pragma unroll
             for (int d = 0; d < 12; ++d) o[12 * c + d] = tri(x[c] * (float)(1 << d));
@@ -125,33 +129,45 @@ __device__ inline void encode_record(const float* x, float* o) {
                 o[12 * c + 2 * d + 1] = cs[d];
             }
         }
-    }
-    float ang[4];
-    const float* rest;
-    if (LAYOUT == NRC_RAW14) {
-        ang[0] = x[3]; ang[1] = x[4]; ang[2] = x[5]; ang[3] = x[6];
-        rest = x + 7;
     } else {
-        sph(x[3], x[4], x[5], ang[0], ang[1]);
-        sph(x[6], x[7], x[8], ang[2], ang[3]);
-        rest = x + 9;
-    }
-    #pragma unroll
-    for (int a = 0; a < 4; ++a) {
-        if (gauss) one_blob4_gauss(ang[a], o + 36 + 4 * a); else one_blob4(ang[a], o + 36 + 4 * a);
-    }
-    if (paper) {
-        if (gauss) one_blob4_gauss(1.0f - expf(-rest[0]), o + 52); else one_blob4(1.0f - expf(-rest[0]), o + 52);
+        constexpr int a0 = PART == 3 ? 0 : 2;      // first angle of this part
+        float ang[2];
+        if (LAYOUT == NRC_RAW14) {
+            ang[0] = x[3 + a0];
+            ang[1] = x[4 + a0];
+        } else {
+            sph(x[3 + 3 * (a0 / 2)], x[4 + 3 * (a0 / 2)], x[5 + 3 * (a0 / 2)], ang[0], ang[1]);
+        }
         #pragma unroll
-        for (int j = 0; j < 6; ++j) o[56 + j] = rest[1 + j];
-        o[62] = 1.0f;
-        o[63] = 1.0f;
-    } else {
-        #pragma unroll
-        for (int j = 0; j < 7; ++j) o[52 + j] = rest[j];
-        #pragma unroll
-        for (int j = 59; j < 64; ++j) o[j] = 0.0f;
+        for (int a = 0; a < 2; ++a) {
+            if (gauss) one_blob4_gauss(ang[a], o + 36 + 4 * (a0 + a)); else one_blob4(ang[a], o + 36 + 4 * (a0 + a));
+        }
+        if constexpr (PART == 4) {
+            const float* rest = x + (LAYOUT == NRC_RAW14 ? 7 : 9);
+            if (paper) {
+                if (gauss) one_blob4_gauss(1.0f - expf(-rest[0]), o + 52); else one_blob4(1.0f - expf(-rest[0]), o + 52);
+                #pragma unroll
+                for (int j = 0; j < 6; ++j) o[56 + j] = rest[1 + j];
+                o[62] = 1.0f;
+                o[63] = 1.0f;
+            } else {
+                #pragma unroll
+                for (int j = 0; j < 7; ++j) o[52 + j] = rest[j];
+                #pragma unroll
+                for (int j = 59; j < 64; ++j) o[j] = 0.0f;
+            }
+        }
     }
+}
+
+// The 64 encoded features of one raw record: all five parts.
+template <int PRESET, int LAYOUT>
+__device__ inline void encode_record(const float* x, float* o) {
+    encode_part<PRESET, LAYOUT, 0>(x, o);
+    encode_part<PRESET, LAYOUT, 1>(x, o);
+    encode_part<PRESET, LAYOUT, 2>(x, o);
+    encode_part<PRESET, LAYOUT, 3>(x, o);
+    encode_part<PRESET, LAYOUT, 4>(x, o);
 }
 
 }  // namespace nrc

@@ -179,10 +179,13 @@ __device__ inline void mlp_tile(const typename Vec8<T>::type* sfr, typename Vec8
 // eight products and its epilogue before the next block starts, so the
 // epilogue of one block can issue beside the matrix instructions of the next.
 // Every accumulator sees the same products in the same order as mlp_tile, so
-// the outputs are equal bit for bit.
-template <typename T, int COLS, int NH>
+// the outputs are equal bit for bit.  hook(l, acc) runs after the first column
+// block's products of layer l have been issued (acc: that block's first
+// accumulator), so vector work placed there can overlap the layer's remaining
+// matrix instructions.
+template <typename T, int COLS, int NH, typename Hook>
 __device__ inline void mlp_tile_colwise(const typename Vec8<T>::type* sfr, typename Vec8<T>::type (&b)[COLS][2],
-                                        int lane, f32x4 (&o)[COLS]) {
+                                        int lane, f32x4 (&o)[COLS], Hook&& hook) {
     using V = typename Vec8<T>::type;
     constexpr int MB = 4;
     const Geo geo(64, NH);
@@ -201,6 +204,7 @@ __device__ inline void mlp_tile_colwise(const typename Vec8<T>::type* sfr, typen
             for (int mb = 0; mb < MB; ++mb) acc[mb] = mfma(a[mb][0], b[col][0], f32x4{0.f, 0.f, 0.f, 0.f});
             #pragma unroll
             for (int mb = 0; mb < MB; ++mb) acc[mb] = mfma(a[mb][1], b[col][1], acc[mb]);
+            if (col == 0) hook(l, acc[0]);
             #pragma unroll
             for (int c = 0; c < 2; ++c) b[col][c] = relu_packed(pack8<T, V>(acc[2 * c], acc[2 * c + 1]));
         }
@@ -445,17 +449,17 @@ __global__ __launch_bounds__(64 * NW) void k_fwd_raw_mfma(const T* __restrict__ 
 // rounded diffuse plus the rounded specular albedo per channel, the same
 // arithmetic reflectance_operand does on the B operand, here in the lane that
 // holds the record instead of three shuffles per channel and column.
-template <typename T, int PRESET, int LAYOUT>
-__device__ inline void encode_to_lds(const float* x, T* dst, int fcol) {
+// Features 8q .. 8q + 7 of f, rounded to T, into an LDS row.
+template <typename T>
+__device__ inline void store8(T* dst, const float* f, int q) {
     using V = typename Vec8<T>::type;
-    float f[64];
-    encode_record<PRESET, LAYOUT>(x, f);
-    #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        const f32x4 lo = f32x4{f[8 * q], f[8 * q + 1], f[8 * q + 2], f[8 * q + 3]};
-        const f32x4 hi = f32x4{f[8 * q + 4], f[8 * q + 5], f[8 * q + 6], f[8 * q + 7]};
-        *reinterpret_cast<V*>(dst + 8 * q) = pack8<T, V>(lo, hi);
-    }
+    const f32x4 lo = f32x4{f[8 * q], f[8 * q + 1], f[8 * q + 2], f[8 * q + 3]};
+    const f32x4 hi = f32x4{f[8 * q + 4], f[8 * q + 5], f[8 * q + 6], f[8 * q + 7]};
+    *reinterpret_cast<V*>(dst + 8 * q) = pack8<T, V>(lo, hi);
+}
+
+template <typename T, int PRESET>
+__device__ inline void store_reflectance(T* dst, const float* f, int fcol) {
     f32x4 r = f32x4{1.0f, 1.0f, 1.0f, 0.0f};
     constexpr int ac = PRESET == NRC_PRESET_CONFIG ? kAlbedoColConfig : kAlbedoColPaper;
     if (fcol) {
@@ -463,6 +467,15 @@ __device__ inline void encode_to_lds(const float* x, T* dst, int fcol) {
         for (int c = 0; c < 3; ++c) r[c] = (float)to_t<T>(f[ac + c]) + (float)to_t<T>(f[ac + 3 + c]);
     }
     *reinterpret_cast<f32x4*>(dst + 64) = r;
+}
+
+template <typename T, int PRESET, int LAYOUT>
+__device__ inline void encode_to_lds(const float* x, T* dst, int fcol) {
+    float f[64];
+    encode_record<PRESET, LAYOUT>(x, f);
+    #pragma unroll
+    for (int q = 0; q < 8; ++q) store8<T>(dst, f, q);
+    store_reflectance<T, PRESET>(dst, f, fcol);
 }
 
 // Orders a wave's LDS accesses: those before complete before those after,
@@ -489,6 +502,7 @@ __global__ __launch_bounds__(64 * NW) void k_fwd_raw_mfma_fixed(const T* __restr
     using V = typename Vec8<T>::type;
     constexpr int W = 64, COLS = 4, KC = 2;
     constexpr int RW = LAYOUT == NRC_RAW14 ? 14 : 16;
+    static_assert(NH == 5, "the next tile's encoding is spread over five hidden layers");
     constexpr int ROW = 72;                                // LDS row stride of an encoded record
     constexpr int NF = 2 * (W / 16) + (NH - 1) * (W / 16) * KC + KC;   // forward fragments
     __shared__ V sfr[NF * 64];
@@ -538,11 +552,45 @@ __global__ __launch_bounds__(64 * NW) void k_fwd_raw_mfma_fixed(const T* __restr
             r[col][0] = rv[0]; r[col][1] = rv[1]; r[col][2] = rv[2];
         }
         wave_lds_sync();                   // and read by every lane before they are rewritten
-        // the next tile's encoding (vector ALUs) beside this tile's network (matrix cores)
-        encode_to_lds<T, PRESET, LAYOUT>(x, senc + lane * ROW, fcol);
-        load_raw(tile + 2 * tstride);
+        // the next tile's encoding (vector ALUs) beside this tile's network
+        // (matrix cores): part l of the record's features after layer l's
+        // first products, tied to them by an empty asm so the compiler cannot
+        // hoist the encoding ahead of the matrix instructions
+        float f[64];
+        T* row = senc + lane * ROW;
+        auto hook = [&](int l, const f32x4& dep) {
+            float xd = x[0];
+            asm volatile("" : "+v"(xd) : "v"(dep[0]));
+            float xs[RW];
+            #pragma unroll
+            for (int k = 0; k < RW; ++k) xs[k] = x[k];
+            xs[0] = xd;
+            #pragma unroll
+            for (int k = 1; k < RW; ++k) asm volatile("" : "+v"(xs[k]) : "v"(xd));
+            if (l == 0) {
+                encode_part<PRESET, LAYOUT, 0>(xs, f);
+                store8<T>(row, f, 0);
+            } else if (l == 1) {
+                encode_part<PRESET, LAYOUT, 1>(xs, f);
+                store8<T>(row, f, 1);
+                store8<T>(row, f, 2);
+            } else if (l == 2) {
+                encode_part<PRESET, LAYOUT, 2>(xs, f);
+                store8<T>(row, f, 3);
+            } else if (l == 3) {
+                encode_part<PRESET, LAYOUT, 3>(xs, f);
+                store8<T>(row, f, 4);
+            } else if (l == 4) {
+                encode_part<PRESET, LAYOUT, 4>(xs, f);
+                store8<T>(row, f, 5);
+                store8<T>(row, f, 6);
+                store8<T>(row, f, 7);
+                store_reflectance<T, PRESET>(row, f, fcol);
+            }
+        };
         f32x4 o[COLS];
-        mlp_tile_colwise<T, COLS, NH>(sfr, b, lane, o);
+        mlp_tile_colwise<T, COLS, NH>(sfr, b, lane, o, hook);
+        load_raw(tile + 2 * tstride);
         store_rgb<COLS>(o, r, tile * 64, n, g, ln, rgb);
     }
 }
