@@ -24,6 +24,8 @@
 // layer, reading delta and h with LDS transpose loads so that the record
 // index runs along K.  Each tile writes its weight-gradient partial sums; a
 // fixed-order reduction follows (no atomics).
+#include <atomic>
+
 #include "encode_impl.h"
 #include "nrc_internal.h"
 
@@ -488,9 +490,9 @@ __device__ inline void wave_lds_sync() {
 
 // Fused raw -> encode -> network inference for a depth fixed at compile time
 // (NH hidden layers of width 64), software-pipelined: while a wave's matrix
-// cores run tile t, its vector ALUs encode tile t + stride into the wave's LDS
-// rows.  The whole tile is one basic block (layers unrolled, loads clamped
-// instead of branched), and the weights and encode rows are distinct
+// cores run one tile, its vector ALUs encode the wave's next tile into the
+// wave's LDS rows.  The whole tile is one basic block (layers unrolled, loads
+// clamped instead of branched), and the weights and encode rows are distinct
 // __shared__ arrays, so the compiler may interleave the two instruction
 // streams.  Results equal k_fwd_raw_mfma's bit for bit: every record goes
 // through the same arithmetic.  (Measured: matrix and vector work of one wave
@@ -507,14 +509,28 @@ __global__ __launch_bounds__(64 * NW) void k_fwd_raw_mfma_fixed(const T* __restr
     constexpr int NF = 2 * (W / 16) + (NH - 1) * (W / 16) * KC + KC;   // forward fragments
     __shared__ V sfr[NF * 64];
     __shared__ __attribute__((aligned(16))) T senc_all[NW * 64 * ROW];
+    __shared__ int claimed;                                // tiles of the share handed out so far
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int g = lane >> 4, ln = lane & 15;
     T* senc = senc_all + wave * 64 * ROW;
+    if (threadIdx.x == 0) claimed = 0;
     stage_frags<64 * NW>(sfr, reinterpret_cast<const V*>(ffr), NF);
     __syncthreads();
 
+    // The workgroup owns a contiguous share of the tiles; its waves claim them
+    // one at a time (an LDS counter), so a wave the SIMD's issue arbitration
+    // favours takes more tiles and all waves of the CU finish together.
+    // (Measured with a fixed tile per wave and stride: the waves of a CU ran at
+    // 3.3 to 7.3 us per tile and the pass ended with the slowest.)
     const int64_t n_tiles = (n + 63) / 64;
-    const int64_t tstride = (int64_t)gridDim.x * NW;
+    const int64_t per = n_tiles / gridDim.x, extra = n_tiles % gridDim.x;
+    const int64_t t_begin = (int64_t)blockIdx.x * per + ((int64_t)blockIdx.x < extra ? blockIdx.x : extra);
+    const int64_t t_end = t_begin + per + ((int64_t)blockIdx.x < extra ? 1 : 0);
+    auto claim = [&]() -> int64_t {
+        int k = 0;
+        if (lane == 0) k = atomicAdd(&claimed, 1);
+        return t_begin + __builtin_amdgcn_readfirstlane(k);
+    };
     float x[RW];
     auto load_raw = [&](int64_t t) {      // rows past the end read the last row
         int64_t row = t * 64 + lane;
@@ -534,12 +550,14 @@ __global__ __launch_bounds__(64 * NW) void k_fwd_raw_mfma_fixed(const T* __restr
             }
         }
     };
-    int64_t tile = (int64_t)blockIdx.x * NW + wave;
-    if (tile >= n_tiles) return;
+    int64_t tile = claim();
+    if (tile >= t_end) return;
     load_raw(tile);
     encode_to_lds<T, PRESET, LAYOUT>(x, senc + lane * ROW, fcol);
-    load_raw(tile + tstride);
-    for (; tile < n_tiles; tile += tstride) {
+    int64_t nxt = claim();                 // its record is in x while tile computes
+    load_raw(nxt);
+    while (tile < t_end) {
+        const int64_t nn = claim();
         wave_lds_sync();                   // this tile's rows are written
         V b[COLS][KC];
         float r[COLS][3];
@@ -590,8 +608,10 @@ __global__ __launch_bounds__(64 * NW) void k_fwd_raw_mfma_fixed(const T* __restr
         };
         f32x4 o[COLS];
         mlp_tile_colwise<T, COLS, NH>(sfr, b, lane, o, hook);
-        load_raw(tile + 2 * tstride);
+        load_raw(nn);
         store_rgb<COLS>(o, r, tile * 64, n, g, ln, rgb);
+        tile = nxt;
+        nxt = nn;
     }
 }
 
@@ -992,15 +1012,17 @@ hipError_t fwd_dispatch(const Geo& d, const void* ffr, const void* enc, int64_t 
     return hipGetLastError();
 }
 
-// Waves per workgroup of the fused kernel and the persistent grid's size:
-// 12 waves share one LDS copy of the weights (42 KB) beside their 12 encode
-// buffers (110 KB), one workgroup per CU, three waves per SIMD.
+// Waves per workgroup of the fused kernel: 12 waves share one LDS copy of the
+// weights (42 KB) beside their 12 encode buffers (110 KB), so one workgroup
+// fits per CU, three waves per SIMD; the persistent grid has one workgroup
+// per CU.  (Measured: with twice as many workgroups as CUs the second half
+// waited ~10 us after the first half had finished before it was dispatched,
+// and the 1080p pass took ~78 us instead of ~45.)
 constexpr int kRawWaves = 12;
-constexpr int kRawMaxBlocks = 512;
 
 template <typename T, int W, int PRESET, int LAYOUT, int NW = kRawWaves>
 hipError_t fwd_raw_launch(const Geo& d, const void* ffr, const float* raw, int64_t n, float* rgb,
-                          hipStream_t s, int max_blocks = kRawMaxBlocks) {
+                          hipStream_t s, int max_blocks) {
     const int64_t tiles = (n + 63) / 64;
     if (tiles == 0) return hipSuccess;
     const size_t lds = (size_t)d.n_fwd_frags() * 1024 + (size_t)NW * 64 * 72 * sizeof(T);
@@ -1016,7 +1038,8 @@ hipError_t fwd_raw_launch(const Geo& d, const void* ffr, const float* raw, int64
 // The fixed-depth, software-pipelined kernel for the paper's 5 hidden layers.
 template <typename T, int PRESET, int LAYOUT>
 hipError_t fwd_raw_fixed_launch(const Geo& d, const void* ffr, const float* raw, int64_t n, float* rgb,
-                                hipStream_t s, int max_blocks = kRawMaxBlocks) {
+                                hipStream_t s) {
+    const int max_blocks = device_cu_count();
     constexpr int NW = kRawWaves;
     const int64_t tiles = (n + 63) / 64;
     if (tiles == 0) return hipSuccess;
@@ -1033,8 +1056,11 @@ template <typename T, int W, int PRESET, int LAYOUT>
 hipError_t fwd_raw_generic(const Geo& d, const void* ffr, const float* raw, int64_t n, float* rgb,
                            hipStream_t s) {
     const size_t lds12 = (size_t)d.n_fwd_frags() * 1024 + (size_t)12 * 64 * 72 * sizeof(T);
-    if (lds12 <= 160 * 1024) return fwd_raw_launch<T, W, PRESET, LAYOUT, 12>(d, ffr, raw, n, rgb, s);
-    return fwd_raw_launch<T, W, PRESET, LAYOUT, 8>(d, ffr, raw, n, rgb, s, 2 * kRawMaxBlocks);
+    const size_t lds8 = (size_t)d.n_fwd_frags() * 1024 + (size_t)8 * 64 * 72 * sizeof(T);
+    const int cus = device_cu_count();
+    if (lds12 <= 160 * 1024) return fwd_raw_launch<T, W, PRESET, LAYOUT, 12>(d, ffr, raw, n, rgb, s, cus);
+    return fwd_raw_launch<T, W, PRESET, LAYOUT, 8>(d, ffr, raw, n, rgb, s,
+                                                   cus * (int)((160 * 1024) / lds8 > 0 ? (160 * 1024) / lds8 : 1));
 }
 
 template <typename T, int W>
@@ -1106,6 +1132,21 @@ hipError_t train_dispatch(const Geo& d, const void* ffr, const void* bfr, const 
 }
 
 }  // namespace
+
+int device_cu_count() {
+    static std::atomic<int> cache[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = -1;
+    if (dev >= 0) {
+        const int c = cache[dev].load(std::memory_order_relaxed);
+        if (c > 0) return c;
+    }
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev < 0 ? 0 : dev) != hipSuccess || cus <= 0)
+        cus = 256;   // MI355X
+    if (dev >= 0) cache[dev].store(cus, std::memory_order_relaxed);
+    return cus;
+}
 
 size_t mfma_train_lds_bytes(int width, int n_hidden) {
     return (size_t)train_lds_bytes(width, n_hidden) + 16;

@@ -216,6 +216,11 @@ struct EmaArgs {
 // Host launch wrappers (return hipError_t of the launch).
 // ---------------------------------------------------------------------------
 // encode.hip
+// Compute units of the current device (cached per device): persistent grids
+// are sized to what is resident at once, so no workgroup waits for a second
+// round of dispatch.
+int device_cu_count();
+
 hipError_t launch_encode(int precision, int preset, int layout, const float* raw, int64_t n,
                          void* enc, hipStream_t s);
 // mlp_fp32.hip
