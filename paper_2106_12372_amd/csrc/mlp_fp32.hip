@@ -30,7 +30,6 @@ constexpr int kW = 64;      // the FP32 form supports width 64
 constexpr int kLd = 68;     // padded LDS row stride (floats)
 constexpr int kTile = 64;       // training records per workgroup
 constexpr int kQWaves = 8;      // waves per query workgroup (two per SIMD)
-constexpr int kQMaxBlocks = 256;    // query workgroups: one per CU (LDS-bound)
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 
@@ -164,15 +163,25 @@ template <bool RAW, int PRESET, int LAYOUT>
 __device__ inline void query_fp32(const float* __restrict__ w, const float* __restrict__ in, int64_t n,
                                   float* __restrict__ rgb, int H, int fcol) {
     extern __shared__ f4 sw[];
+    __shared__ int claimed;                 // tiles of the workgroup's share handed out so far
     constexpr int RW = LAYOUT == NRC_RAW14 ? 14 : 16;
+    if (threadIdx.x == 0) claimed = 0;
     stage_query_frags(sw, w, H);
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
     float4 wo[kNOut][4];
     load_out_weights(w, H, lane >> 4, wo);
     __syncthreads();
+    // The workgroup owns a contiguous share of the tiles and its waves claim
+    // them one at a time, so all waves of the CU finish together.
     const int64_t n_tiles = (n + 63) / 64;
-    const int64_t stride = (int64_t)gridDim.x * kQWaves;
-    for (int64_t t = (int64_t)blockIdx.x * kQWaves + wave; t < n_tiles; t += stride) {
+    const int64_t per = n_tiles / gridDim.x, extra = n_tiles % gridDim.x;
+    const int64_t t_begin = (int64_t)blockIdx.x * per + ((int64_t)blockIdx.x < extra ? blockIdx.x : extra);
+    const int64_t t_end = t_begin + per + ((int64_t)blockIdx.x < extra ? 1 : 0);
+    for (;;) {
+        int k = 0;
+        if (lane == 0) k = atomicAdd(&claimed, 1);
+        const int64_t t = t_begin + __builtin_amdgcn_readfirstlane(k);
+        if (t >= t_end) break;
         int64_t s = t * 64 + lane;
         const bool valid = s < n;
         if (!valid) s = n - 1;
@@ -615,13 +624,14 @@ __global__ __launch_bounds__(64 * (kChainWaves + kGradWaves)) void k_train_fp32(
 }
 
 // Query grid: one workgroup of kQWaves waves per CU (the fragments of every
-// hidden layer, 16 H KB, fill most of the CU's LDS), each wave striding over
-// 64-query tiles.
+// hidden layer, 16 H KB, fill most of the CU's LDS), its waves claiming the
+// 64-query tiles of the workgroup's share.
 inline size_t query_lds_bytes(const Geo& d) { return (size_t)(16 * d.H) * 64 * sizeof(f4); }
 inline int64_t query_blocks(int64_t n) {
     const int64_t tiles = (n + 63) / 64;
     const int64_t b = (tiles + kQWaves - 1) / kQWaves;
-    return b < kQMaxBlocks ? b : kQMaxBlocks;
+    const int64_t cus = device_cu_count();
+    return b < cus ? b : cus;
 }
 
 template <typename K>
