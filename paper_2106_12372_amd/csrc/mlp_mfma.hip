@@ -981,6 +981,17 @@ __global__ __launch_bounds__(512) void k_train_mfma(const T* __restrict__ ffr,
     if (tid == 0) tile_bad[tile] = any_bad ? 1 : 0;
 }
 
+// Workgroups of the persistent inference kernels that are resident at once:
+// as many per CU as their weight copies fit in the 160 KB of LDS, at most four
+// (the kernels' register budget allows two waves per SIMD per workgroup
+// size), so the grid is covered in one round of dispatch.
+inline int64_t resident_fwd_blocks(size_t lds) {
+    int64_t per_cu = (int64_t)((160 * 1024) / (lds > 0 ? lds : 1));
+    if (per_cu < 1) per_cu = 1;
+    if (per_cu > 4) per_cu = 4;
+    return per_cu * device_cu_count();
+}
+
 template <typename T, int W>
 hipError_t fwd_segs_dispatch(const Geo& d, const void* ffr, const SegList& segs, hipStream_t s) {
     constexpr int COLS = 4;
@@ -988,7 +999,8 @@ hipError_t fwd_segs_dispatch(const Geo& d, const void* ffr, const SegList& segs,
     if (tiles == 0) return hipSuccess;
     const size_t lds = (size_t)d.n_fwd_frags() * 64 * 16;
     int64_t blocks = (tiles + 3) / 4;
-    if (blocks > 2048) blocks = 2048;
+    const int64_t resident = resident_fwd_blocks(lds);
+    if (blocks > resident) blocks = resident;
     auto k = k_fwd_mfma_segs<T, W, COLS>;
     (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(256), lds, s, (const T*)ffr, d.n_fwd_frags(), segs, d.H,
@@ -1004,7 +1016,8 @@ hipError_t fwd_dispatch(const Geo& d, const void* ffr, const void* enc, int64_t 
     if (tiles == 0) return hipSuccess;
     const size_t lds = (size_t)d.n_fwd_frags() * 64 * 16;
     int64_t blocks = (tiles + 3) / 4;
-    if (blocks > 2048) blocks = 2048;   // persistent: 2048 workgroups cover the 256 CUs several times
+    const int64_t resident = resident_fwd_blocks(lds);
+    if (blocks > resident) blocks = resident;
     auto k = k_fwd_mfma<T, W, COLS>;
     (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(256), lds, s, (const T*)ffr, d.n_fwd_frags(),
