@@ -555,7 +555,7 @@ __global__ __launch_bounds__(64 * NW) void k_fwd_raw_mfma_fixed(const T* __restr
     load_raw(tile);
     encode_to_lds<T, PRESET, LAYOUT>(x, senc + lane * ROW, fcol);
     int64_t nxt = claim();                 // its record is in x while tile computes
-    load_raw(nxt);
+    if (nxt < t_end) load_raw(nxt);        // past the share: nothing to read (the encoding is never used)
     while (tile < t_end) {
         const int64_t nn = claim();
         wave_lds_sync();                   // this tile's rows are written
@@ -608,7 +608,7 @@ __global__ __launch_bounds__(64 * NW) void k_fwd_raw_mfma_fixed(const T* __restr
         };
         f32x4 o[COLS];
         mlp_tile_colwise<T, COLS, NH>(sfr, b, lane, o, hook);
-        load_raw(nn);
+        if (nn < t_end) load_raw(nn);
         store_rgb<COLS>(o, r, tile * 64, n, g, ln, rgb);
         tile = nxt;
         nxt = nn;
