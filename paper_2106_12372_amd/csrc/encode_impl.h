@@ -79,9 +79,13 @@ __device__ inline float tri(float x) { return 2.0f * fabsf(mod2(x) - 1.0f) - 1.0
 // evaluated directly (sincospi_r of the exactly reduced phase); the two octaves
 // after each come from the double-angle identities sin 2a = 2 sin a cos a,
 // cos 2a = (cos a - sin a)(cos a + sin a), which at most quadruple the
-// absolute rounding error (a few 1e-7).
+// absolute rounding error (a few 1e-7).  Each product is rounded as written:
+// with contraction the compiler may fuse either octave's product into the
+// next octave's sum, and which one it picks depends on the surrounding code,
+// so the stand-alone and fused encodings would round differently.
 template <int NOCT>
 __device__ inline void octaves(float p, float* sn, float* cs) {
+    #pragma clang fp contract(off)
     #pragma unroll
     for (int d = 0; d < NOCT; ++d) {
         if (d % 3 == 0) {

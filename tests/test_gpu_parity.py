@@ -284,18 +284,24 @@ def test_forward_raw_equals_encode_then_forward(N, prec, preset, layout, n):
 
 
 @pytest.mark.parametrize("prec", PRECS)
-def test_forward_past_one_round_of_resident_waves(N, prec):
-    # The query kernels keep a fixed grid resident and stride each wave over
-    # 64-query tiles: 256 workgroups of 8 waves in FP32, 512 of 12 in FP16 and
-    # BF16.  65 queries past one full round give every wave a second tile and
-    # end on a ragged one; every row is checked against the oracle.
-    waves = 256 * 8 if prec == "fp32" else 512 * 12
-    n = waves * 64 + 65
-    c, w = make_cache(N, prec)
-    raw = sd.raw_records(n, 301)
-    fused = N.nrc_forward_raw(c, dev(raw))
-    assert torch.equal(fused, N.nrc_forward(c, N.nrc_encode(c, dev(raw))))
-    check_outputs(fused.cpu().numpy(), O.predict(state_of(w), O.encode(raw)), FWD_TOL[prec], FWD_TOL_MAX[prec])
+@pytest.mark.parametrize("preset", [0, 1, 2, 3])
+@pytest.mark.parametrize("layout", [0, 1])
+def test_forward_past_one_round_of_resident_waves(N, prec, preset, layout):
+    # The query kernels keep one workgroup per CU resident, each owning a
+    # contiguous share of the 64-query tiles, which its waves claim one at a
+    # time; the fused FP16/BF16 kernel encodes a wave's next tile while the
+    # current one runs through the network, so every tile after a wave's first
+    # is encoded there.  6145 tiles give each of the 3072 waves of 256 CUs two
+    # or more and end on a ragged one; the fused pass equals the stand-alone
+    # encoding followed by the network bit for bit, and (default preset) every
+    # row is checked against the oracle.
+    n = 256 * 12 * 64 + 65
+    c, w = make_cache(N, prec, preset=preset)
+    raw = sd.raw_records(n, 301, layout)
+    fused = N.nrc_forward_raw(c, dev(raw), layout)
+    assert torch.equal(fused, N.nrc_forward(c, N.nrc_encode(c, dev(raw), layout)))
+    if preset == 0 and layout == 0:
+        check_outputs(fused.cpu().numpy(), O.predict(state_of(w), O.encode(raw)), FWD_TOL[prec], FWD_TOL_MAX[prec])
 
 
 @pytest.mark.parametrize("prec", PRECS)
