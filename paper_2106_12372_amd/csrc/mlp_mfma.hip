@@ -576,15 +576,15 @@ __global__ __launch_bounds__(64 * NW) void k_fwd_raw_mfma_fixed(const T* __restr
         // hoist the encoding ahead of the matrix instructions
         float f[64];
         T* row = senc + lane * ROW;
+        // Each part reads its own raw fields (a position coordinate, the
+        // direction, the rest), used by no other part, so they are tied in place.
         auto hook = [&](int l, const f32x4& dep) {
-            float xd = x[0];
-            asm volatile("" : "+v"(xd) : "v"(dep[0]));
-            float xs[RW];
+            const int lo = l <= 2 ? l : l == 3 ? 3 : (LAYOUT == NRC_RAW14 ? 5 : 6);
+            const int hi = l <= 2 ? l : l == 3 ? (LAYOUT == NRC_RAW14 ? 4 : 5) : RW - 1;
             #pragma unroll
-            for (int k = 0; k < RW; ++k) xs[k] = x[k];
-            xs[0] = xd;
-            #pragma unroll
-            for (int k = 1; k < RW; ++k) asm volatile("" : "+v"(xs[k]) : "v"(xd));
+            for (int k = 0; k < RW; ++k)
+                if (k >= lo && k <= hi) asm volatile("" : "+v"(x[k]) : "v"(dep[0]));
+            const float* xs = x;
             if (l == 0) {
                 encode_part<PRESET, LAYOUT, 0>(xs, f);
                 store8<T>(row, f, 0);
