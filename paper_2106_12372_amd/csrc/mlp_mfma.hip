@@ -303,6 +303,77 @@ __global__ __launch_bounds__(256, 2) void k_fwd_mfma(const T* __restrict__ ffr, 
     }
 }
 
+// Inference from encoded rows for the paper's network (width 64, five hidden
+// layers) with depth fixed at compile time: one workgroup per CU shares one
+// LDS copy of the weights; it owns a contiguous share of the 64-record tiles
+// and its waves claim them one at a time (an LDS counter), loading the next
+// claimed tile's rows while the current one runs through the network.  Same
+// products and epilogue as k_fwd_mfma, so the outputs are equal bit for bit.
+template <typename T, int NW>
+__global__ __launch_bounds__(64 * NW) void k_fwd_mfma_fixed(const T* __restrict__ ffr,
+                                                           const T* __restrict__ enc, int64_t n,
+                                                           float* __restrict__ rgb, int fcol) {
+    using V = typename Vec8<T>::type;
+    constexpr int W = 64, NH = 5, COLS = 4, KC = 2;
+    constexpr int NF = 2 * (W / 16) + (NH - 1) * (W / 16) * KC + KC;   // forward fragments
+    __shared__ V sfr[NF * 64];
+    __shared__ int claimed;
+    const int lane = threadIdx.x & 63;
+    const int g = lane >> 4, ln = lane & 15;
+    if (threadIdx.x == 0) claimed = 0;
+    stage_frags<64 * NW>(sfr, reinterpret_cast<const V*>(ffr), NF);
+    __syncthreads();
+
+    const int64_t n_tiles = (n + 63) / 64;
+    const int64_t per = n_tiles / gridDim.x, extra = n_tiles % gridDim.x;
+    const int64_t t_begin = (int64_t)blockIdx.x * per + ((int64_t)blockIdx.x < extra ? blockIdx.x : extra);
+    const int64_t t_end = t_begin + per + ((int64_t)blockIdx.x < extra ? 1 : 0);
+    auto claim = [&]() -> int64_t {
+        int k = 0;
+        if (lane == 0) k = atomicAdd(&claimed, 1);
+        return t_begin + __builtin_amdgcn_readfirstlane(k);
+    };
+    // Two operand buffers, alternating: the next claimed tile's rows load into
+    // one while the other runs through the network (no copies between them).
+    V ba[COLS][KC], bb[COLS][KC];
+    auto load_tile = [&](V (&dst)[COLS][KC], int64_t t) {      // rows past the end read the last row
+        #pragma unroll
+        for (int col = 0; col < COLS; ++col) {
+            int64_t row = t * 64 + 16 * col + ln;
+            row = row < n ? row : n - 1;
+            #pragma unroll
+            for (int c = 0; c < KC; ++c)
+                dst[col][c] = *reinterpret_cast<const V*>(enc + row * kEncWidth + 32 * c + 8 * g);
+        }
+    };
+    auto run_tile = [&](V (&b)[COLS][KC], int64_t t) {
+        // the weights are read from LDS per tile: held in registers across the
+        // loop (42 fragments, 168 VGPRs) they would spill
+        asm volatile("" ::: "memory");
+        float r[COLS][3];
+        #pragma unroll
+        for (int col = 0; col < COLS; ++col) reflectance_operand(b[col][1], fcol, ln, r[col]);
+        f32x4 o[COLS];
+        mlp_tile_colwise<T, COLS, NH>(sfr, b, lane, o, [](int, const f32x4&) {});
+        store_rgb<COLS>(o, r, t * 64, n, g, ln, rgb);
+    };
+    int64_t tile = claim();
+    if (tile >= t_end) return;
+    load_tile(ba, tile);
+    for (;;) {
+        int64_t nt = claim();
+        if (nt < t_end) load_tile(bb, nt);
+        run_tile(ba, tile);
+        if (nt >= t_end) break;
+        tile = nt;
+        nt = claim();
+        if (nt < t_end) load_tile(ba, nt);
+        run_tile(bb, tile);
+        if (nt >= t_end) break;
+        tile = nt;
+    }
+}
+
 // Inference over several request segments in one launch (serving: queued
 // queries of one cache that no training step separates).  Tile t of the
 // launch belongs to the segment whose cumulative tile range holds it; within
@@ -1008,12 +1079,23 @@ hipError_t fwd_segs_dispatch(const Geo& d, const void* ffr, const SegList& segs,
     return hipGetLastError();
 }
 
+// Waves per workgroup of k_fwd_mfma_fixed (one workgroup per CU).
+constexpr int kEncWaves = 12;
+
 template <typename T, int W>
 hipError_t fwd_dispatch(const Geo& d, const void* ffr, const void* enc, int64_t n, float* rgb,
                         hipStream_t s) {
     constexpr int COLS = 4;
     const int64_t tiles = (n + 16 * COLS - 1) / (16 * COLS);
     if (tiles == 0) return hipSuccess;
+    if (W == 64 && d.H == 5) {
+        constexpr int NW = kEncWaves;
+        int64_t blocks = (tiles + NW - 1) / NW;
+        if (blocks > device_cu_count()) blocks = device_cu_count();
+        hipLaunchKernelGGL((k_fwd_mfma_fixed<T, NW>), dim3((unsigned)blocks), dim3(64 * NW), 0, s,
+                           (const T*)ffr, (const T*)enc, n, rgb, d.F);
+        return hipGetLastError();
+    }
     const size_t lds = (size_t)d.n_fwd_frags() * 64 * 16;
     int64_t blocks = (tiles + 3) / 4;
     const int64_t resident = resident_fwd_blocks(lds);
