@@ -303,16 +303,39 @@ __global__ __launch_bounds__(256, 2) void k_fwd_mfma(const T* __restrict__ ffr, 
     }
 }
 
+// Where k_fwd_mfma_fixed's tiles come from: one batch of encoded rows, or
+// the request segments of one launch (serving: queued queries of one cache
+// that no training step separates; tile t belongs to the segment whose
+// cumulative tile range holds it).  locate gives tile t's rows, the
+// segment's row count and its output.
+struct EncBatch {
+    const void* enc;
+    int64_t n;
+    float* rgb;
+    __device__ int64_t n_tiles() const { return (n + 63) / 64; }
+    __device__ void locate(int64_t t, const void*& e, int64_t& base, int64_t& cnt, float*& out) const {
+        e = enc; base = t * 64; cnt = n; out = rgb;
+    }
+};
+struct EncSegs {
+    SegList s;
+    __device__ int64_t n_tiles() const { return s.tile_end[s.count - 1]; }
+    __device__ void locate(int64_t t, const void*& e, int64_t& base, int64_t& cnt, float*& out) const {
+        int sg = 0;
+        while (t >= s.tile_end[sg]) ++sg;
+        e = s.enc[sg]; base = (t - (sg ? s.tile_end[sg - 1] : 0)) * 64; cnt = s.n[sg]; out = s.rgb[sg];
+    }
+};
+
 // Inference from encoded rows for the paper's network (width 64, five hidden
 // layers) with depth fixed at compile time: one workgroup per CU shares one
 // LDS copy of the weights; it owns a contiguous share of the 64-record tiles
 // and its waves claim them one at a time (an LDS counter), loading the next
 // claimed tile's rows while the current one runs through the network.  Same
-// products and epilogue as k_fwd_mfma, so the outputs are equal bit for bit.
-template <typename T, int NW>
-__global__ __launch_bounds__(64 * NW) void k_fwd_mfma_fixed(const T* __restrict__ ffr,
-                                                           const T* __restrict__ enc, int64_t n,
-                                                           float* __restrict__ rgb, int fcol) {
+// products and epilogue as k_fwd_mfma / k_fwd_mfma_segs, so the outputs are
+// equal bit for bit.
+template <typename T, int NW, typename Src>
+__global__ __launch_bounds__(64 * NW) void k_fwd_mfma_fixed(const T* __restrict__ ffr, Src src, int fcol) {
     using V = typename Vec8<T>::type;
     constexpr int W = 64, NH = 5, COLS = 4, KC = 2;
     constexpr int NF = 2 * (W / 16) + (NH - 1) * (W / 16) * KC + KC;   // forward fragments
@@ -324,7 +347,7 @@ __global__ __launch_bounds__(64 * NW) void k_fwd_mfma_fixed(const T* __restrict_
     stage_frags<64 * NW>(sfr, reinterpret_cast<const V*>(ffr), NF);
     __syncthreads();
 
-    const int64_t n_tiles = (n + 63) / 64;
+    const int64_t n_tiles = src.n_tiles();
     const int64_t per = n_tiles / gridDim.x, extra = n_tiles % gridDim.x;
     const int64_t t_begin = (int64_t)blockIdx.x * per + ((int64_t)blockIdx.x < extra ? blockIdx.x : extra);
     const int64_t t_end = t_begin + per + ((int64_t)blockIdx.x < extra ? 1 : 0);
@@ -337,10 +360,15 @@ __global__ __launch_bounds__(64 * NW) void k_fwd_mfma_fixed(const T* __restrict_
     // one while the other runs through the network (no copies between them).
     V ba[COLS][KC], bb[COLS][KC];
     auto load_tile = [&](V (&dst)[COLS][KC], int64_t t) {      // rows past the end read the last row
+        const void* e;
+        int64_t base, cnt;
+        float* out;
+        src.locate(t, e, base, cnt, out);
+        const T* enc = reinterpret_cast<const T*>(e);
         #pragma unroll
         for (int col = 0; col < COLS; ++col) {
-            int64_t row = t * 64 + 16 * col + ln;
-            row = row < n ? row : n - 1;
+            int64_t row = base + 16 * col + ln;
+            row = row < cnt ? row : cnt - 1;
             #pragma unroll
             for (int c = 0; c < KC; ++c)
                 dst[col][c] = *reinterpret_cast<const V*>(enc + row * kEncWidth + 32 * c + 8 * g);
@@ -355,7 +383,11 @@ __global__ __launch_bounds__(64 * NW) void k_fwd_mfma_fixed(const T* __restrict_
         for (int col = 0; col < COLS; ++col) reflectance_operand(b[col][1], fcol, ln, r[col]);
         f32x4 o[COLS];
         mlp_tile_colwise<T, COLS, NH>(sfr, b, lane, o, [](int, const f32x4&) {});
-        store_rgb<COLS>(o, r, t * 64, n, g, ln, rgb);
+        const void* e;
+        int64_t base, cnt;
+        float* out;
+        src.locate(t, e, base, cnt, out);
+        store_rgb<COLS>(o, r, base, cnt, g, ln, out);
     };
     int64_t tile = claim();
     if (tile >= t_end) return;
@@ -1063,11 +1095,25 @@ inline int64_t resident_fwd_blocks(size_t lds) {
     return per_cu * device_cu_count();
 }
 
+// Waves per workgroup of k_fwd_mfma_fixed (one workgroup per CU).
+constexpr int kEncWaves = 12;
+
+template <typename T, typename Src>
+hipError_t fwd_fixed_launch(const void* ffr, const Src& src, int64_t tiles, int fcol, hipStream_t s) {
+    constexpr int NW = kEncWaves;
+    int64_t blocks = (tiles + NW - 1) / NW;
+    if (blocks > device_cu_count()) blocks = device_cu_count();
+    hipLaunchKernelGGL((k_fwd_mfma_fixed<T, NW, Src>), dim3((unsigned)blocks), dim3(64 * NW), 0, s,
+                       (const T*)ffr, src, fcol);
+    return hipGetLastError();
+}
+
 template <typename T, int W>
 hipError_t fwd_segs_dispatch(const Geo& d, const void* ffr, const SegList& segs, hipStream_t s) {
     constexpr int COLS = 4;
     const int64_t tiles = segs.tile_end[segs.count - 1];
     if (tiles == 0) return hipSuccess;
+    if (W == 64 && d.H == 5) return fwd_fixed_launch<T>(ffr, EncSegs{segs}, tiles, d.F, s);
     const size_t lds = (size_t)d.n_fwd_frags() * 64 * 16;
     int64_t blocks = (tiles + 3) / 4;
     const int64_t resident = resident_fwd_blocks(lds);
@@ -1079,8 +1125,6 @@ hipError_t fwd_segs_dispatch(const Geo& d, const void* ffr, const SegList& segs,
     return hipGetLastError();
 }
 
-// Waves per workgroup of k_fwd_mfma_fixed (one workgroup per CU).
-constexpr int kEncWaves = 12;
 
 template <typename T, int W>
 hipError_t fwd_dispatch(const Geo& d, const void* ffr, const void* enc, int64_t n, float* rgb,
@@ -1088,14 +1132,7 @@ hipError_t fwd_dispatch(const Geo& d, const void* ffr, const void* enc, int64_t 
     constexpr int COLS = 4;
     const int64_t tiles = (n + 16 * COLS - 1) / (16 * COLS);
     if (tiles == 0) return hipSuccess;
-    if (W == 64 && d.H == 5) {
-        constexpr int NW = kEncWaves;
-        int64_t blocks = (tiles + NW - 1) / NW;
-        if (blocks > device_cu_count()) blocks = device_cu_count();
-        hipLaunchKernelGGL((k_fwd_mfma_fixed<T, NW>), dim3((unsigned)blocks), dim3(64 * NW), 0, s,
-                           (const T*)ffr, (const T*)enc, n, rgb, d.F);
-        return hipGetLastError();
-    }
+    if (W == 64 && d.H == 5) return fwd_fixed_launch<T>(ffr, EncBatch{enc, n, rgb}, tiles, d.F, s);
     const size_t lds = (size_t)d.n_fwd_frags() * 64 * 16;
     int64_t blocks = (tiles + 3) / 4;
     const int64_t resident = resident_fwd_blocks(lds);
