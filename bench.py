@@ -48,7 +48,7 @@ PEAK_TFLOPS = {"fp32": 157.3, "fp16": 2500.0, "bf16": 2500.0, "fp32_valu": 78.6}
 BOUND = {"fp32": "mfma", "fp16": "mfma", "bf16": "mfma", "fp32_valu": "alu"}
 QUERY_KERNEL = {"fp32": "k_fwd_raw_fp32", "fp16": "k_fwd_raw_mfma_fixed", "bf16": "k_fwd_raw_mfma_fixed",
                 "fp32_valu": "k_fwd_raw_fp32_valu"}
-MLP_KERNEL = {"fp32": "k_fwd_fp32", "fp16": "k_fwd_mfma", "bf16": "k_fwd_mfma", "fp32_valu": "k_fwd_fp32_valu"}
+MLP_KERNEL = {"fp32": "k_fwd_fp32", "fp16": "k_fwd_mfma_fixed", "bf16": "k_fwd_mfma_fixed", "fp32_valu": "k_fwd_fp32_valu"}
 HBM_PEAK_GBS = 8000.0
 
 
