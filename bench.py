@@ -49,6 +49,10 @@ BOUND = {"fp32": "mfma", "fp16": "mfma", "bf16": "mfma", "fp32_valu": "alu"}
 QUERY_KERNEL = {"fp32": "k_fwd_raw_fp32", "fp16": "k_fwd_raw_mfma_fixed", "bf16": "k_fwd_raw_mfma_fixed",
                 "fp32_valu": "k_fwd_raw_fp32_valu"}
 MLP_KERNEL = {"fp32": "k_fwd_fp32", "fp16": "k_fwd_mfma_fixed", "bf16": "k_fwd_mfma_fixed", "fp32_valu": "k_fwd_fp32_valu"}
+# The frame's training records go to the training kernels raw (encoded there,
+# nrc_train_frame_raw) except in BF16, where the in-kernel encoding measured
+# slower than the separate encoding pass (17.7 against 15.2 us per step).
+RAW_TRAIN = {"fp32": True, "fp16": True, "bf16": False, "fp32_valu": True}
 HBM_PEAK_GBS = 8000.0
 
 
@@ -127,13 +131,21 @@ def frame_bench(form: str, steps: int, warmup: int, settle_s: float):
         N.nrc_forward_raw(cache, raw_q, rgb=rgb)           # encode + inference, one kernel
         if evs is not None:
             evs[1].record(stream)
-        N.nrc_encode(cache, raw_r, enc=enc_r)
-        if evs is not None:
-            evs[2].record(stream)
         # LCG shuffle, then 4 steps on disjoint batches, a new shuffle each frame
-        last["loss"], last["skipped"] = N.nrc_train_frame(cache, enc_r, y, steps=N_TRAIN_BATCHES,
-                                                          batch=TRAIN_BATCH, seed=frame_no[0],
-                                                          scratch=frame_scratch)
+        if RAW_TRAIN[form]:
+            # the training kernels encode the gathered raw records themselves
+            if evs is not None:
+                evs[2].record(stream)
+            last["loss"], last["skipped"] = N.nrc_train_frame_raw(cache, raw_r, y, steps=N_TRAIN_BATCHES,
+                                                                  batch=TRAIN_BATCH, seed=frame_no[0],
+                                                                  scratch=frame_scratch)
+        else:
+            N.nrc_encode(cache, raw_r, enc=enc_r)
+            if evs is not None:
+                evs[2].record(stream)
+            last["loss"], last["skipped"] = N.nrc_train_frame(cache, enc_r, y, steps=N_TRAIN_BATCHES,
+                                                              batch=TRAIN_BATCH, seed=frame_no[0],
+                                                              scratch=frame_scratch)
         frame_no[0] += 1
         if evs is not None:
             evs[3].record(stream)
@@ -141,18 +153,22 @@ def frame_bench(form: str, steps: int, warmup: int, settle_s: float):
     settled = settle(step, settle_s)
     for _ in range(warmup):
         step(None)
-    # the timed steps run back to back; each step's events are read after the
-    # closing synchronisation
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
+    # The timed steps run back to back with nothing else on the stream; the
+    # components are timed in a second pass with events between them (an event
+    # between two kernels costs the stream a few microseconds).
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(steps):
-        step(evs[k])
+        step(None)
     t_enq = time.perf_counter() - t0
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    comp = np.mean([[e[i].elapsed_time(e[i + 1]) for i in range(3)] for e in evs], axis=0)
     ms = elapsed * 1e3 / steps
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
+    for k in range(steps):
+        step(evs[k])
+    torch.cuda.synchronize()
+    comp = np.mean([[e[i].elapsed_time(e[i + 1]) for i in range(3)] for e in evs], axis=0)
 
     # The same queries through the two-kernel path (encode to HBM, then inference).
     uevs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
@@ -174,6 +190,7 @@ def frame_bench(form: str, steps: int, warmup: int, settle_s: float):
         "ms_per_step": ms,
         "queries_per_s": N_QUERIES / (ms * 1e-3),
         "train_samples_per_s": N_TRAIN_BATCHES * TRAIN_BATCH / (ms * 1e-3),
+        # encode_records is 0 where the training kernels encode the raw records
         "components_ms": {"query_pass_fused": comp[0], "encode_records": comp[1],
                           "shuffle_and_train_4_steps": comp[2]},
         "unfused_ms": {"encode_queries": ue[0], "forward": ue[1]},
@@ -477,7 +494,9 @@ def main():
                                         "(v_mfma_f32_16x16x4_f32), not the vector ALUs",
                                 "fp16": "FP16 matrix cores, FP32 accumulation",
                                 "bf16": "BF16 matrix cores, FP32 accumulation",
-                                "fp32_valu": "FP32 on the vector ALUs, no matrix instructions"}[args.form]},
+                                "fp32_valu": "FP32 on the vector ALUs, no matrix instructions"}[args.form],
+                   "training_records": ("raw, encoded inside the training kernels" if RAW_TRAIN[args.form]
+                                        else "encoded by a separate pass, then trained")},
         "train_samples_per_s": main_res["train_samples_per_s"],
         "components_ms": main_res["components_ms"],
         "unfused_ms": main_res["unfused_ms"],

@@ -331,6 +331,21 @@ int nrc_train_frame_indexed(nrc_cache* cache, const void* enc, const float* targ
                             size_t scratch_bytes, float* losses_dev, int32_t* skipped_dev, void* stream);
 
 /*
+ * nrc_train_frame on raw training records (the path-vertex records of Sec.
+ * 3.6, Table "parameters", before the input encoding): the training kernels
+ * encode each gathered record with the cache's preset, exactly as
+ * nrc_encode would, so the result equals nrc_encode followed by
+ * nrc_train_frame bit for bit, without the encoded copy of the records.
+ * raw: device FP32 [n_records][14] (NRC_RAW14) or [n_records][16]
+ * (NRC_RAW16), 16-byte aligned; raw_layout one of those.  Width 64 only
+ * (NRC_EINVAL otherwise), as nrc_forward_raw.  Other arguments, the scratch
+ * size (nrc_frame_scratch_bytes) and the errors as for nrc_train_frame.
+ */
+int nrc_train_frame_raw(nrc_cache* cache, const float* raw, int raw_layout, const float* target,
+                        int64_t n_records, int steps, int64_t batch, uint64_t seed, void* scratch,
+                        size_t scratch_bytes, float* losses_dev, int32_t* skipped_dev, void* stream);
+
+/*
  * Self-training targets (Sec. 3.2, Sec. 6 "Self-training"): a training
  * record's target is the radiance gathered from its vertex to the end of its
  * path plus the throughput from its vertex to the path's tail times the

@@ -256,7 +256,11 @@ constexpr int kChainWaves = 4, kGradWaves = 4;
 
 template <int ACT> constexpr int fp32_train_waves() { return ACT == kActStore ? kChainWaves : kChainWaves + kGradWaves; }
 
-template <bool UPSTREAM, bool GENC, int ACT = kActNone>
+// Training records given raw (RAWL = their layout, PRESET = the cache's
+// encoding; RAWL < 0: encoded rows): enc then points at the raw records,
+// FP32 [n][14 or 16], and lane j of each chain wave encodes its record into
+// the record's h_0 row before the wave reads its operands back from it.
+template <bool UPSTREAM, bool GENC, int ACT = kActNone, int RAWL = -1, int PRESET = NRC_PRESET_CONFIG>
 __global__ __launch_bounds__(64 * (kChainWaves + kGradWaves)) void k_train_fp32(
         const float* __restrict__ w, const float* __restrict__ enc, const float* __restrict__ tgt,
         const int32_t* __restrict__ idx, int64_t n, int n_hidden, int n_params, float loss_eps,
@@ -302,7 +306,45 @@ __global__ __launch_bounds__(64 * (kChainWaves + kGradWaves)) void k_train_fp32(
     // ---- h_0, targets and reflectance factor of the lane's record ----------
     float a[16];   // chain: a[4b + r] = neuron 16b + 4g + r of record sl (activations, later deltas)
     float r[kNOut] = {1.f, 1.f, 1.f}, t[kNOut] = {0.f, 0.f, 0.f};
-    if (chain) {
+    if constexpr (RAWL >= 0) {
+      static_assert(!UPSTREAM && !GENC && ACT == kActNone, "raw records feed the training step only");
+      if (chain) {
+        constexpr int RW = RAWL == NRC_RAW14 ? 14 : 16;
+        float* h0 = hs + sl * kLd;
+        if (g == 0) {
+            float f[64];
+            if (valid) {
+                const float* rr = enc + src * RW;
+                float x[RW];
+                #pragma unroll
+                for (int k = 0; k < RW; ++k) x[k] = rr[k];
+                encode_record<PRESET, RAWL>(x, f);
+            } else {
+                #pragma unroll
+                for (int k = 0; k < 64; ++k) f[k] = 0.0f;
+            }
+            #pragma unroll
+            for (int q = 0; q < 16; ++q)
+                *reinterpret_cast<float4*>(h0 + 4 * q) = make_float4(f[4 * q], f[4 * q + 1], f[4 * q + 2], f[4 * q + 3]);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        #pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const float4 v = *reinterpret_cast<const float4*>(h0 + 16 * b + 4 * g);
+            a[4 * b] = v.x; a[4 * b + 1] = v.y; a[4 * b + 2] = v.z; a[4 * b + 3] = v.w;
+        }
+        if (out_lane && valid) {
+            if (fcol) {
+                #pragma unroll
+                for (int o = 0; o < kNOut; ++o) r[o] = h0[fcol + o] + h0[fcol + 3 + o];
+            }
+            #pragma unroll
+            for (int o = 0; o < kNOut; ++o) t[o] = tgt[src * 3 + o];
+        }
+      }
+    } else if (chain) {
         // record src (record 0 for slots past the end, whose features are then zeroed)
         const float* er = enc + src * kEncWidth;
         float4 v[4];
@@ -676,7 +718,7 @@ size_t fp32_train_lds_bytes(int n_hidden) {
     return ((size_t)(n_hidden + 1) * kTile * kLd + 2 * kTile * kLd + 2 * kTile * 4) * sizeof(float);
 }
 
-template <bool UP, bool GE, int ACT = kActNone>
+template <bool UP, bool GE, int ACT = kActNone, int RAWL = -1, int PRESET = NRC_PRESET_CONFIG>
 hipError_t train_fp32_launch(const Geo& d, const float* w, const float* enc, const float* tgt,
                              const int32_t* idx, int64_t n, float loss_eps, float grad_scale,
                              float* partials, float* loss_part, int32_t* tile_bad, float* genc,
@@ -685,7 +727,7 @@ hipError_t train_fp32_launch(const Geo& d, const float* w, const float* enc, con
     const int64_t tiles = (n + kTile - 1) / kTile;
     if (tiles == 0) return hipSuccess;
     const size_t lds = fp32_train_lds_bytes(d.H);
-    auto k = k_train_fp32<UP, GE, ACT>;
+    auto k = k_train_fp32<UP, GE, ACT, RAWL, PRESET>;
     (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL(k, dim3((unsigned)tiles), dim3(64 * fp32_train_waves<ACT>()), lds, s, w, enc, tgt, idx, n,
                        d.H, d.n_params(), loss_eps, grad_scale, partials, loss_part, tile_bad, genc, d.F, act, rgb,
@@ -713,6 +755,27 @@ hipError_t launch_train_fp32(const Geo& d, const float* w, const float* enc, con
                                              tile_bad, genc, s);
     return train_fp32_launch<true, false>(d, w, enc, tgt, idx, n, loss_eps, grad_scale, partials, loss_part,
                                           tile_bad, genc, s);
+}
+
+hipError_t launch_train_fp32_raw(const Geo& d, int preset, int layout, const float* w, const float* raw,
+                                 const float* tgt, const int32_t* idx, int64_t n, float loss_eps, float grad_scale,
+                                 float* partials, float* loss_part, int32_t* tile_bad, hipStream_t s,
+                                 LcgGather lg) {
+#define NRC_TRAIN_RAW(PR, LA)                                                                                  \
+    return train_fp32_launch<false, false, kActNone, LA, PR>(d, w, raw, tgt, idx, n, loss_eps, grad_scale,    \
+                                                             partials, loss_part, tile_bad, nullptr, s,       \
+                                                             nullptr, nullptr, lg)
+    const bool r14 = layout == NRC_RAW14;
+    if (preset == NRC_PRESET_PAPER_GAUSS) {
+        if (r14) NRC_TRAIN_RAW(NRC_PRESET_PAPER_GAUSS, NRC_RAW14); else NRC_TRAIN_RAW(NRC_PRESET_PAPER_GAUSS, NRC_RAW16);
+    } else if (preset == NRC_PRESET_PAPER_TRI) {
+        if (r14) NRC_TRAIN_RAW(NRC_PRESET_PAPER_TRI, NRC_RAW14); else NRC_TRAIN_RAW(NRC_PRESET_PAPER_TRI, NRC_RAW16);
+    } else if (preset == NRC_PRESET_PAPER) {
+        if (r14) NRC_TRAIN_RAW(NRC_PRESET_PAPER, NRC_RAW14); else NRC_TRAIN_RAW(NRC_PRESET_PAPER, NRC_RAW16);
+    }
+    if (r14) NRC_TRAIN_RAW(NRC_PRESET_CONFIG, NRC_RAW14);
+    NRC_TRAIN_RAW(NRC_PRESET_CONFIG, NRC_RAW16);
+#undef NRC_TRAIN_RAW
 }
 
 hipError_t launch_fwd_train_fp32(const Geo& d, const float* w, const float* enc, int64_t n, float* act,

@@ -114,7 +114,10 @@ __global__ __launch_bounds__(256) void k_fwd_raw_fp32_valu(const float* __restri
 // (forward and data backward, lane = record) and FPW rows of each dW_l (lane =
 // input feature).  More waves per tile give each SIMD more waves to hide the
 // latency of LDS and scalar weight loads.
-template <bool UPSTREAM, bool GENC, int NWV>
+// RAWL >= 0: the training records are given raw (that layout, encoded with
+// PRESET): enc points at FP32 [n][14 or 16] records and the first wave's lane s
+// encodes sample s into its h_0 row.
+template <bool UPSTREAM, bool GENC, int NWV, int RAWL = -1, int PRESET = NRC_PRESET_CONFIG>
 __global__ __launch_bounds__(64 * NWV) void k_train_fp32_valu(const float* __restrict__ w,
                                                          const float* __restrict__ enc,
                                                          const float* __restrict__ tgt,
@@ -145,12 +148,34 @@ __global__ __launch_bounds__(64 * NWV) void k_train_fp32_valu(const float* __res
     const int f0 = FPW * wave;                            // this wave's first feature / dW row
 
     // Stage the tile's inputs as h_0 (zeros past the end of the batch).
-    for (int i = tid; i < kTile * 16; i += NT) {
-        const int s = i >> 4, q = i & 15;
-        const int64_t r = tile * kTile + s;
-        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (r < n) v = reinterpret_cast<const float4*>(enc + gather_row(idx, lg, r) * kEncWidth)[q];
-        *reinterpret_cast<float4*>(hs + s * kLd + 4 * q) = v;
+    if constexpr (RAWL >= 0) {
+        static_assert(!UPSTREAM && !GENC, "raw records feed the training step only");
+        constexpr int RW = RAWL == NRC_RAW14 ? 14 : 16;
+        if (wave == 0) {
+            float f[64];
+            if (valid) {
+                const float* rr = enc + src * RW;
+                float x[RW];
+                #pragma unroll
+                for (int k = 0; k < RW; ++k) x[k] = rr[k];
+                encode_record<PRESET, RAWL>(x, f);
+            } else {
+                #pragma unroll
+                for (int k = 0; k < 64; ++k) f[k] = 0.0f;
+            }
+            #pragma unroll
+            for (int q = 0; q < 16; ++q)
+                *reinterpret_cast<float4*>(hs + lane * kLd + 4 * q) =
+                    make_float4(f[4 * q], f[4 * q + 1], f[4 * q + 2], f[4 * q + 3]);
+        }
+    } else {
+        for (int i = tid; i < kTile * 16; i += NT) {
+            const int s = i >> 4, q = i & 15;
+            const int64_t r = tile * kTile + s;
+            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (r < n) v = reinterpret_cast<const float4*>(enc + gather_row(idx, lg, r) * kEncWidth)[q];
+            *reinterpret_cast<float4*>(hs + s * kLd + 4 * q) = v;
+        }
     }
     __syncthreads();
 
@@ -342,14 +367,14 @@ inline size_t train_lds_bytes(int n_hidden) {
     return ((size_t)(n_hidden + 1) * kTile * kLd + 2 * kTile * kLd + 2 * kTile * 4) * sizeof(float);
 }
 
-template <bool UP, bool GE>
+template <bool UP, bool GE, int RAWL = -1, int PRESET = NRC_PRESET_CONFIG>
 hipError_t train_launch(const Geo& d, const float* w, const float* enc, const float* tgt, const int32_t* idx,
                         int64_t n, float loss_eps, float grad_scale, float* partials, float* loss_part,
                         int32_t* tile_bad, float* genc, LcgGather lg, hipStream_t s) {
     const int64_t tiles = (n + kTile - 1) / kTile;
     if (tiles == 0) return hipSuccess;
     const size_t lds = train_lds_bytes(d.H);
-    auto k = k_train_fp32_valu<UP, GE, kTrainWaves>;
+    auto k = k_train_fp32_valu<UP, GE, kTrainWaves, RAWL, PRESET>;
     (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL(k, dim3((unsigned)tiles), dim3(64 * kTrainWaves), lds, s, w, enc, tgt, idx, n, d.H,
                        d.n_params(), loss_eps, grad_scale, partials, loss_part, tile_bad, genc, d.F, lg);
@@ -391,6 +416,26 @@ hipError_t launch_fwd_raw_fp32_valu(const Geo& d, int preset, int layout, const 
             return r14 ? raw_launch<NRC_PRESET_CONFIG, NRC_RAW14>(d, w, raw, n, rgb, s)
                        : raw_launch<NRC_PRESET_CONFIG, NRC_RAW16>(d, w, raw, n, rgb, s);
     }
+}
+
+hipError_t launch_train_fp32_valu_raw(const Geo& d, int preset, int layout, const float* w, const float* raw,
+                                      const float* tgt, const int32_t* idx, int64_t n, float loss_eps,
+                                      float grad_scale, float* partials, float* loss_part, int32_t* tile_bad,
+                                      hipStream_t s, LcgGather lg) {
+#define NRC_TRAIN_RAW(PR, LA)                                                                                  \
+    return train_launch<false, false, LA, PR>(d, w, raw, tgt, idx, n, loss_eps, grad_scale, partials,        \
+                                              loss_part, tile_bad, nullptr, lg, s)
+    const bool r14 = layout == NRC_RAW14;
+    if (preset == NRC_PRESET_PAPER_GAUSS) {
+        if (r14) NRC_TRAIN_RAW(NRC_PRESET_PAPER_GAUSS, NRC_RAW14); else NRC_TRAIN_RAW(NRC_PRESET_PAPER_GAUSS, NRC_RAW16);
+    } else if (preset == NRC_PRESET_PAPER_TRI) {
+        if (r14) NRC_TRAIN_RAW(NRC_PRESET_PAPER_TRI, NRC_RAW14); else NRC_TRAIN_RAW(NRC_PRESET_PAPER_TRI, NRC_RAW16);
+    } else if (preset == NRC_PRESET_PAPER) {
+        if (r14) NRC_TRAIN_RAW(NRC_PRESET_PAPER, NRC_RAW14); else NRC_TRAIN_RAW(NRC_PRESET_PAPER, NRC_RAW16);
+    }
+    if (r14) NRC_TRAIN_RAW(NRC_PRESET_CONFIG, NRC_RAW14);
+    NRC_TRAIN_RAW(NRC_PRESET_CONFIG, NRC_RAW16);
+#undef NRC_TRAIN_RAW
 }
 
 hipError_t launch_train_fp32_valu(const Geo& d, const float* w, const float* enc, const float* tgt,

@@ -747,7 +747,13 @@ constexpr int kActNone = 0, kActStore = 1, kActLoad = 2;
 // Weight-gradient waves beside the chain waves (none in the forward-only form).
 template <int W, int ACT> constexpr int train_helpers() { return ACT == kActStore ? 0 : TrainShape<W>::NW; }
 
-template <typename T, int W, bool UPSTREAM, bool GENC, int ACT = kActNone>
+// Training records given raw (RAWL = their layout, PRESET = the cache's
+// encoding; RAWL < 0: encoded rows): the kernel's enc argument then points at
+// the raw records, FP32 [n][14 or 16], and lane ln of each chain wave encodes
+// its record into the record's h_0 row, where the stand-alone encoding kernel
+// would have written it, before the wave reads its operands back.
+template <typename T, int W, bool UPSTREAM, bool GENC, int ACT = kActNone, int RAWL = -1,
+          int PRESET = NRC_PRESET_CONFIG>
 __global__ __launch_bounds__(512) void k_train_mfma(const T* __restrict__ ffr,
                                                     const T* __restrict__ bfr,
                                                     const T* __restrict__ enc,
@@ -819,10 +825,38 @@ __global__ __launch_bounds__(512) void k_train_mfma(const T* __restrict__ ffr,
 
     // ---- forward (each wave: its 16 records, activations in VGPRs) ----------
     V b[KC];
-    #pragma unroll
-    for (int c = 0; c < 2; ++c) {
-        b[c] = valid ? *reinterpret_cast<const V*>(enc + src * kEncWidth + 32 * c + 8 * g) : zero8<V>();
-        if (chain) *reinterpret_cast<V*>(hT + sl * LD0 + 32 * c + 8 * g) = b[c];
+    if constexpr (RAWL >= 0) {
+        static_assert(!UPSTREAM && !GENC && ACT == kActNone, "raw records feed the training step only");
+        constexpr int RW = RAWL == NRC_RAW14 ? 14 : 16;
+        if (chain) {
+            T* h0 = hT + sl * LD0;
+            if (g == 0) {
+                float f[64];
+                if (valid) {
+                    const float* rr = reinterpret_cast<const float*>(enc) + src * RW;
+                    float x[RW];
+                    #pragma unroll
+                    for (int k = 0; k < RW; ++k) x[k] = rr[k];
+                    encode_record<PRESET, RAWL>(x, f);
+                } else {
+                    #pragma unroll
+                    for (int k = 0; k < 64; ++k) f[k] = 0.0f;
+                }
+                #pragma unroll
+                for (int q = 0; q < 8; ++q) store8<T>(h0, f, q);
+            }
+            wave_lds_sync();
+            #pragma unroll
+            for (int c = 0; c < 2; ++c) b[c] = *reinterpret_cast<const V*>(h0 + 32 * c + 8 * g);
+        } else {
+            b[0] = b[1] = zero8<V>();
+        }
+    } else {
+        #pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            b[c] = valid ? *reinterpret_cast<const V*>(enc + src * kEncWidth + 32 * c + 8 * g) : zero8<V>();
+            if (chain) *reinterpret_cast<V*>(hT + sl * LD0 + 32 * c + 8 * g) = b[c];
+        }
     }
     float r[3];                      // reflectance factor of record sl (lanes 0..15)
     reflectance_operand(b[1], fcol, ln, r);
@@ -1224,7 +1258,7 @@ hipError_t fwd_raw_dispatch(const Geo& d, int preset, int layout, const void* ff
                                : fwd_raw_generic<T, W, NRC_PRESET_CONFIG, NRC_RAW16>(d, ffr, raw, n, rgb, s);
 }
 
-template <typename T, int W, bool UP, bool GE, int ACT = kActNone>
+template <typename T, int W, bool UP, bool GE, int ACT = kActNone, int RAWL = -1, int PRESET = NRC_PRESET_CONFIG>
 hipError_t train_launch(const Geo& d, const void* ffr, const void* bfr, const void* enc,
                         const float* tgt, const int32_t* idx, int64_t n, float loss_eps, float grad_scale,
                         float* partials, float* loss_part, int32_t* tile_bad, float* genc,
@@ -1233,7 +1267,7 @@ hipError_t train_launch(const Geo& d, const void* ffr, const void* bfr, const vo
     const int64_t tiles = (n + S::TS - 1) / S::TS;
     if (tiles == 0) return hipSuccess;
     const size_t lds = (size_t)train_lds_bytes(W, d.H);
-    auto k = k_train_mfma<T, W, UP, GE, ACT>;
+    auto k = k_train_mfma<T, W, UP, GE, ACT, RAWL, PRESET>;
     (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL(k, dim3((unsigned)tiles), dim3(64 * (S::NW + train_helpers<W, ACT>())), lds, s, (const T*)ffr, (const T*)bfr,
                        (const T*)enc, tgt, idx, n, d.H, loss_eps, grad_scale, partials, loss_part, tile_bad,
@@ -1261,6 +1295,29 @@ hipError_t train_dispatch(const Geo& d, const void* ffr, const void* bfr, const 
                                               partials, loss_part, tile_bad, genc, s);
     return train_launch<T, W, true, false>(d, ffr, bfr, enc, tgt, idx, n, loss_eps, grad_scale,
                                            partials, loss_part, tile_bad, genc, s);
+}
+
+// The training step on raw records (width 64, as the fused query path).
+template <typename T>
+hipError_t train_raw_dispatch(const Geo& d, int preset, int layout, const void* ffr, const void* bfr,
+                              const float* raw, const float* tgt, const int32_t* idx, int64_t n, float loss_eps,
+                              float grad_scale, float* partials, float* loss_part, int32_t* tile_bad,
+                              hipStream_t s, LcgGather lg) {
+#define NRC_TRAIN_RAW(PR, LA)                                                                                 \
+    return train_launch<T, 64, false, false, kActNone, LA, PR>(d, ffr, bfr, raw, tgt, idx, n, loss_eps,      \
+                                                               grad_scale, partials, loss_part, tile_bad,     \
+                                                               nullptr, s, nullptr, nullptr, lg)
+    const bool r14 = layout == NRC_RAW14;
+    if (preset == NRC_PRESET_PAPER_GAUSS) {
+        if (r14) NRC_TRAIN_RAW(NRC_PRESET_PAPER_GAUSS, NRC_RAW14); else NRC_TRAIN_RAW(NRC_PRESET_PAPER_GAUSS, NRC_RAW16);
+    } else if (preset == NRC_PRESET_PAPER_TRI) {
+        if (r14) NRC_TRAIN_RAW(NRC_PRESET_PAPER_TRI, NRC_RAW14); else NRC_TRAIN_RAW(NRC_PRESET_PAPER_TRI, NRC_RAW16);
+    } else if (preset == NRC_PRESET_PAPER) {
+        if (r14) NRC_TRAIN_RAW(NRC_PRESET_PAPER, NRC_RAW14); else NRC_TRAIN_RAW(NRC_PRESET_PAPER, NRC_RAW16);
+    }
+    if (r14) NRC_TRAIN_RAW(NRC_PRESET_CONFIG, NRC_RAW14);
+    NRC_TRAIN_RAW(NRC_PRESET_CONFIG, NRC_RAW16);
+#undef NRC_TRAIN_RAW
 }
 
 }  // namespace
@@ -1328,6 +1385,18 @@ hipError_t launch_train_mfma(int precision, const Geo& d, const void* ffr, const
                                                   grad_scale, partials, loss_part, tile_bad, genc, s, act, lg)
                      : train_dispatch<__bf16, 128>(d, ffr, bfr, enc, tgt, idx, n, upstream, loss_eps,
                                                    grad_scale, partials, loss_part, tile_bad, genc, s, act, lg);
+}
+
+hipError_t launch_train_mfma_raw(int precision, const Geo& d, int preset, int layout, const void* ffr,
+                                 const void* bfr, const float* raw, const float* tgt, const int32_t* idx,
+                                 int64_t n, float loss_eps, float grad_scale, float* partials, float* loss_part,
+                                 int32_t* tile_bad, hipStream_t s, LcgGather lg) {
+    if (d.W != 64) return hipErrorInvalidValue;
+    if (precision == NRC_FP16)
+        return train_raw_dispatch<_Float16>(d, preset, layout, ffr, bfr, raw, tgt, idx, n, loss_eps, grad_scale,
+                                            partials, loss_part, tile_bad, s, lg);
+    return train_raw_dispatch<__bf16>(d, preset, layout, ffr, bfr, raw, tgt, idx, n, loss_eps, grad_scale,
+                                      partials, loss_part, tile_bad, s, lg);
 }
 
 template <typename T, int W>

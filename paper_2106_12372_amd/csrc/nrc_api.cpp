@@ -139,7 +139,7 @@ Geo kernel_geo(const nrc_config& c) {
 // Enqueue one training step (forward, loss, backward, reduction, Adam) on s.
 int enqueue_train_step(nrc_cache* c, const void* enc, const float* target, const int32_t* idx,
                        int64_t n, char* scratch, float* loss_dev, int32_t* skipped_dev, hipStream_t s,
-                       LcgGather lg) {
+                       LcgGather lg, int raw_layout) {
     const nrc_config& cfg = c->cfg;
     const Geo d = kernel_geo(cfg);
     const ScratchLayout sl = scratch_layout(cfg, n);
@@ -149,7 +149,18 @@ int enqueue_train_step(nrc_cache* c, const void* enc, const float* target, const
     const float scale = cfg.loss_scale;
     const float grad_scale = (float)((double)scale / (3.0 * (double)n));
     hipError_t e;
-    if (cfg.precision == NRC_FP32_VALU)
+    if (raw_layout >= 0) {
+        const float* raw = (const float*)enc;
+        if (cfg.precision == NRC_FP32_VALU)
+            e = launch_train_fp32_valu_raw(d, cfg.enc_preset, raw_layout, c->w(), raw, target, idx, n, cfg.loss_eps,
+                                           grad_scale, partials, loss_part, tile_bad, s, lg);
+        else if (cfg.precision == NRC_FP32)
+            e = launch_train_fp32_raw(d, cfg.enc_preset, raw_layout, c->w(), raw, target, idx, n, cfg.loss_eps,
+                                      grad_scale, partials, loss_part, tile_bad, s, lg);
+        else
+            e = launch_train_mfma_raw(cfg.precision, d, cfg.enc_preset, raw_layout, c->ffr(), c->bfr(), raw, target,
+                                      idx, n, cfg.loss_eps, grad_scale, partials, loss_part, tile_bad, s, lg);
+    } else if (cfg.precision == NRC_FP32_VALU)
         e = launch_train_fp32_valu(d, c->w(), (const float*)enc, target, idx, n, false, cfg.loss_eps, grad_scale,
                                    partials, loss_part, tile_bad, nullptr, s, lg);
     else if (cfg.precision == NRC_FP32)
@@ -635,12 +646,12 @@ namespace {
 // The frame's training steps on perm (validated arguments, scratch checked).
 int enqueue_frame_steps(nrc_cache* cache, const void* enc, const float* target, const int32_t* perm,
                         int64_t n_records, int steps, int64_t batch, char* step_scratch, float* losses_dev,
-                        int32_t* skipped_dev, hipStream_t s) {
+                        int32_t* skipped_dev, hipStream_t s, int raw_layout = -1) {
     const int64_t used = n_records < steps * batch ? n_records : steps * batch;
     for (int k = 0; k < steps; ++k) {
         const int64_t lo = k * used / steps, hi = (k + 1) * used / steps;
         const int rc = enqueue_train_step(cache, enc, target, perm + lo, hi - lo, step_scratch, losses_dev + k,
-                                          skipped_dev + k, s);
+                                          skipped_dev + k, s, LcgGather{}, raw_layout);
         if (rc != NRC_OK) return rc;
     }
     return ok();
@@ -663,13 +674,12 @@ int check_frame_buffers(nrc_cache* cache, const void* enc, const float* target, 
 }
 }  // namespace
 
-int nrc_train_frame(nrc_cache* cache, const void* enc, const float* target, int64_t n_records, int steps,
-                    int64_t batch, uint64_t seed, void* scratch, size_t scratch_bytes, float* losses_dev,
-                    int32_t* skipped_dev, void* stream) {
-    FrameLayout L;
-    const int rc = check_frame_buffers(cache, enc, target, n_records, steps, batch, scratch, scratch_bytes,
-                                       losses_dev, skipped_dev, &L);
-    if (rc != NRC_OK) return rc;
+namespace {
+// nrc_train_frame's steps after validation; raw_layout >= 0: enc holds raw
+// records the training kernels encode.
+int enqueue_frame(nrc_cache* cache, const void* enc, const float* target, int64_t n_records, int steps,
+                  int64_t batch, uint64_t seed, void* scratch, const FrameLayout& L, float* losses_dev,
+                  int32_t* skipped_dev, void* stream, int raw_layout) {
     char* sc = (char*)scratch;
     hipStream_t s = (hipStream_t)stream;
     if ((n_records & (n_records - 1)) == 0) {
@@ -684,7 +694,7 @@ int nrc_train_frame(nrc_cache* cache, const void* enc, const float* target, int6
             const int64_t lo = k * used / steps, hi = (k + 1) * used / steps;
             const LcgGather lg{step, apply(power(step, (uint64_t)lo), x0) & mask, mask};
             const int rc2 = enqueue_train_step(cache, enc, target, nullptr, hi - lo, sc + L.step, losses_dev + k,
-                                               skipped_dev + k, s, lg);
+                                               skipped_dev + k, s, lg, raw_layout);
             if (rc2 != NRC_OK) return rc2;
         }
         return ok();
@@ -693,7 +703,33 @@ int nrc_train_frame(nrc_cache* cache, const void* enc, const float* target, int6
     hipError_t e = launch_shuffle(n_records, seed, perm, (int32_t*)(sc + L.counts), s);
     if (e != hipSuccess) return device_fail(e, "shuffle launch");
     return enqueue_frame_steps(cache, enc, target, perm, n_records, steps, batch, sc + L.step, losses_dev,
-                               skipped_dev, s);
+                               skipped_dev, s, raw_layout);
+}
+}  // namespace
+
+int nrc_train_frame(nrc_cache* cache, const void* enc, const float* target, int64_t n_records, int steps,
+                    int64_t batch, uint64_t seed, void* scratch, size_t scratch_bytes, float* losses_dev,
+                    int32_t* skipped_dev, void* stream) {
+    FrameLayout L;
+    const int rc = check_frame_buffers(cache, enc, target, n_records, steps, batch, scratch, scratch_bytes,
+                                       losses_dev, skipped_dev, &L);
+    if (rc != NRC_OK) return rc;
+    return enqueue_frame(cache, enc, target, n_records, steps, batch, seed, scratch, L, losses_dev, skipped_dev,
+                         stream, -1);
+}
+
+int nrc_train_frame_raw(nrc_cache* cache, const float* raw, int raw_layout, const float* target,
+                        int64_t n_records, int steps, int64_t batch, uint64_t seed, void* scratch,
+                        size_t scratch_bytes, float* losses_dev, int32_t* skipped_dev, void* stream) {
+    if (!cache) return fail(NRC_EINVAL, "cache is NULL");
+    if (raw_layout != NRC_RAW14 && raw_layout != NRC_RAW16) return fail(NRC_EINVAL, "unknown raw layout %d", raw_layout);
+    if (cache->cfg.width != 64) return fail(NRC_EINVAL, "the fused raw-record path supports width 64");
+    FrameLayout L;
+    const int rc = check_frame_buffers(cache, raw, target, n_records, steps, batch, scratch, scratch_bytes,
+                                       losses_dev, skipped_dev, &L);
+    if (rc != NRC_OK) return rc;
+    return enqueue_frame(cache, raw, target, n_records, steps, batch, seed, scratch, L, losses_dev, skipped_dev,
+                         stream, raw_layout);
 }
 
 int nrc_train_frame_indexed(nrc_cache* cache, const void* enc, const float* target, const int32_t* perm,

@@ -60,8 +60,10 @@ struct nrc_cache {
 namespace nrc {
 // idx (may be NULL): the batch is records idx[0..n) of enc / target; lg (if
 // its mask is set and idx is NULL): the batch is n records of the LCG orbit.
+// raw_layout >= 0: enc holds raw records (FP32, that layout) that the
+// training kernel encodes itself.
 int enqueue_train_step(nrc_cache* c, const void* enc, const float* target, const int32_t* idx,
                        int64_t n, char* scratch, float* loss_dev, int32_t* skipped_dev, hipStream_t s,
-                       LcgGather lg = LcgGather{});
+                       LcgGather lg = LcgGather{}, int raw_layout = -1);
 int enqueue_forward(nrc_cache* c, const void* enc, int64_t n, float* rgb, hipStream_t s);
 }  // namespace nrc

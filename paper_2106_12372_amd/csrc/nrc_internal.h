@@ -233,6 +233,21 @@ hipError_t launch_train_fp32(const Geo& d, const float* w, const float* enc, con
                              hipStream_t s, const float* act = nullptr, LcgGather lg = LcgGather{});
 hipError_t launch_fwd_train_fp32(const Geo& d, const float* w, const float* enc, int64_t n, float* act,
                                  float* rgb, hipStream_t s);
+// The training steps of the three forms on raw records (layout, the cache's
+// preset): each kernel encodes its records as the encoding kernel would, so the
+// results equal encode-then-train bit for bit.  FP16/BF16: width 64 only.
+hipError_t launch_train_fp32_raw(const Geo& d, int preset, int layout, const float* w, const float* raw,
+                                 const float* tgt, const int32_t* idx, int64_t n, float loss_eps, float grad_scale,
+                                 float* partials, float* loss_part, int32_t* tile_bad, hipStream_t s,
+                                 LcgGather lg);
+hipError_t launch_train_fp32_valu_raw(const Geo& d, int preset, int layout, const float* w, const float* raw,
+                                      const float* tgt, const int32_t* idx, int64_t n, float loss_eps,
+                                      float grad_scale, float* partials, float* loss_part, int32_t* tile_bad,
+                                      hipStream_t s, LcgGather lg);
+hipError_t launch_train_mfma_raw(int precision, const Geo& d, int preset, int layout, const void* ffr,
+                                 const void* bfr, const float* raw, const float* tgt, const int32_t* idx,
+                                 int64_t n, float loss_eps, float grad_scale, float* partials, float* loss_part,
+                                 int32_t* tile_bad, hipStream_t s, LcgGather lg);
 hipError_t launch_fwd_raw_fp32(const Geo& d, int preset, int layout, const float* w, const float* raw,
                                int64_t n, float* rgb, hipStream_t s);
 // mlp_fp32_valu.hip (NRC_FP32_VALU: vector ALUs only)

@@ -104,6 +104,7 @@ _decl("nrc_train_step_indexed", c_int, _P, _P, _P, _P, c_int64, _P, c_size_t, _P
 _decl("nrc_frame_scratch_bytes", c_size_t, POINTER(nrc_config), c_int64, c_int, c_int64)
 _decl("nrc_train_frame", c_int, _P, _P, _P, c_int64, c_int, c_int64, c_uint64, _P, c_size_t, _P, _P, _P)
 _decl("nrc_train_frame_indexed", c_int, _P, _P, _P, _P, c_int64, c_int, c_int64, _P, c_size_t, _P, _P, _P)
+_decl("nrc_train_frame_raw", c_int, _P, _P, c_int, _P, c_int64, c_int, c_int64, c_uint64, _P, c_size_t, _P, _P, _P)
 _decl("nrc_self_training_targets", c_int, _P, _P, _P, _P, c_int64, c_int64, _P, _P)
 _decl("nrc_error_norms_scratch_bytes", c_size_t, c_int64)
 _decl("nrc_error_norms", c_int, _P, _P, c_int64, _P, c_size_t, _P, _P)
@@ -121,7 +122,7 @@ EXPORTED = ["nrc_config_default", "nrc_last_error", "nrc_param_count", "nrc_cach
             "nrc_get_state", "nrc_set_state", "nrc_get_ema", "nrc_set_ema", "nrc_encode", "nrc_forward", "nrc_forward_raw", "nrc_train_step",
             "nrc_train_step_noalloc",
             "nrc_act_ws_bytes", "nrc_forward_train", "nrc_backward", "nrc_shuffle_scratch_bytes", "nrc_shuffle", "nrc_train_step_indexed",
-            "nrc_frame_scratch_bytes", "nrc_train_frame", "nrc_train_frame_indexed", "nrc_self_training_targets", "nrc_error_norms_scratch_bytes", "nrc_error_norms", "nrc_serve_create", "nrc_serve_set_weights", "nrc_serve_get_weights",
+            "nrc_frame_scratch_bytes", "nrc_train_frame", "nrc_train_frame_indexed", "nrc_train_frame_raw", "nrc_self_training_targets", "nrc_error_norms_scratch_bytes", "nrc_error_norms", "nrc_serve_create", "nrc_serve_set_weights", "nrc_serve_get_weights",
             "nrc_serve_submit", "nrc_serve_poll", "nrc_serve_drain", "nrc_serve_destroy"]
 
 
@@ -469,6 +470,28 @@ def nrc_train_frame_indexed(cache: Cache, enc, target, perm, steps: int = 4, bat
     check(lib.nrc_train_frame_indexed(cache.handle, _ptr(enc), _ptr(target), _ptr(perm), n, steps, batch,
                                       _ptr(scratch), scratch.numel(), _ptr(losses), _ptr(skipped),
                                       _stream(stream)))
+    return losses, skipped
+
+
+def nrc_train_frame_raw(cache: Cache, raw, target, layout: int = NRC_RAW14, steps: int = 4, batch: int = 16384,
+                        seed: int = 0, scratch=None, stream=None):
+    """nrc_train_frame on raw records (FP32 [n][14] or [n][16]), encoded inside
+    the training kernels; returns (losses[steps], skipped[steps])."""
+    torch = _torch()
+    width = 14 if layout == NRC_RAW14 else 16
+    _need(raw, torch.float32, (width,), "raw")
+    _need(target, torch.float32, (3,), "target")
+    n = raw.shape[0]
+    if target.shape[0] != n:
+        raise ValueError("raw and target differ in length")
+    if scratch is None:
+        scratch = _aligned_bytes(nrc_frame_scratch_bytes(cache.cfg, n, steps, batch), raw.device)
+    losses = torch.empty(steps, dtype=torch.float32, device=raw.device)
+    skipped = torch.empty(steps, dtype=torch.int32, device=raw.device)
+    _keep(stream, scratch, losses, skipped)
+    check(lib.nrc_train_frame_raw(cache.handle, _ptr(raw), layout, _ptr(target), n, steps, batch,
+                                  seed & (2 ** 64 - 1), _ptr(scratch), scratch.numel(), _ptr(losses),
+                                  _ptr(skipped), _stream(stream)))
     return losses, skipped
 
 

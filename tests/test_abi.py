@@ -112,6 +112,8 @@ def test_record_pipeline_rejects_bad_arguments_before_device_calls(N):
                                  P(4096), None) == N.NRC_EINVAL
     assert N.lib.nrc_train_frame_indexed(None, P(4096), P(4096), P(4096), 65536, 4, 16384, P(4096), 1 << 30,
                                          P(4096), P(4096), None) == N.NRC_EINVAL
+    assert N.lib.nrc_train_frame_raw(None, P(4096), N.NRC_RAW14, P(4096), 65536, 4, 16384, 0, P(4096), 1 << 30,
+                                     P(4096), P(4096), None) == N.NRC_EINVAL
     assert N.lib.nrc_self_training_targets(P(4096), P(4096), P(4096), P(4096), 10, 0, P(4096), None) == N.NRC_EINVAL
     assert N.lib.nrc_self_training_targets(None, P(4096), P(4096), P(4096), 10, 5, P(4096), None) == N.NRC_EINVAL
     assert N.lib.nrc_self_training_targets(None, None, None, None, 0, 0, None, None) == N.NRC_OK

@@ -78,6 +78,39 @@ def test_indexed_step_equals_step_on_gathered_batch(N, prec):
     assert np.array_equal(a.get_weights(), b.get_weights())
 
 
+@pytest.mark.parametrize("prec", ["fp32", "fp16", "bf16", "fp32_valu"])
+@pytest.mark.parametrize("preset", [0, 1, 2, 3])
+@pytest.mark.parametrize("layout", [0, 1])
+@pytest.mark.parametrize("n_records", [32768, 20001])
+def test_raw_frame_equals_encode_then_frame(N, prec, preset, layout, n_records):
+    # The training kernels encode each gathered raw record with the encoding
+    # kernel's arithmetic and rounding, so a frame on raw records equals the
+    # frame on their encoding bit for bit: losses, skip flags, weights, Adam
+    # moments and step count.  32,768 records take the in-kernel LCG orbit,
+    # 20,001 the shuffle's permutation (steps of 5,000 and 5,001 records,
+    # ragged tiles).  Every other preset factorises by the reflectance, whose
+    # albedo columns the kernels then read from the encoded row.
+    raw = sd.raw_records(n_records, 90 + n_records, layout)
+    y = dev(sd.targets(raw))
+    fact = preset % 2 == 0
+    a, _ = make_cache(N, prec, preset=preset, factorize=fact)
+    b, _ = make_cache(N, prec, preset=preset, factorize=fact)
+    la, sa = N.nrc_train_frame(a, N.nrc_encode(a, dev(raw), layout), y, steps=4, batch=8192, seed=11)
+    lb, sb = N.nrc_train_frame_raw(b, dev(raw), y, layout=layout, steps=4, batch=8192, seed=11)
+    assert torch.equal(la, lb) and torch.equal(sa, sb)
+    assert int(sa.sum().item()) == 0
+    for x, z in zip(a.get_state()[:3], b.get_state()[:3]):
+        assert np.array_equal(x, z)
+    assert a.get_state()[3] == b.get_state()[3] == 4
+
+
+def test_raw_frame_needs_width_64(N):
+    c, _ = make_cache(N, "fp16", width=128)
+    raw = sd.raw_records(4096, 5)
+    with pytest.raises(N.NrcError):
+        N.nrc_train_frame_raw(c, dev(raw), dev(sd.targets(raw)), steps=4, batch=1024)
+
+
 @pytest.mark.parametrize("prec", ["fp32", "fp16", "bf16"])
 @pytest.mark.parametrize("n_records", [65536, 50001, 70000])
 def test_frame_steps_match_oracle_from_the_same_state(N, prec, n_records):
