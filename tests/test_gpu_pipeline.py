@@ -104,6 +104,24 @@ def test_raw_frame_equals_encode_then_frame(N, prec, preset, layout, n_records):
     assert a.get_state()[3] == b.get_state()[3] == 4
 
 
+@pytest.mark.parametrize("prec", ["fp32", "fp16", "bf16", "fp32_valu"])
+def test_raw_frame_with_a_non_finite_record_skips_like_the_encoded_frame(N, prec):
+    # A NaN position encodes to NaN features in both paths, so the step that
+    # gathers that record has a non-finite gradient and is skipped; the other
+    # steps go ahead.  Both paths agree bit for bit, skip flags included.
+    raw = sd.raw_records(32768, 17)
+    raw[12345, 0] = np.nan
+    y = dev(sd.targets(np.nan_to_num(raw)))
+    a, _ = make_cache(N, prec)
+    b, _ = make_cache(N, prec)
+    la, sa = N.nrc_train_frame(a, N.nrc_encode(a, dev(raw), 0), y, steps=4, batch=8192, seed=5)
+    lb, sb = N.nrc_train_frame_raw(b, dev(raw), y, steps=4, batch=8192, seed=5)
+    assert torch.equal(sa, sb) and int(sa.sum().item()) == 1
+    assert torch.equal(la.isnan(), lb.isnan())
+    assert torch.equal(la[~la.isnan()], lb[~lb.isnan()])
+    assert np.array_equal(a.get_weights(), b.get_weights())
+
+
 def test_raw_frame_needs_width_64(N):
     c, _ = make_cache(N, "fp16", width=128)
     raw = sd.raw_records(4096, 5)
