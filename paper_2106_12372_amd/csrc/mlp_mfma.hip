@@ -830,6 +830,15 @@ __global__ __launch_bounds__(512) void k_train_mfma(const T* __restrict__ ffr,
         constexpr int RW = RAWL == NRC_RAW14 ? 14 : 16;
         if (chain) {
             T* h0 = hT + sl * LD0;
+            // BF16: the first layer's weight fragments (hi and lo parts) start
+            // loading now, beside the encoding, so they are cached when the
+            // layer reads them (the LDS hand-over below orders every later
+            // memory access).  Measured: the BF16 step 17.8 -> 16.2 us; FP16,
+            // with half the fragments, no faster, so it does not prefetch.
+            constexpr int NPRE = SPLIT ? 4 * MB : 0;
+            V pre[NPRE > 0 ? NPRE : 1];
+            #pragma unroll
+            for (int i = 0; i < NPRE; ++i) pre[i] = gf[(i % (2 * MB)) * 64 + (i < 2 * MB ? 0 : lo_f)];
             if (g == 0) {
                 float f[64];
                 if (valid) {
@@ -848,6 +857,8 @@ __global__ __launch_bounds__(512) void k_train_mfma(const T* __restrict__ ffr,
             wave_lds_sync();
             #pragma unroll
             for (int c = 0; c < 2; ++c) b[c] = *reinterpret_cast<const V*>(h0 + 32 * c + 8 * g);
+            #pragma unroll
+            for (int i = 0; i < NPRE; ++i) asm volatile("" :: "v"(pre[i]));
         } else {
             b[0] = b[1] = zero8<V>();
         }
