@@ -1,7 +1,7 @@
 // Validation-error reductions in FP64 on the device: per-channel norms of the
 // difference between a batch of FP32 predictions and FP64 reference values,
-// the inputs of the per-channel relative errors the precision forms are
-// judged by (normwise in the L2 and the max norm).  Two kernels: each
+// the inputs of the per-channel relative errors that measure the precision
+// forms (normwise in the L2 and the max norm).  Two kernels: each
 // workgroup reduces a fixed contiguous chunk of the records with a fixed
 // tree, then one workgroup combines the chunk results in chunk order, so the
 // sums are bitwise reproducible.
