@@ -122,6 +122,22 @@ def test_raw_frame_with_a_non_finite_record_skips_like_the_encoded_frame(N, prec
     assert np.array_equal(a.get_weights(), b.get_weights())
 
 
+@pytest.mark.parametrize("prec", ["fp32", "fp16", "bf16", "fp32_valu"])
+@pytest.mark.parametrize("layout", [0, 1])
+def test_raw_frame_on_edge_records_equals_encode_then_frame(N, prec, layout):
+    # The method's edge inputs (positions far outside [0, 1), exact 0 and 1,
+    # RAW16 poles, angles on bin edges, roughness 0 and large) through the
+    # in-kernel encoding of the training step, against the encoding kernel.
+    raw = sd.edge_records(8000, 77 + layout, layout)
+    y = dev(sd.targets(raw))
+    a, _ = make_cache(N, prec, preset=1)
+    b, _ = make_cache(N, prec, preset=1)
+    la, sa = N.nrc_train_frame(a, N.nrc_encode(a, dev(raw), layout), y, steps=4, batch=2048, seed=2)
+    lb, sb = N.nrc_train_frame_raw(b, dev(raw), y, layout=layout, steps=4, batch=2048, seed=2)
+    assert torch.equal(la, lb) and torch.equal(sa, sb)
+    assert np.array_equal(a.get_weights(), b.get_weights())
+
+
 def test_raw_frame_needs_width_64(N):
     c, _ = make_cache(N, "fp16", width=128)
     raw = sd.raw_records(4096, 5)
