@@ -75,24 +75,32 @@ __device__ inline void stage_query_frags(f4* sw, const float* __restrict__ w, in
     }
 }
 
-// The output layer's weights a lane needs: wo[o][b] = W_out[o][16b + 4g .. +3],
-// the neurons lane group g holds.
-__device__ inline void load_out_weights(const float* __restrict__ w, int H, int g, float4 (&wo)[kNOut][4]) {
-    const float* base = w + H * kW * kW + 4 * g;
+// The output-layer weights a lane supplies as the A operand of the 4 x 4 x 1
+// products: wo[b] = W_out[o][16b + 4g .. +3] for o = lane % 4 (the block row
+// the lane feeds; row 3 is padding, zero), over the neurons lane group g holds.
+__device__ inline void load_out_weights(const float* __restrict__ w, int H, int lane, f4 (&wo)[4]) {
+    const int g = lane >> 4, o = lane & 3;
+    const float* base = w + H * kW * kW + (o < kNOut ? o : 0) * kW + 4 * g;
     #pragma unroll
-    for (int o = 0; o < kNOut; ++o)
-        #pragma unroll
-        for (int b = 0; b < 4; ++b) wo[o][b] = *reinterpret_cast<const float4*>(base + o * kW + 16 * b);
+    for (int b = 0; b < 4; ++b) {
+        const float4 v = *reinterpret_cast<const float4*>(base + 16 * b);
+        wo[b] = o < kNOut ? f4{v.x, v.y, v.z, v.w} : f4{0.0f, 0.0f, 0.0f, 0.0f};
+    }
 }
 
 // The network on the wave's 64 queries.  h: this lane's 64 input features; y:
-// this lane's 3 outputs.  The hidden layers run on the matrix cores; the
-// 3-row output layer, which would use 3 of an MFMA block's 16 rows, runs on
-// the vector ALUs: each lane forms the partial dots over the 16 neurons it
-// holds for its four columns' queries, and one transpose per channel gathers
-// the four lane groups' partials onto the lane that loaded the query.
+// this lane's 3 outputs.  The hidden layers run on the 16 x 16 x 4 matrix
+// instructions.  The 3-row output layer runs on v_mfma_f32_4x4x1f32, sixteen
+// 4 x 4 blocks of K = 1: block 4g + j/4 of lane (g, j) takes A = W_out[o][n]
+// from lanes 4(4g + j/4) + o and B = neuron n of the records 16c + 4(j/4) ..
+// +3 of column c, so after the 16 neurons n its group holds (in the vector
+// form's order) lane (g, j) has in register o the group's partial dot of
+// channel o for query 16c + j; each product adds with one rounding, as the
+// fmaf chain of the training kernel's output layer.  One transpose per
+// channel gathers the four lane groups' partials onto the lane that loaded
+// the query.
 __device__ inline void mlp_query_mfma(const f4* __restrict__ sw, int H, int lane,
-                                      const float4 (&wo)[kNOut][4], const float (&h)[kW],
+                                      const f4 (&wo)[4], const float (&h)[kW],
                                       float (&y)[kNOut]) {
     float act[4][16];   // [column][K step]: lane group g, step 4b + r = neuron 16b + 4g + r
     #pragma unroll
@@ -133,21 +141,19 @@ __device__ inline void mlp_query_mfma(const f4* __restrict__ sw, int H, int lane
                 #pragma unroll
                 for (int r = 0; r < 4; ++r) act[c][4 * ob + r] = relu(acc[c][ob][r]);
     }
+    f4 po[4];   // po[c][o]: this lane group's share of channel o for column c's query
+    #pragma unroll
+    for (int c = 0; c < 4; ++c) po[c] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+    #pragma unroll
+    for (int b = 0; b < 4; ++b)
+        #pragma unroll
+        for (int r = 0; r < 4; ++r)
+            #pragma unroll
+            for (int c = 0; c < 4; ++c)
+                po[c] = __builtin_amdgcn_mfma_f32_4x4x1f32(wo[b][r], act[c][4 * b + r], po[c], 0, 0, 0);
     #pragma unroll
     for (int o = 0; o < kNOut; ++o) {
-        float p[4];   // p[c]: this lane group's share of channel o for column c's query
-        #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            float acc = 0.0f;
-            #pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                acc = fmaf(wo[o][b].x, act[c][4 * b], acc);
-                acc = fmaf(wo[o][b].y, act[c][4 * b + 1], acc);
-                acc = fmaf(wo[o][b].z, act[c][4 * b + 2], acc);
-                acc = fmaf(wo[o][b].w, act[c][4 * b + 3], acc);
-            }
-            p[c] = acc;
-        }
+        float p[4] = {po[0][o], po[1][o], po[2][o], po[3][o]};
         // afterwards register c of group g holds group c's share for column
         // g's query: the four registers of a lane add up to its own query
         xpose4(p[0], p[1], p[2], p[3]);
@@ -168,8 +174,8 @@ __device__ inline void query_fp32(const float* __restrict__ w, const float* __re
     if (threadIdx.x == 0) claimed = 0;
     stage_query_frags(sw, w, H);
     const int lane = threadIdx.x & 63;
-    float4 wo[kNOut][4];
-    load_out_weights(w, H, lane >> 4, wo);
+    f4 wo[4];
+    load_out_weights(w, H, lane, wo);
     __syncthreads();
     // The workgroup owns a contiguous share of the tiles and its waves claim
     // them one at a time, so all waves of the CU finish together.
