@@ -113,8 +113,9 @@ ScratchLayout scratch_layout(const nrc_config& c, int64_t n) {
     L.loss_part = take(tiles * 4);
     L.grad = take(P * 4);
     L.flags = take(tiles * 4);
+    // the step's loss and skip flag side by side, so one 8-byte copy reads both
     L.loss = take(16);
-    L.skipped = take(16);
+    L.skipped = L.loss + 4;
     L.total = off;
     return L;
 }

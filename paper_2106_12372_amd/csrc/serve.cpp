@@ -27,6 +27,7 @@
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
+#include <cstddef>
 #include <list>
 #include <map>
 #include <mutex>
@@ -123,6 +124,7 @@ struct nrc_server {
     std::vector<hipEvent_t> slot_event;     // completion event per in-flight slot
     std::vector<int> slot_free;
     struct HostOut { float loss; int32_t skipped; int32_t pad[2]; };
+    static_assert(offsetof(HostOut, skipped) == 4, "one copy fills loss and skipped");
     HostOut* host_out = nullptr;            // pinned, one per slot
 
     std::mutex mu;
@@ -189,8 +191,8 @@ bool nrc_server::try_launch(std::vector<Request>& rs, std::unique_lock<std::mute
                                 (int32_t*)(sc + sl.skipped), s);
         enqueued = true;                  // even a failed enqueue may have queued the training kernel
         if (rc == NRC_OK) {
-            if (hipMemcpyAsync(&host_out[slot].loss, sc + sl.loss, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
-                hipMemcpyAsync(&host_out[slot].skipped, sc + sl.skipped, 4, hipMemcpyDeviceToHost, s) != hipSuccess)
+            // loss and skip flag are adjacent in the scratch and in HostOut
+            if (hipMemcpyAsync(&host_out[slot].loss, sc + sl.loss, 8, hipMemcpyDeviceToHost, s) != hipSuccess)
                 rc = NRC_EDEVICE;
         }
     } else if (rs.size() == 1) {
