@@ -601,19 +601,64 @@ __global__ __launch_bounds__(64 * (kChainWaves + kGradWaves)) void k_train_fp32(
         } else if (l >= 1 || GENC) {
             // W_l^T delta_{l+1}: lane (g, i) supplies W_l[16 obp + 4g + r][16 ob + i]
             // in K step (obp, r); a holds delta_{l+1} in the same order.
-            const float* wl = w + l * kW * kW + 4 * g * kW + j;
+            // W_{l-1}, which the next iteration needs, is staged transposed
+            // (WT[k][o] = W[o][k], rows of kLd floats) into the LDS row block of
+            // h_{l+1}, which no later step reads: chain thread tid moves
+            // W[tid % 64][16 (tid / 64) ..+15], so a wave's stores fall in
+            // consecutive banks.  W_l itself comes from the block
+            // the previous iteration filled, or, in the first iteration, from
+            // the L2-resident master weights.
+            const bool stage = l >= 2 || (GENC && l == 1);
+            float4 wn[4];
+            if (stage) {
+                const float4* src = reinterpret_cast<const float4*>(w + (l - 1) * kW * kW + (tid & 63) * kW +
+                                                                    16 * (tid >> 6));
+                #pragma unroll
+                for (int u = 0; u < 4; ++u) wn[u] = src[u];
+            }
             f4 acc[4];
             #pragma unroll
             for (int ob = 0; ob < 4; ++ob) acc[ob] = f4{0.0f, 0.0f, 0.0f, 0.0f};
-            #pragma unroll
-            for (int obp = 0; obp < 4; ++obp)
+            if (l <= n_hidden - 2) {
+                // fragment (ob, obp) of lane (g, j): WT[16 ob + j][16 obp + 4g .. +3]
+                const float* wt = hrow(l + 2) + j * kLd + 4 * g;
+                f4 fr[4][4];
                 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const float* wr = wl + (16 * obp + q) * kW;
+                for (int obp = 0; obp < 4; ++obp)
                     #pragma unroll
                     for (int ob = 0; ob < 4; ++ob)
-                        acc[ob] = __builtin_amdgcn_mfma_f32_16x16x4f32(wr[16 * ob], a[4 * obp + q], acc[ob], 0, 0, 0);
+                        fr[obp][ob] = *reinterpret_cast<const f4*>(wt + 16 * ob * kLd + 16 * obp);
+                #pragma unroll
+                for (int obp = 0; obp < 4; ++obp)
+                    #pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        #pragma unroll
+                        for (int ob = 0; ob < 4; ++ob)
+                            acc[ob] = __builtin_amdgcn_mfma_f32_16x16x4f32(fr[obp][ob][q], a[4 * obp + q], acc[ob],
+                                                                           0, 0, 0);
+            } else {
+                const float* wl = w + l * kW * kW + 4 * g * kW + j;
+                #pragma unroll
+                for (int obp = 0; obp < 4; ++obp)
+                    #pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const float* wr = wl + (16 * obp + q) * kW;
+                        #pragma unroll
+                        for (int ob = 0; ob < 4; ++ob)
+                            acc[ob] = __builtin_amdgcn_mfma_f32_16x16x4f32(wr[16 * ob], a[4 * obp + q], acc[ob],
+                                                                           0, 0, 0);
+                    }
+            }
+            if (stage) {
+                float* dst = hrow(l + 1) + 16 * (tid >> 6) * kLd + (tid & 63);
+                #pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    dst[(4 * u) * kLd] = wn[u].x;
+                    dst[(4 * u + 1) * kLd] = wn[u].y;
+                    dst[(4 * u + 2) * kLd] = wn[u].z;
+                    dst[(4 * u + 3) * kLd] = wn[u].w;
                 }
+            }
 
             if (l >= 1) {
                 // delta_l = (W_l^T delta_{l+1}) masked by ReLU'(z_l)
