@@ -260,6 +260,11 @@ __global__ __launch_bounds__(64 * kQWaves) void k_fwd_raw_fp32(const float* __re
 constexpr int kActNone = 0, kActStore = 1, kActLoad = 2;
 constexpr int kChainWaves = 4, kGradWaves = 4;
 
+// Whether the training kernel keeps W_{H-1} transposed in LDS for the first
+// backward iteration: H >= 2 (it is staged for the forward pass) and H <= 5
+// (with H = 6 the activations fill the LDS).
+__host__ __device__ constexpr bool fp32_train_wlast(int n_hidden) { return n_hidden >= 2 && n_hidden <= 5; }
+
 template <int ACT> constexpr int fp32_train_waves() { return ACT == kActStore ? kChainWaves : kChainWaves + kGradWaves; }
 
 // Training records given raw (RAWL = their layout, PRESET = the cache's
@@ -281,6 +286,10 @@ __global__ __launch_bounds__(64 * (kChainWaves + kGradWaves)) void k_train_fp32(
     float* dbuf1 = dbuf0 + kTile * kLd;
     float* dout = dbuf1 + kTile * kLd;                    // [64][4]: dL/d(network output)
     float* fout = dout + kTile * 4;                       // [64][4]: network output
+    // W_{H-1} transposed for the first backward iteration, written while it is
+    // staged for the forward pass (2 <= H <= 5, where it fits beside the rest)
+    float* wlast = fout + kTile * 4;
+    const bool wlast_on = ACT == kActNone && fp32_train_wlast(n_hidden);
     auto hrow = [&](int l) { return hs + l * kTile * kLd; };
 
     // The wave index is uniform across the wave; saying so lets addresses that
@@ -447,6 +456,18 @@ __global__ __launch_bounds__(64 * (kChainWaves + kGradWaves)) void k_train_fp32(
             *reinterpret_cast<float4*>(dst + 16 * kLd) = s1;
             *reinterpret_cast<float4*>(dst + 32 * kLd) = s2;
             *reinterpret_cast<float4*>(dst + 48 * kLd) = s3;
+            if (wlast_on && l + 2 == n_hidden) {
+                // WT[k][o] = W_{H-1}[o][k]: this thread holds rows srow + 16u, columns scol ..+3
+                float* t = wlast + scol * kLd + srow;
+                const float4 sv[4] = {s0, s1, s2, s3};
+                #pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    t[16 * u] = sv[u].x;
+                    t[kLd + 16 * u] = sv[u].y;
+                    t[2 * kLd + 16 * u] = sv[u].z;
+                    t[3 * kLd + 16 * u] = sv[u].w;
+                }
+            }
         }
         __syncthreads();   // W_{l+1} staged; W_l's buffer free
     }
@@ -607,7 +628,8 @@ __global__ __launch_bounds__(64 * (kChainWaves + kGradWaves)) void k_train_fp32(
             // W[tid % 64][16 (tid / 64) ..+15], so a wave's stores fall in
             // consecutive banks.  W_l itself comes from the block
             // the previous iteration filled, or, in the first iteration, from
-            // the L2-resident master weights.
+            // the transposed copy the forward pass left (else from the
+            // L2-resident master weights).
             const bool stage = l >= 2 || (GENC && l == 1);
             float4 wn[4];
             if (stage) {
@@ -619,9 +641,10 @@ __global__ __launch_bounds__(64 * (kChainWaves + kGradWaves)) void k_train_fp32(
             f4 acc[4];
             #pragma unroll
             for (int ob = 0; ob < 4; ++ob) acc[ob] = f4{0.0f, 0.0f, 0.0f, 0.0f};
-            if (l <= n_hidden - 2) {
+            const float* wtb = l <= n_hidden - 2 ? hrow(l + 2) : wlast_on ? wlast : nullptr;
+            if (wtb) {
                 // fragment (ob, obp) of lane (g, j): WT[16 ob + j][16 obp + 4g .. +3]
-                const float* wt = hrow(l + 2) + j * kLd + 4 * g;
+                const float* wt = wtb + j * kLd + 4 * g;
                 f4 fr[4][4];
                 #pragma unroll
                 for (int obp = 0; obp < 4; ++obp)
@@ -766,7 +789,8 @@ hipError_t launch_fwd_raw_fp32(const Geo& d, int preset, int layout, const float
 }
 
 size_t fp32_train_lds_bytes(int n_hidden) {
-    return ((size_t)(n_hidden + 1) * kTile * kLd + 2 * kTile * kLd + 2 * kTile * 4) * sizeof(float);
+    return ((size_t)(n_hidden + 1) * kTile * kLd + 2 * kTile * kLd + 2 * kTile * 4 +
+            (fp32_train_wlast(n_hidden) ? (size_t)kTile * kLd : 0)) * sizeof(float);
 }
 
 template <bool UP, bool GE, int ACT = kActNone, int RAWL = -1, int PRESET = NRC_PRESET_CONFIG>
