@@ -540,8 +540,6 @@ __global__ __launch_bounds__(64 * (kChainWaves + kGradWaves)) void k_train_fp32(
             *reinterpret_cast<float4*>(dout + sl * 4) = make_float4(d[0], d[1], d[2], 0.f);
             if (GENC) *reinterpret_cast<float4*>(fout + sl * 4) = make_float4(f[0], f[1], f[2], 0.f);
         }
-        const float tot = wave_sum_compensated(lterm);
-        if (lane == 0) wsum[wave] = tot;
     }
     __syncthreads();   // dL/dy and h_0 .. h_H are in LDS
 
@@ -725,6 +723,13 @@ __global__ __launch_bounds__(64 * (kChainWaves + kGradWaves)) void k_train_fp32(
             float* tp = dcur; dcur = dnxt; dnxt = tp;
         }
     }
+    // The chain waves' loss sums are formed last: nothing before needs them,
+    // and the chain waves wait here while the others finish dW_0.
+    if (chain) {
+        const float tot = wave_sum_compensated(lterm);
+        if (lane == 0) wsum[wave] = tot;
+    }
+    const int any_bad = __syncthreads_or(bad ? 1 : 0);
     if (tid == 0) {
         // compensated combine of the chain waves' loss sums, in wave order
         float ts = 0.0f, tc = 0.0f;
@@ -734,9 +739,8 @@ __global__ __launch_bounds__(64 * (kChainWaves + kGradWaves)) void k_train_fp32(
             ts = u;
         }
         loss_part[tile] = ts + tc;
+        tile_bad[tile] = any_bad ? 1 : 0;
     }
-    const int any_bad = __syncthreads_or(bad ? 1 : 0);
-    if (tid == 0) tile_bad[tile] = any_bad ? 1 : 0;
 }
 
 // Query grid: one workgroup of kQWaves waves per CU (the fragments of every
