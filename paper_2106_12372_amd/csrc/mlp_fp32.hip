@@ -326,20 +326,40 @@ __global__ __launch_bounds__(64 * (kChainWaves + kGradWaves)) void k_train_fp32(
       if (chain) {
         constexpr int RW = RAWL == NRC_RAW14 ? 14 : 16;
         float* h0 = hs + sl * kLd;
-        if (g == 0) {
-            float f[64];
-            if (valid) {
-                const float* rr = enc + src * RW;
-                float x[RW];
+        // The four lane groups of a record share its encoding: groups 0..2 the
+        // frequency encoding of position coordinate g (the same code for the
+        // three, features 12g ..12g + 11), group 3 the rest (features 36 ..63).
+        float x[RW];
+        if (valid) {
+            const float* rr = enc + src * RW;
+            #pragma unroll
+            for (int k = 0; k < RW; ++k) x[k] = rr[k];
+        } else {
+            #pragma unroll
+            for (int k = 0; k < RW; ++k) x[k] = 0.0f;
+        }
+        float f[64];
+        if (g < 3) {
+            float xc[RW];
+            xc[0] = g == 0 ? x[0] : g == 1 ? x[1] : x[2];
+            encode_part<PRESET, RAWL, 0>(xc, f);
+            if (!valid) {
                 #pragma unroll
-                for (int k = 0; k < RW; ++k) x[k] = rr[k];
-                encode_record<PRESET, RAWL>(x, f);
-            } else {
-                #pragma unroll
-                for (int k = 0; k < 64; ++k) f[k] = 0.0f;
+                for (int k = 0; k < 12; ++k) f[k] = 0.0f;
             }
             #pragma unroll
-            for (int q = 0; q < 16; ++q)
+            for (int q = 0; q < 3; ++q)
+                *reinterpret_cast<float4*>(h0 + 12 * g + 4 * q) =
+                    make_float4(f[4 * q], f[4 * q + 1], f[4 * q + 2], f[4 * q + 3]);
+        } else {
+            encode_part<PRESET, RAWL, 3>(x, f);
+            encode_part<PRESET, RAWL, 4>(x, f);
+            if (!valid) {
+                #pragma unroll
+                for (int k = 36; k < 64; ++k) f[k] = 0.0f;
+            }
+            #pragma unroll
+            for (int q = 9; q < 16; ++q)
                 *reinterpret_cast<float4*>(h0 + 4 * q) = make_float4(f[4 * q], f[4 * q + 1], f[4 * q + 2], f[4 * q + 3]);
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
