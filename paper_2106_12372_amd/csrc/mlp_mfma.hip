@@ -563,6 +563,21 @@ __device__ inline void store8(T* dst, const float* f, int q) {
     *reinterpret_cast<V*>(dst + 8 * q) = pack8<T, V>(lo, hi);
 }
 
+// Features f[0 .. 3], rounded to T, into an LDS row (8-byte aligned); the same
+// rounding as store8.
+template <typename T>
+__device__ inline void store4(T* dst, const float* f) {
+    if constexpr (sizeof(T) == 2 && !__is_same(T, _Float16)) {
+        uint2 r;
+        r.x = __builtin_bit_cast(unsigned int, __builtin_convertvector(f32x2{f[0], f[1]}, bf16x2));
+        r.y = __builtin_bit_cast(unsigned int, __builtin_convertvector(f32x2{f[2], f[3]}, bf16x2));
+        *reinterpret_cast<uint2*>(dst) = r;
+    } else {
+        typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+        *reinterpret_cast<h4*>(dst) = __builtin_convertvector(f32x4{f[0], f[1], f[2], f[3]}, h4);
+    }
+}
+
 template <typename T, int PRESET>
 __device__ inline void store_reflectance(T* dst, const float* f, int fcol) {
     f32x4 r = f32x4{1.0f, 1.0f, 1.0f, 0.0f};
@@ -839,20 +854,38 @@ __global__ __launch_bounds__(512) void k_train_mfma(const T* __restrict__ ffr,
             V pre[NPRE > 0 ? NPRE : 1];
             #pragma unroll
             for (int i = 0; i < NPRE; ++i) pre[i] = gf[(i % (2 * MB)) * 64 + (i < 2 * MB ? 0 : lo_f)];
-            if (g == 0) {
-                float f[64];
-                if (valid) {
-                    const float* rr = reinterpret_cast<const float*>(enc) + src * RW;
-                    float x[RW];
+            // The four lane groups of a record share its encoding: groups 0..2
+            // the frequency encoding of position coordinate g (the same code
+            // for the three, features 12g ..12g + 11), group 3 the rest (36 ..63).
+            float x[RW];
+            if (valid) {
+                const float* rr = reinterpret_cast<const float*>(enc) + src * RW;
+                #pragma unroll
+                for (int k = 0; k < RW; ++k) x[k] = rr[k];
+            } else {
+                #pragma unroll
+                for (int k = 0; k < RW; ++k) x[k] = 0.0f;
+            }
+            float f[64];
+            if (g < 3) {
+                float xc[RW];
+                xc[0] = g == 0 ? x[0] : g == 1 ? x[1] : x[2];
+                encode_part<PRESET, RAWL, 0>(xc, f);
+                if (!valid) {
                     #pragma unroll
-                    for (int k = 0; k < RW; ++k) x[k] = rr[k];
-                    encode_record<PRESET, RAWL>(x, f);
-                } else {
-                    #pragma unroll
-                    for (int k = 0; k < 64; ++k) f[k] = 0.0f;
+                    for (int k = 0; k < 12; ++k) f[k] = 0.0f;
                 }
                 #pragma unroll
-                for (int q = 0; q < 8; ++q) store8<T>(h0, f, q);
+                for (int q = 0; q < 3; ++q) store4<T>(h0 + 12 * g + 4 * q, f + 4 * q);
+            } else {
+                encode_part<PRESET, RAWL, 3>(x, f);
+                encode_part<PRESET, RAWL, 4>(x, f);
+                if (!valid) {
+                    #pragma unroll
+                    for (int k = 36; k < 64; ++k) f[k] = 0.0f;
+                }
+                #pragma unroll
+                for (int q = 9; q < 16; ++q) store4<T>(h0 + 4 * q, f + 4 * q);
             }
             wave_lds_sync();
             #pragma unroll
