@@ -269,8 +269,9 @@ template <int ACT> constexpr int fp32_train_waves() { return ACT == kActStore ? 
 
 // Training records given raw (RAWL = their layout, PRESET = the cache's
 // encoding; RAWL < 0: encoded rows): enc then points at the raw records,
-// FP32 [n][14 or 16], and lane j of each chain wave encodes its record into
-// the record's h_0 row before the wave reads its operands back from it.
+// FP32 [n][14 or 16], and the four lanes (g, j) of each chain wave encode
+// record j into the record's h_0 row, a share of its features each, before the
+// wave reads its operands back from it.
 template <bool UPSTREAM, bool GENC, int ACT = kActNone, int RAWL = -1, int PRESET = NRC_PRESET_CONFIG>
 __global__ __launch_bounds__(64 * (kChainWaves + kGradWaves)) void k_train_fp32(
         const float* __restrict__ w, const float* __restrict__ enc, const float* __restrict__ tgt,

@@ -764,9 +764,10 @@ template <int W, int ACT> constexpr int train_helpers() { return ACT == kActStor
 
 // Training records given raw (RAWL = their layout, PRESET = the cache's
 // encoding; RAWL < 0: encoded rows): the kernel's enc argument then points at
-// the raw records, FP32 [n][14 or 16], and lane ln of each chain wave encodes
-// its record into the record's h_0 row, where the stand-alone encoding kernel
-// would have written it, before the wave reads its operands back.
+// the raw records, FP32 [n][14 or 16], and the four lanes (g, j) of each chain
+// wave encode record j, a share of its features each, into the record's h_0
+// row, where the stand-alone encoding kernel would have written it, before the
+// wave reads its operands back.
 template <typename T, int W, bool UPSTREAM, bool GENC, int ACT = kActNone, int RAWL = -1,
           int PRESET = NRC_PRESET_CONFIG>
 __global__ __launch_bounds__(512) void k_train_mfma(const T* __restrict__ ffr,
