@@ -153,8 +153,16 @@ __global__ __launch_bounds__(256) void k_reduce(const float* __restrict__ partia
     }
     float s = 0.0f, c = 0.0f;
     if (sidx < P) {
-        // 16 loads in flight per thread before the (order-preserving) sums
+        // 32 (then 16) loads in flight per thread before the (order-preserving) sums
         int t = grp;
+        for (; t + 31 * kRedGroups < n_tiles; t += 32 * kRedGroups) {
+            float x[32];
+            #pragma unroll
+            for (int u = 0; u < 32; ++u)
+                x[u] = __builtin_nontemporal_load(&partials[(int64_t)(t + u * kRedGroups) * P + sidx]);
+            #pragma unroll
+            for (int u = 0; u < 32; ++u) neumaier_add(s, c, x[u]);
+        }
         for (; t + 15 * kRedGroups < n_tiles; t += 16 * kRedGroups) {
             float x[16];
             #pragma unroll
